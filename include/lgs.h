@@ -1,0 +1,240 @@
+/*
+ * lgs.h - C ABI of the MI355X (gfx950) Top-K Gaussian-splatting renderer.
+ *
+ * The library renders colour, depth and opacity by front-to-back alpha blending
+ * (Eq. 1 of LangGS-SLAM, arXiv 2602.06991, Sec. 3.1), keeps per pixel the K
+ * Gaussians with the largest blending weights (Eq. 2, Sec. 3.2), renders the
+ * D-dimensional language-feature map from those K alone (Eq. 3-4), and provides
+ * the adjoint of every step for the joint optimisation of Sec. 3.4.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers unless marked (host).  Arrays are row-major and
+ *    contiguous.  Per-pixel arrays are indexed p = y * width + x ("pixel-major").
+ *  - The caller owns every buffer.  The library never allocates device memory
+ *    except inside the workspace the caller passes to lgs_bin_sort, and never
+ *    frees caller memory.
+ *  - Every call is asynchronous on `stream` (it may be NULL, the default stream),
+ *    except lgs_bin_sort, which reads the pair count back to the host once.
+ *  - Gradient outputs ACCUMULATE (+=) unless stated; the caller zeroes them.
+ *  - Arguments are validated on the host before any launch.  A failing call
+ *    returns a negative lgs_status, launches nothing and leaves outputs untouched;
+ *    lgs_last_error() then describes it.  No C++ exception crosses the ABI.
+ *  - Calls are reentrant when they use distinct buffers and workspaces.
+ *
+ * Geometry conventions (readings of Sec. 3.1, which follows the 3DGS rasterizer):
+ *  - Gaussians: mean (3), log-scale (3), rotation quaternion (w, x, y, z; need not be
+ *    unit), opacity logit (o = sigmoid), RGB colour (3, no spherical harmonics).
+ *  - Camera: world->camera [R|t] with OpenCV axes (x right, y down, z forward),
+ *    pinhole fx, fy, cx, cy; pixel (x, y) has its centre at (x + 1/2, y + 1/2).
+ *  - Depth key: the FP32 value fmaf(R22, mz, fmaf(R21, my, fmaf(R20, mx, t2))),
+ *    correctly rounded at each step.  It is also the z used for the depth map.
+ *  - Culled (never rendered, zero gradient): a non-finite parameter, an all-zero
+ *    quaternion, a log-scale above 10, an opacity logit below -ln(254) (opacity
+ *    under 1/255), or a depth key <= 0.2.
+ *  - Projection: Sigma2D = J R Sigma R^T J^T + 0.3 I with the lateral position in J
+ *    clamped to 1.3x the half field of view; conic = Sigma2D^-1 stored as (a, b, c)
+ *    with sigma(d) = a dx^2/2 + b dx dy + c dy^2/2 for d = pixel centre - mean2D.
+ *  - Blend: alpha = min(0.99, o exp(-sigma)); a Gaussian with alpha < 1/255 is
+ *    skipped; blending stops BEFORE a Gaussian that would take the transmittance
+ *    T (1 - alpha) below 1e-4.  Ties of the depth key blend in id order.
+ *  - Top-K (Eq. 2): the K largest weights w = alpha T among the blended Gaussians,
+ *    slot 0 the largest; equal weights keep blend order (smaller depth key, then
+ *    smaller id).  Unused slots hold id -1 and weight 0.
+ *  - Tiles are 16 x 16 pixels; results do not depend on the tiling.
+ */
+#ifndef LGS_H
+#define LGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LGS_ABI_VERSION 1
+#define LGS_TILE 16
+
+typedef enum {
+    LGS_OK = 0,
+    LGS_ERR_INVALID_ARG = -1,   /* null or misaligned pointer, bad size */
+    LGS_ERR_UNSUPPORTED = -2,   /* K, D or dtype combination not compiled */
+    LGS_ERR_CAPACITY = -3,      /* pair buffer too small; *n_pairs holds the need */
+    LGS_ERR_HIP = -4            /* a HIP runtime call or launch failed */
+} lgs_status;
+
+typedef enum {
+    LGS_F32 = 0,        /* IEEE binary32 */
+    LGS_BF16 = 1,       /* bfloat16, round-to-nearest-even from FP32 */
+    LGS_FP8_E4M3 = 2    /* OCP E4M3FN code + one FP32 scale per Gaussian row */
+} lgs_dtype;
+
+/* Host struct.  Rt: world->camera [R|t], 3x4 row-major. */
+typedef struct {
+    float Rt[12];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} lgs_camera;
+
+/* ABI version of the loaded library (LGS_ABI_VERSION at build time). */
+int lgs_abi_version(void);
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char *lgs_last_error(void);
+
+/* Supported Top-K sizes, as a host array of *count entries (static storage). */
+const int32_t *lgs_supported_k(int32_t *count);
+
+/*
+ * Projection (Sec. 3.1; the EWA splat of 3DGS), one thread per Gaussian.
+ * In:  means[n*3], log_scales[n*3], quats[n*4] (w,x,y,z), opacity_logits[n], rgb[n*3].
+ * Out: mean2d[n*2] (pixels), conic[n*3] (a,b,c), depth[n] (the depth key),
+ *      opacity[n], tile_rect[n*4] = half-open tile box (tx0, ty0, tx1, ty1) that
+ *      holds every pixel where alpha >= 1/255 (plus a one-pixel margin),
+ *      tiles_touched[n] = (tx1-tx0)*(ty1-ty0), 0 for culled Gaussians.
+ * Errors: INVALID_ARG for n < 0, a null pointer with n > 0, or a camera with
+ * non-positive size or focal length.
+ */
+lgs_status lgs_project_fwd(const lgs_camera *cam, int32_t n,
+                           const float *means, const float *log_scales, const float *quats,
+                           const float *opacity_logits, const float *rgb,
+                           float *mean2d, float *conic, float *depth, float *opacity,
+                           int32_t *tile_rect, int32_t *tiles_touched, hipStream_t stream);
+
+/*
+ * Workspace bytes lgs_bin_sort needs for n Gaussians, an image of width x height and
+ * room for max_pairs (tile, Gaussian) pairs.  *bytes is a host pointer.
+ */
+lgs_status lgs_bin_sort_workspace(int32_t n, int32_t width, int32_t height, int64_t max_pairs,
+                                  size_t *bytes);
+
+/*
+ * Tile binning and depth sort (the tile-based rasterizer of 3DGS that Sec. 3.1
+ * follows).  Every Gaussian is duplicated into each tile of its tile_rect; the pairs
+ * are ordered by (tile, depth key, Gaussian id) with an on-device radix sort.
+ * Out: sorted_ids[max_pairs] (the first *n_pairs are valid),
+ *      tile_ranges[tiles*2] = [start, end) of every tile's run in sorted_ids,
+ *      tiles = ceil(width/16) * ceil(height/16), tile index ty * ceil(width/16) + tx.
+ * *n_pairs (host) receives the pair count.  If it exceeds max_pairs the call
+ * returns LGS_ERR_CAPACITY with *n_pairs set to the need and the outputs
+ * untouched: grow the buffers and call again.  This call synchronises `stream`
+ * once to read the count.  workspace: ws_bytes >= lgs_bin_sort_workspace(...),
+ * 256-byte aligned.
+ */
+lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float *depth,
+                        const int32_t *tile_rect, const int32_t *tiles_touched,
+                        void *workspace, size_t ws_bytes, int64_t max_pairs,
+                        int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
+                        hipStream_t stream);
+
+/*
+ * Colour/depth/opacity alpha blending (Eq. 1) that records the Top-K (Eq. 2) ids
+ * and weights of every pixel during the same pass (Sec. 3.2, implementation).
+ * In:  the projection outputs, rgb[n*3], and the lgs_bin_sort outputs.
+ * Out: color[P*3], depth_map[P], alpha_map[P] (= 1 - T_final), T_final[P],
+ *      n_contrib[P] (entries of the tile's sorted run up to and including the last
+ *      blended Gaussian; the backward replays from there), topk_ids[P*k],
+ *      topk_w[P*k] (raw weights w), with P = width * height.
+ * Errors: UNSUPPORTED if k is not one of lgs_supported_k().
+ */
+lgs_status lgs_rasterize_topk_fwd(const lgs_camera *cam, int32_t k,
+                                  const float *mean2d, const float *conic, const float *opacity,
+                                  const float *rgb, const float *depth,
+                                  const int32_t *sorted_ids, const int32_t *tile_ranges,
+                                  float *color, float *depth_map, float *alpha_map,
+                                  float *T_final, int32_t *n_contrib,
+                                  int32_t *topk_ids, float *topk_w, hipStream_t stream);
+
+/*
+ * Top-K feature render (Eq. 3-4): W = sum_k w_k, F[p] = sum_k (w_k / W) f[id_k],
+ * F[p] = 0 where W = 0; FP32 accumulation, one rounding at the store.
+ * feat[n*d] in feat_dt (FP32, BF16 or FP8 codes with feat_scale[n]: value =
+ * code * scale); F[n_pix*d] in map_dt (FP32 or BF16).  Pixels are stacked views of
+ * width x height images; n_pix = width * height * views.
+ * Supported: (F32 -> F32), (BF16 -> BF16), (BF16 -> F32), (FP8 -> BF16), (FP8 -> F32).
+ * d must be a positive multiple of 8; feat and F 16-byte aligned.
+ */
+lgs_status lgs_feature_render_fwd(int32_t width, int32_t height, int32_t views, int32_t k,
+                                  int32_t d, lgs_dtype feat_dt, const void *feat,
+                                  const float *feat_scale, const int32_t *topk_ids,
+                                  const float *topk_w, lgs_dtype map_dt, void *F,
+                                  hipStream_t stream);
+
+/*
+ * Adjoint of the feature render.  For every pixel with W > 0:
+ *   g_k = <dL_dF[p], f_k>,  gamma_k = (g_k - sum_j w'_j g_j) / W,
+ *   dL_dfeat[id_k] += (w_k / W) dL_dF[p]   (FP32, accumulated),
+ *   dL_dtopkw[p*k + k'] = gamma_k          (overwritten; 0 where W = 0 or unused).
+ * Same dtype and layout rules as the forward; dL_dF is in map_dt.
+ */
+lgs_status lgs_feature_render_bwd(int32_t width, int32_t height, int32_t views, int32_t k,
+                                  int32_t d, lgs_dtype feat_dt, const void *feat,
+                                  const float *feat_scale, const int32_t *topk_ids,
+                                  const float *topk_w, lgs_dtype map_dt, const void *dL_dF,
+                                  float *dL_dfeat, float *dL_dtopkw, hipStream_t stream);
+
+/*
+ * Adjoint of the blend (Eq. 1) including the Top-K weight path, replayed back to
+ * front per pixel from T_final and n_contrib.  dL_dalpha and dL_dtopkw may be NULL.
+ * Accumulates per-Gaussian screen-space gradients:
+ *   dL_dmean2d[n*2], dL_dconic[n*3] (w.r.t. a, b, c), dL_dopacity[n], dL_drgb[n*3],
+ *   dL_ddepth_g[n] (w.r.t. the depth z of each Gaussian).
+ */
+lgs_status lgs_rasterize_topk_bwd(const lgs_camera *cam, int32_t k,
+                                  const float *mean2d, const float *conic, const float *opacity,
+                                  const float *rgb, const float *depth,
+                                  const int32_t *sorted_ids, const int32_t *tile_ranges,
+                                  const float *T_final, const int32_t *n_contrib,
+                                  const int32_t *topk_ids, const float *topk_w,
+                                  const float *dL_dcolor, const float *dL_ddepth,
+                                  const float *dL_dalpha, const float *dL_dtopkw,
+                                  float *dL_dmean2d, float *dL_dconic, float *dL_dopacity,
+                                  float *dL_drgb, float *dL_ddepth_g, hipStream_t stream);
+
+/*
+ * Adjoint of the projection: chain rule from the screen-space gradients to the
+ * Gaussian parameters, accumulated into dL_dmeans[n*3], dL_dlog_scales[n*3],
+ * dL_dquats[n*4] and dL_dopacity_logits[n].  Culled Gaussians receive nothing.
+ */
+lgs_status lgs_project_bwd(const lgs_camera *cam, int32_t n,
+                           const float *means, const float *log_scales, const float *quats,
+                           const float *opacity_logits, const float *rgb,
+                           const float *dL_dmean2d, const float *dL_dconic,
+                           const float *dL_dopacity, const float *dL_ddepth_g,
+                           float *dL_dmeans, float *dL_dlog_scales, float *dL_dquats,
+                           float *dL_dopacity_logits, hipStream_t stream);
+
+/*
+ * Storage quantization of the feature table (the precision forms of the renderer):
+ * dst_dt = BF16: round-to-nearest-even; dst_dt = FP8_E4M3: per row, scale
+ * s = 2^floor(log2(amax / 224)) (s = 1 for an all-zero row) so x / s is exact and
+ * amax / s lies in [224, 448), then round-to-nearest-even E4M3FN codes of x / s,
+ * saturating at +-448.  dst_scale[n] is written for FP8 only.
+ */
+lgs_status lgs_quantize_features(int32_t n, int32_t d, const float *src, lgs_dtype dst_dt,
+                                 void *dst, float *dst_scale, hipStream_t stream);
+
+/*
+ * L1 loss gradient (Eq. 9 and the L1 terms of Eq. 8): grad[i] = scale * sign(x[i] -
+ * target[i]), sign(0) = 0, over n elements of dtype dt (F32 or BF16, all three
+ * arrays the same dtype).
+ */
+lgs_status lgs_l1_grad(int64_t n, lgs_dtype dt, const void *x, const void *target, float scale,
+                       void *grad, hipStream_t stream);
+
+/*
+ * Number of distinct Gaussians over all pixels' Top-K slots (ids in [0, n) in
+ * topk_ids[n_pix*k]); the U of the feature adjoint's memory traffic.  flags[n + 1]
+ * is caller scratch (overwritten); *count (host) receives the result.
+ * Synchronises `stream`.
+ */
+lgs_status lgs_union_count(int64_t n_pix, int32_t k, int32_t n, const int32_t *topk_ids,
+                           int32_t *flags, int64_t *count, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGS_H */

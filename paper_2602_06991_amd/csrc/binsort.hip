@@ -1,0 +1,388 @@
+// Tile binning and depth sort of the tile-based rasterizer (Sec. 3.1 follows 3DGS).
+//
+// Instead of one radix sort of 64-bit (tile | depth) keys over every (tile, Gaussian)
+// pair, the Gaussians are sorted once by their 32-bit depth key (N items), the pairs
+// are then written out in that depth order, and a stable sort by the tile index alone
+// (ceil(log2 tiles) bits) finishes the (tile, depth, id) order.  Equal depth keys
+// keep id order because every pass is stable and the first starts in id order.
+//
+// Every sort pass is an LSD radix pass with 8-bit digits in three launches:
+// per-block digit histograms, a per-digit scan over blocks, and a stable scatter in
+// which each wave ranks equal digits with ballots.
+#include "lgs_device.hpp"
+#include "lgs_host.hpp"
+
+namespace lgs {
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortIpt = 16;
+constexpr int kSortItems = kSortThreads * kSortIpt;   // 4096 items per block
+constexpr int kScanItems = 4096;
+
+// Exclusive scan of one value per thread over a 256-thread block.
+template <typename T>
+__device__ T block_exscan256(T v, T *lds, T &total) {
+    int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        T x = t >= off ? lds[t - off] : (T)0;
+        __syncthreads();
+        lds[t] += x;
+        __syncthreads();
+    }
+    T inc = lds[t];
+    total = lds[255];
+    __syncthreads();
+    return inc - v;
+}
+
+__global__ __launch_bounds__(256) void depth_keys_kernel(int n, const float *__restrict__ depth,
+                                                         const int *__restrict__ touched,
+                                                         uint32_t *__restrict__ keys,
+                                                         int *__restrict__ vals) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // positive depths order like their bit patterns; culled Gaussians go last
+    keys[i] = touched[i] > 0 ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
+    vals[i] = i;
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
+                                                                  int n, int shift, int nb,
+                                                                  int *__restrict__ hist) {
+    __shared__ int h[256];
+    int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    long base = (long)blockIdx.x * kSortItems;
+    for (int r = 0; r < kSortIpt; ++r) {
+        long i = base + r * kSortThreads + t;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[t * nb + blockIdx.x] = h[t];
+}
+
+// One block per digit: exclusive scan of that digit's per-block counts, in place.
+__global__ __launch_bounds__(256) void radix_scan_digits_kernel(int *__restrict__ hist, int nb,
+                                                                int *__restrict__ totals) {
+    __shared__ int lds[256];
+    int d = blockIdx.x;
+    int *row = hist + (long)d * nb;
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        int i = b0 + threadIdx.x;
+        int v = i < nb ? row[i] : 0;
+        int tot;
+        int ex = block_exscan256(v, lds, tot);
+        if (i < nb) row[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[d] = carry;
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const uint32_t *__restrict__ kin, const int *__restrict__ vin, int n, int shift, int nb,
+    const int *__restrict__ hist, const int *__restrict__ totals, uint32_t *__restrict__ kout,
+    int *__restrict__ vout) {
+    __shared__ int base[256];
+    __shared__ int run[256];
+    __shared__ int wcnt[4][256];
+    __shared__ int pre[4][256];
+    __shared__ int scan_lds[256];
+    int t = threadIdx.x;
+    int wave = t >> 6;
+    int lane = t & 63;
+    int tot;
+    int ex = block_exscan256(totals[t], scan_lds, tot);
+    base[t] = ex + hist[t * nb + blockIdx.x];
+    run[t] = 0;
+    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    long b0 = (long)blockIdx.x * kSortItems;
+    for (int r = 0; r < kSortIpt; ++r) {
+        long i = b0 + r * kSortThreads + t;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u;
+        int val = valid ? vin[i] : 0;
+        uint32_t d = (key >> shift) & 255u;
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            bool on = (d >> bit) & 1u;
+            uint64_t bb = __ballot(on);
+            mask &= on ? bb : ~bb;
+        }
+        int rank = __popcll(mask & lt);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(mask);
+        __syncthreads();
+        {
+            int c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+            int p = run[t];
+            pre[0][t] = p;
+            pre[1][t] = p + c0;
+            pre[2][t] = p + c0 + c1;
+            pre[3][t] = p + c0 + c1 + c2;
+            run[t] = p + c0 + c1 + c2 + c3;
+            wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
+        }
+        __syncthreads();
+        if (valid) {
+            int dst = base[d] + pre[wave][d] + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- int64 scan
+
+__global__ __launch_bounds__(256) void gather_counts_kernel(int n, const int *__restrict__ order,
+                                                            const int *__restrict__ touched,
+                                                            long long *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cnt[i] = touched[order[i]];
+}
+
+__global__ __launch_bounds__(256) void scan_partial_kernel(const long long *__restrict__ in, long n,
+                                                           long long *__restrict__ sums) {
+    __shared__ long long lds[256];
+    long base = (long)blockIdx.x * kScanItems;
+    long long s = 0;
+    for (int j = 0; j < kScanItems / 256; ++j) {
+        long i = base + j * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    long long tot;
+    block_exscan256(s, lds, tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void scan_sums_kernel(long long *__restrict__ sums, int nb,
+                                                        long long *__restrict__ total) {
+    __shared__ long long lds[256];
+    long long carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        int i = b0 + threadIdx.x;
+        long long v = i < nb ? sums[i] : 0;
+        long long tot;
+        long long ex = block_exscan256(v, lds, tot);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void scan_final_kernel(const long long *__restrict__ in, long n,
+                                                         const long long *__restrict__ sums,
+                                                         long long *__restrict__ out) {
+    __shared__ long long lds[256];
+    // thread t owns 16 consecutive items of the block's 4096
+    constexpr int per = kScanItems / 256;
+    long base = (long)blockIdx.x * kScanItems + (long)threadIdx.x * per;
+    long long v[per];
+    long long s = 0;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        long i = base + j;
+        v[j] = i < n ? in[i] : 0;
+        s += v[j];
+    }
+    long long tot;
+    long long run = block_exscan256(s, lds, tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        long i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+__global__ __launch_bounds__(256) void duplicate_kernel(int n, const int *__restrict__ order,
+                                                        const long long *__restrict__ offs,
+                                                        const int4 *__restrict__ rect,
+                                                        const int *__restrict__ touched, int ntx,
+                                                        uint32_t *__restrict__ tile_keys,
+                                                        int *__restrict__ ids) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int g = order[s];
+    if (touched[g] <= 0) return;
+    int4 r = rect[g];
+    long o = offs[s];
+    for (int ty = r.y; ty < r.w; ++ty)
+        for (int tx = r.x; tx < r.z; ++tx) {
+            tile_keys[o] = (uint32_t)(ty * ntx + tx);
+            ids[o] = g;
+            ++o;
+        }
+}
+
+__global__ __launch_bounds__(256) void zero_ranges_kernel(int n2, int *__restrict__ ranges) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n2) ranges[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void mark_ranges_kernel(int m, const uint32_t *__restrict__ keys,
+                                                          int *__restrict__ ranges) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) ranges[2 * k] = i;
+    if (i == m - 1 || keys[i + 1] != k) ranges[2 * k + 1] = i + 1;
+}
+
+// ---------------------------------------------------------------- host side
+
+struct Layout {
+    size_t dk0, dv0, dk1, dv1, cnt, offs, sums, total, hist, totals, pk0, pk1, pv1, bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout_of(long n, long max_pairs) {
+    Layout L;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = at;
+        at = align256(at + bytes);
+        return o;
+    };
+    long items = n > max_pairs ? n : max_pairs;
+    long nb_sort = (items + kSortItems - 1) / kSortItems;
+    long nb_scan = (n + kScanItems - 1) / kScanItems;
+    L.dk0 = take(4 * (size_t)n);
+    L.dv0 = take(4 * (size_t)n);
+    L.dk1 = take(4 * (size_t)n);
+    L.dv1 = take(4 * (size_t)n);
+    L.cnt = take(8 * (size_t)n);
+    L.offs = take(8 * (size_t)n);
+    L.sums = take(8 * (size_t)(nb_scan + 1));
+    L.total = take(8);
+    L.hist = take(4 * 256 * (size_t)(nb_sort + 1));
+    L.totals = take(4 * 256);
+    L.pk0 = take(4 * (size_t)max_pairs);
+    L.pk1 = take(4 * (size_t)max_pairs);
+    L.pv1 = take(4 * (size_t)max_pairs);
+    L.bytes = at;
+    return L;
+}
+
+// One stable LSD pass over bits [shift, shift + 8).
+lgs_status radix_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int n,
+                      int shift, int *hist, int *totals, hipStream_t st) {
+    int nb = (n + kSortItems - 1) / kSortItems;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, n, shift, nb, hist);
+    hipLaunchKernelGGL(radix_scan_digits_kernel, dim3(256), dim3(256), 0, st, hist, nb, totals);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, n, shift,
+                       nb, hist, totals, kout, vout);
+    return check_launch("radix pass");
+}
+
+}  // namespace
+}  // namespace lgs
+
+using namespace lgs;
+
+extern "C" lgs_status lgs_bin_sort_workspace(int32_t n, int32_t width, int32_t height,
+                                             int64_t max_pairs, size_t *bytes) {
+    LGS_REQUIRE(bytes, LGS_ERR_INVALID_ARG, "bytes is NULL");
+    LGS_REQUIRE(n >= 0 && width > 0 && height > 0 && max_pairs >= 0 && max_pairs <= 0x7FFFFFFF,
+                LGS_ERR_INVALID_ARG, "lgs_bin_sort_workspace: bad sizes");
+    *bytes = layout_of(n, max_pairs).bytes;
+    return LGS_OK;
+}
+
+extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float *depth,
+                                   const int32_t *tile_rect, const int32_t *tiles_touched,
+                                   void *workspace, size_t ws_bytes, int64_t max_pairs,
+                                   int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
+                                   hipStream_t stream) {
+    lgs_status st = check_camera(cam);
+    if (st) return st;
+    LGS_REQUIRE(n_pairs, LGS_ERR_INVALID_ARG, "n_pairs is NULL");
+    LGS_REQUIRE(n >= 0 && max_pairs >= 0 && max_pairs <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG,
+                "lgs_bin_sort: bad sizes");
+    LGS_REQUIRE(tile_ranges, LGS_ERR_INVALID_ARG, "tile_ranges is NULL");
+    const int ntx = tiles_x(cam->width), nty = tiles_y(cam->height);
+    const int T = ntx * nty;
+    if (n == 0) {
+        hipLaunchKernelGGL(zero_ranges_kernel, dim3((2 * T + 255) / 256), dim3(256), 0, stream,
+                           2 * T, tile_ranges);
+        *n_pairs = 0;
+        return check_launch("bin_sort zero");
+    }
+    LGS_REQUIRE(depth && tile_rect && tiles_touched && workspace && (sorted_ids || max_pairs == 0),
+                LGS_ERR_INVALID_ARG, "lgs_bin_sort: NULL pointer");
+    LGS_REQUIRE(((uintptr_t)workspace & 255u) == 0, LGS_ERR_INVALID_ARG,
+                "workspace must be 256-byte aligned");
+    LGS_REQUIRE(aligned16(tile_rect), LGS_ERR_INVALID_ARG, "tile_rect must be 16-byte aligned");
+    Layout L = layout_of(n, max_pairs);
+    LGS_REQUIRE(ws_bytes >= L.bytes, LGS_ERR_INVALID_ARG, "workspace too small: %zu < %zu", ws_bytes,
+                L.bytes);
+    char *ws = (char *)workspace;
+    uint32_t *dk0 = (uint32_t *)(ws + L.dk0), *dk1 = (uint32_t *)(ws + L.dk1);
+    int *dv0 = (int *)(ws + L.dv0), *dv1 = (int *)(ws + L.dv1);
+    long long *cnt = (long long *)(ws + L.cnt), *offs = (long long *)(ws + L.offs);
+    long long *sums = (long long *)(ws + L.sums), *total = (long long *)(ws + L.total);
+    int *hist = (int *)(ws + L.hist), *totals = (int *)(ws + L.totals);
+
+    // 1. sort Gaussians by depth key (4 passes of 8 bits), ending in dk0/dv0
+    unsigned g1 = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(depth_keys_kernel, dim3(g1), dim3(256), 0, stream, n, depth, tiles_touched,
+                       dk0, dv0);
+    for (int pass = 0; pass < 4; ++pass) {
+        bool even = (pass & 1) == 0;
+        st = radix_pass(even ? dk0 : dk1, even ? dv0 : dv1, even ? dk1 : dk0, even ? dv1 : dv0, n,
+                        8 * pass, hist, totals, stream);
+        if (st) return st;
+    }
+    // 2. pair offsets in depth order
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(g1), dim3(256), 0, stream, n, dv0, tiles_touched,
+                       cnt);
+    int nbs = (n + kScanItems - 1) / kScanItems;
+    hipLaunchKernelGGL(scan_partial_kernel, dim3(nbs), dim3(256), 0, stream, cnt, (long)n, sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, stream, sums, nbs, total);
+    hipLaunchKernelGGL(scan_final_kernel, dim3(nbs), dim3(256), 0, stream, cnt, (long)n, sums, offs);
+    st = check_launch("bin_sort scan");
+    if (st) return st;
+    long long M = 0;
+    st = check_hip(hipMemcpyAsync(&M, total, sizeof(M), hipMemcpyDeviceToHost, stream), "pair count copy");
+    if (st) return st;
+    st = check_hip(hipStreamSynchronize(stream), "pair count sync");
+    if (st) return st;
+    *n_pairs = M;
+    if (M > max_pairs) {
+        set_error("lgs_bin_sort: %lld pairs exceed max_pairs %lld", M, (long long)max_pairs);
+        return LGS_ERR_CAPACITY;
+    }
+    hipLaunchKernelGGL(zero_ranges_kernel, dim3((2 * T + 255) / 256), dim3(256), 0, stream, 2 * T,
+                       tile_ranges);
+    if (M == 0) return check_launch("bin_sort zero");
+    // 3. duplicate into (tile, id) pairs in depth order, then stable sort by tile
+    int tile_bits = 0;
+    while ((1 << tile_bits) < T) ++tile_bits;
+    int passes = (tile_bits + 7) / 8;
+    uint32_t *pk0 = (uint32_t *)(ws + L.pk0), *pk1 = (uint32_t *)(ws + L.pk1);
+    int *pv1 = (int *)(ws + L.pv1);
+    // the last pass must land in sorted_ids: start there if the pass count is even
+    int *pv0 = sorted_ids;
+    uint32_t *kcur = pk0, *knext = pk1;
+    int *vcur = (passes % 2 == 0) ? pv0 : pv1, *vnext = (passes % 2 == 0) ? pv1 : pv0;
+    hipLaunchKernelGGL(duplicate_kernel, dim3(g1), dim3(256), 0, stream, n, dv0, offs,
+                       (const int4 *)tile_rect, tiles_touched, ntx, kcur, vcur);
+    st = check_launch("bin_sort duplicate");
+    if (st) return st;
+    for (int pass = 0; pass < passes; ++pass) {
+        st = radix_pass(kcur, vcur, knext, vnext, (int)M, 8 * pass, hist, totals, stream);
+        if (st) return st;
+        uint32_t *tk = kcur; kcur = knext; knext = tk;
+        int *tv = vcur; vcur = vnext; vnext = tv;
+    }
+    hipLaunchKernelGGL(mark_ranges_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream,
+                       (int)M, kcur, tile_ranges);
+    return check_launch("bin_sort ranges");
+}

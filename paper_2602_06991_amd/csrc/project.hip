@@ -1,0 +1,321 @@
+// Projection of 3D Gaussians to screen-space splats (Sec. 3.1, the EWA splat of the
+// 3DGS rasterizer the paper follows) and its adjoint.  One thread per Gaussian;
+// FP32 throughout, with the depth key as an explicit fused chain.
+#include "lgs_device.hpp"
+#include "lgs_host.hpp"
+
+namespace lgs {
+namespace {
+
+struct CamDev {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int W, H;
+    float limx, limy;   // guard band: 1.3x the half field of view (tan)
+};
+
+CamDev make_cam(const lgs_camera *c) {
+    CamDev d;
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) d.R[3 * i + j] = c->Rt[4 * i + j];
+        d.t[i] = c->Rt[4 * i + 3];
+    }
+    d.fx = c->fx; d.fy = c->fy; d.cx = c->cx; d.cy = c->cy;
+    d.W = c->width; d.H = c->height;
+    d.limx = 1.3f * (0.5f * (float)c->width / c->fx);
+    d.limy = 1.3f * (0.5f * (float)c->height / c->fy);
+    return d;
+}
+
+// Everything the forward computes for one Gaussian, kept for the adjoint.
+struct Splat {
+    float t[3];          // view-space mean; t[2] is the depth key
+    float s[3];          // scales
+    float qn[4], qlen;   // unit quaternion and |q|
+    float Rq[9];         // rotation of the unit quaternion
+    float Sg[6];         // 3D covariance xx xy xz yy yz zz
+    float T[6];          // J R, 2x3 row-major
+    float A, B, C;       // Sigma2D
+    float ca, cb, cc;    // conic
+    float mx, my, o;
+    bool clampx, clampy;
+};
+
+__device__ __forceinline__ bool finite3(const float *p) {
+    return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
+}
+
+// Returns false for a culled Gaussian.
+__device__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means,
+                         const float *__restrict__ log_scales, const float *__restrict__ quats,
+                         const float *__restrict__ opacity_logits, const float *__restrict__ rgb,
+                         Splat &s) {
+    const float *m = means + 3 * g;
+    const float *ls = log_scales + 3 * g;
+    const float *q = quats + 4 * g;
+    float opl = opacity_logits[g];
+    if (!finite3(m) || !finite3(ls) || !finite3(rgb + 3 * g) || !isfinite(opl) ||
+        !isfinite(q[0]) || !isfinite(q[1]) || !isfinite(q[2]) || !isfinite(q[3]))
+        return false;
+    if (q[0] == 0.0f && q[1] == 0.0f && q[2] == 0.0f && q[3] == 0.0f) return false;
+    if (ls[0] > 10.0f || ls[1] > 10.0f || ls[2] > 10.0f) return false;
+    if (opl < -5.53733427f) return false;                 // opacity < 1/255
+    float mx = m[0], my = m[1], mz = m[2];
+    float z = fmaf(c.R[8], mz, fmaf(c.R[7], my, fmaf(c.R[6], mx, c.t[2])));
+    if (!(z > 0.2f)) return false;
+    s.t[0] = fmaf(c.R[0], mx, fmaf(c.R[1], my, fmaf(c.R[2], mz, c.t[0])));
+    s.t[1] = fmaf(c.R[3], mx, fmaf(c.R[4], my, fmaf(c.R[5], mz, c.t[1])));
+    s.t[2] = z;
+    for (int i = 0; i < 3; ++i) s.s[i] = expf(ls[i]);
+    // normalise the quaternion; pre-scale by its largest entry so tiny ones survive
+    float qm = fmaxf(fmaxf(fabsf(q[0]), fabsf(q[1])), fmaxf(fabsf(q[2]), fabsf(q[3])));
+    float qs[4] = {q[0] / qm, q[1] / qm, q[2] / qm, q[3] / qm};
+    float ql = sqrtf(qs[0] * qs[0] + qs[1] * qs[1] + qs[2] * qs[2] + qs[3] * qs[3]);
+    for (int i = 0; i < 4; ++i) s.qn[i] = qs[i] / ql;
+    s.qlen = ql * qm;
+    float w = s.qn[0], x = s.qn[1], y = s.qn[2], zq = s.qn[3];
+    float *R = s.Rq;
+    R[0] = 1.f - 2.f * (y * y + zq * zq); R[1] = 2.f * (x * y - w * zq);       R[2] = 2.f * (x * zq + w * y);
+    R[3] = 2.f * (x * y + w * zq);       R[4] = 1.f - 2.f * (x * x + zq * zq); R[5] = 2.f * (y * zq - w * x);
+    R[6] = 2.f * (x * zq - w * y);       R[7] = 2.f * (y * zq + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+    // Sigma = M M^T, M = Rq diag(s)
+    float M[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = R[3 * i + j] * s.s[j];
+    int k6 = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j)
+            s.Sg[k6++] = M[3 * i] * M[3 * j] + M[3 * i + 1] * M[3 * j + 1] + M[3 * i + 2] * M[3 * j + 2];
+    // perspective Jacobian with the guard-band clamp
+    float tx = s.t[0], ty = s.t[1];
+    float rx = tx / z, ry = ty / z;
+    s.clampx = rx < -c.limx || rx > c.limx;
+    s.clampy = ry < -c.limy || ry > c.limy;
+    float xt = fminf(fmaxf(rx, -c.limx), c.limx) * z;
+    float yt = fminf(fmaxf(ry, -c.limy), c.limy) * z;
+    float j00 = c.fx / z, j02 = -c.fx * xt / (z * z);
+    float j11 = c.fy / z, j12 = -c.fy * yt / (z * z);
+    for (int j = 0; j < 3; ++j) {
+        s.T[j] = j00 * c.R[j] + j02 * c.R[6 + j];
+        s.T[3 + j] = j11 * c.R[3 + j] + j12 * c.R[6 + j];
+    }
+    // Sigma2D = T Sigma T^T + 0.3 I
+    const float *S = s.Sg;
+    float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+    float TS0[3], TS1[3];
+    for (int j = 0; j < 3; ++j) {
+        TS0[j] = s.T[0] * Sf[j] + s.T[1] * Sf[3 + j] + s.T[2] * Sf[6 + j];
+        TS1[j] = s.T[3] * Sf[j] + s.T[4] * Sf[3 + j] + s.T[5] * Sf[6 + j];
+    }
+    s.A = TS0[0] * s.T[0] + TS0[1] * s.T[1] + TS0[2] * s.T[2] + 0.3f;
+    s.B = TS0[0] * s.T[3] + TS0[1] * s.T[4] + TS0[2] * s.T[5];
+    s.C = TS1[0] * s.T[3] + TS1[1] * s.T[4] + TS1[2] * s.T[5] + 0.3f;
+    float det = s.A * s.C - s.B * s.B;
+    if (!(det > 0.0f) || !isfinite(det)) return false;
+    s.ca = s.C / det;
+    s.cb = -s.B / det;
+    s.cc = s.A / det;
+    s.mx = c.fx * tx / z + c.cx;
+    s.my = c.fy * ty / z + c.cy;
+    s.o = 1.0f / (1.0f + expf(-opl));
+    return true;
+}
+
+__global__ __launch_bounds__(256) void project_fwd_kernel(
+    CamDev c, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
+    const float *__restrict__ quats, const float *__restrict__ opacity_logits,
+    const float *__restrict__ rgb, float2 *__restrict__ mean2d, float *__restrict__ conic,
+    float *__restrict__ depth, float *__restrict__ opacity, int4 *__restrict__ tile_rect,
+    int *__restrict__ tiles_touched) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    Splat s;
+    if (!splat_of(c, g, means, log_scales, quats, opacity_logits, rgb, s)) {
+        mean2d[g] = make_float2(0.f, 0.f);
+        conic[3 * g] = conic[3 * g + 1] = conic[3 * g + 2] = 0.f;
+        depth[g] = 0.f;
+        opacity[g] = 0.f;
+        tile_rect[g] = make_int4(0, 0, 0, 0);
+        tiles_touched[g] = 0;
+        return;
+    }
+    mean2d[g] = make_float2(s.mx, s.my);
+    conic[3 * g] = s.ca;
+    conic[3 * g + 1] = s.cb;
+    conic[3 * g + 2] = s.cc;
+    depth[g] = s.t[2];
+    opacity[g] = s.o;
+    // support {alpha >= 1/255} is the ellipse d^T Sigma2D^-1 d <= 2 ln(255 o); its box
+    // has half extents sqrt(2 ln(255 o) A), sqrt(2 ln(255 o) C); pad by a pixel
+    float lvl = fmaxf(2.0f * logf(255.0f * s.o), 0.0f);
+    float hx = sqrtf(lvl * s.A), hy = sqrtf(lvl * s.C);
+    float fx0 = ceilf(s.mx - hx - 0.5f) - 1.0f, fx1 = floorf(s.mx + hx - 0.5f) + 1.0f;
+    float fy0 = ceilf(s.my - hy - 0.5f) - 1.0f, fy1 = floorf(s.my + hy - 0.5f) + 1.0f;
+    fx0 = fmaxf(fx0, 0.0f);
+    fy0 = fmaxf(fy0, 0.0f);
+    fx1 = fminf(fx1, (float)(c.W - 1));
+    fy1 = fminf(fy1, (float)(c.H - 1));
+    if (!(fx1 >= fx0) || !(fy1 >= fy0)) {
+        tile_rect[g] = make_int4(0, 0, 0, 0);
+        tiles_touched[g] = 0;
+        return;
+    }
+    int tx0 = (int)fx0 / kTile, tx1 = (int)fx1 / kTile + 1;
+    int ty0 = (int)fy0 / kTile, ty1 = (int)fy1 / kTile + 1;
+    tile_rect[g] = make_int4(tx0, ty0, tx1, ty1);
+    tiles_touched[g] = (tx1 - tx0) * (ty1 - ty0);
+}
+
+__global__ __launch_bounds__(256) void project_bwd_kernel(
+    CamDev c, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
+    const float *__restrict__ quats, const float *__restrict__ opacity_logits,
+    const float *__restrict__ rgb, const float *__restrict__ d_mean2d,
+    const float *__restrict__ d_conic, const float *__restrict__ d_opac,
+    const float *__restrict__ d_depth, float *__restrict__ d_means, float *__restrict__ d_ls,
+    float *__restrict__ d_quats, float *__restrict__ d_opl) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    Splat s;
+    if (!splat_of(c, g, means, log_scales, quats, opacity_logits, rgb, s)) return;
+    float gmx = d_mean2d[2 * g], gmy = d_mean2d[2 * g + 1];
+    float ga = d_conic[3 * g], gb = d_conic[3 * g + 1], gc = d_conic[3 * g + 2];
+    float go = d_opac[g], gz = d_depth[g];
+
+    // conic -> Sigma2D: dSigma2D = -Q G Q with G = [[ga, gb/2], [gb/2, gc]]
+    float a = s.ca, b = s.cb, cq = s.cc;
+    float hb = 0.5f * gb;
+    float q00 = a * ga + b * hb, q01 = a * hb + b * gc;
+    float q10 = b * ga + cq * hb, q11 = b * hb + cq * gc;
+    float G00 = -(q00 * a + q01 * b);
+    float G01 = -(q00 * b + q01 * cq);
+    float G11 = -(q10 * b + q11 * cq);
+    // Sigma2D = T Sigma T^T: dSigma = T^T G T, dT = 2 G T Sigma
+    const float *T = s.T;
+    float GT0[3], GT1[3];   // rows of G T
+    for (int j = 0; j < 3; ++j) {
+        GT0[j] = G00 * T[j] + G01 * T[3 + j];
+        GT1[j] = G01 * T[j] + G11 * T[3 + j];
+    }
+    float dS[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dS[3 * i + j] = T[i] * GT0[j] + T[3 + i] * GT1[j];
+    const float *S = s.Sg;
+    float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+    float dT[6];
+    for (int j = 0; j < 3; ++j) {
+        dT[j] = 2.f * (GT0[0] * Sf[j] + GT0[1] * Sf[3 + j] + GT0[2] * Sf[6 + j]);
+        dT[3 + j] = 2.f * (GT1[0] * Sf[j] + GT1[1] * Sf[3 + j] + GT1[2] * Sf[6 + j]);
+    }
+    // T = J R: dJ = dT R^T; only J00, J02, J11, J12 are non-zero
+    float dJ00 = dT[0] * c.R[0] + dT[1] * c.R[1] + dT[2] * c.R[2];
+    float dJ02 = dT[0] * c.R[6] + dT[1] * c.R[7] + dT[2] * c.R[8];
+    float dJ11 = dT[3] * c.R[3] + dT[4] * c.R[4] + dT[5] * c.R[5];
+    float dJ12 = dT[3] * c.R[6] + dT[4] * c.R[7] + dT[5] * c.R[8];
+    float tx = s.t[0], ty = s.t[1], z = s.t[2];
+    float iz = 1.0f / z, iz2 = iz * iz;
+    float dtx = 0.f, dty = 0.f, dtz = 0.f;
+    dtz -= (c.fx * dJ00 + c.fy * dJ11) * iz2;
+    if (!s.clampx) {
+        dtx -= c.fx * iz2 * dJ02;
+        dtz += 2.f * c.fx * tx * iz2 * iz * dJ02;
+    } else {
+        float L = tx < 0.f ? -c.limx : c.limx;
+        dtz += c.fx * L * iz2 * dJ02;
+    }
+    if (!s.clampy) {
+        dty -= c.fy * iz2 * dJ12;
+        dtz += 2.f * c.fy * ty * iz2 * iz * dJ12;
+    } else {
+        float L = ty < 0.f ? -c.limy : c.limy;
+        dtz += c.fy * L * iz2 * dJ12;
+    }
+    // mean2D and the rendered depth
+    dtx += gmx * c.fx * iz;
+    dty += gmy * c.fy * iz;
+    dtz -= (gmx * c.fx * tx + gmy * c.fy * ty) * iz2;
+    dtz += gz;
+    // t = R mu + t_cam
+    for (int j = 0; j < 3; ++j)
+        d_means[3 * g + j] += c.R[j] * dtx + c.R[3 + j] * dty + c.R[6 + j] * dtz;
+    // Sigma = M M^T, M = Rq diag(s): dM = (dS + dS^T) M
+    float M[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = s.Rq[3 * i + j] * s.s[j];
+    float dR[9];
+    for (int j = 0; j < 3; ++j) {
+        float ds = 0.f;
+        for (int i = 0; i < 3; ++i) {
+            float dM = 0.f;
+            for (int k = 0; k < 3; ++k) dM += (dS[3 * i + k] + dS[3 * k + i]) * M[3 * k + j];
+            ds += dM * s.Rq[3 * i + j];
+            dR[3 * i + j] = dM * s.s[j];
+        }
+        d_ls[3 * g + j] += ds * s.s[j];
+    }
+    // rotation matrix of the unit quaternion (w, x, y, z)
+    float w = s.qn[0], x = s.qn[1], y = s.qn[2], zq = s.qn[3];
+    float dw = 2.f * (zq * (dR[3] - dR[1]) + y * (dR[2] - dR[6]) + x * (dR[7] - dR[5]));
+    float dx = 2.f * (y * (dR[1] + dR[3]) + zq * (dR[2] + dR[6]) + w * (dR[7] - dR[5]) -
+                      2.f * x * (dR[4] + dR[8]));
+    float dy = 2.f * (x * (dR[1] + dR[3]) + w * (dR[2] - dR[6]) + zq * (dR[5] + dR[7]) -
+                      2.f * y * (dR[0] + dR[8]));
+    float dz = 2.f * (w * (dR[3] - dR[1]) + x * (dR[2] + dR[6]) + y * (dR[5] + dR[7]) -
+                      2.f * zq * (dR[0] + dR[4]));
+    float dot = dw * w + dx * x + dy * y + dz * zq;
+    float il = 1.0f / s.qlen;
+    d_quats[4 * g] += (dw - w * dot) * il;
+    d_quats[4 * g + 1] += (dx - x * dot) * il;
+    d_quats[4 * g + 2] += (dy - y * dot) * il;
+    d_quats[4 * g + 3] += (dz - zq * dot) * il;
+    d_opl[g] += go * s.o * (1.0f - s.o);
+}
+
+}  // namespace
+}  // namespace lgs
+
+using namespace lgs;
+
+extern "C" lgs_status lgs_project_fwd(const lgs_camera *cam, int32_t n, const float *means,
+                                      const float *log_scales, const float *quats,
+                                      const float *opacity_logits, const float *rgb,
+                                      float *mean2d, float *conic, float *depth, float *opacity,
+                                      int32_t *tile_rect, int32_t *tiles_touched,
+                                      hipStream_t stream) {
+    lgs_status st = check_camera(cam);
+    if (st) return st;
+    LGS_REQUIRE(n >= 0, LGS_ERR_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return LGS_OK;
+    LGS_REQUIRE(means && log_scales && quats && opacity_logits && rgb && mean2d && conic && depth &&
+                    opacity && tile_rect && tiles_touched,
+                LGS_ERR_INVALID_ARG, "lgs_project_fwd: NULL pointer");
+    LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && aligned16(tile_rect), LGS_ERR_INVALID_ARG,
+                "lgs_project_fwd: mean2d must be 8-byte and tile_rect 16-byte aligned");
+    CamDev c = make_cam(cam);
+    hipLaunchKernelGGL(project_fwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, c, n, means,
+                       log_scales, quats, opacity_logits, rgb, (float2 *)mean2d, conic, depth,
+                       opacity, (int4 *)tile_rect, tiles_touched);
+    return check_launch("project_fwd");
+}
+
+extern "C" lgs_status lgs_project_bwd(const lgs_camera *cam, int32_t n, const float *means,
+                                      const float *log_scales, const float *quats,
+                                      const float *opacity_logits, const float *rgb,
+                                      const float *dL_dmean2d, const float *dL_dconic,
+                                      const float *dL_dopacity, const float *dL_ddepth_g,
+                                      float *dL_dmeans, float *dL_dlog_scales, float *dL_dquats,
+                                      float *dL_dopacity_logits, hipStream_t stream) {
+    lgs_status st = check_camera(cam);
+    if (st) return st;
+    LGS_REQUIRE(n >= 0, LGS_ERR_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return LGS_OK;
+    LGS_REQUIRE(means && log_scales && quats && opacity_logits && rgb && dL_dmean2d && dL_dconic &&
+                    dL_dopacity && dL_ddepth_g && dL_dmeans && dL_dlog_scales && dL_dquats &&
+                    dL_dopacity_logits,
+                LGS_ERR_INVALID_ARG, "lgs_project_bwd: NULL pointer");
+    CamDev c = make_cam(cam);
+    hipLaunchKernelGGL(project_bwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, c, n, means,
+                       log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic, dL_dopacity,
+                       dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats, dL_dopacity_logits);
+    return check_launch("project_bwd");
+}

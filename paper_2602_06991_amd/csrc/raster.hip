@@ -1,0 +1,332 @@
+// Per-tile alpha blending of colour, depth and opacity (Eq. 1) that keeps each
+// pixel's K largest blending weights in registers (Eq. 2; recorded during the same
+// pass, Sec. 3.2), and its adjoint replayed back to front from the saved final
+// transmittance.  One 256-thread block per 16x16 tile, one thread per pixel; the
+// tile's depth-sorted Gaussians are staged through LDS in batches of 256.
+#include "lgs_device.hpp"
+#include "lgs_host.hpp"
+
+namespace lgs {
+namespace {
+
+struct RasterArgs {
+    int W, H, ntx, nty;
+    const float2 *mean2d;
+    const float *conic;
+    const float *opacity;
+    const float *rgb;
+    const float *depth;
+    const int *sorted_ids;
+    const int2 *ranges;
+};
+
+template <int K>
+__device__ __forceinline__ void topk_insert(float (&tw)[K], int (&ti)[K], float w, int id) {
+    // strictly larger weights displace; equal weights keep blend order
+    if (w > tw[K - 1]) {
+        tw[K - 1] = w;
+        ti[K - 1] = id;
+#pragma unroll
+        for (int i = K - 1; i > 0; --i) {
+            if (tw[i] > tw[i - 1]) {
+                float a = tw[i]; tw[i] = tw[i - 1]; tw[i - 1] = a;
+                int b = ti[i]; ti[i] = ti[i - 1]; ti[i - 1] = b;
+            }
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void raster_fwd_kernel(RasterArgs a, float *__restrict__ color,
+                                                         float *__restrict__ depth_map,
+                                                         float *__restrict__ alpha_map,
+                                                         float *__restrict__ T_final,
+                                                         int *__restrict__ n_contrib,
+                                                         int *__restrict__ topk_ids,
+                                                         float *__restrict__ topk_w) {
+    __shared__ int s_id[256];
+    __shared__ float2 s_xy[256];
+    __shared__ float4 s_co[256];   // conic a, b, c, opacity
+    __shared__ float4 s_cz[256];   // r, g, b, depth
+    const int ntiles = a.ntx * a.nty;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int t = threadIdx.x;
+    const int px = (tile % a.ntx) * kTile + (t & 15);
+    const int py = (tile / a.ntx) * kTile + (t >> 4);
+    const bool inside = px < a.W && py < a.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int2 rg = a.ranges[tile];
+    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, Dz = 0.f;
+    int last = 0;
+    float tw[K];
+    int ti[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { tw[k] = 0.0f; ti[k] = -1; }
+    bool done = !inside;
+    for (int base = rg.x; base < rg.y; base += 256) {
+        if (__syncthreads_count(done) == 256) break;
+        int idx = base + t;
+        if (idx < rg.y) {
+            int g = a.sorted_ids[idx];
+            s_id[t] = g;
+            s_xy[t] = a.mean2d[g];
+            s_co[t] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
+            s_cz[t] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[g]);
+        }
+        __syncthreads();
+        const int cnt = min(256, rg.y - base);
+        for (int j = 0; j < cnt && !done; ++j) {
+            float2 m = s_xy[j];
+            float4 co = s_co[j];
+            float dx, dy, raw, ex;
+            float alpha = blend_alpha(fx, fy, m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
+            if (alpha < kAlphaMin) continue;
+            float nT = T * (1.0f - alpha);
+            if (nT < kTMin) { done = true; break; }
+            float w = alpha * T;
+            float4 cz = s_cz[j];
+            C0 = fmaf(cz.x, w, C0);
+            C1 = fmaf(cz.y, w, C1);
+            C2 = fmaf(cz.z, w, C2);
+            Dz = fmaf(cz.w, w, Dz);
+            T = nT;
+            last = base + j - rg.x + 1;
+            topk_insert<K>(tw, ti, w, s_id[j]);
+        }
+    }
+    if (!inside) return;
+    const long p = (long)py * a.W + px;
+    color[3 * p] = C0;
+    color[3 * p + 1] = C1;
+    color[3 * p + 2] = C2;
+    depth_map[p] = Dz;
+    alpha_map[p] = 1.0f - T;
+    T_final[p] = T;
+    n_contrib[p] = last;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        topk_ids[p * K + k] = ti[k];
+        topk_w[p * K + k] = tw[k];
+    }
+}
+
+constexpr int kNG = 10;   // per-Gaussian gradient slots: mean2d 2, conic 3, opacity, rgb 3, depth
+
+template <int K>
+__global__ __launch_bounds__(256) void raster_bwd_kernel(
+    RasterArgs a, const float *__restrict__ T_final, const int *__restrict__ n_contrib,
+    const int *__restrict__ topk_ids, const float *__restrict__ dL_dtopkw,
+    const float *__restrict__ dL_dcolor, const float *__restrict__ dL_ddepth,
+    const float *__restrict__ dL_dalpha, float *__restrict__ g_mean2d, float *__restrict__ g_conic,
+    float *__restrict__ g_opac, float *__restrict__ g_rgb, float *__restrict__ g_depth) {
+    __shared__ int s_id[256];
+    __shared__ float2 s_xy[256];
+    __shared__ float4 s_co[256];
+    __shared__ float4 s_cz[256];
+    __shared__ float s_part[4][kNG][256];
+    __shared__ int s_max;
+    const int ntiles = a.ntx * a.nty;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int t = threadIdx.x;
+    const int wave = t >> 6;
+    const int px = (tile % a.ntx) * kTile + (t & 15);
+    const int py = (tile / a.ntx) * kTile + (t >> 4);
+    const bool inside = px < a.W && py < a.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int2 rg = a.ranges[tile];
+    const long p = (long)py * a.W + px;
+
+    float T = 1.0f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gO = 0.f;
+    int last = 0;
+    int ti[K];
+    float gam[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { ti[k] = -1; gam[k] = 0.f; }
+    if (inside) {
+        T = T_final[p];
+        last = n_contrib[p];
+        gC0 = dL_dcolor[3 * p];
+        gC1 = dL_dcolor[3 * p + 1];
+        gC2 = dL_dcolor[3 * p + 2];
+        gD = dL_ddepth[p];
+        gO = dL_dalpha ? dL_dalpha[p] : 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            ti[k] = topk_ids[p * K + k];
+            gam[k] = dL_dtopkw ? dL_dtopkw[p * K + k] : 0.f;
+        }
+    }
+    if (t == 0) s_max = 0;
+    __syncthreads();
+    atomicMax(&s_max, last);
+    __syncthreads();
+    const int maxl = s_max;
+    float A = 0.0f;   // sum over later blended Gaussians of e_j w_j
+    for (int hi = maxl; hi > 0; hi -= 256) {
+        const int lo = hi > 256 ? hi - 256 : 0;
+        const int cnt = hi - lo;
+        __syncthreads();
+        if (t < cnt) {
+            int g = a.sorted_ids[rg.x + lo + t];
+            s_id[t] = g;
+            s_xy[t] = a.mean2d[g];
+            s_co[t] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
+            s_cz[t] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[g]);
+        }
+        __syncthreads();
+        for (int j = cnt - 1; j >= 0; --j) {
+            float v[kNG];
+#pragma unroll
+            for (int q = 0; q < kNG; ++q) v[q] = 0.f;
+            bool hit = false;
+            if (lo + j < last) {
+                float2 m = s_xy[j];
+                float4 co = s_co[j];
+                float dx, dy, raw, ex;
+                float alpha = blend_alpha(fx, fy, m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
+                if (alpha >= kAlphaMin) {
+                    hit = true;
+                    float om = 1.0f - alpha;
+                    T = T / om;                   // transmittance in front of this Gaussian
+                    float w = alpha * T;
+                    float4 cz = s_cz[j];
+                    int g = s_id[j];
+                    float e = gC0 * cz.x + gC1 * cz.y + gC2 * cz.z + gD * cz.w + gO;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) e += (ti[k] == g) ? gam[k] : 0.f;
+                    float dal = T * e - A / om;
+                    A = fmaf(e, w, A);
+                    v[5] = w * gC0;
+                    v[6] = w * gC1;
+                    v[7] = w * gC2;
+                    v[8] = w * gD;
+                    if (raw <= kAlphaMax) {       // unclamped: alpha = o e^-sigma
+                        float ds = -alpha * dal;
+                        v[0] = -ds * (co.x * dx + co.y * dy);
+                        v[1] = -ds * (co.y * dx + co.z * dy);
+                        v[2] = ds * 0.5f * dx * dx;
+                        v[3] = ds * dx * dy;
+                        v[4] = ds * 0.5f * dy * dy;
+                        v[9] = dal * ex;
+                    }
+                }
+            }
+            // wave-level reduction (every lane takes part), one partial per wave
+            if (__ballot(hit) != 0ull) {
+#pragma unroll
+                for (int q = 0; q < kNG; ++q) {
+                    float s = wave_sum(v[q]);
+                    if ((t & 63) == 0) s_part[wave][q][j] = s;
+                }
+            } else if ((t & 63) == 0) {
+#pragma unroll
+                for (int q = 0; q < kNG; ++q) s_part[wave][q][j] = 0.f;
+            }
+        }
+        __syncthreads();
+        if (t < cnt) {
+            int g = s_id[t];
+            float s[kNG];
+#pragma unroll
+            for (int q = 0; q < kNG; ++q)
+                s[q] = (s_part[0][q][t] + s_part[1][q][t]) + (s_part[2][q][t] + s_part[3][q][t]);
+            if (s[0] != 0.f) unsafeAtomicAdd(&g_mean2d[2 * g], s[0]);
+            if (s[1] != 0.f) unsafeAtomicAdd(&g_mean2d[2 * g + 1], s[1]);
+            if (s[2] != 0.f) unsafeAtomicAdd(&g_conic[3 * g], s[2]);
+            if (s[3] != 0.f) unsafeAtomicAdd(&g_conic[3 * g + 1], s[3]);
+            if (s[4] != 0.f) unsafeAtomicAdd(&g_conic[3 * g + 2], s[4]);
+            if (s[9] != 0.f) unsafeAtomicAdd(&g_opac[g], s[9]);
+            if (s[5] != 0.f) unsafeAtomicAdd(&g_rgb[3 * g], s[5]);
+            if (s[6] != 0.f) unsafeAtomicAdd(&g_rgb[3 * g + 1], s[6]);
+            if (s[7] != 0.f) unsafeAtomicAdd(&g_rgb[3 * g + 2], s[7]);
+            if (s[8] != 0.f) unsafeAtomicAdd(&g_depth[g], s[8]);
+        }
+    }
+}
+
+template <int K>
+void launch_fwd(RasterArgs a, float *color, float *depth_map, float *alpha_map, float *T_final,
+                int *n_contrib, int *topk_ids, float *topk_w, hipStream_t st) {
+    hipLaunchKernelGGL(raster_fwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(256), 0,
+                       st, a, color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w);
+}
+
+template <int K>
+void launch_bwd(RasterArgs a, const float *T_final, const int *n_contrib, const int *topk_ids,
+                const float *dL_dtopkw, const float *dL_dcolor, const float *dL_ddepth,
+                const float *dL_dalpha, float *gm, float *gc, float *go, float *grgb, float *gz,
+                hipStream_t st) {
+    hipLaunchKernelGGL(raster_bwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(256), 0,
+                       st, a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha,
+                       gm, gc, go, grgb, gz);
+}
+
+#define LGS_K_SWITCH(k, CALL)            \
+    switch (k) {                         \
+    case 1: CALL(1); break;              \
+    case 2: CALL(2); break;              \
+    case 3: CALL(3); break;              \
+    case 4: CALL(4); break;              \
+    case 5: CALL(5); break;              \
+    case 8: CALL(8); break;              \
+    case 10: CALL(10); break;            \
+    case 16: CALL(16); break;            \
+    }
+
+}  // namespace
+}  // namespace lgs
+
+using namespace lgs;
+
+extern "C" lgs_status lgs_rasterize_topk_fwd(const lgs_camera *cam, int32_t k, const float *mean2d,
+                                             const float *conic, const float *opacity,
+                                             const float *rgb, const float *depth,
+                                             const int32_t *sorted_ids, const int32_t *tile_ranges,
+                                             float *color, float *depth_map, float *alpha_map,
+                                             float *T_final, int32_t *n_contrib, int32_t *topk_ids,
+                                             float *topk_w, hipStream_t stream) {
+    lgs_status st = check_camera(cam);
+    if (st) return st;
+    LGS_REQUIRE(k_supported(k), LGS_ERR_UNSUPPORTED, "K = %d is not compiled", k);
+    LGS_REQUIRE(mean2d && conic && opacity && rgb && depth && sorted_ids && tile_ranges && color &&
+                    depth_map && alpha_map && T_final && n_contrib && topk_ids && topk_w,
+                LGS_ERR_INVALID_ARG, "lgs_rasterize_topk_fwd: NULL pointer");
+    LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && ((uintptr_t)tile_ranges & 7u) == 0,
+                LGS_ERR_INVALID_ARG, "mean2d and tile_ranges must be 8-byte aligned");
+    RasterArgs a{cam->width, cam->height, tiles_x(cam->width), tiles_y(cam->height),
+                 (const float2 *)mean2d, conic, opacity, rgb, depth, sorted_ids,
+                 (const int2 *)tile_ranges};
+#define CALL_FWD(KK) launch_fwd<KK>(a, color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w, stream)
+    LGS_K_SWITCH(k, CALL_FWD)
+#undef CALL_FWD
+    return check_launch("rasterize_topk_fwd");
+}
+
+extern "C" lgs_status lgs_rasterize_topk_bwd(
+    const lgs_camera *cam, int32_t k, const float *mean2d, const float *conic, const float *opacity,
+    const float *rgb, const float *depth, const int32_t *sorted_ids, const int32_t *tile_ranges,
+    const float *T_final, const int32_t *n_contrib, const int32_t *topk_ids, const float *topk_w,
+    const float *dL_dcolor, const float *dL_ddepth, const float *dL_dalpha, const float *dL_dtopkw,
+    float *dL_dmean2d, float *dL_dconic, float *dL_dopacity, float *dL_drgb, float *dL_ddepth_g,
+    hipStream_t stream) {
+    lgs_status st = check_camera(cam);
+    if (st) return st;
+    LGS_REQUIRE(k_supported(k), LGS_ERR_UNSUPPORTED, "K = %d is not compiled", k);
+    LGS_REQUIRE(mean2d && conic && opacity && rgb && depth && sorted_ids && tile_ranges && T_final &&
+                    n_contrib && topk_ids && topk_w && dL_dcolor && dL_ddepth && dL_dmean2d &&
+                    dL_dconic && dL_dopacity && dL_drgb && dL_ddepth_g,
+                LGS_ERR_INVALID_ARG, "lgs_rasterize_topk_bwd: NULL pointer");
+    LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && ((uintptr_t)tile_ranges & 7u) == 0,
+                LGS_ERR_INVALID_ARG, "mean2d and tile_ranges must be 8-byte aligned");
+    RasterArgs a{cam->width, cam->height, tiles_x(cam->width), tiles_y(cam->height),
+                 (const float2 *)mean2d, conic, opacity, rgb, depth, sorted_ids,
+                 (const int2 *)tile_ranges};
+#define CALL_BWD(KK)                                                                             \
+    launch_bwd<KK>(a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha, \
+                   dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream)
+    LGS_K_SWITCH(k, CALL_BWD)
+#undef CALL_BWD
+    return check_launch("rasterize_topk_bwd");
+}

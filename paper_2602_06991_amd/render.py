@@ -1,0 +1,240 @@
+"""Torch-facing renderer: device memory and streams from PyTorch, every step of the
+path in liblgs.so (see lgs.py for the C ABI).
+
+    r = Renderer(K=4, feat_dtype="bf16")
+    C, D, O, F = r.render(params, camera)            # a torch.autograd.Function
+
+`params` is a dict of CUDA tensors: means[N,3], log_scales[N,3], quats[N,4],
+opacity_logits[N], rgb[N,3] and feat[N,D] (FP32 master copy).  For BF16 / FP8
+storage, call ``r.set_features(feat)`` after each update of the master copy to
+refresh the quantized table the kernels read.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import lgs
+
+_TORCH_MAP = {"f32": torch.float32, "bf16": torch.bfloat16}
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("liblgs needs contiguous CUDA tensors")
+
+
+class Binner:
+    """Reusable workspace and pair buffer for lgs_bin_sort; grows on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.cap = 0
+        self.ws = None
+        self.ids = None
+
+    def _ensure(self, n, W, H, cap):
+        need = lgs.lgs_bin_sort_workspace(n, W, H, cap)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        if self.ids is None or self.ids.numel() < max(cap, 1):
+            self.ids = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        self.cap = cap
+
+    def __call__(self, cam, n, depth, tile_rect, touched):
+        ntiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+        ranges = torch.empty(ntiles * 2, dtype=torch.int32, device=self.device)
+        if self.cap == 0:
+            self._ensure(n, cam.width, cam.height, max(4 * n, 1 << 16))
+        while True:
+            ws = self.ws
+            st, m = lgs.lgs_bin_sort(cam, n, _p(depth), _p(tile_rect), _p(touched), _p(ws),
+                                     ws.numel(), self.cap, _p(self.ids), _p(ranges), _stream())
+            if st == lgs.LGS_OK:
+                return self.ids[:m], ranges.view(ntiles, 2), m
+            self._ensure(n, cam.width, cam.height, int(m * 1.25) + 4096)
+
+
+def project(cam, P):
+    n = P["means"].shape[0]
+    dev = P["means"].device
+    out = dict(mean2d=torch.empty(n, 2, device=dev), conic=torch.empty(n, 3, device=dev),
+               depth=torch.empty(n, device=dev), opacity=torch.empty(n, device=dev),
+               tile_rect=torch.empty(n, 4, dtype=torch.int32, device=dev),
+               tiles_touched=torch.empty(n, dtype=torch.int32, device=dev))
+    _need_cuda(*(P[k] for k in ("means", "log_scales", "quats", "opacity_logits", "rgb")))
+    lgs.lgs_project_fwd(cam, n, _p(P["means"]), _p(P["log_scales"]), _p(P["quats"]),
+                        _p(P["opacity_logits"]), _p(P["rgb"]), _p(out["mean2d"]), _p(out["conic"]),
+                        _p(out["depth"]), _p(out["opacity"]), _p(out["tile_rect"]),
+                        _p(out["tiles_touched"]), _stream())
+    return out
+
+
+def rasterize(cam, K, proj, rgb, sorted_ids, ranges):
+    H, W = cam.height, cam.width
+    dev = rgb.device
+    out = dict(C=torch.empty(H, W, 3, device=dev), D=torch.empty(H, W, device=dev),
+               O=torch.empty(H, W, device=dev), T=torch.empty(H, W, device=dev),
+               n_contrib=torch.empty(H, W, dtype=torch.int32, device=dev),
+               ids=torch.empty(H, W, K, dtype=torch.int32, device=dev),
+               w=torch.empty(H, W, K, device=dev))
+    lgs.lgs_rasterize_topk_fwd(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
+                               _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(out["C"]),
+                               _p(out["D"]), _p(out["O"]), _p(out["T"]), _p(out["n_contrib"]),
+                               _p(out["ids"]), _p(out["w"]), _stream())
+    return out
+
+
+def quantize(feat, dtype):
+    """FP32 [N,D] -> storage (bf16 tensor, or (uint8 codes, f32 scale) for fp8)."""
+    n, d = feat.shape
+    _need_cuda(feat)
+    if dtype == "f32":
+        return feat, None
+    if dtype == "bf16":
+        out = torch.empty(n, d, dtype=torch.bfloat16, device=feat.device)
+        lgs.lgs_quantize_features(n, d, _p(feat), lgs.LGS_BF16, _p(out), None, _stream())
+        return out, None
+    if dtype == "fp8":
+        out = torch.empty(n, d, dtype=torch.uint8, device=feat.device)
+        scale = torch.empty(n, dtype=torch.float32, device=feat.device)
+        lgs.lgs_quantize_features(n, d, _p(feat), lgs.LGS_FP8_E4M3, _p(out), _p(scale), _stream())
+        return out, scale
+    raise ValueError(dtype)
+
+
+def feature_fwd(ids, w, feat_store, feat_scale, feat_dtype, map_dtype, views=1):
+    """Eq. 3-4 for per-pixel Top-K ids/w [V*H, W, K] (or [H, W, K])."""
+    K = ids.shape[-1]
+    Hs, W = ids.shape[0], ids.shape[1]
+    d = feat_store.shape[1]
+    F = torch.empty(Hs, W, d, dtype=_TORCH_MAP[map_dtype], device=ids.device)
+    _need_cuda(ids, w, feat_store, feat_scale)
+    lgs.lgs_feature_render_fwd(W, Hs // views, views, K, d, lgs.DTYPES[feat_dtype], _p(feat_store),
+                               _p(feat_scale), _p(ids), _p(w), lgs.DTYPES[map_dtype], _p(F), _stream())
+    return F
+
+
+def feature_bwd(ids, w, feat_store, feat_scale, feat_dtype, map_dtype, dF, dfeat, views=1):
+    K = ids.shape[-1]
+    Hs, W = ids.shape[0], ids.shape[1]
+    d = feat_store.shape[1]
+    dtw = torch.empty(Hs, W, K, device=ids.device)
+    _need_cuda(ids, w, feat_store, feat_scale, dF, dfeat)
+    lgs.lgs_feature_render_bwd(W, Hs // views, views, K, d, lgs.DTYPES[feat_dtype], _p(feat_store),
+                               _p(feat_scale), _p(ids), _p(w), lgs.DTYPES[map_dtype], _p(dF),
+                               _p(dfeat), _p(dtw), _stream())
+    return dtw
+
+
+def rasterize_bwd(cam, K, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads):
+    lgs.lgs_rasterize_topk_bwd(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
+                               _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(fwd["T"]),
+                               _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(fwd["w"]), _p(gC), _p(gD),
+                               _p(gO), _p(dtw), _p(grads["mean2d"]), _p(grads["conic"]),
+                               _p(grads["opacity"]), _p(grads["rgb"]), _p(grads["depth"]), _stream())
+
+
+def project_bwd(cam, P, sgrads, pgrads):
+    n = P["means"].shape[0]
+    lgs.lgs_project_bwd(cam, n, _p(P["means"]), _p(P["log_scales"]), _p(P["quats"]),
+                        _p(P["opacity_logits"]), _p(P["rgb"]), _p(sgrads["mean2d"]),
+                        _p(sgrads["conic"]), _p(sgrads["opacity"]), _p(sgrads["depth"]),
+                        _p(pgrads["means"]), _p(pgrads["log_scales"]), _p(pgrads["quats"]),
+                        _p(pgrads["opacity_logits"]), _stream())
+
+
+def screen_grad_buffers(n, device):
+    return dict(mean2d=torch.zeros(n, 2, device=device), conic=torch.zeros(n, 3, device=device),
+                opacity=torch.zeros(n, device=device), rgb=torch.zeros(n, 3, device=device),
+                depth=torch.zeros(n, device=device))
+
+
+def l1_grad(x, target, scale):
+    """scale * sign(x - target) in x's dtype (f32 or bf16)."""
+    g = torch.empty_like(x)
+    dt = lgs.LGS_BF16 if x.dtype == torch.bfloat16 else lgs.LGS_F32
+    _need_cuda(x, target)
+    lgs.lgs_l1_grad(x.numel(), dt, _p(x), _p(target), float(scale), _p(g), _stream())
+    return g
+
+
+def union_count(ids, n):
+    flags = torch.empty(n + 1, dtype=torch.int32, device=ids.device)
+    K = ids.shape[-1]
+    return lgs.lgs_union_count(ids.numel() // K, K, n, _p(ids), _p(flags), _stream())
+
+
+class _TopKRender(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, rgb, feat, r, cam):
+        P = dict(means=means, log_scales=log_scales, quats=quats, opacity_logits=opacity_logits,
+                 rgb=rgb)
+        proj = project(cam, P)
+        ids, ranges, _ = r.binner(cam, means.shape[0], proj["depth"], proj["tile_rect"],
+                                  proj["tiles_touched"])
+        fw = rasterize(cam, r.K, proj, rgb, ids, ranges)
+        store, scale = (feat, None) if r.feat_dtype == "f32" else (r.store, r.scale)
+        F = feature_fwd(fw["ids"], fw["w"], store, scale, r.feat_dtype, r.map_dtype)
+        ctx.r, ctx.cam, ctx.P, ctx.proj, ctx.fw = r, cam, P, proj, fw
+        ctx.sorted_ids, ctx.ranges = ids.clone(), ranges
+        ctx.store, ctx.scale, ctx.n, ctx.d = store, scale, means.shape[0], feat.shape[1]
+        return fw["C"], fw["D"], fw["O"], F
+
+    @staticmethod
+    def backward(ctx, gC, gD, gO, gF):
+        r, cam, fw = ctx.r, ctx.cam, ctx.fw
+        dev = fw["C"].device
+        gC = torch.zeros_like(fw["C"]) if gC is None else gC.contiguous()
+        gD = torch.zeros_like(fw["D"]) if gD is None else gD.contiguous()
+        gO = None if gO is None else gO.contiguous()
+        dfeat = torch.zeros(ctx.n, ctx.d, device=dev)
+        if gF is not None:
+            dtw = feature_bwd(fw["ids"], fw["w"], ctx.store, ctx.scale, r.feat_dtype, r.map_dtype,
+                              gF.contiguous(), dfeat)
+        else:
+            dtw = None
+        sg = screen_grad_buffers(ctx.n, dev)
+        rasterize_bwd(cam, r.K, ctx.proj, ctx.P["rgb"], ctx.sorted_ids, ctx.ranges, fw, gC, gD, gO,
+                      dtw, sg)
+        pg = dict(means=torch.zeros(ctx.n, 3, device=dev), log_scales=torch.zeros(ctx.n, 3, device=dev),
+                  quats=torch.zeros(ctx.n, 4, device=dev), opacity_logits=torch.zeros(ctx.n, device=dev))
+        project_bwd(cam, ctx.P, sg, pg)
+        return (pg["means"], pg["log_scales"], pg["quats"], pg["opacity_logits"], sg["rgb"], dfeat,
+                None, None)
+
+
+class Renderer:
+    """Top-K renderer with a fixed K and feature storage / map precision.
+
+    feat_dtype: "f32" (map f32), "bf16" (map bf16), or "fp8" (map bf16 by default).
+    """
+
+    def __init__(self, K=4, feat_dtype="f32", map_dtype=None, device="cuda"):
+        if K not in lgs.lgs_supported_k():
+            raise ValueError(f"K={K} not supported")
+        self.K = K
+        self.feat_dtype = feat_dtype
+        self.map_dtype = map_dtype or ("f32" if feat_dtype == "f32" else "bf16")
+        self.binner = Binner(device)
+        self.store = None
+        self.scale = None
+
+    def set_features(self, feat):
+        if self.feat_dtype != "f32":
+            self.store, self.scale = quantize(feat.detach(), self.feat_dtype)
+
+    def render(self, params, cam):
+        c = cam if isinstance(cam, lgs.lgs_camera) else lgs.make_camera(cam)
+        if self.feat_dtype != "f32" and self.store is None:
+            self.set_features(params["feat"])
+        return _TopKRender.apply(params["means"], params["log_scales"], params["quats"],
+                                 params["opacity_logits"], params["rgb"], params["feat"], self, c)

@@ -1,0 +1,211 @@
+"""Kernel-level parity of the HIP path against the oracle (and, for the sort, against
+numpy's lexsort on synthetic keys).  Each kernel is fed inputs the oracle or the
+seeded generator produced, never another HIP kernel's output."""
+import numpy as np
+import pytest
+
+from gpu_util import FLAG_EPS, dev_params, normwise, rel_close
+from paper_2602_06991_amd.scenegen import make_scene, make_tiny
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_06991_amd import lgs
+    lgs.load()
+    return t
+
+
+def test_quantize_bit_exact(torch, orc):
+    from paper_2602_06991_amd import render
+    rng = np.random.default_rng(0)
+    n, d = 3000, 512
+    x = (rng.standard_normal((n, d)) * np.exp(rng.uniform(-20, 20, (n, 1)))).astype(np.float32)
+    x[0] = 0
+    x[1, :] = 1e-40          # subnormal row
+    x[2, 5] = 448.0 * 3      # row whose amax sets a larger scale
+    t = torch.from_numpy(x).cuda()
+    b, _ = render.quantize(t, "bf16")
+    q, s = render.quantize(t, "fp8")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(b.view(torch.int16).cpu().numpy().view(np.uint16), orc.bf16_bits(x))
+    codes, scale = orc.fp8_quantize(x)
+    np.testing.assert_array_equal(s.cpu().numpy(), scale)
+    np.testing.assert_array_equal(q.cpu().numpy(), codes)
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "c0", "c1"])
+def test_project_parity(torch, orc, cfg):
+    from paper_2602_06991_amd import lgs, render
+    if cfg == "tiny":
+        g, cam = make_tiny(3, n=200, W=48, H=40, spread=(-0.8, 1.8), scale=(-2.0, 1.0))
+    else:
+        sc = make_scene(int(cfg[1]))
+        g, cam = sc.gaussians, sc.cameras[0]
+    # a few degenerate Gaussians the culls must agree on
+    g.means[0] = np.nan
+    g.quats[1] = 0
+    g.log_scales[2, 0] = 10.5
+    g.opacity_logits[3] = -5.6
+    P = dev_params(g)
+    proj = render.project(lgs.make_camera(cam), P)
+    torch.cuda.synchronize()
+    o = orc.project(g, cam)
+    valid = o["valid"].astype(bool)
+    gv = proj["tiles_touched"].cpu().numpy() > 0
+    # a GPU-visible Gaussian must be oracle-valid; oracle-valid ones off-screen may have 0 tiles
+    assert not np.any(gv & ~valid)
+    assert not valid[:4].any()
+    zk = proj["depth"].cpu().numpy()
+    np.testing.assert_array_equal(zk[valid], o["zkey"][valid])   # bit-exact depth key
+    m2 = proj["mean2d"].cpu().numpy()
+    # fx tx/tz + cx in FP32: a few ulp of the larger of the two terms
+    scale_px = np.abs(o["mean2d"][valid]) + max(cam.cx, cam.cy) + max(cam.fx, cam.fy)
+    assert np.all(np.abs(m2[valid] - o["mean2d"][valid]) <= 1e-6 * scale_px)
+    con = proj["conic"].cpu().numpy()
+    cs = np.maximum(np.abs(o["conic"][valid]).max(1, keepdims=True), 1e-12)
+    assert np.all(np.abs(con[valid] - o["conic"][valid]) <= 1e-5 * cs)
+    op = proj["opacity"].cpu().numpy()
+    assert np.all(rel_close(op[valid], o["opacity"][valid], 1e-6, 1e-3))
+    # every pixel of the oracle's support box lies in the GPU's tile box
+    rect = proj["tile_rect"].cpu().numpy()
+    orect = o["rect"]
+    has = valid & (orect[:, 2] >= orect[:, 0]) & (orect[:, 3] >= orect[:, 1])
+    assert np.all(gv[has])
+    assert np.all(rect[has, 0] * 16 <= orect[has, 0]) and np.all(rect[has, 1] * 16 <= orect[has, 1])
+    assert np.all(rect[has, 2] * 16 > orect[has, 2]) and np.all(rect[has, 3] * 16 > orect[has, 3])
+
+
+@pytest.mark.parametrize("n,W,H,seed", [(1, 16, 16, 0), (1000, 64, 48, 1), (20000, 640, 480, 2),
+                                        (100000, 1200, 680, 3)])
+def test_bin_sort_matches_lexsort(torch, n, W, H, seed):
+    """Synthetic rects and depth keys (with deliberate ties): the pairs must come out
+    ordered by (tile, depth key, id), exactly as numpy's lexsort orders them."""
+    from paper_2602_06991_amd import lgs, render
+    rng = np.random.default_rng(seed)
+    ntx, nty = (W + 15) // 16, (H + 15) // 16
+    tx0 = rng.integers(0, ntx, n)
+    ty0 = rng.integers(0, nty, n)
+    tx1 = np.minimum(tx0 + rng.integers(1, 4, n), ntx)
+    ty1 = np.minimum(ty0 + rng.integers(1, 4, n), nty)
+    touched = ((tx1 - tx0) * (ty1 - ty0)).astype(np.int32)
+    touched[rng.random(n) < 0.2] = 0                       # culled
+    depth = rng.choice(rng.uniform(0.3, 9.0, max(n // 3, 1)).astype(np.float32), n)  # many ties
+    rect = np.stack([tx0, ty0, tx1, ty1], 1).astype(np.int32)
+    cam = lgs.lgs_camera()
+    cam.width, cam.height, cam.fx, cam.fy = W, H, 1.0, 1.0
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    b = render.Binner()
+    b._ensure(n, W, H, 64)                                  # force the capacity retry path
+    ids, ranges, m = b(cam, n, tt(depth), tt(rect), tt(touched))
+    torch.cuda.synchronize()
+    exp_t, exp_g = [], []
+    for g in range(n):
+        if touched[g] == 0:
+            continue
+        for ty in range(ty0[g], ty1[g]):
+            for tx in range(tx0[g], tx1[g]):
+                exp_t.append(ty * ntx + tx)
+                exp_g.append(g)
+    exp_t = np.array(exp_t, np.int64)
+    exp_g = np.array(exp_g, np.int64)
+    order = np.lexsort((exp_g, depth[exp_g], exp_t))
+    assert m == len(exp_t)
+    np.testing.assert_array_equal(ids.cpu().numpy(), exp_g[order])
+    r = ranges.cpu().numpy()
+    cnt = np.bincount(exp_t, minlength=ntx * nty)
+    np.testing.assert_array_equal(r[:, 1] - r[:, 0], cnt)
+    starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    np.testing.assert_array_equal(r[cnt > 0, 0], starts[cnt > 0])
+
+
+def _oracle_topk(orc, g, cam, K):
+    r = orc.render(g, cam, K)
+    return r
+
+
+@pytest.mark.parametrize("K,fdt,mdt", [(4, "f32", "f32"), (1, "f32", "f32"), (8, "f32", "f32"),
+                                       (4, "bf16", "bf16"), (4, "bf16", "f32"), (8, "fp8", "bf16"),
+                                       (3, "fp8", "f32"), (16, "bf16", "bf16")])
+def test_feature_fwd_parity(torch, orc, K, fdt, mdt):
+    from paper_2602_06991_amd import render
+    sc = make_scene(0)
+    g, cam = sc.gaussians, sc.cameras[0]
+    r = orc.render(g, cam, K)
+    ids = torch.from_numpy(r["ids"]).cuda()
+    w = torch.from_numpy(r["w"].astype(np.float32)).cuda()
+    feat = torch.from_numpy(g.feat).cuda()
+    store, scale = render.quantize(feat, fdt)
+    F = render.feature_fwd(ids, w, store, scale, fdt, mdt)
+    torch.cuda.synchronize()
+    Fg = F.float().cpu().numpy().astype(np.float64)
+    if fdt == "f32":
+        f64 = g.feat.astype(np.float64)
+    elif fdt == "bf16":
+        f64 = orc.bf16_to_f64(orc.bf16_bits(g.feat)).reshape(g.feat.shape)
+    else:
+        codes, s = orc.fp8_quantize(g.feat)
+        f64 = orc.fp8_dequant(codes, s)
+    # the oracle takes the same FP32-rounded weights the kernel got
+    Fo = orc.feature(r["ids"], r["w"].astype(np.float32).astype(np.float64), f64)
+    err = normwise(Fg, Fo, 1e-2)
+    tol = 1e-4 if mdt == "f32" else 1e-2
+    print(f"K={K} {fdt}->{mdt}: max normwise err vs stored features {err.max():.3g}")
+    assert err.max() <= tol
+    if fdt != "f32":
+        # end to end against the unquantized features
+        Fu = orc.feature(r["ids"], r["w"], g.feat.astype(np.float64))
+        e2 = normwise(Fg, Fu, 1e-2)
+        print(f"   vs unquantized FP64: max {e2.max():.3g} mean {e2.mean():.3g}")
+        assert e2.max() <= (1e-2 if fdt == "bf16" else 3e-2)
+    W = r["w"].sum(-1)
+    assert np.all(Fg[W == 0] == 0)
+
+
+@pytest.mark.parametrize("K,fdt,mdt", [(4, "f32", "f32"), (1, "f32", "f32"), (8, "bf16", "bf16"),
+                                       (4, "fp8", "bf16"), (16, "f32", "f32")])
+def test_feature_bwd_parity(torch, orc, K, fdt, mdt):
+    from paper_2602_06991_amd import render
+    sc = make_scene(1, N=60000, W=200, H=150)
+    g, cam = sc.gaussians, sc.cameras[0]
+    r = orc.render(g, cam, K)
+    rng = np.random.default_rng(K)
+    gF = rng.standard_normal((cam.H, cam.W, g.d)).astype(np.float32)
+    tmap = torch.float32 if mdt == "f32" else torch.bfloat16
+    gF_dev = torch.from_numpy(gF).cuda().to(tmap)
+    gF64 = gF_dev.float().cpu().numpy().astype(np.float64)
+    ids = torch.from_numpy(r["ids"]).cuda()
+    w = torch.from_numpy(r["w"].astype(np.float32)).cuda()
+    feat = torch.from_numpy(g.feat).cuda()
+    store, scale = render.quantize(feat, fdt)
+    dfeat = torch.zeros(g.n, g.d, device="cuda")
+    dtw = render.feature_bwd(ids, w, store, scale, fdt, mdt, gF_dev, dfeat)
+    torch.cuda.synchronize()
+    if fdt == "f32":
+        f64 = g.feat.astype(np.float64)
+    elif fdt == "bf16":
+        f64 = orc.bf16_to_f64(orc.bf16_bits(g.feat)).reshape(g.feat.shape)
+    else:
+        codes, s = orc.fp8_quantize(g.feat)
+        f64 = orc.fp8_dequant(codes, s)
+    # the oracle's feature adjoint for the same Top-K: isolate it with gC = gD = gO = 0
+    from types import SimpleNamespace
+    gg = SimpleNamespace(means=g.means, log_scales=g.log_scales, quats=g.quats,
+                         opacity_logits=g.opacity_logits, rgb=g.rgb, feat=g.feat)
+    b = orc.backward(gg, cam, K, f64, None, None, None, gF64)
+    df = dfeat.cpu().numpy()
+    touched = np.abs(b["d_feat"]).sum(1) > 0
+    err = normwise(df[touched], b["d_feat"][touched], 1e-6)
+    print(f"K={K} {fdt}/{mdt}: dL/df rows {touched.sum()}, max normwise err {err.max():.3g}")
+    assert err.max() <= 1e-4
+    assert np.all(df[~touched] == 0)
+    # gamma: compare with the scale of the pixel's dot products
+    gam = dtw.cpu().numpy()
+    scl = np.abs(b["d_topkw"]).max(-1, keepdims=True) + 1e-6
+    e = np.abs(gam - b["d_topkw"]) / scl
+    print(f"   gamma max err (rel to pixel max) {e.max():.3g}")
+    assert e.max() <= 1e-4
