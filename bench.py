@@ -1,0 +1,299 @@
+"""Benchmark of the Top-K renderer's forward + backward step on one MI355X.
+
+Workload (default): 1200x680 px single view, 500k Gaussians on a seeded synthetic
+room with 60 object boxes, D = 512 language features, K = 4, with the feature
+table stored in BF16 (FP32 accumulation) and, for comparison, the plain FP32 form.
+
+One step = one pass of the whole hot path over one frame:
+  quantize the FP32 master features to the storage format (BF16 form only),
+  project -> bin + sort -> blend with Top-K -> feature render,
+  L1 loss gradients of colour and depth against a target frame,
+  zero the gradient buffers, feature adjoint fused with the feature L1 loss gradient
+  -> blend adjoint -> projection adjoint.
+All inputs are resident in HBM before timing starts.
+
+Prints one JSON line (metric, value = BF16 fwd+bwd ms per frame, roofline of the
+dominant feature kernel from live HIP-event timings, and the FP64 oracle's CPU time
+for one full frame of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--K", type=int, default=4)
+    ap.add_argument("--sweep", action="store_true", help="also time K = 1 and 8")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="bf16,f32")
+    return ap.parse_args()
+
+
+class Step:
+    """All buffers of one frame's forward + backward, reused across steps."""
+
+    def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form):
+        self.t, self.render, self.lgs = torch, render, lgs
+        self.P, self.target, self.cam, self.K, self.form = scene_dev, target, cam, K, form
+        self.map = "f32" if form == "f32" else "bf16"
+        self.binner = render.Binner()
+        n, d = scene_dev["feat"].shape
+        self.n, self.d = n, d
+        dev = "cuda"
+        self.dfeat = torch.empty(n, d, device=dev)
+        self.sg = render.screen_grad_buffers(n, dev)
+        self.pg = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
+                       quats=torch.empty(n, 4, device=dev), opacity_logits=torch.empty(n, device=dev))
+        self.npix = cam.width * cam.height
+        self.events = None
+
+    def _mark(self, name):
+        if self.events is not None:
+            e = self.t.cuda.Event(enable_timing=True)
+            e.record()
+            self.events.append((name, e))
+
+    def __call__(self):
+        r, P, c = self.render, self.P, self.cam
+        self._mark("start")
+        if self.form == "f32":
+            store, scale = P["feat"], None
+        else:
+            store, scale = r.quantize(P["feat"], self.form)
+        self._mark("quantize")
+        proj = r.project(c, P)
+        self._mark("project_fwd")
+        ids, ranges, m = self.binner(c, self.n, proj["depth"], proj["tile_rect"], proj["tiles_touched"])
+        self._mark("bin_sort")
+        fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges)
+        self._mark("rasterize_topk_fwd")
+        F = r.feature_fwd(fw["ids"], fw["w"], store, scale, self.form, self.map)
+        self._mark("feature_render_fwd")
+        tC, tD, tF = self.target
+        gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
+        gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
+        self._mark("l1_grad")
+        self.dfeat.zero_()
+        for v in self.sg.values():
+            v.zero_()
+        for v in self.pg.values():
+            v.zero_()
+        self._mark("zero_grads")
+        # Eq. 9's L1 feature loss: its gradient is formed inside the feature adjoint
+        dtw = r.feature_bwd_l1(fw["ids"], fw["w"], store, scale, self.form, self.map, tF,
+                               1.0 / (self.npix * self.d), self.dfeat)
+        self._mark("feature_render_bwd")
+        r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg)
+        self._mark("rasterize_topk_bwd")
+        r.project_bwd(c, P, self.sg, self.pg)
+        self._mark("project_bwd")
+        self.last = dict(fw=fw, pairs=m, F=F)
+
+
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    # whole-step timing
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    # per-phase timing: the same steps with an event after every phase
+    phases = {}
+    for _ in range(steps):
+        step.events = []
+        step()
+        torch.cuda.synchronize()
+        ev = step.events
+        for (_, a), (name, b) in zip(ev[:-1], ev[1:]):
+            phases.setdefault(name, []).append(a.elapsed_time(b))
+    step.events = None
+    return total_ms / steps, {k: float(np.median(v)) for k, v in phases.items()}
+
+
+def tile_union_stats(ids, W, H):
+    """Distinct Top-K Gaussians per 16x16 tile (host-side diagnostic)."""
+    ids = ids.cpu().numpy()
+    K = ids.shape[-1]
+    out = []
+    for ty in range(0, H, 16):
+        for tx in range(0, W, 16):
+            t = ids[ty:ty + 16, tx:tx + 16].reshape(-1)
+            out.append(len(np.unique(t[t >= 0])))
+    out = np.array(out)
+    return dict(mean=round(float(out.mean()), 1), p99=int(np.percentile(out, 99)), max=int(out.max()))
+
+
+def feature_bytes(npix, K, D, U, s_map, s_f, fp8):
+    fwd = npix * D * s_map + 8 * npix * K + U * D * s_f + (4 * U if fp8 else 0)
+    bwd = npix * D * s_map + 12 * npix * K + U * D * (s_f + 4) + (4 * U if fp8 else 0)
+    return fwd, bwd
+
+
+def cpu_baseline(scene, K, form):
+    """The FP64 oracle (test infrastructure, timed as a reported baseline, never tuned)
+    rendering and differentiating one full frame of the same workload on the host."""
+    from oracle import oracle as O
+    from paper_2602_06991_amd.scenegen import random_upstream
+    cam = scene.cameras[0]
+    g = scene.gaussians
+    feat64 = g.feat.astype(np.float64)
+    gC, gD, gO, gF = random_upstream(1, cam.W * cam.H, g.d)
+    t0 = time.perf_counter()
+    r = O.render(g, cam, K)
+    O.feature(r["ids"], r["w"], feat64)
+    t1 = time.perf_counter()
+    O.backward(g, cam, K, feat64, gC, gD, None, gF)
+    t2 = time.perf_counter()
+    return dict(value=round((t2 - t0) * 1e3, 1), unit="ms/frame", cores=O.num_threads(),
+                kind="oracle",
+                sample=f"one full {cam.W}x{cam.H} frame, FP64 features (storage form {form} "
+                       f"not applied): fwd {1e3 * (t1 - t0):.0f} ms + bwd {1e3 * (t2 - t1):.0f} ms")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this renderer runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+    import torch
+    from paper_2602_06991_amd import lgs, render
+    from paper_2602_06991_amd.scenegen import make_scene
+    lgs.load()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    t_gen = time.perf_counter()
+    scene = make_scene(args.config)
+    cfg = scene.config
+    print(f"# scene {cfg['W']}x{cfg['H']} N={cfg['N']} D={cfg['D']} generated in "
+          f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    cam_np = scene.cameras[0]
+    cam = lgs.make_camera(cam_np)
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    P = {k: f(v) for k, v in zip(("means", "log_scales", "quats", "opacity_logits", "rgb", "feat"),
+                                 scene.gaussians.arrays())}
+    PT = {k: f(v) for k, v in zip(("means", "log_scales", "quats", "opacity_logits", "rgb", "feat"),
+                                  scene.target.arrays())}
+    del scene.target
+    K = args.K
+    forms = args.forms.split(",")
+    results = {}
+    for form in forms:
+        mp = "f32" if form == "f32" else "bf16"
+        # target frame: the perturbed scene rendered by the same path, outside timing
+        tproj = render.project(cam, PT)
+        tb = render.Binner()
+        tids, tranges, _ = tb(cam, PT["means"].shape[0], tproj["depth"], tproj["tile_rect"],
+                              tproj["tiles_touched"])
+        tfw = render.rasterize(cam, K, tproj, PT["rgb"], tids, tranges)
+        tstore, tscale = render.quantize(PT["feat"], form)
+        tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp)
+        target = (tfw["C"].clone(), tfw["D"].clone(), tF.clone())
+        del tproj, tb, tids, tranges, tfw, tstore, tscale, tF
+        step = Step(torch, render, lgs, P, target, cam, K, form)
+        ms, phases = time_steps(torch, step, args.steps, args.warmup)
+        fw = step.last["fw"]
+        U = render.union_count(fw["ids"], P["feat"].shape[0])
+        npix = cam.width * cam.height
+        s_map = 4 if mp == "f32" else 2
+        s_f = {"f32": 4, "bf16": 2, "fp8": 1}[form]
+        bf, bb = feature_bytes(npix, K, cfg["D"], U, s_map, s_f, form == "fp8")
+        results[form] = dict(ms=ms, phases=phases, U=U, pairs=int(step.last["pairs"]),
+                             bytes_fwd=bf, bytes_bwd=bb,
+                             tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
+        print(f"# {form}: {ms:.3f} ms/step, U={U}, pairs={step.last['pairs']}, phases "
+              + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()), file=sys.stderr, flush=True)
+        del step, target
+        torch.cuda.empty_cache()
+    sweep = {}
+    if args.sweep:
+        for k2 in (1, 8):
+            for form in forms:
+                mp = "f32" if form == "f32" else "bf16"
+                tproj = render.project(cam, PT)
+                tb = render.Binner()
+                tids, tranges, _ = tb(cam, PT["means"].shape[0], tproj["depth"], tproj["tile_rect"],
+                                      tproj["tiles_touched"])
+                tfw = render.rasterize(cam, k2, tproj, PT["rgb"], tids, tranges)
+                tstore, tscale = render.quantize(PT["feat"], form)
+                tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp)
+                step = Step(torch, render, lgs, P, (tfw["C"].clone(), tfw["D"].clone(), tF.clone()), cam,
+                            k2, form)
+                ms, ph = time_steps(torch, step, max(5, args.steps // 2), 2)
+                sweep[f"K{k2}_{form}"] = dict(ms_per_frame=round(ms, 4),
+                                              feature_fwd_bwd_ms=round(ph["feature_render_fwd"] +
+                                                                       ph["feature_render_bwd"], 4))
+                del step
+                torch.cuda.empty_cache()
+
+    main_form = forms[0]
+    R = results[main_form]
+    ph = R["phases"]
+    # dominant kernel of the feature path: the slower of the two feature kernels
+    kern = max(("feature_render_fwd", "feature_render_bwd"), key=lambda k: ph[k])
+    kbytes = R["bytes_fwd"] if kern == "feature_render_fwd" else R["bytes_bwd"]
+    achieved = kbytes / (ph[kern] * 1e-3) / 1e9
+    feat_ms = ph["feature_render_fwd"] + ph["feature_render_bwd"]
+    feat_gbs = (R["bytes_fwd"] + R["bytes_bwd"]) / (feat_ms * 1e-3) / 1e9
+    line = {
+        "metric": "Top-K feature render fwd+bwd ms/frame + HBM GB/s, BF16 vs FP32, D=512, 1 GPU",
+        "value": round(R["ms"], 4),
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(R["ms"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 storage, f32 accumulate" if main_form == "bf16" else main_form,
+        "data": "synthetic (seeded room scene; Replica/TUM stand-in)",
+        "config": {"workload": f"{cfg['W']}x{cfg['H']} px x1 view, N={cfg['N']} Gaussians, "
+                               f"D={cfg['D']}, K={K}, features {main_form}",
+                   "W": cfg["W"], "H": cfg["H"], "N": cfg["N"], "D": cfg["D"], "K": K,
+                   "feature_dtype": main_form},
+        "feature_fwd_bwd_ms": round(feat_ms, 4),
+        "feature_fwd_bwd_GBps": round(feat_gbs, 1),
+        "feature_fwd_bwd_hbm_frac": round(feat_gbs / HBM_PEAK_GBS, 4),
+        "forms": {k: {"ms_per_frame": round(v["ms"], 4),
+                      "feature_fwd_bwd_ms": round(v["phases"]["feature_render_fwd"] +
+                                                  v["phases"]["feature_render_bwd"], 4),
+                      "phases_ms": {p: round(x, 4) for p, x in v["phases"].items()},
+                      "U": v["U"], "pairs": v["pairs"], "tile_union": v["tile_union"]}
+                  for k, v in results.items()},
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes": int(kbytes),
+                     "avg_ms": round(ph[kern], 4)},
+    }
+    if sweep:
+        line["k_sweep"] = sweep
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, K, main_form)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,21 @@ lgs_status lgs_feature_render_bwd(int32_t width, int32_t height, int32_t views, 
                                   float *dL_dfeat, float *dL_dtopkw, hipStream_t stream);
 
 /*
+ * Feature adjoint fused with the L1 feature loss of Eq. 9: identical to
+ * lgs_feature_render_bwd with dL/dF = scale * sign(F - F_target) (sign(0) = 0, the
+ * scale rounded to map_dt), where F is recomputed from the Top-K rows exactly as
+ * lgs_feature_render_fwd computes and rounds it.  Reads the target map instead of a
+ * materialised dL/dF, so the loss gradient never travels through HBM.
+ * F_target[n_pix*d] is in map_dt, 16-byte aligned.
+ */
+lgs_status lgs_feature_render_bwd_l1(int32_t width, int32_t height, int32_t views, int32_t k,
+                                     int32_t d, lgs_dtype feat_dt, const void *feat,
+                                     const float *feat_scale, const int32_t *topk_ids,
+                                     const float *topk_w, lgs_dtype map_dt, const void *F_target,
+                                     float scale, float *dL_dfeat, float *dL_dtopkw,
+                                     hipStream_t stream);
+
+/*
  * Adjoint of the blend (Eq. 1) including the Top-K weight path, replayed back to
  * front per pixel from T_final and n_contrib.  dL_dalpha and dL_dtopkw may be NULL.
  * Accumulates per-Gaussian screen-space gradients:
@@ -219,7 +234,7 @@ lgs_status lgs_quantize_features(int32_t n, int32_t d, const float *src, lgs_dty
 /*
  * L1 loss gradient (Eq. 9 and the L1 terms of Eq. 8): grad[i] = scale * sign(x[i] -
  * target[i]), sign(0) = 0, over n elements of dtype dt (F32 or BF16, all three
- * arrays the same dtype).
+ * arrays the same dtype, 16-byte aligned).  For BF16 the scale is rounded to BF16.
  */
 lgs_status lgs_l1_grad(int64_t n, lgs_dtype dt, const void *x, const void *target, float scale,
                        void *grad, hipStream_t stream);

@@ -473,6 +473,38 @@ int orc_feature(long n_pix, int K, int D, const int *ids, const double *w, const
     return 0;
 }
 
+/* Adjoint of Eq. 3-4 alone, for given Top-K ids/weights and upstream gF[P*D]:
+   with W = sum_k w_k, w'_k = w_k / W, g_k = <gF, f_k>:
+     d_feat[id_k] += w'_k gF  (d_feat[n*D] is overwritten first),
+     d_w[p*K + k] = (g_k - sum_j w'_j g_j) / W  (0 where W = 0 or the slot is empty). */
+int orc_feature_backward(long n_pix, int K, int D, int n, const int *ids, const double *w,
+                         const double *feat, const double *gF, double *d_feat, double *d_w)
+{
+    memset(d_feat, 0, sizeof(double) * (size_t)n * D);
+    for (long p = 0; p < n_pix; ++p) {
+        double Wsum = 0, gk[64], mean = 0;
+        for (int k = 0; k < K; ++k) Wsum += w[p * K + k];
+        for (int k = 0; k < K; ++k) {
+            gk[k] = 0;
+            d_w[p * K + k] = 0;
+        }
+        if (Wsum == 0) continue;
+        for (int k = 0; k < K; ++k) {
+            int g = ids[p * K + k];
+            if (g < 0) continue;
+            double s = 0;
+            for (int c = 0; c < D; ++c) s += gF[p * D + c] * feat[(long)g * D + c];
+            gk[k] = s;
+            double wp = w[p * K + k] / Wsum;
+            mean += wp * s;
+            for (int c = 0; c < D; ++c) d_feat[(long)g * D + c] += wp * gF[p * D + c];
+        }
+        for (int k = 0; k < K; ++k)
+            if (ids[p * K + k] >= 0) d_w[p * K + k] = (gk[k] - mean) / Wsum;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------- backward */
 
 /* Per-Gaussian screen-space gradient slots. */

@@ -52,9 +52,10 @@ def lib():
         L.orc_fp8_quantize.argtypes = [Lg, I, P, P, P]
         L.orc_e4m3_table.argtypes = [P]
         L.orc_topk_select.argtypes = [I, P, I, P]
+        L.orc_feature_backward.argtypes = [Lg, I, I, I, P, P, P, P, P, P]
         for f in (L.orc_project, L.orc_render, L.orc_feature, L.orc_backward,
                   L.orc_bf16_from_f32, L.orc_fp8_quantize, L.orc_e4m3_table, L.orc_num_threads,
-                  L.orc_topk_select):
+                  L.orc_topk_select, L.orc_feature_backward):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -132,6 +133,24 @@ def feature(ids, w, feat64):
     if rc:
         raise RuntimeError(f"orc_feature failed: {rc}")
     return F
+
+
+def feature_backward(ids, w, feat64, gF):
+    """Adjoint of Eq. 3-4 for given Top-K ids/w [..., K], FP64 features [N, D] and
+    upstream gF [..., D]: returns (d_feat [N, D], d_w [..., K])."""
+    ids = np.ascontiguousarray(ids, np.int32)
+    K = ids.shape[-1]
+    n_pix = ids.size // K
+    feat64 = _f64(feat64)
+    n, D = feat64.shape
+    w = _f64(w)
+    gF = _f64(gF)
+    d_feat = np.zeros((n, D))
+    d_w = np.zeros(ids.shape)
+    rc = lib().orc_feature_backward(n_pix, K, D, n, _p(ids), _p(w), _p(feat64), _p(gF), _p(d_feat), _p(d_w))
+    if rc:
+        raise RuntimeError(f"orc_feature_backward failed: {rc}")
+    return d_feat, d_w
 
 
 def backward(g, cam, K, feat64, gC=None, gD=None, gO=None, gF=None):

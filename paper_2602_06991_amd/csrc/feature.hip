@@ -13,6 +13,8 @@
 // dot products from it, and each distinct Gaussian's gradient row chunk is summed
 // in registers over its list and added to global memory with one coalesced atomic
 // per channel - U_t atomics per channel per tile instead of 256 K.
+#include <type_traits>
+
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
@@ -67,286 +69,461 @@ __device__ __forceinline__ void store8(void *F, long row, int D, int c, const fl
     }
 }
 
-constexpr int kFwdPixPerBlock = 64;   // 16 pixels per wave, consecutive in memory
+// ---------------------------------------------------------------- row cache
+
+// Both feature kernels give one 16x16 tile to a 256-thread block; wave w streams the
+// tile's rows 4w..4w+3 (64 pixels, one pixel at a time, lanes across channels).
+// Neighbouring pixels select mostly the same Gaussians, so each wave keeps the last
+// R feature rows it read in registers, keyed by Gaussian id with least-recently-used
+// replacement.  A pixel's K rows then come from registers; a row is read from memory
+// only when it enters the cache.  The backward also keeps, beside each cached row,
+// the running sum of w'_k dL/dF over the pixels that selected it, and adds it to
+// dL/df with coalesced atomics when the row leaves the cache.  Channels are covered
+// CPL per lane per pass; D > 64 CPL takes several passes.
+constexpr int kFB = 256;                  // threads per feature block
+constexpr int kPixPerWave = 64;
+
+template <int K> struct CacheCfg {
+    static constexpr int CPL = K <= 4 ? 8 : (K <= 8 ? 4 : 2);   // channels per lane per pass
+    static constexpr int R = K <= 4 ? 8 : (K <= 8 ? 12 : 20);    // cached rows per wave
+};
+
+template <int FT> struct Bytes { static constexpr int v = FT == FT_F32 ? 4 : FT == FT_BF16 ? 2 : 1; };
+
+// CPL consecutive values (storage format FT) starting at element index `at`.
+template <int FT, int CPL>
+__device__ __forceinline__ void loadc(const void *__restrict__ base, long at, float (&v)[CPL]) {
+    if constexpr (FT == FT_F32) {
+        const float *p = (const float *)base + at;
+        if constexpr (CPL == 8) {
+            f32x4 a = ((const f32x4 *)p)[0], b = ((const f32x4 *)p)[1];
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else if constexpr (CPL == 4) {
+            f32x4 a = *(const f32x4 *)p;
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        } else {
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            f32x2 a = *(const f32x2 *)p;
+            v[0] = a.x; v[1] = a.y;
+        }
+    } else if constexpr (FT == FT_BF16) {
+        const uint16_t *p = (const uint16_t *)base + at;
+        if constexpr (CPL == 8) {
+            u32x4 a = *(const u32x4 *)p;
+            uint32_t w4[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { v[2 * i] = bf16_to_f32(w4[i] & 0xFFFFu); v[2 * i + 1] = bf16_to_f32(w4[i] >> 16); }
+        } else if constexpr (CPL == 4) {
+            u32x2 a = *(const u32x2 *)p;
+            v[0] = bf16_to_f32(a.x & 0xFFFFu); v[1] = bf16_to_f32(a.x >> 16);
+            v[2] = bf16_to_f32(a.y & 0xFFFFu); v[3] = bf16_to_f32(a.y >> 16);
+        } else {
+            uint32_t a = *(const uint32_t *)p;
+            v[0] = bf16_to_f32(a & 0xFFFFu); v[1] = bf16_to_f32(a >> 16);
+        }
+    } else {
+        const uint8_t *p = (const uint8_t *)base + at;
+        if constexpr (CPL == 8) {
+            u32x2 a = *(const u32x2 *)p;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { v[i] = e4m3_to_f32((a.x >> (8 * i)) & 0xFFu); v[4 + i] = e4m3_to_f32((a.y >> (8 * i)) & 0xFFu); }
+        } else if constexpr (CPL == 4) {
+            uint32_t a = *(const uint32_t *)p;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = e4m3_to_f32((a >> (8 * i)) & 0xFFu);
+        } else {
+            uint32_t a = *(const uint16_t *)p;
+            v[0] = e4m3_to_f32(a & 0xFFu); v[1] = e4m3_to_f32(a >> 8);
+        }
+    }
+}
+
+template <int MT, int CPL>
+__device__ __forceinline__ void storec(void *__restrict__ base, long at, const float (&v)[CPL]) {
+    if constexpr (MT == MT_F32) {
+        float *p = (float *)base + at;
+        if constexpr (CPL == 8) {
+            f32x4 a = {v[0], v[1], v[2], v[3]}, b = {v[4], v[5], v[6], v[7]};
+            __builtin_nontemporal_store(a, (f32x4 *)p);
+            __builtin_nontemporal_store(b, (f32x4 *)p + 1);
+        } else if constexpr (CPL == 4) {
+            f32x4 a = {v[0], v[1], v[2], v[3]};
+            __builtin_nontemporal_store(a, (f32x4 *)p);
+        } else {
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            f32x2 a = {v[0], v[1]};
+            __builtin_nontemporal_store(a, (f32x2 *)p);
+        }
+    } else {
+        uint16_t *p = (uint16_t *)base + at;
+        uint32_t w[CPL / 2];
+#pragma unroll
+        for (int i = 0; i < CPL / 2; ++i)
+            w[i] = (uint32_t)f32_to_bf16(v[2 * i]) | ((uint32_t)f32_to_bf16(v[2 * i + 1]) << 16);
+        if constexpr (CPL == 8) {
+            u32x4 a = {w[0], w[1], w[2], w[3]};
+            __builtin_nontemporal_store(a, (u32x4 *)p);
+        } else if constexpr (CPL == 4) {
+            u32x2 a = {w[0], w[1]};
+            __builtin_nontemporal_store(a, (u32x2 *)p);
+        } else {
+            __builtin_nontemporal_store(w[0], (uint32_t *)p);
+        }
+    }
+}
+
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float rdlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Per-pixel Top-K slots of the wave's 64 pixels, one pixel per lane: ids, renormalised
+// weights w'_k (0 for empty slots) and the raw weight sum W.
+template <int K>
+struct WaveSlots {
+    int id[K];
+    float wp[K];
+    float W;
+};
+
+template <int K>
+__device__ __forceinline__ void load_wave_slots(bool valid, long p, const int *__restrict__ ids,
+                                                const float *__restrict__ tw, WaveSlots<K> &s) {
+    float wv[K];
+    s.W = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s.id[k] = valid ? ids[p * K + k] : -1;
+        wv[k] = valid ? tw[p * K + k] : 0.f;
+        s.W += wv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s.wp[k] = (s.W > 0.f && s.id[k] >= 0) ? wv[k] / s.W : 0.f;
+        if (!(s.W > 0.f)) s.id[k] = -1;
+    }
+}
+
+// The cache: uniform keys and ages, per-lane row values (and, backward, gradient sums).
+template <int R, int CPL, bool ACC>
+struct RowCache {
+    int key[R];
+    int age[R];
+    float sc[R];           // FP8 row scale (1 otherwise)
+    float row[R][CPL];
+    float acc[ACC ? R : 1][CPL];
+};
+
+template <int CPL>
+__device__ __forceinline__ void flush_row(const float (&a)[CPL], int g, int D, int pass_c0, int lane,
+                                          float *__restrict__ dfeat, float *xbuf) {
+    // transpose through wave-private LDS so each atomic instruction covers 64
+    // consecutive channels
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) xbuf[lane * CPL + j] = a[j];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    float *dst = dfeat + (long)g * D + pass_c0;
+    const int span = min(64 * CPL, D - pass_c0);
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        int c = j * 64 + lane;
+        float v = xbuf[c];
+        if (c < span && v != 0.f) unsafeAtomicAdd(&dst[c], v);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Slot of `u` in the cache (uniform), filling the least recently used slot on a miss.
+// On a miss in the backward the evicted row's gradient sum is flushed first.
+template <int FT, int R, int CPL, bool ACC>
+__device__ __forceinline__ int cache_slot(RowCache<R, CPL, ACC> &c, int u, int now, int D, int c0,
+                                          bool lane_on, const void *__restrict__ feat,
+                                          const float *__restrict__ scale, float *__restrict__ dfeat,
+                                          float *xbuf) {
+    // (keys, ages and scales are updated with selects, never with a variable index,
+    // so they stay in registers)
+    int hit = -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) hit = (c.key[r] == u) ? r : hit;
+    if (hit < 0) {
+        int victim = 0, oldest = c.age[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const bool older = c.age[r] < oldest;
+            oldest = older ? c.age[r] : oldest;
+            victim = older ? r : victim;
+        }
+        hit = victim;
+        const int lane = threadIdx.x & 63;
+        const float su = (FT == FT_FP8) ? scale[u] : 1.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r == victim) {
+                if constexpr (ACC) {
+                    if (c.key[r] >= 0) flush_row<CPL>(c.acc[r], c.key[r], D, c0 - lane * CPL, lane, dfeat, xbuf);
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) c.acc[r][j] = 0.f;
+                }
+                if (lane_on) loadc<FT, CPL>(feat, (long)u * D + c0, c.row[r]);
+                else {
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) c.row[r][j] = 0.f;
+                }
+            }
+            c.sc[r] = (r == victim) ? su : c.sc[r];
+            c.key[r] = (r == victim) ? u : c.key[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) c.age[r] = (r == hit) ? now : c.age[r];
+    return hit;
+}
+
+struct TileGeom {
+    int view, tx0, ty0;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(int tile, int W, int H) {
+    const int ntx = (W + kTile - 1) / kTile, nty = (H + kTile - 1) / kTile;
+    TileGeom g;
+    g.view = tile / (ntx * nty);
+    int tv = tile - g.view * ntx * nty;
+    g.tx0 = (tv % ntx) * kTile;
+    g.ty0 = (tv / ntx) * kTile;
+    return g;
+}
+
+// ---------------------------------------------------------------- forward
 
 template <int K, int FT, int MT>
-__global__ __launch_bounds__(256) void feature_fwd_kernel(long n_pix, int D, const void *__restrict__ feat,
+__global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int views, int D,
+                                                          const void *__restrict__ feat,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ ids,
                                                           const float *__restrict__ tw,
                                                           void *__restrict__ F) {
-    const int nblk = (int)((n_pix + kFwdPixPerBlock - 1) / kFwdPixPerBlock);
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    if (b >= nblk) return;
+    constexpr int CPL = CacheCfg<K>::CPL, R = CacheCfg<K>::R;
+    const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const TileGeom tg = tile_geom(tile, W, H);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int groups = D >> 3;
-    const long p0 = (long)b * kFwdPixPerBlock;
-    for (int i = wave; i < kFwdPixPerBlock; i += 4) {
-        const long p = p0 + i;
-        if (p >= n_pix) break;
-        int id[K];
-        float wk[K];
-        float W = 0.f;
+    // lane i holds the slots of the wave's pixel i
+    const int my_x = tg.tx0 + (lane & 15), my_y = tg.ty0 + wave * 4 + (lane >> 4);
+    const bool my_valid = my_x < W && my_y < H;
+    const long my_p = (long)tg.view * W * H + (long)my_y * W + my_x;
+    WaveSlots<K> sl;
+    load_wave_slots<K>(my_valid, my_p, ids, tw, sl);
+    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
+    for (int pass = 0; pass < passes; ++pass) {
+        const int c0 = pass * 64 * CPL + lane * CPL;
+        const bool lane_on = c0 < D;
+        RowCache<R, CPL, false> cache;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            id[k] = ids[p * K + k];
-            wk[k] = tw[p * K + k];
-            W += wk[k];
-        }
+        for (int r = 0; r < R; ++r) { cache.key[r] = -1; cache.age[r] = -1 - r; }
+        for (int i = 0; i < kPixPerWave; ++i) {
+            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
+            if (x >= W || y >= H) continue;
+            const long p = (long)tg.view * W * H + (long)y * W + x;
+            float out[CPL];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            float wp = (W > 0.f && id[k] >= 0) ? wk[k] / W : 0.f;
-            if constexpr (FT == FT_FP8) wp = (id[k] >= 0) ? wp * scale[id[k]] : 0.f;
-            wk[k] = wp;
-        }
-        for (int gi = lane; gi < groups; gi += 64) {
-            float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < CPL; ++j) out[j] = 0.f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                if (id[k] < 0) continue;
-                float v[8];
-                load8<FT>(feat, id[k], D, gi * 8, v);
+                const int u = rdlane(sl.id[k], i);
+                if (u < 0) continue;
+                const float wp = rdlane(sl.wp[k], i);
+                const int s = cache_slot<FT, R, CPL, false>(cache, u, i, D, c0, lane_on, feat, scale, nullptr, nullptr);
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] = fmaf(wk[k], v[c], acc[c]);
+                for (int r = 0; r < R; ++r) {
+                    if (r != s) continue;
+                    const float wf = wp * cache.sc[r];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) out[j] = fmaf(wf, cache.row[r][j], out[j]);
+                }
             }
-            store8<MT>(F, p, D, gi * 8, acc);
+            if (lane_on) storec<MT, CPL>(F, p * D + c0, out);
         }
     }
 }
 
 // ---------------------------------------------------------------- backward
 
-constexpr int kCh = 32;          // channels per chunk
-constexpr int kGStride = kCh + 1;
-
-struct BwdLds {
-    // byte offsets into the dynamic LDS buffer
-    int region;      // hash keys [HS] (phase 1), then G[256][33] floats
-    int region_bytes;
-    int uid;         // [256K] distinct Gaussian ids
-    int wp;          // [256K] renormalised weights, index t*K + k
-    int elist;       // [256K] list entries t*K + k grouped by distinct Gaussian
-    int lstart;      // [256K + 1] list starts (counts first)
-    int total;
-};
-
-__host__ __device__ inline int hash_size(int K) {
-    int need = 2 * 256 * K, hs = 1;
-    while (hs < need) hs <<= 1;
-    return hs;
-}
-
-__host__ __device__ inline BwdLds bwd_lds(int K) {
-    BwdLds L;
-    int hs = hash_size(K);
-    int a = hs * 4, b = 256 * kGStride * 4;
-    L.region = 0;
-    L.region_bytes = a > b ? a : b;
-    L.uid = L.region_bytes;
-    L.wp = L.uid + 256 * K * 4;
-    L.elist = L.wp + 256 * K * 4;
-    L.lstart = L.elist + 256 * K * 4;
-    L.total = L.lstart + (256 * K + 1) * 4;
-    return L;
-}
-
-template <int K, int FT, int MT>
-__global__ __launch_bounds__(256) void feature_bwd_kernel(int W, int H, int views, int D,
+// L1 = false: dF holds dL/dF (map dtype).  L1 = true: dF holds the target map F^ and
+// dL/dF = l1_scale * sign(F - F^) is formed on the fly from F recomputed exactly as
+// the forward kernel computes and rounds it.
+template <int K, int FT, int MT, bool L1>
+__global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int views, int D,
                                                           const void *__restrict__ feat,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ ids,
                                                           const float *__restrict__ tw,
-                                                          const void *__restrict__ dF,
+                                                          const void *__restrict__ dF, float l1_scale,
                                                           float *__restrict__ dfeat,
                                                           float *__restrict__ dtw) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    constexpr int HS = (2 * 256 * K <= 512) ? 512 : (2 * 256 * K <= 1024) ? 1024 :
-                       (2 * 256 * K <= 2048) ? 2048 : (2 * 256 * K <= 4096) ? 4096 : 8192;
-    const BwdLds L = bwd_lds(K);
-    int *hkey = (int *)(lds + L.region);
-    float *G = (float *)(lds + L.region);
-    int *uid = (int *)(lds + L.uid);
-    float *wps = (float *)(lds + L.wp);
-    int *elist = (int *)(lds + L.elist);
-    int *lstart = (int *)(lds + L.lstart);
-    __shared__ int s_scan[256];
-
-    const int ntx = (W + kTile - 1) / kTile, nty = (H + kTile - 1) / kTile;
-    const int ntiles = ntx * nty * views;
+    constexpr int CPL = CacheCfg<K>::CPL, R = CacheCfg<K>::R;
+    __shared__ float s_dot[4][kPixPerWave][K];
+    __shared__ float s_x[4][64 * CPL];
+    const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
-    const int view = tile / (ntx * nty);
-    const int tv = tile - view * ntx * nty;
-    const int t = threadIdx.x;
-    const int px = (tv % ntx) * kTile + (t & 15);
-    const int py = (tv / ntx) * kTile + (t >> 4);
-    const bool inside = px < W && py < H;
-    const long p = (long)view * W * H + (long)py * W + px;
-
-    // phase 0: this pixel's slots
-    int id[K];
-    float wv[K];
-    float Wsum = 0.f;
+    const TileGeom tg = tile_geom(tile, W, H);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float *xbuf = s_x[wave];
+    const int my_x = tg.tx0 + (lane & 15), my_y = tg.ty0 + wave * 4 + (lane >> 4);
+    const bool my_valid = my_x < W && my_y < H;
+    const long my_p = (long)tg.view * W * H + (long)my_y * W + my_x;
+    WaveSlots<K> sl;
+    load_wave_slots<K>(my_valid, my_p, ids, tw, sl);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        id[k] = inside ? ids[p * K + k] : -1;
-        wv[k] = inside ? tw[p * K + k] : 0.f;
-        Wsum += wv[k];
-    }
+    for (int k = 0; k < K; ++k) s_dot[wave][lane][k] = 0.f;
+    const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
+    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
+    for (int pass = 0; pass < passes; ++pass) {
+        const int c0 = pass * 64 * CPL + lane * CPL;
+        const bool lane_on = c0 < D;
+        RowCache<R, CPL, true> cache;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        float wp = (Wsum > 0.f && id[k] >= 0) ? wv[k] / Wsum : 0.f;
-        if (!(Wsum > 0.f)) id[k] = -1;
-        wps[t * K + k] = wp;
-    }
-
-    // phase 1: union of ids through an LDS hash table (linear probing)
-    for (int h = t; h < HS; h += 256) hkey[h] = -1;
-    __syncthreads();
-    int slot[K];
+        for (int r = 0; r < R; ++r) {
+            cache.key[r] = -1;
+            cache.age[r] = -1 - r;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        slot[k] = -1;
-        if (id[k] < 0) continue;
-        uint32_t h = ((uint32_t)id[k] * 2654435761u) & (HS - 1);
-        while (true) {
-            int prev = atomicCAS(&hkey[h], -1, id[k]);
-            if (prev == -1 || prev == id[k]) break;
-            h = (h + 1) & (HS - 1);
+            for (int j = 0; j < CPL; ++j) cache.acc[r][j] = 0.f;
         }
-        slot[k] = (int)h;
-    }
-    __syncthreads();
-    // dense index of every occupied slot, in slot order
-    constexpr int per = HS / 256;
-    int occ = 0;
-#pragma unroll
-    for (int j = 0; j < per; ++j) occ += hkey[t * per + j] >= 0;
-    s_scan[t] = occ;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        int x = t >= off ? s_scan[t - off] : 0;
-        __syncthreads();
-        s_scan[t] += x;
-        __syncthreads();
-    }
-    const int U = s_scan[255];
-    int u = s_scan[t] - occ;
-#pragma unroll
-    for (int j = 0; j < per; ++j) {
-        int h = t * per + j;
-        int key = hkey[h];
-        if (key >= 0) {
-            uid[u] = key;
-            hkey[h] = u;    // the slot now maps to its dense index
-            ++u;
-        }
-    }
-    for (int i = t; i <= U; i += 256) lstart[i] = 0;
-    __syncthreads();
-    int uk[K];
-    int pos[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        uk[k] = slot[k] >= 0 ? hkey[slot[k]] : -1;
-        pos[k] = uk[k] >= 0 ? atomicAdd(&lstart[uk[k]], 1) : 0;
-    }
-    __syncthreads();
-    // exclusive scan of the list lengths (U <= 256 K entries)
-    {
-        const int chunk = (U + 255) / 256;
-        int s = 0;
-        for (int j = 0; j < chunk; ++j) {
-            int i = t * chunk + j;
-            if (i < U) s += lstart[i];
-        }
-        s_scan[t] = s;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            int x = t >= off ? s_scan[t - off] : 0;
-            __syncthreads();
-            s_scan[t] += x;
-            __syncthreads();
-        }
-        int run = s_scan[t] - s;
-        for (int j = 0; j < chunk; ++j) {
-            int i = t * chunk + j;
-            if (i < U) {
-                int c = lstart[i];
-                lstart[i] = run;
-                run += c;
+        // dL/dF (or the target map) is streamed in batches of PB pixels, raw and
+        // double-buffered: batch b + 1 loads while batch b computes.
+        constexpr int PB = MT == MT_F32 ? 2 : 4;
+        constexpr int NW = MT == MT_F32 ? CPL : CPL / 2;    // 32-bit words per pixel per lane
+        auto want = [&](int i) {
+            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
+            return x < W && y < H && rdlane(sl.W, i) > 0.f;
+        };
+        auto fetch = [&](int i, uint32_t (&dst)[NW]) {
+            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
+            if (!(want(i) && lane_on)) return;
+            const long at = ((long)tg.view * W * H + (long)y * W + x) * D + c0;
+            const uint32_t *src = MT == MT_F32 ? (const uint32_t *)((const float *)dF + at)
+                                               : (const uint32_t *)((const uint16_t *)dF + at);
+            if constexpr (NW == 8) {
+                u32x4 q0 = ((const u32x4 *)src)[0], q1 = ((const u32x4 *)src)[1];
+                dst[0] = q0.x; dst[1] = q0.y; dst[2] = q0.z; dst[3] = q0.w;
+                dst[4] = q1.x; dst[5] = q1.y; dst[6] = q1.z; dst[7] = q1.w;
+            } else if constexpr (NW == 4) {
+                u32x4 q = *(const u32x4 *)src;
+                dst[0] = q.x; dst[1] = q.y; dst[2] = q.z; dst[3] = q.w;
+            } else if constexpr (NW == 2) {
+                u32x2 q = *(const u32x2 *)src;
+                dst[0] = q.x; dst[1] = q.y;
+            } else {
+                dst[0] = *src;
             }
+        };
+        uint32_t cur_b[PB][NW], nxt_b[PB][NW];
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) { cur_b[j][w] = 0u; nxt_b[j][w] = 0u; }
+            fetch(j, cur_b[j]);
         }
-        if (t == 255) lstart[U] = s_scan[255];
-        __syncthreads();
-    }
+        for (int i0 = 0; i0 < kPixPerWave; i0 += PB) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (uk[k] >= 0) elist[lstart[uk[k]] + pos[k]] = t * K + k;
-    __syncthreads();
-
-    // phase 2: channel chunks
-    float dot[K];
+            for (int j = 0; j < PB; ++j)
+                if (i0 + PB + j < kPixPerWave) fetch(i0 + PB + j, nxt_b[j]);
+#pragma unroll 1
+            for (int jj = 0; jj < PB; ++jj) {
+                const int i = i0 + jj;
+                if (!want(i)) continue;
+                // this pixel's raw words, picked with uniform selects
+                uint32_t rw[NW];
 #pragma unroll
-    for (int k = 0; k < K; ++k) dot[k] = 0.f;
-    const int wave = t >> 6, lane = t & 63;
-    const int worker = wave * 2 + (lane >> 5);   // 8 half-wave row workers
-    const int cl = lane & 31;
-    const int tile_x0 = (tv % ntx) * kTile, tile_y0 = (tv / ntx) * kTile;
-    for (int c0 = 0; c0 < D; c0 += kCh) {
-        const int cw = min(kCh, D - c0);      // a multiple of 8
-        // stage dL/dF[256 pixels][cw] as FP32
-        for (int q = t; q < 256 * (kCh / 8); q += 256) {
-            int pix = q >> 2, part = q & 3;   // 4 groups of 8 channels per pixel
-            int c = part * 8;
-            int lx = tile_x0 + (pix & 15), ly = tile_y0 + (pix >> 4);
-            float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (c < cw && lx < W && ly < H) {
-                long pp = (long)view * W * H + (long)ly * W + lx;
-                if constexpr (MT == MT_F32) load8<FT_F32>(dF, pp, D, c0 + c, v);
-                else load8<FT_BF16>(dF, pp, D, c0 + c, v);
-            }
+                for (int w = 0; w < NW; ++w) {
+                    uint32_t v = cur_b[0][w];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) G[pix * kGStride + c + i] = v[i];
-        }
-        __syncthreads();
-        // dot products of this pixel's dL/dF chunk with its K feature rows
-        if (Wsum > 0.f) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (id[k] < 0) continue;
-                float s = 0.f;
-                for (int c = 0; c < cw; c += 8) {
-                    float v[8];
-                    load8<FT>(feat, id[k], D, c0 + c, v);
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) s = fmaf(v[i], G[t * kGStride + c + i], s);
+                    for (int j = 1; j < PB; ++j) v = (jj == j) ? cur_b[j][w] : v;
+                    rw[w] = v;
                 }
-                if constexpr (FT == FT_FP8) s *= scale[id[k]];
-                dot[k] += s;
-            }
-        }
-        // gradient rows: each half-wave sums one distinct Gaussian's entries
-        for (int uu = worker; uu < U; uu += 8) {
-            float acc = 0.f;
-            const int e1 = lstart[uu + 1];
-            for (int e = lstart[uu]; e < e1; ++e) {
-                int ent = elist[e];
-                int tp = ent / K;
-                acc = fmaf(wps[ent], G[tp * kGStride + cl], acc);
-            }
-            if (cl < cw) unsafeAtomicAdd(&dfeat[(long)uid[uu] * D + c0 + cl], acc);
-        }
-        __syncthreads();
-    }
-    // phase 3: gamma_k = (g_k - sum_j w'_j g_j) / W
-    if (!inside) return;
-    float mean = 0.f;
+                float cur[CPL];
 #pragma unroll
-    for (int k = 0; k < K; ++k) mean = fmaf(wps[t * K + k], dot[k], mean);
+                for (int c = 0; c < CPL; ++c)
+                    cur[c] = MT == MT_F32 ? __uint_as_float(rw[c < NW ? c : 0])
+                                          : bf16_to_f32((rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu);
+                int slot[K];
+                float wp[K];
+                // the pixel's rows into the cache (all K fit: R >= K and they are the newest)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int u = rdlane(sl.id[k], i);
+                    wp[k] = rdlane(sl.wp[k], i);
+                    slot[k] = u < 0 ? -1 : cache_slot<FT, R, CPL, true>(cache, u, i, D, c0, lane_on, feat, scale, dfeat, xbuf);
+                }
+                float G[CPL];
+                if constexpr (L1) {
+                    float Fv[CPL];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) Fv[j] = 0.f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            if (r != slot[k]) continue;
+                            const float wf = wp[k] * cache.sc[r];
+#pragma unroll
+                            for (int j = 0; j < CPL; ++j) Fv[j] = fmaf(wf, cache.row[r][j], Fv[j]);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) {
+                        const float fm = MT == MT_F32 ? Fv[j] : bf16_to_f32(f32_to_bf16(Fv[j]));
+                        const float d = lane_on ? fm - cur[j] : 0.f;
+                        G[j] = d > 0.f ? gs : (d < 0.f ? -gs : 0.f);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) G[j] = lane_on ? cur[j] : 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    float part = 0.f;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r != slot[k]) continue;
+#pragma unroll
+                        for (int j = 0; j < CPL; ++j) {
+                            part = fmaf(G[j], cache.row[r][j], part);
+                            cache.acc[r][j] = fmaf(wp[k], G[j], cache.acc[r][j]);
+                        }
+                        part *= cache.sc[r];
+                    }
+                    const float g = wave_sum(part);
+                    if (lane == 0) s_dot[wave][i][k] += g;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) { cur_b[j][w] = nxt_b[j][w]; nxt_b[j][w] = 0u; }
+            }
+        }
+        // rows still cached
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (cache.key[r] >= 0) flush_row<CPL>(cache.acc[r], cache.key[r], D, pass * 64 * CPL, lane, dfeat, xbuf);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // gamma_k = (g_k - sum_j w'_j g_j) / W for the lane's own pixel
+    if (!my_valid) return;
+    float g[K], mean = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        g[k] = s_dot[wave][lane][k];
+        mean = fmaf(sl.wp[k], g[k], mean);
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        dtw[p * K + k] = (Wsum > 0.f && id[k] >= 0) ? (dot[k] - mean) / Wsum : 0.f;
+        dtw[my_p * K + k] = (sl.W > 0.f && sl.id[k] >= 0) ? (g[k] - mean) / sl.W : 0.f;
 }
 
 // ---------------------------------------------------------------- quantize, L1, union
@@ -405,19 +582,50 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const floa
     if (lane == 0) scale[row] = s;
 }
 
+__device__ __forceinline__ float l1_sign(float d, float g) { return d > 0.f ? g : (d < 0.f ? -g : 0.f); }
+
+// grad = scale * sign(x - target), eight elements per thread with 16-byte accesses;
+// the last thread also finishes the n % 8 tail element by element.
 template <int DT>
 __global__ __launch_bounds__(256) void l1_grad_kernel(long n, const void *__restrict__ x,
                                                       const void *__restrict__ tgt, float scale,
                                                       void *__restrict__ grad) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const long n8 = n >> 3;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if constexpr (DT == MT_F32) {
-        float d = ((const float *)x)[i] - ((const float *)tgt)[i];
-        ((float *)grad)[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+        if (i < n8) {
+            const f32x4 *a = (const f32x4 *)x + 2 * i, *b = (const f32x4 *)tgt + 2 * i;
+            f32x4 a0 = a[0], a1 = a[1], b0 = b[0], b1 = b[1];
+            f32x4 o0 = {l1_sign(a0.x - b0.x, scale), l1_sign(a0.y - b0.y, scale),
+                        l1_sign(a0.z - b0.z, scale), l1_sign(a0.w - b0.w, scale)};
+            f32x4 o1 = {l1_sign(a1.x - b1.x, scale), l1_sign(a1.y - b1.y, scale),
+                        l1_sign(a1.z - b1.z, scale), l1_sign(a1.w - b1.w, scale)};
+            f32x4 *g = (f32x4 *)grad + 2 * i;
+            g[0] = o0;
+            g[1] = o1;
+        }
+        if (i == n8)
+            for (long j = n8 * 8; j < n; ++j)
+                ((float *)grad)[j] = l1_sign(((const float *)x)[j] - ((const float *)tgt)[j], scale);
     } else {
-        float d = bf16_to_f32(((const uint16_t *)x)[i]) - bf16_to_f32(((const uint16_t *)tgt)[i]);
-        float g = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-        ((uint16_t *)grad)[i] = f32_to_bf16(g);
+        const float gs = bf16_to_f32(f32_to_bf16(scale));
+        const uint32_t pos = f32_to_bf16(gs), neg = f32_to_bf16(-gs);
+        auto pick = [&](uint32_t xa, uint32_t xb) -> uint32_t {
+            float d = bf16_to_f32(xa) - bf16_to_f32(xb);
+            return d > 0.f ? pos : (d < 0.f ? neg : 0u);
+        };
+        if (i < n8) {
+            u32x4 a = ((const u32x4 *)x)[i], b = ((const u32x4 *)tgt)[i];
+            u32x4 o;
+            o.x = pick(a.x & 0xFFFFu, b.x & 0xFFFFu) | (pick(a.x >> 16, b.x >> 16) << 16);
+            o.y = pick(a.y & 0xFFFFu, b.y & 0xFFFFu) | (pick(a.y >> 16, b.y >> 16) << 16);
+            o.z = pick(a.z & 0xFFFFu, b.z & 0xFFFFu) | (pick(a.z >> 16, b.z >> 16) << 16);
+            o.w = pick(a.w & 0xFFFFu, b.w & 0xFFFFu) | (pick(a.w >> 16, b.w >> 16) << 16);
+            ((u32x4 *)grad)[i] = o;
+        }
+        if (i == n8)
+            for (long j = n8 * 8; j < n; ++j)
+                ((uint16_t *)grad)[j] = (uint16_t)pick(((const uint16_t *)x)[j], ((const uint16_t *)tgt)[j]);
     }
 }
 
@@ -449,39 +657,46 @@ __global__ __launch_bounds__(256) void union_sum_kernel(int n, int *__restrict__
 // ---------------------------------------------------------------- dispatch
 
 template <int FT, int MT>
-lgs_status fwd_dispatch(int k, long n_pix, int D, const void *feat, const float *scale, const int *ids,
-                        const float *tw, void *F, hipStream_t st) {
-    unsigned grid = padded_grid((n_pix + kFwdPixPerBlock - 1) / kFwdPixPerBlock);
+lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
+                        const int *ids, const float *tw, void *F, hipStream_t st) {
+    unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
-        hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(256), 0, st, n_pix, D, \
-                           feat, scale, ids, tw, F);                                                 \
+        hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(kFB), 0, st, W, H,    \
+                           views, D, feat, scale, ids, tw, F);                                       \
         break;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
     return check_launch("feature_render_fwd");
 }
 
-template <int FT, int MT>
+template <int FT, int MT, bool L1>
 lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
-                        const int *ids, const float *tw, const void *dF, float *dfeat, float *dtw,
-                        hipStream_t st) {
-    long tiles = (long)tiles_x(W) * tiles_y(H) * views;
-    unsigned grid = padded_grid(tiles);
-    size_t lds = (size_t)bwd_lds(k).total;
-#define CALL(KK)                                                                                    \
-    case KK:                                                                                        \
-        if (hipFuncSetAttribute((const void *)feature_bwd_kernel<KK, FT, MT>,                      \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) { \
-            set_error("feature_render_bwd: %zu bytes of LDS unavailable", lds);                     \
-            return LGS_ERR_UNSUPPORTED;                                                             \
-        }                                                                                           \
-        hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT>), dim3(grid), dim3(256), lds, st, W, H, \
-                           views, D, feat, scale, ids, tw, dF, dfeat, dtw);                         \
+                        const int *ids, const float *tw, const void *dF, float l1_scale, float *dfeat,
+                        float *dtw, hipStream_t st) {
+    unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
+#define CALL(KK)                                                                                     \
+    case KK:                                                                                         \
+        hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, L1>), dim3(grid), dim3(kFB), 0, st, W, H, \
+                           views, D, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw);                 \
         break;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
     return check_launch("feature_render_bwd");
+}
+
+template <bool L1>
+lgs_status bwd_entry(int32_t width, int32_t height, int32_t views, int32_t k, int32_t d, lgs_dtype feat_dt,
+                     const void *feat, const float *feat_scale, const int32_t *topk_ids, const float *topk_w,
+                     lgs_dtype map_dt, const void *dF, float l1_scale, float *dL_dfeat, float *dL_dtopkw,
+                     hipStream_t stream) {
+#define ARGS k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dF, l1_scale, dL_dfeat, dL_dtopkw, stream
+    if (feat_dt == LGS_F32) return bwd_dispatch<FT_F32, MT_F32, L1>(ARGS);
+    if (feat_dt == LGS_BF16 && map_dt == LGS_BF16) return bwd_dispatch<FT_BF16, MT_BF16, L1>(ARGS);
+    if (feat_dt == LGS_BF16) return bwd_dispatch<FT_BF16, MT_F32, L1>(ARGS);
+    if (map_dt == LGS_BF16) return bwd_dispatch<FT_FP8, MT_BF16, L1>(ARGS);
+    return bwd_dispatch<FT_FP8, MT_F32, L1>(ARGS);
+#undef ARGS
 }
 
 lgs_status check_feature_args(int W, int H, int views, int k, int d, lgs_dtype fdt, const void *feat,
@@ -512,13 +727,13 @@ extern "C" lgs_status lgs_feature_render_fwd(int32_t width, int32_t height, int3
     if (st) return st;
     LGS_REQUIRE(topk_ids && topk_w && F, LGS_ERR_INVALID_ARG, "lgs_feature_render_fwd: NULL pointer");
     LGS_REQUIRE(aligned16(F), LGS_ERR_INVALID_ARG, "F must be 16-byte aligned");
-    long n_pix = (long)width * height * views;
-    if (feat_dt == LGS_F32) return fwd_dispatch<FT_F32, MT_F32>(k, n_pix, d, feat, feat_scale, topk_ids, topk_w, F, stream);
-    if (feat_dt == LGS_BF16 && map_dt == LGS_BF16)
-        return fwd_dispatch<FT_BF16, MT_BF16>(k, n_pix, d, feat, feat_scale, topk_ids, topk_w, F, stream);
-    if (feat_dt == LGS_BF16) return fwd_dispatch<FT_BF16, MT_F32>(k, n_pix, d, feat, feat_scale, topk_ids, topk_w, F, stream);
-    if (map_dt == LGS_BF16) return fwd_dispatch<FT_FP8, MT_BF16>(k, n_pix, d, feat, feat_scale, topk_ids, topk_w, F, stream);
-    return fwd_dispatch<FT_FP8, MT_F32>(k, n_pix, d, feat, feat_scale, topk_ids, topk_w, F, stream);
+#define ARGS k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, F, stream
+    if (feat_dt == LGS_F32) return fwd_dispatch<FT_F32, MT_F32>(ARGS);
+    if (feat_dt == LGS_BF16 && map_dt == LGS_BF16) return fwd_dispatch<FT_BF16, MT_BF16>(ARGS);
+    if (feat_dt == LGS_BF16) return fwd_dispatch<FT_BF16, MT_F32>(ARGS);
+    if (map_dt == LGS_BF16) return fwd_dispatch<FT_FP8, MT_BF16>(ARGS);
+    return fwd_dispatch<FT_FP8, MT_F32>(ARGS);
+#undef ARGS
 }
 
 extern "C" lgs_status lgs_feature_render_bwd(int32_t width, int32_t height, int32_t views, int32_t k,
@@ -531,15 +746,23 @@ extern "C" lgs_status lgs_feature_render_bwd(int32_t width, int32_t height, int3
     LGS_REQUIRE(topk_ids && topk_w && dL_dF && dL_dfeat && dL_dtopkw, LGS_ERR_INVALID_ARG,
                 "lgs_feature_render_bwd: NULL pointer");
     LGS_REQUIRE(aligned16(dL_dF), LGS_ERR_INVALID_ARG, "dL_dF must be 16-byte aligned");
-    if (feat_dt == LGS_F32)
-        return bwd_dispatch<FT_F32, MT_F32>(k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dL_dF, dL_dfeat, dL_dtopkw, stream);
-    if (feat_dt == LGS_BF16 && map_dt == LGS_BF16)
-        return bwd_dispatch<FT_BF16, MT_BF16>(k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dL_dF, dL_dfeat, dL_dtopkw, stream);
-    if (feat_dt == LGS_BF16)
-        return bwd_dispatch<FT_BF16, MT_F32>(k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dL_dF, dL_dfeat, dL_dtopkw, stream);
-    if (map_dt == LGS_BF16)
-        return bwd_dispatch<FT_FP8, MT_BF16>(k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dL_dF, dL_dfeat, dL_dtopkw, stream);
-    return bwd_dispatch<FT_FP8, MT_F32>(k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dL_dF, dL_dfeat, dL_dtopkw, stream);
+    return bwd_entry<false>(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w, map_dt,
+                            dL_dF, 0.0f, dL_dfeat, dL_dtopkw, stream);
+}
+
+extern "C" lgs_status lgs_feature_render_bwd_l1(int32_t width, int32_t height, int32_t views, int32_t k,
+                                                int32_t d, lgs_dtype feat_dt, const void *feat,
+                                                const float *feat_scale, const int32_t *topk_ids,
+                                                const float *topk_w, lgs_dtype map_dt, const void *F_target,
+                                                float scale, float *dL_dfeat, float *dL_dtopkw,
+                                                hipStream_t stream) {
+    lgs_status st = check_feature_args(width, height, views, k, d, feat_dt, feat, feat_scale, map_dt);
+    if (st) return st;
+    LGS_REQUIRE(topk_ids && topk_w && F_target && dL_dfeat && dL_dtopkw, LGS_ERR_INVALID_ARG,
+                "lgs_feature_render_bwd_l1: NULL pointer");
+    LGS_REQUIRE(aligned16(F_target), LGS_ERR_INVALID_ARG, "F_target must be 16-byte aligned");
+    return bwd_entry<true>(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w, map_dt,
+                           F_target, scale, dL_dfeat, dL_dtopkw, stream);
 }
 
 extern "C" lgs_status lgs_quantize_features(int32_t n, int32_t d, const float *src, lgs_dtype dst_dt,
@@ -566,7 +789,9 @@ extern "C" lgs_status lgs_l1_grad(int64_t n, lgs_dtype dt, const void *x, const 
     LGS_REQUIRE(n >= 0, LGS_ERR_INVALID_ARG, "n must be >= 0");
     if (n == 0) return LGS_OK;
     LGS_REQUIRE(x && target && grad, LGS_ERR_INVALID_ARG, "lgs_l1_grad: NULL pointer");
-    unsigned grid = (unsigned)((n + 255) / 256);
+    LGS_REQUIRE(aligned16(x) && aligned16(target) && aligned16(grad), LGS_ERR_INVALID_ARG,
+                "lgs_l1_grad: arrays must be 16-byte aligned");
+    unsigned grid = (unsigned)(((n >> 3) + 1 + 255) / 256);
     if (dt == LGS_F32)
         hipLaunchKernelGGL(l1_grad_kernel<MT_F32>, dim3(grid), dim3(256), 0, stream, (long)n, x, target, scale, grad);
     else if (dt == LGS_BF16)

@@ -65,6 +65,8 @@ _SIG = {
                                ctypes.c_int, _P, _P],
     "lgs_feature_render_bwd": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                ctypes.c_int, _P, _P, _P, _P],
+    "lgs_feature_render_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
+                                  ctypes.c_int, _P, _F, _P, _P, _P],
     "lgs_rasterize_topk_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -84,6 +86,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime under the same soname; load it first so this
+    # library binds to the runtime that owns torch's device memory and streams
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     for name, args in _SIG.items():
         f = getattr(L, name)
@@ -161,6 +169,13 @@ def lgs_feature_render_bwd(width, height, views, k, d, feat_dt, feat, feat_scale
     return _check(load().lgs_feature_render_bwd(width, height, views, k, d, feat_dt, feat, feat_scale,
                                                 topk_ids, topk_w, map_dt, dL_dF, dL_dfeat,
                                                 dL_dtopkw, stream))
+
+
+def lgs_feature_render_bwd_l1(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w,
+                              map_dt, F_target, scale, dL_dfeat, dL_dtopkw, stream=None):
+    return _check(load().lgs_feature_render_bwd_l1(width, height, views, k, d, feat_dt, feat, feat_scale,
+                                                   topk_ids, topk_w, map_dt, F_target, scale, dL_dfeat,
+                                                   dL_dtopkw, stream))
 
 
 def lgs_rasterize_topk_bwd(cam, k, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,

@@ -2,7 +2,10 @@
 path through the C ABI, and compare with the oracle."""
 import numpy as np
 
-FLAG_EPS = dict(eps_skip=1e-3, eps_clamp=1e-3, eps_T=1e-3, eps_topk=1e-3)
+# Decision-margin thresholds: 4x the largest FP32 relative error of the blending
+# weights measured on the GPU at 640x480 (5.2e-5); no pixel whose Top-K differed had a
+# margin above 1.4e-5.
+FLAG_EPS = dict(eps_skip=2.5e-4, eps_clamp=2.5e-4, eps_T=2.5e-4, eps_topk=2.5e-4)
 
 
 def torch_mod():

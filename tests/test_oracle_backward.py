@@ -100,3 +100,50 @@ def test_screen_space_gradients_match_differences_of_a_linear_functional(orc):
     np.testing.assert_allclose(b["d_rgb"][:, 0], tot, rtol=1e-12, atol=1e-15)
     b2 = orc.backward(g, cam, 4, g.feat.astype(np.float64), None, ones, None, None)
     np.testing.assert_allclose(b2["d_z"], tot, rtol=1e-12, atol=1e-15)
+
+
+def test_feature_adjoint_by_differences(orc):
+    """The stand-alone feature adjoint: F is linear in f and a ratio in w, so central
+    differences in w and f of L = <R, F(w, f)> pin d_w and d_feat."""
+    rng = np.random.default_rng(9)
+    n, D, K, P = 30, 6, 4, 50
+    ids = np.stack([rng.choice(n, K, replace=False) for _ in range(P)]).astype(np.int32)
+    ids[3, 2:] = -1
+    w = rng.uniform(0.01, 0.5, (P, K))
+    w[ids < 0] = 0
+    w[7] = 0
+    ids[7] = -1
+    f = rng.standard_normal((n, D))
+    R = rng.standard_normal((P, D))
+    d_feat, d_w = orc.feature_backward(ids, w, f, R)
+    L = lambda w_, f_: (orc.feature(ids, w_, f_) * R).sum()
+    h = 1e-6
+    for _ in range(40):
+        p, k = rng.integers(P), rng.integers(K)
+        if ids[p, k] < 0:
+            assert d_w[p, k] == 0
+            continue
+        wp, wm = w.copy(), w.copy()
+        wp[p, k] += h
+        wm[p, k] -= h
+        fd = (L(wp, f) - L(wm, f)) / (2 * h)
+        assert abs(fd - d_w[p, k]) <= 1e-6 * max(1, abs(fd))
+    for _ in range(40):
+        g, c = rng.integers(n), rng.integers(D)
+        fp, fm = f.copy(), f.copy()
+        fp[g, c] += h
+        fm[g, c] -= h
+        fd = (L(w, fp) - L(w, fm)) / (2 * h)
+        assert abs(fd - d_feat[g, c]) <= 1e-6 * max(1, abs(fd))
+    assert np.all(d_w[7] == 0)
+
+
+def test_feature_adjoint_agrees_with_full_adjoint(orc):
+    sc = make_scene(0, N=3000, W=48, H=40, D=8)
+    g, cam = sc.gaussians, sc.cameras[0]
+    r = orc.render(g, cam, 4)
+    gF = np.random.default_rng(2).standard_normal((cam.H, cam.W, 8))
+    b = orc.backward(g, cam, 4, g.feat.astype(np.float64), None, None, None, gF)
+    d_feat, d_w = orc.feature_backward(r["ids"], r["w"], g.feat.astype(np.float64), gF)
+    np.testing.assert_allclose(d_feat, b["d_feat"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(d_w, b["d_topkw"], rtol=1e-12, atol=1e-13)
