@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--sweep", action="store_true", help="also time K = 1 and 8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bf16,f32")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy three times (a known-size kernel "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -184,6 +187,14 @@ def main():
     from paper_2602_06991_amd.scenegen import make_scene
     lgs.load()
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, device="cuda")          # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: 3 x {src.numel() * 4} bytes read and written", file=sys.stderr)
+        del src, dst
     t_gen = time.perf_counter()
     scene = make_scene(args.config)
     cfg = scene.config

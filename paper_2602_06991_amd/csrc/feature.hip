@@ -69,23 +69,27 @@ __device__ __forceinline__ void store8(void *F, long row, int D, int c, const fl
     }
 }
 
-// ---------------------------------------------------------------- row cache
+// ---------------------------------------------------------------- tile union
 
-// Both feature kernels give one 16x16 tile to a 256-thread block; wave w streams the
-// tile's rows 4w..4w+3 (64 pixels, one pixel at a time, lanes across channels).
-// Neighbouring pixels select mostly the same Gaussians, so each wave keeps the last
-// R feature rows it read in registers, keyed by Gaussian id with least-recently-used
-// replacement.  A pixel's K rows then come from registers; a row is read from memory
-// only when it enters the cache.  The backward also keeps, beside each cached row,
-// the running sum of w'_k dL/dF over the pixels that selected it, and adds it to
-// dL/df with coalesced atomics when the row leaves the cache.  Channels are covered
-// CPL per lane per pass; D > 64 CPL takes several passes.
-constexpr int kFB = 256;                  // threads per feature block
+// Both feature kernels give one 16x16 tile to a 256-thread block.  Wave w owns the
+// tile's rows 4w..4w+3 (64 pixels) and streams them one pixel at a time with lanes
+// across channels (CPL consecutive channels per lane per pass).
+//
+// Prologue: lane i loads the Top-K slots of the wave's pixel i.  The wave lists its
+// distinct Gaussian ids with a ballot loop (one iteration per distinct id, no
+// contention), the four wave lists merge through a small LDS hash table into the
+// tile's union, and the union's feature rows are staged once into LDS (at most
+// `ucap` of them; rare larger unions read the rest from global memory).  The forward
+// then builds each pixel's row from LDS and writes it; the backward adds w'_k dL/dF
+// into per-wave register accumulators indexed by the wave-local id index, and adds
+// each accumulator to dL/df once, with coalesced atomics.
+constexpr int kFB = 256;          // threads per feature block
 constexpr int kPixPerWave = 64;
 
-template <int K> struct CacheCfg {
+template <int K> struct TileCfg {
     static constexpr int CPL = K <= 4 ? 8 : (K <= 8 ? 4 : 2);   // channels per lane per pass
-    static constexpr int R = K <= 4 ? 8 : (K <= 8 ? 12 : 20);    // cached rows per wave
+    static constexpr int RA = K <= 4 ? 12 : (K <= 8 ? 16 : 24);  // register accumulators per wave
+    static constexpr int HS = 1024;                               // union hash slots
 };
 
 template <int FT> struct Bytes { static constexpr int v = FT == FT_F32 ? 4 : FT == FT_BF16 ? 2 : 1; };
@@ -177,110 +181,6 @@ __device__ __forceinline__ float rdlane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Per-pixel Top-K slots of the wave's 64 pixels, one pixel per lane: ids, renormalised
-// weights w'_k (0 for empty slots) and the raw weight sum W.
-template <int K>
-struct WaveSlots {
-    int id[K];
-    float wp[K];
-    float W;
-};
-
-template <int K>
-__device__ __forceinline__ void load_wave_slots(bool valid, long p, const int *__restrict__ ids,
-                                                const float *__restrict__ tw, WaveSlots<K> &s) {
-    float wv[K];
-    s.W = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        s.id[k] = valid ? ids[p * K + k] : -1;
-        wv[k] = valid ? tw[p * K + k] : 0.f;
-        s.W += wv[k];
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        s.wp[k] = (s.W > 0.f && s.id[k] >= 0) ? wv[k] / s.W : 0.f;
-        if (!(s.W > 0.f)) s.id[k] = -1;
-    }
-}
-
-// The cache: uniform keys and ages, per-lane row values (and, backward, gradient sums).
-template <int R, int CPL, bool ACC>
-struct RowCache {
-    int key[R];
-    int age[R];
-    float sc[R];           // FP8 row scale (1 otherwise)
-    float row[R][CPL];
-    float acc[ACC ? R : 1][CPL];
-};
-
-template <int CPL>
-__device__ __forceinline__ void flush_row(const float (&a)[CPL], int g, int D, int pass_c0, int lane,
-                                          float *__restrict__ dfeat, float *xbuf) {
-    // transpose through wave-private LDS so each atomic instruction covers 64
-    // consecutive channels
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) xbuf[lane * CPL + j] = a[j];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    float *dst = dfeat + (long)g * D + pass_c0;
-    const int span = min(64 * CPL, D - pass_c0);
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        int c = j * 64 + lane;
-        float v = xbuf[c];
-        if (c < span && v != 0.f) unsafeAtomicAdd(&dst[c], v);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Slot of `u` in the cache (uniform), filling the least recently used slot on a miss.
-// On a miss in the backward the evicted row's gradient sum is flushed first.
-template <int FT, int R, int CPL, bool ACC>
-__device__ __forceinline__ int cache_slot(RowCache<R, CPL, ACC> &c, int u, int now, int D, int c0,
-                                          bool lane_on, const void *__restrict__ feat,
-                                          const float *__restrict__ scale, float *__restrict__ dfeat,
-                                          float *xbuf) {
-    // (keys, ages and scales are updated with selects, never with a variable index,
-    // so they stay in registers)
-    int hit = -1;
-#pragma unroll
-    for (int r = 0; r < R; ++r) hit = (c.key[r] == u) ? r : hit;
-    if (hit < 0) {
-        int victim = 0, oldest = c.age[0];
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-            const bool older = c.age[r] < oldest;
-            oldest = older ? c.age[r] : oldest;
-            victim = older ? r : victim;
-        }
-        hit = victim;
-        const int lane = threadIdx.x & 63;
-        const float su = (FT == FT_FP8) ? scale[u] : 1.0f;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (r == victim) {
-                if constexpr (ACC) {
-                    if (c.key[r] >= 0) flush_row<CPL>(c.acc[r], c.key[r], D, c0 - lane * CPL, lane, dfeat, xbuf);
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) c.acc[r][j] = 0.f;
-                }
-                if (lane_on) loadc<FT, CPL>(feat, (long)u * D + c0, c.row[r]);
-                else {
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) c.row[r][j] = 0.f;
-                }
-            }
-            c.sc[r] = (r == victim) ? su : c.sc[r];
-            c.key[r] = (r == victim) ? u : c.key[r];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) c.age[r] = (r == hit) ? now : c.age[r];
-    return hit;
-}
-
 struct TileGeom {
     int view, tx0, ty0;
 };
@@ -295,34 +195,183 @@ __device__ __forceinline__ TileGeom tile_geom(int tile, int W, int H) {
     return g;
 }
 
+// Per-lane state after the prologue: the lane's pixel slots and, for each slot, the
+// wave-local index of its Gaussian.
+template <int K>
+struct Slots {
+    int id[K];
+    int wl[K];     // wave-local index of the slot's Gaussian (-1: empty)
+    int u[K];      // tile union index (-1: empty)
+    float wp[K];   // renormalised weight w'_k
+    float wf[K];   // weight applied to the stored row: w'_k, times the row scale for FP8
+    float W;
+};
+
+// LDS shared by both kernels (static part; staged rows are dynamic LDS).
+template <int K>
+struct UnionLds {
+    int hkey[TileCfg<K>::HS];
+    int hval[TileCfg<K>::HS];
+    int wlist[4][kPixPerWave * K];   // wave-local distinct ids
+    int wmap[4][kPixPerWave * K];    // wave-local index -> tile union index
+    int uid[4 * kPixPerWave * K];    // tile union index -> Gaussian id
+    float uscale[4 * kPixPerWave * K];  // tile union index -> FP8 row scale
+    int nw[4];
+    int nU;
+};
+
+// Builds the tile union and stages its first min(U, ucap) rows into `rows`.
+// Returns the wave's number of distinct ids.
+template <int K, int FT>
+__device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H, int D, int ucap,
+                                          const int *__restrict__ ids, const float *__restrict__ tw,
+                                          const void *__restrict__ feat,
+                                          const float *__restrict__ scale, UnionLds<K> &L,
+                                          unsigned char *rows, Slots<K> &s, int &U) {
+    constexpr int HS = TileCfg<K>::HS;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int x = tg.tx0 + (lane & 15), y = tg.ty0 + wave * 4 + (lane >> 4);
+    const bool valid = x < W && y < H;
+    const long p = (long)tg.view * W * H + (long)y * W + x;
+    float wv[K];
+    s.W = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s.id[k] = valid ? ids[p * K + k] : -1;
+        wv[k] = valid ? tw[p * K + k] : 0.f;
+        s.W += wv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s.wp[k] = (s.W > 0.f && s.id[k] >= 0) ? wv[k] / s.W : 0.f;
+        if (!(s.W > 0.f)) s.id[k] = -1;
+        s.wl[k] = -1;
+    }
+    for (int h = t; h < HS; h += kFB) L.hkey[h] = -1;
+    if (t == 0) L.nU = 0;
+    // distinct ids of the wave: each iteration takes the first pending slot's id and
+    // resolves every slot of every lane that holds it
+    int nw = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        while (true) {
+            const uint64_t m = __ballot(s.wl[k] < 0 && s.id[k] >= 0);
+            if (m == 0ull) break;
+            const int lid = rdlane(s.id[k], (int)__builtin_ctzll(m));
+#pragma unroll
+            for (int k2 = k; k2 < K; ++k2) s.wl[k2] = (s.id[k2] == lid) ? nw : s.wl[k2];
+            if (lane == 0) L.wlist[wave][nw] = lid;
+            ++nw;
+        }
+    }
+    if (lane == 0) L.nw[wave] = nw;
+    __syncthreads();
+    const int ntot = L.nw[0] + L.nw[1] + L.nw[2] + L.nw[3];
+    if (ntot <= HS / 2) {
+        // merge the four lists through the hash table (at most half full, so every
+        // probe sequence ends): one dense index per distinct id
+        for (int j = lane; j < nw; j += 64) {
+            const int g = L.wlist[wave][j];
+            uint32_t h = ((uint32_t)g * 2654435761u) & (HS - 1);
+            for (int probe = 0; probe < HS; ++probe) {
+                const int prev = atomicCAS(&L.hkey[h], -1, g);
+                if (prev == -1) {
+                    const int u = atomicAdd(&L.nU, 1);
+                    L.uid[u] = g;
+                    if constexpr (FT == FT_FP8) L.uscale[u] = scale[g];
+                    L.hval[h] = u;
+                    break;
+                }
+                if (prev == g) break;
+                h = (h + 1) & (HS - 1);
+            }
+        }
+        __syncthreads();
+        for (int j = lane; j < nw; j += 64) {
+            const int g = L.wlist[wave][j];
+            uint32_t h = ((uint32_t)g * 2654435761u) & (HS - 1);
+            for (int probe = 0; probe < HS && L.hkey[h] != g; ++probe) h = (h + 1) & (HS - 1);
+            L.wmap[wave][j] = L.hval[h];
+        }
+    } else {
+        // very large unions: concatenate the wave lists (a Gaussian seen by several
+        // waves gets several rows; only the staging budget notices)
+        int off = 0;
+        for (int w2 = 0; w2 < wave; ++w2) off += L.nw[w2];
+        for (int j = lane; j < nw; j += 64) {
+            const int g = L.wlist[wave][j];
+            L.uid[off + j] = g;
+            if constexpr (FT == FT_FP8) L.uscale[off + j] = scale[g];
+            L.wmap[wave][j] = off + j;
+        }
+        if (t == 0) L.nU = ntot;
+        __syncthreads();
+    }
+    U = L.nU;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s.u[k] = s.wl[k] >= 0 ? L.wmap[wave][s.wl[k]] : -1;
+        s.wf[k] = s.wp[k];
+        if constexpr (FT == FT_FP8) s.wf[k] = s.u[k] >= 0 ? s.wp[k] * L.uscale[s.u[k]] : 0.f;
+    }
+    // stage the first min(U, ucap) rows: 16-byte pieces (8-byte for FP8 rows)
+    typedef typename std::conditional<FT == FT_FP8, u32x2, u32x4>::type piece;
+    const int nr = min(U, ucap);
+    const int rb = D * Bytes<FT>::v;
+    const int chunks = rb / (int)sizeof(piece);
+    for (int q = t; q < nr * chunks; q += kFB) {
+        const int r = q / chunks, c = q - r * chunks;
+        const piece *src = (const piece *)((const unsigned char *)feat + (long)L.uid[r] * rb) + c;
+        ((piece *)(rows + (long)r * rb))[c] = *src;
+    }
+    __syncthreads();
+    return nw;
+}
+
+// CPL values of union row u from LDS (staged) or global memory.
+template <int FT, int CPL>
+__device__ __forceinline__ void urow(const unsigned char *rows, int ucap, const int *uid, int u,
+                                     const void *__restrict__ feat, int D, int c0, float (&v)[CPL]) {
+    if (u < ucap) loadc<FT, CPL>(rows, (long)u * D + c0, v);
+    else loadc<FT, CPL>(feat, (long)uid[u] * D + c0, v);
+}
+
+template <int CPL>
+__device__ __forceinline__ void flush_row(const float (&a)[CPL], int g, int D, int pass_c0, int lane,
+                                          float *__restrict__ dfeat, float *xbuf) {
+    // transpose through wave-private LDS so each atomic instruction covers 64
+    // consecutive channels
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) xbuf[lane * CPL + j] = a[j];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    float *dst = dfeat + (long)g * D + pass_c0;
+    const int span = min(64 * CPL, D - pass_c0);
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int c = j * 64 + lane;
+        const float v = xbuf[c];
+        if (c < span && v != 0.f) unsafeAtomicAdd(&dst[c], v);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ---------------------------------------------------------------- forward
 
-template <int K, int FT, int MT>
-__global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int views, int D,
-                                                          const void *__restrict__ feat,
-                                                          const float *__restrict__ scale,
-                                                          const int *__restrict__ ids,
-                                                          const float *__restrict__ tw,
-                                                          void *__restrict__ F) {
-    constexpr int CPL = CacheCfg<K>::CPL, R = CacheCfg<K>::R;
-    const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const TileGeom tg = tile_geom(tile, W, H);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // lane i holds the slots of the wave's pixel i
-    const int my_x = tg.tx0 + (lane & 15), my_y = tg.ty0 + wave * 4 + (lane >> 4);
-    const bool my_valid = my_x < W && my_y < H;
-    const long my_p = (long)tg.view * W * H + (long)my_y * W + my_x;
-    WaveSlots<K> sl;
-    load_wave_slots<K>(my_valid, my_p, ids, tw, sl);
+// The wave's pixels.  STAGED: every union row of the tile is in LDS, so the loop
+// issues no global loads at all and its stores never have to be waited for.
+template <int K, int FT, int MT, bool STAGED>
+__device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
+                                           const void *__restrict__ feat, void *__restrict__ F,
+                                           const Slots<K> &sl, const UnionLds<K> &L,
+                                           const unsigned char *rows, int wave, int lane) {
+    constexpr int CPL = TileCfg<K>::CPL;
     const int passes = (D + 64 * CPL - 1) / (64 * CPL);
     for (int pass = 0; pass < passes; ++pass) {
         const int c0 = pass * 64 * CPL + lane * CPL;
         const bool lane_on = c0 < D;
-        RowCache<R, CPL, false> cache;
-#pragma unroll
-        for (int r = 0; r < R; ++r) { cache.key[r] = -1; cache.age[r] = -1 - r; }
         for (int i = 0; i < kPixPerWave; ++i) {
             const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
             if (x >= W || y >= H) continue;
@@ -330,18 +379,32 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
             float out[CPL];
 #pragma unroll
             for (int j = 0; j < CPL; ++j) out[j] = 0.f;
+            if constexpr (STAGED) {
+                // branch-free: an empty slot reads row 0 with weight 0, a lane past D
+                // reads channel 0 and stores nothing; all K reads issue together
+                const int cc = lane_on ? c0 : 0;
+                float v[K][CPL];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int u = rdlane(sl.id[k], i);
-                if (u < 0) continue;
-                const float wp = rdlane(sl.wp[k], i);
-                const int s = cache_slot<FT, R, CPL, false>(cache, u, i, D, c0, lane_on, feat, scale, nullptr, nullptr);
+                for (int k = 0; k < K; ++k) {
+                    const int u = rdlane(sl.u[k], i);
+                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * D + cc, v[k]);
+                }
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (r != s) continue;
-                    const float wf = wp * cache.sc[r];
+                for (int k = 0; k < K; ++k) {
+                    const float wf = rdlane(sl.wf[k], i);
 #pragma unroll
-                    for (int j = 0; j < CPL; ++j) out[j] = fmaf(wf, cache.row[r][j], out[j]);
+                    for (int j = 0; j < CPL; ++j) out[j] = fmaf(wf, v[k][j], out[j]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int u = rdlane(sl.u[k], i);
+                    if (u < 0 || !lane_on) continue;
+                    const float wf = rdlane(sl.wf[k], i);
+                    float v[CPL];
+                    urow<FT, CPL>(rows, ucap, L.uid, u, feat, D, c0, v);
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) out[j] = fmaf(wf, v[j], out[j]);
                 }
             }
             if (lane_on) storec<MT, CPL>(F, p * D + c0, out);
@@ -349,13 +412,153 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
     }
 }
 
+template <int K, int FT, int MT>
+__global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int views, int D, int ucap,
+                                                          const void *__restrict__ feat,
+                                                          const float *__restrict__ scale,
+                                                          const int *__restrict__ ids,
+                                                          const float *__restrict__ tw,
+                                                          void *__restrict__ F) {
+    constexpr int CPL = TileCfg<K>::CPL;
+    extern __shared__ __align__(16) unsigned char rows[];
+    __shared__ UnionLds<K> L;
+    const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const TileGeom tg = tile_geom(tile, W, H);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Slots<K> sl;
+    int U;
+    tile_union<K, FT>(tg, W, H, D, ucap, ids, tw, feat, scale, L, rows, sl, U);
+    if (U >= 1 && U <= ucap) fwd_pixels<K, FT, MT, true>(tg, W, H, D, ucap, feat, F, sl, L, rows, wave, lane);
+    else fwd_pixels<K, FT, MT, false>(tg, W, H, D, ucap, feat, F, sl, L, rows, wave, lane);
+}
+
 // ---------------------------------------------------------------- backward
+
+// The wave's pixels for one channel pass after another.  STAGED: every union row of
+// the tile is in LDS, so the only global traffic in the loop is dL/dF (or the target).
+template <int K, int FT, int MT, bool L1, bool STAGED>
+__device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
+                                           const void *__restrict__ feat, const void *__restrict__ dF,
+                                           float l1_scale, float *__restrict__ dfeat,
+                                           const Slots<K> &sl, const UnionLds<K> &L,
+                                           const unsigned char *rows, int nw,
+                                           float (*sdot)[K], float *xbuf, int wave, int lane) {
+    constexpr int CPL = TileCfg<K>::CPL, RA = TileCfg<K>::RA;
+    const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
+    constexpr int MS = MT == MT_F32 ? FT_F32 : FT_BF16;
+    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
+    for (int pass = 0; pass < passes; ++pass) {
+        const int c0 = pass * 64 * CPL + lane * CPL;
+        const bool lane_on = c0 < D;
+        float acc[RA][CPL];
+#pragma unroll
+        for (int r = 0; r < RA; ++r)
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) acc[r][j] = 0.f;
+        // dL/dF (or the target) one pixel ahead of its use
+        auto want = [&](int i) {
+            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
+            return x < W && y < H && rdlane(sl.W, i) > 0.f;
+        };
+        auto fetch = [&](int i, float (&dst)[CPL]) {
+            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) dst[j] = 0.f;
+            if (want(i) && lane_on)
+                loadc<MS, CPL>(dF, ((long)tg.view * W * H + (long)y * W + x) * D + c0, dst);
+        };
+        float nxt[CPL];
+        fetch(0, nxt);
+        for (int i = 0; i < kPixPerWave; ++i) {
+            float cur[CPL];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) cur[j] = nxt[j];
+            if (i + 1 < kPixPerWave) fetch(i + 1, nxt);
+            if (!want(i)) continue;
+            int wl[K];
+            float wp[K], v[K][CPL];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                wl[k] = rdlane(sl.wl[k], i);
+                wp[k] = rdlane(sl.wp[k], i);
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) v[k][j] = 0.f;
+                const int u = rdlane(sl.u[k], i);
+                if constexpr (STAGED) {
+                    // branch-free (see the forward); empty slots carry weight 0 and
+                    // their dot product is never used
+                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * D + (lane_on ? c0 : 0), v[k]);
+                    if (!lane_on) {
+#pragma unroll
+                        for (int j = 0; j < CPL; ++j) v[k][j] = 0.f;
+                    }
+                } else if (u >= 0 && lane_on) {
+                    urow<FT, CPL>(rows, ucap, L.uid, u, feat, D, c0, v[k]);
+                }
+            }
+            float G[CPL];
+            if constexpr (L1) {
+                float Fv[CPL];
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) Fv[j] = 0.f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (wl[k] < 0) continue;
+                    const float wf = rdlane(sl.wf[k], i);
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) Fv[j] = fmaf(wf, v[k][j], Fv[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) {
+                    const float fm = MT == MT_F32 ? Fv[j] : bf16_to_f32(f32_to_bf16(Fv[j]));
+                    const float d = lane_on ? fm - cur[j] : 0.f;
+                    G[j] = d > 0.f ? gs : (d < 0.f ? -gs : 0.f);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) G[j] = cur[j];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                float part = 0.f;
+#pragma unroll
+                for (int j = 0; j < CPL; ++j) part = fmaf(G[j], v[k][j], part);
+                if constexpr (FT == FT_FP8) {
+                    const int u = rdlane(sl.u[k], i);
+                    part *= (u >= 0 ? L.uscale[u] : 0.f);
+                }
+                const float g = wave_sum(part);
+                if (lane == 0) sdot[i][k] += g;
+                if (wl[k] < 0) continue;
+                if (wl[k] < RA) {
+#pragma unroll
+                    for (int r = 0; r < RA; ++r) {
+                        if (r != wl[k]) continue;
+#pragma unroll
+                        for (int j = 0; j < CPL; ++j) acc[r][j] = fmaf(wp[k], G[j], acc[r][j]);
+                    }
+                } else {
+                    // beyond the register accumulators: straight to global memory
+                    float a[CPL];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) a[j] = wp[k] * G[j];
+                    flush_row<CPL>(a, L.wlist[wave][wl[k]], D, pass * 64 * CPL, lane, dfeat, xbuf);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RA; ++r)
+            if (r < nw) flush_row<CPL>(acc[r], L.wlist[wave][r], D, pass * 64 * CPL, lane, dfeat, xbuf);
+    }
+}
 
 // L1 = false: dF holds dL/dF (map dtype).  L1 = true: dF holds the target map F^ and
 // dL/dF = l1_scale * sign(F - F^) is formed on the fly from F recomputed exactly as
 // the forward kernel computes and rounds it.
 template <int K, int FT, int MT, bool L1>
-__global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int views, int D,
+__global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int views, int D, int ucap,
                                                           const void *__restrict__ feat,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ ids,
@@ -363,7 +566,9 @@ __global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int view
                                                           const void *__restrict__ dF, float l1_scale,
                                                           float *__restrict__ dfeat,
                                                           float *__restrict__ dtw) {
-    constexpr int CPL = CacheCfg<K>::CPL, R = CacheCfg<K>::R;
+    constexpr int CPL = TileCfg<K>::CPL, RA = TileCfg<K>::RA;
+    extern __shared__ __align__(16) unsigned char rows[];
+    __shared__ UnionLds<K> L;
     __shared__ float s_dot[4][kPixPerWave][K];
     __shared__ float s_x[4][64 * CPL];
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
@@ -372,149 +577,23 @@ __global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int view
     const TileGeom tg = tile_geom(tile, W, H);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *xbuf = s_x[wave];
-    const int my_x = tg.tx0 + (lane & 15), my_y = tg.ty0 + wave * 4 + (lane >> 4);
-    const bool my_valid = my_x < W && my_y < H;
-    const long my_p = (long)tg.view * W * H + (long)my_y * W + my_x;
-    WaveSlots<K> sl;
-    load_wave_slots<K>(my_valid, my_p, ids, tw, sl);
+    Slots<K> sl;
+    int U;
+    const int nw = tile_union<K, FT>(tg, W, H, D, ucap, ids, tw, feat, scale, L, rows, sl, U);
 #pragma unroll
     for (int k = 0; k < K; ++k) s_dot[wave][lane][k] = 0.f;
-    const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
-    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
-    for (int pass = 0; pass < passes; ++pass) {
-        const int c0 = pass * 64 * CPL + lane * CPL;
-        const bool lane_on = c0 < D;
-        RowCache<R, CPL, true> cache;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cache.key[r] = -1;
-            cache.age[r] = -1 - r;
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) cache.acc[r][j] = 0.f;
-        }
-        // dL/dF (or the target map) is streamed in batches of PB pixels, raw and
-        // double-buffered: batch b + 1 loads while batch b computes.
-        constexpr int PB = MT == MT_F32 ? 2 : 4;
-        constexpr int NW = MT == MT_F32 ? CPL : CPL / 2;    // 32-bit words per pixel per lane
-        auto want = [&](int i) {
-            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
-            return x < W && y < H && rdlane(sl.W, i) > 0.f;
-        };
-        auto fetch = [&](int i, uint32_t (&dst)[NW]) {
-            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
-            if (!(want(i) && lane_on)) return;
-            const long at = ((long)tg.view * W * H + (long)y * W + x) * D + c0;
-            const uint32_t *src = MT == MT_F32 ? (const uint32_t *)((const float *)dF + at)
-                                               : (const uint32_t *)((const uint16_t *)dF + at);
-            if constexpr (NW == 8) {
-                u32x4 q0 = ((const u32x4 *)src)[0], q1 = ((const u32x4 *)src)[1];
-                dst[0] = q0.x; dst[1] = q0.y; dst[2] = q0.z; dst[3] = q0.w;
-                dst[4] = q1.x; dst[5] = q1.y; dst[6] = q1.z; dst[7] = q1.w;
-            } else if constexpr (NW == 4) {
-                u32x4 q = *(const u32x4 *)src;
-                dst[0] = q.x; dst[1] = q.y; dst[2] = q.z; dst[3] = q.w;
-            } else if constexpr (NW == 2) {
-                u32x2 q = *(const u32x2 *)src;
-                dst[0] = q.x; dst[1] = q.y;
-            } else {
-                dst[0] = *src;
-            }
-        };
-        uint32_t cur_b[PB][NW], nxt_b[PB][NW];
-#pragma unroll
-        for (int j = 0; j < PB; ++j) {
-#pragma unroll
-            for (int w = 0; w < NW; ++w) { cur_b[j][w] = 0u; nxt_b[j][w] = 0u; }
-            fetch(j, cur_b[j]);
-        }
-        for (int i0 = 0; i0 < kPixPerWave; i0 += PB) {
-#pragma unroll
-            for (int j = 0; j < PB; ++j)
-                if (i0 + PB + j < kPixPerWave) fetch(i0 + PB + j, nxt_b[j]);
-#pragma unroll 1
-            for (int jj = 0; jj < PB; ++jj) {
-                const int i = i0 + jj;
-                if (!want(i)) continue;
-                // this pixel's raw words, picked with uniform selects
-                uint32_t rw[NW];
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    uint32_t v = cur_b[0][w];
-#pragma unroll
-                    for (int j = 1; j < PB; ++j) v = (jj == j) ? cur_b[j][w] : v;
-                    rw[w] = v;
-                }
-                float cur[CPL];
-#pragma unroll
-                for (int c = 0; c < CPL; ++c)
-                    cur[c] = MT == MT_F32 ? __uint_as_float(rw[c < NW ? c : 0])
-                                          : bf16_to_f32((rw[c >> 1] >> (16 * (c & 1))) & 0xFFFFu);
-                int slot[K];
-                float wp[K];
-                // the pixel's rows into the cache (all K fit: R >= K and they are the newest)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int u = rdlane(sl.id[k], i);
-                    wp[k] = rdlane(sl.wp[k], i);
-                    slot[k] = u < 0 ? -1 : cache_slot<FT, R, CPL, true>(cache, u, i, D, c0, lane_on, feat, scale, dfeat, xbuf);
-                }
-                float G[CPL];
-                if constexpr (L1) {
-                    float Fv[CPL];
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) Fv[j] = 0.f;
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            if (r != slot[k]) continue;
-                            const float wf = wp[k] * cache.sc[r];
-#pragma unroll
-                            for (int j = 0; j < CPL; ++j) Fv[j] = fmaf(wf, cache.row[r][j], Fv[j]);
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) {
-                        const float fm = MT == MT_F32 ? Fv[j] : bf16_to_f32(f32_to_bf16(Fv[j]));
-                        const float d = lane_on ? fm - cur[j] : 0.f;
-                        G[j] = d > 0.f ? gs : (d < 0.f ? -gs : 0.f);
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) G[j] = lane_on ? cur[j] : 0.f;
-                }
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    float part = 0.f;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        if (r != slot[k]) continue;
-#pragma unroll
-                        for (int j = 0; j < CPL; ++j) {
-                            part = fmaf(G[j], cache.row[r][j], part);
-                            cache.acc[r][j] = fmaf(wp[k], G[j], cache.acc[r][j]);
-                        }
-                        part *= cache.sc[r];
-                    }
-                    const float g = wave_sum(part);
-                    if (lane == 0) s_dot[wave][i][k] += g;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < PB; ++j) {
-#pragma unroll
-                for (int w = 0; w < NW; ++w) { cur_b[j][w] = nxt_b[j][w]; nxt_b[j][w] = 0u; }
-            }
-        }
-        // rows still cached
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (cache.key[r] >= 0) flush_row<CPL>(cache.acc[r], cache.key[r], D, pass * 64 * CPL, lane, dfeat, xbuf);
-    }
+    if (U >= 1 && U <= ucap)
+        bwd_pixels<K, FT, MT, L1, true>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, rows, nw,
+                                       s_dot[wave], xbuf, wave, lane);
+    else
+        bwd_pixels<K, FT, MT, L1, false>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, rows, nw,
+                                        s_dot[wave], xbuf, wave, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     // gamma_k = (g_k - sum_j w'_j g_j) / W for the lane's own pixel
-    if (!my_valid) return;
+    const int x = tg.tx0 + (lane & 15), y = tg.ty0 + wave * 4 + (lane >> 4);
+    if (x >= W || y >= H) return;
+    const long p = (long)tg.view * W * H + (long)y * W + x;
     float g[K], mean = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -523,7 +602,7 @@ __global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int view
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
-        dtw[my_p * K + k] = (sl.W > 0.f && sl.id[k] >= 0) ? (g[k] - mean) / sl.W : 0.f;
+        dtw[p * K + k] = (sl.W > 0.f && sl.id[k] >= 0) ? (g[k] - mean) / sl.W : 0.f;
 }
 
 // ---------------------------------------------------------------- quantize, L1, union
@@ -656,14 +735,21 @@ __global__ __launch_bounds__(256) void union_sum_kernel(int n, int *__restrict__
 
 // ---------------------------------------------------------------- dispatch
 
+// Staged union rows per block: as many as fit in `budget` bytes (at least 0).
+inline int pick_ucap(int D, int sf, int budget) { return budget / (D * sf); }
+
+constexpr int kRowBudget = 32 * 1024;
+
 template <int FT, int MT>
 lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
                         const int *ids, const float *tw, void *F, hipStream_t st) {
     unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
+    const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
+    const size_t lds = (size_t)ucap * D * Bytes<FT>::v;
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
-        hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(kFB), 0, st, W, H,    \
-                           views, D, feat, scale, ids, tw, F);                                       \
+        hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(kFB), lds, st, W, H,  \
+                           views, D, ucap, feat, scale, ids, tw, F);                                 \
         break;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
@@ -675,10 +761,12 @@ lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
                         const int *ids, const float *tw, const void *dF, float l1_scale, float *dfeat,
                         float *dtw, hipStream_t st) {
     unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
+    const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
+    const size_t lds = (size_t)ucap * D * Bytes<FT>::v;
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
-        hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, L1>), dim3(grid), dim3(kFB), 0, st, W, H, \
-                           views, D, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw);                 \
+        hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, L1>), dim3(grid), dim3(kFB), lds, st, W, \
+                           H, views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw);        \
         break;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL

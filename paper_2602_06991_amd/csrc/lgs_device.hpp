@@ -98,6 +98,29 @@ __device__ __forceinline__ float wave_sum(float v) {
     return (r0 + r1) + (r2 + r3);
 }
 
+// Sums of N values over all 64 lanes at once (independent DPP chains interleave).
+// Rows of 16 are reduced with DPP moves, then row_bcast:15 / row_bcast:31 fold the
+// four row sums into lane 63, which is read back.  Every lane must be active.
+template <int N>
+__device__ __forceinline__ void wave_sum_many(float (&v)[N], float (&out)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0xB1>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x4E>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x141>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x140>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x142, 0xA, 0xF, false));
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x143, 0xC, 0xF, false));
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[q]), 63));
+}
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 // ------------------------------------------------------------------ mapping

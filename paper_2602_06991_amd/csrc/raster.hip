@@ -2,7 +2,8 @@
 // pixel's K largest blending weights in registers (Eq. 2; recorded during the same
 // pass, Sec. 3.2), and its adjoint replayed back to front from the saved final
 // transmittance.  One 256-thread block per 16x16 tile, one thread per pixel; the
-// tile's depth-sorted Gaussians are staged through LDS in batches of 256.
+// tile's depth-sorted Gaussians are staged through LDS in batches (256 forward,
+// 128 backward).
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(256) void raster_fwd_kernel(RasterArgs a, float *__
 }
 
 constexpr int kNG = 10;   // per-Gaussian gradient slots: mean2d 2, conic 3, opacity, rgb 3, depth
+constexpr int kRB = 128;  // Gaussians per LDS batch in the backward
 
 template <int K>
 __global__ __launch_bounds__(256) void raster_bwd_kernel(
@@ -120,11 +122,11 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
     const float *__restrict__ dL_dcolor, const float *__restrict__ dL_ddepth,
     const float *__restrict__ dL_dalpha, float *__restrict__ g_mean2d, float *__restrict__ g_conic,
     float *__restrict__ g_opac, float *__restrict__ g_rgb, float *__restrict__ g_depth) {
-    __shared__ int s_id[256];
-    __shared__ float2 s_xy[256];
-    __shared__ float4 s_co[256];
-    __shared__ float4 s_cz[256];
-    __shared__ float s_part[4][kNG][256];
+    __shared__ int s_id[kRB];
+    __shared__ float2 s_xy[kRB];
+    __shared__ float4 s_co[kRB];
+    __shared__ float4 s_cz[kRB];
+    __shared__ float s_part[4][kNG][kRB];
     __shared__ int s_max;
     const int ntiles = a.ntx * a.nty;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -164,8 +166,8 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
     __syncthreads();
     const int maxl = s_max;
     float A = 0.0f;   // sum over later blended Gaussians of e_j w_j
-    for (int hi = maxl; hi > 0; hi -= 256) {
-        const int lo = hi > 256 ? hi - 256 : 0;
+    for (int hi = maxl; hi > 0; hi -= kRB) {
+        const int lo = hi > kRB ? hi - kRB : 0;
         const int cnt = hi - lo;
         __syncthreads();
         if (t < cnt) {
@@ -188,22 +190,22 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
                 float alpha = blend_alpha(fx, fy, m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
                 if (alpha >= kAlphaMin) {
                     hit = true;
-                    float om = 1.0f - alpha;
-                    T = T / om;                   // transmittance in front of this Gaussian
-                    float w = alpha * T;
-                    float4 cz = s_cz[j];
-                    int g = s_id[j];
+                    const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    T *= r;                         // transmittance in front of this Gaussian
+                    const float w = alpha * T;
+                    const float4 cz = s_cz[j];
+                    const int g = s_id[j];
                     float e = gC0 * cz.x + gC1 * cz.y + gC2 * cz.z + gD * cz.w + gO;
 #pragma unroll
                     for (int k = 0; k < K; ++k) e += (ti[k] == g) ? gam[k] : 0.f;
-                    float dal = T * e - A / om;
+                    const float dal = T * e - A * r;
                     A = fmaf(e, w, A);
                     v[5] = w * gC0;
                     v[6] = w * gC1;
                     v[7] = w * gC2;
                     v[8] = w * gD;
                     if (raw <= kAlphaMax) {       // unclamped: alpha = o e^-sigma
-                        float ds = -alpha * dal;
+                        const float ds = -alpha * dal;
                         v[0] = -ds * (co.x * dx + co.y * dy);
                         v[1] = -ds * (co.y * dx + co.z * dy);
                         v[2] = ds * 0.5f * dx * dx;
@@ -213,12 +215,13 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
                     }
                 }
             }
-            // wave-level reduction (every lane takes part), one partial per wave
+            // wave-level reduction of all ten components (every lane takes part)
             if (__ballot(hit) != 0ull) {
+                float s[kNG];
+                wave_sum_many<kNG>(v, s);
+                if ((t & 63) == 0) {
 #pragma unroll
-                for (int q = 0; q < kNG; ++q) {
-                    float s = wave_sum(v[q]);
-                    if ((t & 63) == 0) s_part[wave][q][j] = s;
+                    for (int q = 0; q < kNG; ++q) s_part[wave][q][j] = s[q];
                 }
             } else if ((t & 63) == 0) {
 #pragma unroll
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
         }
         __syncthreads();
         if (t < cnt) {
-            int g = s_id[t];
+            const int g = s_id[t];
             float s[kNG];
 #pragma unroll
             for (int q = 0; q < kNG; ++q)
