@@ -111,29 +111,45 @@ class Step:
 
 
 def time_steps(torch, step, steps, warmup):
+    """Times `steps` steps after `warmup` untimed ones.  Every phase boundary inside
+    the timed steps carries a HIP event on the stream the kernels run on (torch's
+    current stream), so the per-phase durations come from the timed region itself."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    # whole-step timing
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    # per-phase timing: the same steps with an event after every phase
-    phases = {}
+    marks = []
     for _ in range(steps):
         step.events = []
         step()
-        torch.cuda.synchronize()
-        ev = step.events
+        marks.append(step.events)
+    step.events = None
+    torch.cuda.synchronize()
+    total_ms = marks[0][0][1].elapsed_time(marks[-1][-1][1])
+    phases = {}
+    for ev in marks:
         for (_, a), (name, b) in zip(ev[:-1], ev[1:]):
             phases.setdefault(name, []).append(a.elapsed_time(b))
-    step.events = None
     return total_ms / steps, {k: float(np.median(v)) for k, v in phases.items()}
+
+
+def counter_traffic(kernel, workload_ok):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    summary (already scaled by the copy calibration), or None when the workload
+    differs or the kernel source changed since the counters were taken."""
+    import hashlib
+    if not workload_ok:
+        return None
+    src = os.path.join(ROOT, "paper_2602_06991_amd", "csrc", "feature.hip")
+    prof = os.path.join(ROOT, "profiles", "hbm_counters_c2_1200x680_K4_bf16.md")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(prof):
+        if line.startswith("traffic:"):
+            f = [x.strip() for x in line[len("traffic:"):].split("|")]
+            if f[0] == sha and f[1] == kernel:
+                return dict(read=int(f[2]), write=int(f[3]), total=int(f[2]) + int(f[3]))
+    return None
 
 
 def tile_union_stats(ids, W, H):
@@ -266,6 +282,10 @@ def main():
     kern = max(("feature_render_fwd", "feature_render_bwd"), key=lambda k: ph[k])
     kbytes = R["bytes_fwd"] if kern == "feature_render_fwd" else R["bytes_bwd"]
     achieved = kbytes / (ph[kern] * 1e-3) / 1e9
+    kname = (f"feature_fwd_kernel<{K}, 1, 1>" if kern == "feature_render_fwd"
+             else f"feature_bwd_kernel<{K}, 1, 1, true>")
+    t = counter_traffic(kname, args.config == 2 and K == 4 and main_form == "bf16")
+    traffic = None if t is None else t["total"]
     feat_ms = ph["feature_render_fwd"] + ph["feature_render_bwd"]
     feat_gbs = (R["bytes_fwd"] + R["bytes_bwd"]) / (feat_ms * 1e-3) / 1e9
     line = {
@@ -296,7 +316,9 @@ def main():
                   for k, v in results.items()},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "algorithmic_bytes": int(kbytes),
+                     "traffic": traffic,
+                     "traffic_read_write": None if t is None else [t["read"], t["write"]],
+                     "algorithmic_bytes": int(kbytes),
                      "avg_ms": round(ph[kern], 4)},
     }
     if sweep:
