@@ -13,6 +13,7 @@
 // dot products from it, and each distinct Gaussian's gradient row chunk is summed
 // in registers over its list and added to global memory with one coalesced atomic
 // per channel - U_t atomics per channel per tile instead of 256 K.
+#include <algorithm>
 #include <type_traits>
 
 #include "lgs_device.hpp"
@@ -85,6 +86,9 @@ __device__ __forceinline__ void store8(void *F, long row, int D, int c, const fl
 // each accumulator to dL/df once, with coalesced atomics.
 constexpr int kFB = 256;          // threads per feature block
 constexpr int kPixPerWave = 64;
+constexpr int kUP = 32;           // union rows the MFMA path holds (two 16-row blocks)
+constexpr int kCPW = 4;           // 32-channel chunks per wave on the MFMA path (D <= 512)
+constexpr int kRowBudget = 32 * 1024;   // LDS bytes for staged rows on the per-pixel path
 
 template <int K> struct TileCfg {
     static constexpr int CPL = K <= 4 ? 8 : (K <= 8 ? 4 : 2);   // channels per lane per pass
@@ -218,16 +222,20 @@ struct UnionLds {
     float uscale[4 * kPixPerWave * K];  // tile union index -> FP8 row scale
     int nw[4];
     int nU;
+    // MFMA path (U <= kUP): the union in ascending id order, so both feature
+    // kernels order the K dimension of their products identically
+    int rank[kUP];       // hash-order union index -> ascending-id index
+    int uid2[kUP];       // ascending-id index -> Gaussian id
+    float uscale2[kUP];  // ascending-id index -> FP8 row scale
 };
 
-// Builds the tile union and stages its first min(U, ucap) rows into `rows`.
+// Builds the tile union: L.uid[0, U) and, per lane, the slots' union indices.
 // Returns the wave's number of distinct ids.
 template <int K, int FT>
-__device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H, int D, int ucap,
+__device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H,
                                           const int *__restrict__ ids, const float *__restrict__ tw,
-                                          const void *__restrict__ feat,
                                           const float *__restrict__ scale, UnionLds<K> &L,
-                                          unsigned char *rows, Slots<K> &s, int &U) {
+                                          Slots<K> &s, int &U) {
     constexpr int HS = TileCfg<K>::HS;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int x = tg.tx0 + (lane & 15), y = tg.ty0 + wave * 4 + (lane >> 4);
@@ -315,8 +323,17 @@ __device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H, int 
         s.wf[k] = s.wp[k];
         if constexpr (FT == FT_FP8) s.wf[k] = s.u[k] >= 0 ? s.wp[k] * L.uscale[s.u[k]] : 0.f;
     }
-    // stage the first min(U, ucap) rows: 16-byte pieces (8-byte for FP8 rows)
+    __syncthreads();   // wmap has been read: its space may be reused
+    return nw;
+}
+
+// Stages the first min(U, ucap) union rows in their storage format into `rows`:
+// 16-byte pieces (8-byte for FP8 rows).
+template <int K, int FT>
+__device__ __forceinline__ void stage_rows(const UnionLds<K> &L, int U, int D, int ucap,
+                                           const void *__restrict__ feat, unsigned char *rows) {
     typedef typename std::conditional<FT == FT_FP8, u32x2, u32x4>::type piece;
+    const int t = threadIdx.x;
     const int nr = min(U, ucap);
     const int rb = D * Bytes<FT>::v;
     const int chunks = rb / (int)sizeof(piece);
@@ -326,7 +343,6 @@ __device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H, int 
         ((piece *)(rows + (long)r * rb))[c] = *src;
     }
     __syncthreads();
-    return nw;
 }
 
 // CPL values of union row u from LDS (staged) or global memory.
@@ -356,6 +372,436 @@ __device__ __forceinline__ void flush_row(const float (&a)[CPL], int g, int D, i
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------- MFMA tile path
+//
+// Tiles whose Top-K union has at most kUP Gaussians (BF16 or FP8 storage, BF16 map)
+// run both feature kernels as dense per-tile products on the matrix cores:
+//   F^T[c][p]  = sum_u Ft[u][c] Wa[p][u]         the feature map (Eq. 4), and its L1 recompute
+//   S^T[u][p] += sum_c Ft[u][c] G[p][c]          the dot products g_k = <dL/dF, f_k>
+//   dFt[u][c] += sum_p Wd[p][u] G[p][c]          the feature gradient rows sum_p w'_k dL/dF
+// Ft holds the union's stored rows (FP8 codes widened to BF16, exactly), Wa the
+// renormalised weights w'_k (times the FP8 row scale), Wd the weights w'_k; each is
+// zero outside the pixel's K slots.  An FP32 weight w enters as two BF16 terms
+// hi = RNE(w), lo = RNE(w - hi), i.e. with 16 significant bits, and every product is
+// exact in the FP32 accumulator.
+//
+// Operand layouts (lane l = 16 g + i): v_mfma_f32_16x16x16_bf16 takes A[i][4g..4g+3]
+// and B[4g..4g+3][i]; v_mfma_f32_16x16x32_bf16 takes A[i][8g..8g+7] and
+// B[8g..8g+7][i]; both return D[4g..4g+3][i].
+//
+// Work split: wave w owns a contiguous range of 32-channel chunks for all 256
+// pixels of the tile, so its Ft operands stay in registers for the whole tile and
+// its gradient rows are complete when the tile ends (one atomic per element and
+// tile).  The tile's 16 pixel rows are the MFMA column blocks, processed in turn;
+// per row the weights are scattered into a per-wave LDS buffer and read back in
+// operand layout.  Within a chunk, channel block b (of two) row m stands for
+// channel 8 (m / 4) + 4 b + m % 4, so that after both blocks lane (i, g) holds the
+// eight consecutive channels 8g..8g+7 of pixel i: one 16-byte access per lane.
+// Partial dot products of the four waves meet in LDS and are summed in a fixed
+// order, so dL/dw is deterministic.
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats to packed BF16, round to nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    bf16x2_t r = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, r);
+}
+__device__ __forceinline__ uint16_t bits_bf16(float a) { return __builtin_bit_cast(uint16_t, (__bf16)a); }
+__device__ __forceinline__ i16x4 as_op4(u32x2 v) { return __builtin_bit_cast(i16x4, v); }
+__device__ __forceinline__ i16x8 as_op8(u32x4 v) { return __builtin_bit_cast(i16x8, v); }
+__device__ __forceinline__ f32x4 mfma16(i16x4 a, i16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma32(i16x8 a, i16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(__bf16 __attribute__((ext_vector_type(8))), a),
+                                                   __builtin_bit_cast(__bf16 __attribute__((ext_vector_type(8))), b),
+                                                   c, 0, 0, 0);
+}
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+// Channel of block b, row m within a 32-channel chunk.
+__device__ __forceinline__ int blk_ch(int b, int m) { return 8 * (m >> 2) + 4 * b + (m & 3); }
+
+// Per-wave LDS of the MFMA path.
+struct MfWave {
+    uint16_t wa[2][16][kUP];   // [hi, lo][pixel of the row][union index]
+    uint16_t wd[2][kUP][16];   // [hi, lo][union index][pixel of the row]
+    uint16_t gt[2][16][16];    // [channel block][block row][pixel]: G of one chunk, transposed
+};
+static_assert(sizeof(MfWave) == 5120, "MfWave layout");
+
+// Dynamic LDS of the MFMA path: the staged union rows (BF16, [kUP][D]), which the
+// per-wave partial dot products [4][256][K] later reuse, then four MfWave.
+__host__ __device__ inline size_t mf_region0(int D, int K) {
+    size_t a = (size_t)kUP * D * 2, b = (size_t)4 * kTilePix * K * 4;
+    return ((a > b ? a : b) + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t mf_lds_bytes(int D, int K) { return mf_region0(D, K) + 4 * sizeof(MfWave); }
+
+// The slot table (per pixel: union index, Wa weight, Wd weight) lives where the
+// union's hash table and wave lists were.
+template <int K>
+struct SlotTable {
+    int *u;
+    float *wa, *wd;
+};
+template <int K>
+__device__ __forceinline__ SlotTable<K> slot_table(UnionLds<K> &L) {
+    static_assert(sizeof(L.hkey) + sizeof(L.hval) + sizeof(L.wlist) + sizeof(L.wmap) >=
+                      3 * sizeof(int) * kTilePix * K, "slot table must fit the union scratch");
+    SlotTable<K> st;
+    st.u = &L.hkey[0];
+    st.wa = (float *)(&L.hkey[0] + kTilePix * K);
+    st.wd = st.wa + kTilePix * K;
+    return st;
+}
+
+// Prologue of the MFMA path (all 256 threads; U <= kUP): orders the union by id,
+// writes the slot table and stages the union rows as BF16.
+template <int K, int FT>
+__device__ __forceinline__ void mf_prologue(UnionLds<K> &L, Slots<K> &s, int U, int D,
+                                            const void *__restrict__ feat, uint16_t *ft) {
+    const int t = threadIdx.x;
+    if (t < U) {
+        const int g = L.uid[t];
+        int r = 0;
+        for (int v = 0; v < U; ++v) r += L.uid[v] < g ? 1 : 0;   // ids are distinct
+        L.rank[t] = r;
+        L.uid2[r] = g;
+        if constexpr (FT == FT_FP8) L.uscale2[r] = L.uscale[t];
+    }
+    __syncthreads();
+    SlotTable<K> st = slot_table(L);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s.u[k] = s.u[k] >= 0 ? L.rank[s.u[k]] : -1;
+        st.u[t * K + k] = s.u[k];
+        st.wa[t * K + k] = s.u[k] >= 0 ? s.wf[k] : 0.f;
+        st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
+    }
+    // rows as BF16, 8 channels per step
+    const int c8 = D >> 3;
+    for (int q = t; q < U * c8; q += kFB) {
+        const int r = q / c8, c = (q - r * c8) * 8;
+        const long src = (long)L.uid2[r] * D + c;
+        u32x4 o;
+        if constexpr (FT == FT_BF16) {
+            o = *(const u32x4 *)((const uint16_t *)feat + src);
+        } else {
+            const u32x2 a = *(const u32x2 *)((const uint8_t *)feat + src);
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = e4m3_to_f32((a.x >> (8 * i)) & 0xFFu);
+                v[4 + i] = e4m3_to_f32((a.y >> (8 * i)) & 0xFFu);
+            }
+            o.x = pk_bf16(v[0], v[1]); o.y = pk_bf16(v[2], v[3]);
+            o.z = pk_bf16(v[4], v[5]); o.w = pk_bf16(v[6], v[7]);
+        }
+        *(u32x4 *)(ft + (long)r * D + c) = o;
+    }
+    __syncthreads();
+}
+
+// The wave's chunks: [beg, beg + n) of the ceil(D / 32) chunks.
+struct MfChunks {
+    int beg, n;
+};
+__device__ __forceinline__ MfChunks mf_chunks(int D, int wave) {
+    const int nch = (D + 31) >> 5, cpw = (nch + 3) >> 2;
+    MfChunks m;
+    m.beg = wave * cpw;
+    m.n = max(0, min(cpw, nch - m.beg));
+    return m;
+}
+
+// Register operands from the staged rows (zero outside the union and past D):
+//   opA[i][b][s]: lane (i16, g) = Ft[16 s + 4 g + j][chunk + blk_ch(b, i16)], j < 4
+//   opC[i][s]:    lane (i16, g) = Ft[16 s + i16][chunk + 8 g + j], j < 8
+__device__ __forceinline__ void mf_load_ops(const uint16_t *ft, int U, int D, const MfChunks &mc, int lane,
+                                            i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
+    const int i16 = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < kCPW; ++i) {
+        const int c0 = (mc.beg + i) * 32;
+        const bool on = i < mc.n;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                i16x4 a;
+                const int ch = c0 + blk_ch(b, i16);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int u = 16 * s + 4 * g + j;
+                    a[j] = (on && u < U && ch < D) ? (short)ft[u * D + ch] : (short)0;
+                }
+                opA[i][b][s] = a;
+            }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int u = 16 * s + i16, ch = c0 + 8 * g;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (on && u < U && ch < D) v = *(const u32x4 *)(ft + u * D + ch);
+            opC[i][s] = as_op8(v);
+        }
+    }
+}
+
+// Weights of tile row `row` in operand layout:
+//   wa[s][h]: lane (i16, g) = Wa_h[pixel i16][16 s + 4 g + j], j < 4     (16x16x16 B)
+//   wd[s]:    lane (i16, g) = Wd_{g/2}[pixel 8 (g % 2) + j][16 s + i16]    (16x16x32 A)
+template <int K, bool WD>
+__device__ __forceinline__ void mf_weights(int row, const SlotTable<K> &st, MfWave &mw, int lane,
+                                           i16x4 (&wa)[2][2], i16x8 (&wd)[2]) {
+    u32x4 *z = (u32x4 *)&mw;
+    constexpr int nz = (WD ? sizeof(mw.wa) + sizeof(mw.wd) : sizeof(mw.wa)) / 16;
+    for (int j = lane; j < nz; j += 64) z[j] = (u32x4){0u, 0u, 0u, 0u};
+    wave_lds_sync();
+    const int x = lane & 15, kq = lane >> 4, p = row * 16 + x;
+    for (int k = kq; k < K; k += 4) {
+        const int u = st.u[p * K + k];
+        if (u >= 0) {
+            const float a = st.wa[p * K + k];
+            const float ah = bf16_to_f32(bits_bf16(a));
+            mw.wa[0][x][u] = bits_bf16(a);
+            mw.wa[1][x][u] = bits_bf16(a - ah);
+            if constexpr (WD) {
+                const float d = st.wd[p * K + k];
+                const float dh = bf16_to_f32(bits_bf16(d));
+                mw.wd[0][u][x] = bits_bf16(d);
+                mw.wd[1][u][x] = bits_bf16(d - dh);
+            }
+        }
+    }
+    wave_lds_sync();
+    const int i16 = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) wa[s][h] = *(const i16x4 *)&mw.wa[h][i16][16 * s + 4 * g];
+        if constexpr (WD) wd[s] = *(const i16x8 *)&mw.wd[g >> 1][16 * s + i16][8 * (g & 1)];
+    }
+    wave_lds_sync();
+}
+
+// Map block (chunk i, channel block b) of the current row: lane (i16, g) gets
+// F[pixel i16][chunk + 8 g + 4 b + r], r < 4.  Forward and backward run this same
+// sequence, so the recomputed map is bit-identical to the stored one.
+__device__ __forceinline__ f32x4 mf_map(const i16x4 (&a)[2], const i16x4 (&wa)[2][2], int nub) {
+    f32x4 F = {0.f, 0.f, 0.f, 0.f};
+    F = mfma16(a[0], wa[0][0], F);
+    F = mfma16(a[0], wa[0][1], F);
+    if (nub > 1) {
+        F = mfma16(a[1], wa[1][0], F);
+        F = mfma16(a[1], wa[1][1], F);
+    }
+    return F;
+}
+
+// dL/dF of the L1 feature loss for two packed BF16 map values against the target.
+__device__ __forceinline__ uint32_t l1_grad2(uint32_t f, uint32_t t, float gs) {
+    const float d0 = bf16_to_f32(f & 0xFFFFu) - bf16_to_f32(t & 0xFFFFu);
+    const float d1 = bf16_to_f32(f >> 16) - bf16_to_f32(t >> 16);
+    const float g0 = d0 > 0.f ? gs : (d0 < 0.f ? -gs : 0.f);
+    const float g1 = d1 > 0.f ? gs : (d1 < 0.f ? -gs : 0.f);
+    return pk_bf16(g0, g1);
+}
+
+template <int K, int FT>
+__device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int D, int U,
+                                           const void *__restrict__ feat, uint16_t *__restrict__ F,
+                                           UnionLds<K> &L, Slots<K> &s, unsigned char *dyn) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t *ft = (uint16_t *)dyn;
+    MfWave &mw = ((MfWave *)(dyn + mf_region0(D, K)))[wave];
+    mf_prologue<K, FT>(L, s, U, D, feat, ft);
+    const MfChunks mc = mf_chunks(D, wave);
+    i16x4 opA[kCPW][2][2];
+    i16x8 opC[kCPW][2];
+    mf_load_ops(ft, U, D, mc, lane, opA, opC);
+    const SlotTable<K> st = slot_table(L);
+    const int nub = U > 16 ? 2 : 1;
+    const int i16 = lane & 15, g = lane >> 4;
+    const int x = tg.tx0 + i16;
+    for (int row = 0; row < 16; ++row) {
+        const int y = tg.ty0 + row;
+        if (y >= H) break;
+        i16x4 wa[2][2];
+        i16x8 wd[2];
+        mf_weights<K, false>(row, st, mw, lane, wa, wd);
+        const long pix = (long)tg.view * W * H + (long)y * W + x;
+#pragma unroll
+        for (int i = 0; i < kCPW; ++i) {
+            if (i >= mc.n) break;
+            const f32x4 F0 = mf_map(opA[i][0], wa, nub);
+            const f32x4 F1 = mf_map(opA[i][1], wa, nub);
+            const int ch = (mc.beg + i) * 32 + 8 * g;
+            if (x < W && ch < D) {
+                u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
+                           pk_bf16(F1[2], F1[3])};
+                *(u32x4 *)(F + pix * D + ch) = o;
+            }
+        }
+    }
+}
+
+// Backward of the MFMA path.  L1: dF holds the target map and G = l1_scale
+// sign(F - F^) is formed from the recomputed map; otherwise dF holds dL/dF.
+template <int K, int FT, bool L1, int R>
+__device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, int D, int U,
+                                            const void *__restrict__ feat, const uint16_t *__restrict__ dF,
+                                            float gs, float *__restrict__ dfeat, float *__restrict__ dtw,
+                                            UnionLds<K> &L, Slots<K> &s, unsigned char *dyn) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t *ft = (uint16_t *)dyn;
+    float *sred = (float *)dyn;   // [4][256][K], after the operands are loaded
+    MfWave &mw = ((MfWave *)(dyn + mf_region0(D, K)))[wave];
+    mf_prologue<K, FT>(L, s, U, D, feat, ft);
+    const MfChunks mc = mf_chunks(D, wave);
+    i16x4 opA[kCPW][2][2];
+    i16x8 opC[kCPW][2];
+    mf_load_ops(ft, U, D, mc, lane, opA, opC);
+    __syncthreads();   // staged rows are dead from here on
+    const SlotTable<K> st = slot_table(L);
+    const int nub = U > 16 ? 2 : 1;
+    const int i16 = lane & 15, g = lane >> 4;
+    const int x = tg.tx0 + i16;
+    const int rows = min(16, H - tg.ty0);
+
+    f32x4 acc[kCPW][2][2];   // [chunk][channel block][union block]
+#pragma unroll
+    for (int i = 0; i < kCPW; ++i)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) acc[i][b][v] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    // dL/dF (or the target) of R - 1 rows ahead, in an R-deep register ring;
+    // lane (i16, g) reads channels 8g..8g+7 of each chunk for pixel i16
+    u32x4 tb[R][kCPW];
+    auto fetch = [&](int row, u32x4 (&dst)[kCPW]) {
+        const int y = tg.ty0 + row;
+        const bool pix_on = row < rows && x < W;
+        const long pix = (long)tg.view * W * H + (long)y * W + x;
+#pragma unroll
+        for (int i = 0; i < kCPW; ++i) {
+            const int ch = (mc.beg + i) * 32 + 8 * g;
+            dst[i] = (u32x4){0u, 0u, 0u, 0u};
+            if (pix_on && i < mc.n && ch < D) dst[i] = *(const u32x4 *)(dF + pix * D + ch);
+        }
+    };
+#pragma unroll
+    for (int r = 0; r < R - 1; ++r) fetch(r, tb[r]);
+
+    for (int row0 = 0; row0 < rows; row0 += R) {
+#pragma unroll
+        for (int h = 0; h < R; ++h) {
+            const int row = row0 + h;
+            if (row >= rows) break;
+            fetch(row + R - 1, tb[(h + R - 1) % R]);
+            i16x4 wa[2][2];
+            i16x8 wd[2];
+            mf_weights<K, true>(row, st, mw, lane, wa, wd);
+            f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int i = 0; i < kCPW; ++i) {
+                if (i >= mc.n) break;
+                u32x4 G;
+                if constexpr (L1) {
+                    const f32x4 F0 = mf_map(opA[i][0], wa, nub);
+                    const f32x4 F1 = mf_map(opA[i][1], wa, nub);
+                    G.x = l1_grad2(pk_bf16(F0[0], F0[1]), tb[h][i].x, gs);
+                    G.y = l1_grad2(pk_bf16(F0[2], F0[3]), tb[h][i].y, gs);
+                    G.z = l1_grad2(pk_bf16(F1[0], F1[1]), tb[h][i].z, gs);
+                    G.w = l1_grad2(pk_bf16(F1[2], F1[3]), tb[h][i].w, gs);
+                } else {
+                    G = tb[h][i];
+                }
+                // dot products over the chunk's 32 channels
+                sacc[0] = mfma32(opC[i][0], as_op8(G), sacc[0]);
+                if (nub > 1) sacc[1] = mfma32(opC[i][1], as_op8(G), sacc[1]);
+                // G transposed: block b row 4g + r <- this lane's channel 8g + 4b + r
+                mw.gt[0][4 * g + 0][i16] = (uint16_t)(G.x & 0xFFFFu);
+                mw.gt[0][4 * g + 1][i16] = (uint16_t)(G.x >> 16);
+                mw.gt[0][4 * g + 2][i16] = (uint16_t)(G.y & 0xFFFFu);
+                mw.gt[0][4 * g + 3][i16] = (uint16_t)(G.y >> 16);
+                mw.gt[1][4 * g + 0][i16] = (uint16_t)(G.z & 0xFFFFu);
+                mw.gt[1][4 * g + 1][i16] = (uint16_t)(G.z >> 16);
+                mw.gt[1][4 * g + 2][i16] = (uint16_t)(G.w & 0xFFFFu);
+                mw.gt[1][4 * g + 3][i16] = (uint16_t)(G.w >> 16);
+                wave_lds_sync();
+                // B operand [hi pixels; lo pixels] x 16 block rows: G of pixels 8 (g % 2) + j
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const i16x8 g2 = *(const i16x8 *)&mw.gt[b][i16][8 * (g & 1)];
+                    acc[i][b][0] = mfma32(wd[0], g2, acc[i][b][0]);
+                    if (nub > 1) acc[i][b][1] = mfma32(wd[1], g2, acc[i][b][1]);
+                }
+                wave_lds_sync();
+            }
+            // this wave's share of S^T for the row -> its K slots, through LDS
+            float *spb = (float *)&mw;   // [kUP][16], over the weight buffers
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) spb[(16 * v + 4 * g + r) * 16 + i16] = sacc[v][r];
+            wave_lds_sync();
+            const int p = row * 16 + i16;
+            for (int k = g; k < K; k += 4) {
+                const int u = st.u[p * K + k];
+                sred[(wave * kTilePix + p) * K + k] = u >= 0 ? spb[u * 16 + i16] : 0.f;
+            }
+            wave_lds_sync();
+        }
+    }
+
+    // gradient rows: lane (i16, g) holds dFt[16 v + 4 g + r][chunk + blk_ch(b, i16)]
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        if (v >= nub) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int u = 16 * v + 4 * g + r;
+            if (u >= U) continue;
+            float *dst = dfeat + (long)L.uid2[u] * D;
+#pragma unroll
+            for (int i = 0; i < kCPW; ++i) {
+                if (i >= mc.n) break;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int ch = (mc.beg + i) * 32 + blk_ch(b, i16);
+                    const float val = acc[i][b][v][r];
+                    if (ch < D && val != 0.f) unsafeAtomicAdd(dst + ch, val);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // gamma_k = (g_k - sum_j w'_j g_j) / W for the thread's own pixel
+    const int t = threadIdx.x;
+    const int px = tg.tx0 + (t & 15), py = tg.ty0 + (t >> 4);
+    if (px >= W || py >= H) return;
+    const long p = (long)tg.view * W * H + (long)py * W + px;
+    float gk[K], mean = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float v = sred[(0 * kTilePix + t) * K + k] + sred[(1 * kTilePix + t) * K + k];
+        v += sred[(2 * kTilePix + t) * K + k];
+        v += sred[(3 * kTilePix + t) * K + k];
+        if constexpr (FT == FT_FP8) v *= s.u[k] >= 0 ? L.uscale2[s.u[k]] : 0.f;
+        gk[k] = s.u[k] >= 0 ? v : 0.f;
+        mean = fmaf(s.wp[k], gk[k], mean);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) dtw[p * K + k] = s.u[k] >= 0 ? (gk[k] - mean) / s.W : 0.f;
 }
 
 // ---------------------------------------------------------------- forward
@@ -412,6 +858,12 @@ __device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int
     }
 }
 
+// Tiles take the MFMA path when the storage / map formats allow it and the union fits.
+template <int K, int FT, int MT>
+struct MfOk {
+    static constexpr bool v = (FT == FT_BF16 || FT == FT_FP8) && MT == MT_BF16 && K <= 8;
+};
+
 template <int K, int FT, int MT>
 __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int views, int D, int ucap,
                                                           const void *__restrict__ feat,
@@ -419,8 +871,7 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
                                                           const int *__restrict__ ids,
                                                           const float *__restrict__ tw,
                                                           void *__restrict__ F) {
-    constexpr int CPL = TileCfg<K>::CPL;
-    extern __shared__ __align__(16) unsigned char rows[];
+    extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ UnionLds<K> L;
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -429,9 +880,16 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     Slots<K> sl;
     int U;
-    tile_union<K, FT>(tg, W, H, D, ucap, ids, tw, feat, scale, L, rows, sl, U);
-    if (U >= 1 && U <= ucap) fwd_pixels<K, FT, MT, true>(tg, W, H, D, ucap, feat, F, sl, L, rows, wave, lane);
-    else fwd_pixels<K, FT, MT, false>(tg, W, H, D, ucap, feat, F, sl, L, rows, wave, lane);
+    tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
+    if constexpr (MfOk<K, FT, MT>::v) {
+        if (U <= kUP && D <= 128 * kCPW) {
+            mf_forward<K, FT>(tg, W, H, D, U, feat, (uint16_t *)F, L, sl, dyn);
+            return;
+        }
+    }
+    stage_rows<K, FT>(L, U, D, ucap, feat, dyn);
+    if (U >= 1 && U <= ucap) fwd_pixels<K, FT, MT, true>(tg, W, H, D, ucap, feat, F, sl, L, dyn, wave, lane);
+    else fwd_pixels<K, FT, MT, false>(tg, W, H, D, ucap, feat, F, sl, L, dyn, wave, lane);
 }
 
 // ---------------------------------------------------------------- backward
@@ -557,8 +1015,14 @@ __device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int
 // L1 = false: dF holds dL/dF (map dtype).  L1 = true: dF holds the target map F^ and
 // dL/dF = l1_scale * sign(F - F^) is formed on the fly from F recomputed exactly as
 // the forward kernel computes and rounds it.
+constexpr int kRing = 1;   // rows of dL/dF in flight on the MFMA path, besides the one in use
+
+template <int K, int CPL>
+constexpr size_t fallback_extra() { return (size_t)4 * kPixPerWave * K * 4 + (size_t)4 * 64 * CPL * 4; }
+
+// Two blocks per CU: registers are capped at 256 per lane.
 template <int K, int FT, int MT, bool L1>
-__global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int views, int D, int ucap,
+__global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int views, int D, int ucap,
                                                           const void *__restrict__ feat,
                                                           const float *__restrict__ scale,
                                                           const int *__restrict__ ids,
@@ -566,27 +1030,37 @@ __global__ __launch_bounds__(kFB) void feature_bwd_kernel(int W, int H, int view
                                                           const void *__restrict__ dF, float l1_scale,
                                                           float *__restrict__ dfeat,
                                                           float *__restrict__ dtw) {
-    constexpr int CPL = TileCfg<K>::CPL, RA = TileCfg<K>::RA;
-    extern __shared__ __align__(16) unsigned char rows[];
+    constexpr int CPL = TileCfg<K>::CPL;
+    extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ UnionLds<K> L;
-    __shared__ float s_dot[4][kPixPerWave][K];
-    __shared__ float s_x[4][64 * CPL];
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     const TileGeom tg = tile_geom(tile, W, H);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float *xbuf = s_x[wave];
     Slots<K> sl;
     int U;
-    const int nw = tile_union<K, FT>(tg, W, H, D, ucap, ids, tw, feat, scale, L, rows, sl, U);
+    const int nw = tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
+    if constexpr (MfOk<K, FT, MT>::v) {
+        if (U <= kUP && D <= 128 * kCPW) {
+            const float gs = bf16_to_f32(f32_to_bf16(l1_scale));
+            mf_backward<K, FT, L1, kRing + 1>(tg, W, H, D, U, feat, (const uint16_t *)dF, gs, dfeat, dtw, L,
+                                              sl, dyn);
+            return;
+        }
+    }
+    // per-pixel path: staged rows, then the dot products and the transpose buffers
+    float(*s_dot)[kPixPerWave][K] = (float(*)[kPixPerWave][K])(dyn + kRowBudget);
+    float(*s_x)[64 * CPL] = (float(*)[64 * CPL])(dyn + kRowBudget + (size_t)4 * kPixPerWave * K * 4);
+    float *xbuf = s_x[wave];
+    stage_rows<K, FT>(L, U, D, ucap, feat, dyn);
 #pragma unroll
     for (int k = 0; k < K; ++k) s_dot[wave][lane][k] = 0.f;
     if (U >= 1 && U <= ucap)
-        bwd_pixels<K, FT, MT, L1, true>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, rows, nw,
+        bwd_pixels<K, FT, MT, L1, true>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, dyn, nw,
                                        s_dot[wave], xbuf, wave, lane);
     else
-        bwd_pixels<K, FT, MT, L1, false>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, rows, nw,
+        bwd_pixels<K, FT, MT, L1, false>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, dyn, nw,
                                         s_dot[wave], xbuf, wave, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -738,19 +1212,20 @@ __global__ __launch_bounds__(256) void union_sum_kernel(int n, int *__restrict__
 // Staged union rows per block: as many as fit in `budget` bytes (at least 0).
 inline int pick_ucap(int D, int sf, int budget) { return budget / (D * sf); }
 
-constexpr int kRowBudget = 32 * 1024;
 
 template <int FT, int MT>
 lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
                         const int *ids, const float *tw, void *F, hipStream_t st) {
     unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
     const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
-    const size_t lds = (size_t)ucap * D * Bytes<FT>::v;
+    const size_t rows = (size_t)ucap * D * Bytes<FT>::v;
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
+        lds = MfOk<KK, FT, MT>::v ? std::max(rows, mf_lds_bytes(D, KK)) : rows;                     \
         hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(kFB), lds, st, W, H,  \
                            views, D, ucap, feat, scale, ids, tw, F);                                 \
         break;
+    size_t lds = 0;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
     return check_launch("feature_render_fwd");
@@ -762,12 +1237,14 @@ lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
                         float *dtw, hipStream_t st) {
     unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
     const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
-    const size_t lds = (size_t)ucap * D * Bytes<FT>::v;
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
+        lds = kRowBudget + fallback_extra<KK, TileCfg<KK>::CPL>();                                  \
+        if (MfOk<KK, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, KK));                          \
         hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, L1>), dim3(grid), dim3(kFB), lds, st, W, \
                            H, views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw);        \
         break;
+    size_t lds = 0;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
     return check_launch("feature_render_bwd");

@@ -239,7 +239,14 @@ def _synthetic_topk(rng, views, H, W, K, n, spread):
     (4, "bf16", "bf16", 2, 40, 48, 512, 30000),    # union overflows the LDS cache
     (8, "fp8", "bf16", 1, 33, 70, 768, 500),
     (1, "bf16", "f32", 3, 20, 20, 520, 20),
-    (16, "f32", "f32", 1, 32, 32, 128, 9000)])
+    (16, "f32", "f32", 1, 32, 32, 128, 9000),
+    # unions of 17..32 (two 16-row MFMA blocks), channel tails, idle waves
+    (4, "bf16", "bf16", 1, 16, 16, 512, 28),
+    (4, "bf16", "bf16", 2, 50, 70, 200, 24),
+    (8, "fp8", "bf16", 1, 40, 40, 512, 30),
+    (4, "fp8", "bf16", 1, 33, 35, 96, 12),
+    (2, "bf16", "bf16", 1, 30, 30, 8, 10),
+    (5, "bf16", "bf16", 1, 64, 64, 512, 60)])
 def test_feature_kernels_on_synthetic_topk(torch, orc, K, fdt, mdt, views, H, W, D, spread):
     from paper_2602_06991_amd import render
     rng = np.random.default_rng(K * 100 + D)
@@ -315,3 +322,35 @@ def test_feature_bwd_fused_l1(torch, orc, K, fdt, mdt):
     assert e.max() <= 1e-4, e.max()
     scl = np.abs(d_w).max(-1, keepdims=True) + 1e-12
     assert (np.abs(dtw.cpu().numpy() - d_w) / scl).max() <= 1e-4
+
+
+@pytest.mark.parametrize("K,fdt,D,spread", [(4, "bf16", 512, 24), (8, "fp8", 512, 30),
+                                            (4, "bf16", 256, 20000), (3, "fp8", 200, 14)])
+def test_fused_l1_matches_unfused(torch, K, fdt, D, spread):
+    """The fused L1 adjoint recomputes the map; it must take every sign decision as
+    l1_grad does on the stored map, exact ties (F == F^) and one-ulp gaps included."""
+    from paper_2602_06991_amd import render
+    rng = np.random.default_rng(7 * K + D)
+    views, H, W, n = 1, 48, 64, 30000
+    feat = rng.standard_normal((n, D)).astype(np.float32)
+    ids, w = _synthetic_topk(rng, views, H, W, K, n, spread)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    store, sc8 = render.quantize(dev(feat), fdt)
+    F = render.feature_fwd(dev(ids), dev(w), store, sc8, fdt, "bf16")
+    bits = F.view(torch.int16).clone()
+    pick = torch.from_numpy(rng.integers(0, 3, tuple(bits.shape))).cuda()
+    step = torch.from_numpy(rng.choice([-1, 1], tuple(bits.shape)).astype(np.int16)).cuda()
+    tb = torch.where(pick == 1, bits + step, bits)
+    rnd = torch.from_numpy(rng.standard_normal(tuple(bits.shape)).astype(np.float32)).cuda()
+    target = torch.where(pick == 2, rnd.to(torch.bfloat16), tb.view(torch.bfloat16)).contiguous()
+    scale = 1.0 / F.numel()
+    gF = render.l1_grad(F, target, scale)
+    d1 = torch.zeros(n, D, device="cuda")
+    d2 = torch.zeros(n, D, device="cuda")
+    t1 = render.feature_bwd(dev(ids), dev(w), store, sc8, fdt, "bf16", gF, d1)
+    t2 = render.feature_bwd_l1(dev(ids), dev(w), store, sc8, fdt, "bf16", target, scale, d2)
+    torch.cuda.synchronize()
+    assert torch.equal(t1, t2)
+    assert torch.equal(d1 != 0, d2 != 0)
+    rel = ((d1 - d2).norm(dim=1) / d2.norm(dim=1).clamp_min(1e-30)).max().item()
+    assert rel <= 1e-6, rel
