@@ -93,7 +93,7 @@ constexpr int kRowBudget = 32 * 1024;   // LDS bytes for staged rows on the per-
 template <int K> struct TileCfg {
     static constexpr int CPL = K <= 4 ? 8 : (K <= 8 ? 4 : 2);   // channels per lane per pass
     static constexpr int RA = K <= 4 ? 12 : (K <= 8 ? 16 : 24);  // register accumulators per wave
-    static constexpr int HS = 1024;                               // union hash slots
+    static constexpr int HS = 512;                                // union hash slots
 };
 
 template <int FT> struct Bytes { static constexpr int v = FT == FT_F32 ? 4 : FT == FT_BF16 ? 2 : 1; };
@@ -212,14 +212,14 @@ struct Slots {
 };
 
 // LDS shared by both kernels (static part; staged rows are dynamic LDS).
-template <int K>
+template <int K, int FT>
 struct UnionLds {
     int hkey[TileCfg<K>::HS];
     int hval[TileCfg<K>::HS];
     int wlist[4][kPixPerWave * K];   // wave-local distinct ids
     int wmap[4][kPixPerWave * K];    // wave-local index -> tile union index
     int uid[4 * kPixPerWave * K];    // tile union index -> Gaussian id
-    float uscale[4 * kPixPerWave * K];  // tile union index -> FP8 row scale
+    float uscale[FT == FT_FP8 ? 4 * kPixPerWave * K : 1];  // tile union index -> FP8 row scale
     int nw[4];
     int nU;
     // MFMA path (U <= kUP): the union in ascending id order, so both feature
@@ -234,7 +234,7 @@ struct UnionLds {
 template <int K, int FT>
 __device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H,
                                           const int *__restrict__ ids, const float *__restrict__ tw,
-                                          const float *__restrict__ scale, UnionLds<K> &L,
+                                          const float *__restrict__ scale, UnionLds<K, FT> &L,
                                           Slots<K> &s, int &U) {
     constexpr int HS = TileCfg<K>::HS;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -330,7 +330,7 @@ __device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H,
 // Stages the first min(U, ucap) union rows in their storage format into `rows`:
 // 16-byte pieces (8-byte for FP8 rows).
 template <int K, int FT>
-__device__ __forceinline__ void stage_rows(const UnionLds<K> &L, int U, int D, int ucap,
+__device__ __forceinline__ void stage_rows(const UnionLds<K, FT> &L, int U, int D, int ucap,
                                            const void *__restrict__ feat, unsigned char *rows) {
     typedef typename std::conditional<FT == FT_FP8, u32x2, u32x4>::type piece;
     const int t = threadIdx.x;
@@ -429,56 +429,64 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Channel of block b, row m within a 32-channel chunk.
 __device__ __forceinline__ int blk_ch(int b, int m) { return 8 * (m >> 2) + 4 * b + (m & 3); }
 
-// Per-wave LDS of the MFMA path.
-struct MfWave {
-    uint16_t wa[2][16][kUP];   // [hi, lo][pixel of the row][union index]
-    uint16_t wd[2][kUP][16];   // [hi, lo][union index][pixel of the row]
-    uint16_t gt[2][16][16];    // [channel block][block row][pixel]: G of one chunk, transposed
+// Per-wave LDS of the MFMA path: the weights of the current row (both kernels),
+// their transpose and G of the row's chunks, transposed (backward only).
+struct MfWaveF {
+    uint16_t wa[2][16][kUP];            // [hi, lo][pixel of the row][union index]
 };
-static_assert(sizeof(MfWave) == 5120, "MfWave layout");
+struct MfWaveB {
+    uint16_t wa[2][16][kUP];
+    uint16_t wd[2][kUP][16];            // [hi, lo][union index][pixel of the row]
+    uint16_t gt[kCPW][2][16][16];       // [chunk][channel block][block row][pixel]
+};
+static_assert(sizeof(MfWaveF) == 2048 && sizeof(MfWaveB) == 8192, "MfWave layout");
 
-// Dynamic LDS of the MFMA path: the staged union rows (BF16, [kUP][D]), which the
-// per-wave partial dot products [4][256][K] later reuse, then four MfWave.
+// Dynamic LDS of the MFMA path: [0, R0) half of the union rows staged as BF16
+// ([16][D]), reused by the per-wave partial dot products [4][256][K] once the
+// operands are in registers; then the slot table (per pixel and slot: union index,
+// Wa weight, Wd weight); then the four per-wave buffers.
 __host__ __device__ inline size_t mf_region0(int D, int K) {
-    size_t a = (size_t)kUP * D * 2, b = (size_t)4 * kTilePix * K * 4;
+    size_t a = (size_t)16 * D * 2, b = (size_t)4 * kTilePix * K * 4;
     return ((a > b ? a : b) + 15) & ~(size_t)15;
 }
-__host__ __device__ inline size_t mf_lds_bytes(int D, int K) { return mf_region0(D, K) + 4 * sizeof(MfWave); }
+__host__ __device__ inline size_t mf_slots_bytes(int K) { return (size_t)3 * kTilePix * K * 4; }
+__host__ __device__ inline size_t mf_lds_bytes(int D, int K, bool bwd) {
+    return mf_region0(D, K) + mf_slots_bytes(K) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
+}
 
-// The slot table (per pixel: union index, Wa weight, Wd weight) lives where the
-// union's hash table and wave lists were.
 template <int K>
 struct SlotTable {
     int *u;
     float *wa, *wd;
 };
 template <int K>
-__device__ __forceinline__ SlotTable<K> slot_table(UnionLds<K> &L) {
-    static_assert(sizeof(L.hkey) + sizeof(L.hval) + sizeof(L.wlist) + sizeof(L.wmap) >=
-                      3 * sizeof(int) * kTilePix * K, "slot table must fit the union scratch");
+__device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, int D) {
     SlotTable<K> st;
-    st.u = &L.hkey[0];
-    st.wa = (float *)(&L.hkey[0] + kTilePix * K);
+    st.u = (int *)(dyn + mf_region0(D, K));
+    st.wa = (float *)(st.u + kTilePix * K);
     st.wd = st.wa + kTilePix * K;
     return st;
 }
 
-// Prologue of the MFMA path (all 256 threads; U <= kUP): orders the union by id,
-// writes the slot table and stages the union rows as BF16.
+// Prologue of the MFMA path (all 256 threads; U <= kUP): orders the union by id
+// and writes the slot table.
 template <int K, int FT>
-__device__ __forceinline__ void mf_prologue(UnionLds<K> &L, Slots<K> &s, int U, int D,
-                                            const void *__restrict__ feat, uint16_t *ft) {
+__device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int U, const SlotTable<K> &st) {
     const int t = threadIdx.x;
-    if (t < U) {
-        const int g = L.uid[t];
+    if (t < 128) {   // four threads per member (waves 0 and 1 whole, so the shuffles see every lane)
+        const int u = t >> 2, q = t & 3;
+        const int g = u < U ? L.uid[u] : 0;
         int r = 0;
-        for (int v = 0; v < U; ++v) r += L.uid[v] < g ? 1 : 0;   // ids are distinct
-        L.rank[t] = r;
-        L.uid2[r] = g;
-        if constexpr (FT == FT_FP8) L.uscale2[r] = L.uscale[t];
+        for (int v = q; v < U; v += 4) r += L.uid[v] < g ? 1 : 0;   // ids are distinct
+        r += __shfl_xor(r, 1);
+        r += __shfl_xor(r, 2);
+        if (u < U && q == 0) {
+            L.rank[u] = r;
+            L.uid2[r] = g;
+            if constexpr (FT == FT_FP8) L.uscale2[r] = L.uscale[u];
+        }
     }
     __syncthreads();
-    SlotTable<K> st = slot_table(L);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         s.u[k] = s.u[k] >= 0 ? L.rank[s.u[k]] : -1;
@@ -486,11 +494,17 @@ __device__ __forceinline__ void mf_prologue(UnionLds<K> &L, Slots<K> &s, int U, 
         st.wa[t * K + k] = s.u[k] >= 0 ? s.wf[k] : 0.f;
         st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
     }
-    // rows as BF16, 8 channels per step
+}
+
+// Stages union rows 16 h .. 16 h + 15 (those below U) as BF16 into ft = [16][D].
+template <int K, int FT>
+__device__ __forceinline__ void mf_stage_half(const UnionLds<K, FT> &L, int U, int D, int h,
+                                              const void *__restrict__ feat, uint16_t *ft) {
     const int c8 = D >> 3;
-    for (int q = t; q < U * c8; q += kFB) {
+    const int nr = min(16, U - 16 * h);
+    for (int q = threadIdx.x; q < nr * c8; q += kFB) {
         const int r = q / c8, c = (q - r * c8) * 8;
-        const long src = (long)L.uid2[r] * D + c;
+        const long src = (long)L.uid2[16 * h + r] * D + c;
         u32x4 o;
         if constexpr (FT == FT_BF16) {
             o = *(const u32x4 *)((const uint16_t *)feat + src);
@@ -507,7 +521,6 @@ __device__ __forceinline__ void mf_prologue(UnionLds<K> &L, Slots<K> &s, int U, 
         }
         *(u32x4 *)(ft + (long)r * D + c) = o;
     }
-    __syncthreads();
 }
 
 // The wave's chunks: [beg, beg + n) of the ceil(D / 32) chunks.
@@ -522,48 +535,74 @@ __device__ __forceinline__ MfChunks mf_chunks(int D, int wave) {
     return m;
 }
 
-// Register operands from the staged rows (zero outside the union and past D):
-//   opA[i][b][s]: lane (i16, g) = Ft[16 s + 4 g + j][chunk + blk_ch(b, i16)], j < 4
-//   opC[i][s]:    lane (i16, g) = Ft[16 s + i16][chunk + 8 g + j], j < 8
-__device__ __forceinline__ void mf_load_ops(const uint16_t *ft, int U, int D, const MfChunks &mc, int lane,
-                                            i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
+// Register operands of union block h (rows 16 h .. 16 h + 15, staged in ft), zero
+// outside the union and past D:
+//   opA[i][b][h]: lane (i16, g) = Ft[16 h + 4 g + j][chunk + blk_ch(b, i16)], j < 4
+//   opC[i][h]:    lane (i16, g) = Ft[16 h + i16][chunk + 8 g + j], j < 8
+__device__ __forceinline__ void mf_load_ops(const uint16_t *ft, int U, int D, int h, const MfChunks &mc,
+                                            int lane, i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
     const int i16 = lane & 15, g = lane >> 4;
+    const int nr = U - 16 * h;   // staged rows of this block
 #pragma unroll
     for (int i = 0; i < kCPW; ++i) {
         const int c0 = (mc.beg + i) * 32;
         const bool on = i < mc.n;
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 2; ++b) {
+            i16x4 a;
+            const int ch = c0 + blk_ch(b, i16);
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                i16x4 a;
-                const int ch = c0 + blk_ch(b, i16);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int u = 16 * s + 4 * g + j;
-                    a[j] = (on && u < U && ch < D) ? (short)ft[u * D + ch] : (short)0;
-                }
-                opA[i][b][s] = a;
+            for (int j = 0; j < 4; ++j) {
+                const int r = 4 * g + j;
+                a[j] = (on && r < nr && ch < D) ? (short)ft[r * D + ch] : (short)0;
             }
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int u = 16 * s + i16, ch = c0 + 8 * g;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (on && u < U && ch < D) v = *(const u32x4 *)(ft + u * D + ch);
-            opC[i][s] = as_op8(v);
+            opA[i][b][h] = a;
         }
+        const int ch = c0 + 8 * g;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (on && i16 < nr && ch < D) v = *(const u32x4 *)(ft + i16 * D + ch);
+        opC[i][h] = as_op8(v);
+    }
+}
+
+// Prologue and operands of the MFMA path; on return region 0 is free.
+template <int K, int FT>
+__device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U, int D, const void *__restrict__ feat,
+                                         unsigned char *dyn, const SlotTable<K> &st, const MfChunks &mc, int lane,
+                                         i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
+    uint16_t *ft = (uint16_t *)dyn;
+    mf_prologue<K, FT>(L, s, U, st);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h == 1 && U <= 16) {
+#pragma unroll
+            for (int i = 0; i < kCPW; ++i) {
+                opA[i][0][1] = (i16x4){0, 0, 0, 0};
+                opA[i][1][1] = (i16x4){0, 0, 0, 0};
+                opC[i][1] = (i16x8){0, 0, 0, 0, 0, 0, 0, 0};
+            }
+            break;
+        }
+        mf_stage_half<K, FT>(L, U, D, h, feat, ft);
+        __syncthreads();
+        mf_load_ops(ft, U, D, h, mc, lane, opA, opC);
+        __syncthreads();
     }
 }
 
 // Weights of tile row `row` in operand layout:
 //   wa[s][h]: lane (i16, g) = Wa_h[pixel i16][16 s + 4 g + j], j < 4     (16x16x16 B)
 //   wd[s]:    lane (i16, g) = Wd_{g/2}[pixel 8 (g % 2) + j][16 s + i16]    (16x16x32 A)
-template <int K, bool WD>
-__device__ __forceinline__ void mf_weights(int row, const SlotTable<K> &st, MfWave &mw, int lane,
+template <int K, bool WD, typename MW>
+__device__ __forceinline__ void mf_weights(int row, const SlotTable<K> &st, MW &mw, int lane,
                                            i16x4 (&wa)[2][2], i16x8 (&wd)[2]) {
+    // wa, and for WD the wd buffer right after it
+    uint16_t(*wd_buf)[kUP][16] = (uint16_t(*)[kUP][16])((unsigned char *)&mw + sizeof(mw.wa));
     u32x4 *z = (u32x4 *)&mw;
-    constexpr int nz = (WD ? sizeof(mw.wa) + sizeof(mw.wd) : sizeof(mw.wa)) / 16;
-    for (int j = lane; j < nz; j += 64) z[j] = (u32x4){0u, 0u, 0u, 0u};
+    constexpr int nz = (WD ? 2 : 1) * (int)sizeof(mw.wa) / 16;
+    static_assert(nz % 64 == 0, "whole waves of 16-byte stores");
+#pragma unroll
+    for (int j = 0; j < nz; j += 64) z[j + lane] = (u32x4){0u, 0u, 0u, 0u};
     wave_lds_sync();
     const int x = lane & 15, kq = lane >> 4, p = row * 16 + x;
     for (int k = kq; k < K; k += 4) {
@@ -576,8 +615,8 @@ __device__ __forceinline__ void mf_weights(int row, const SlotTable<K> &st, MfWa
             if constexpr (WD) {
                 const float d = st.wd[p * K + k];
                 const float dh = bf16_to_f32(bits_bf16(d));
-                mw.wd[0][u][x] = bits_bf16(d);
-                mw.wd[1][u][x] = bits_bf16(d - dh);
+                wd_buf[0][u][x] = bits_bf16(d);
+                wd_buf[1][u][x] = bits_bf16(d - dh);
             }
         }
     }
@@ -587,7 +626,7 @@ __device__ __forceinline__ void mf_weights(int row, const SlotTable<K> &st, MfWa
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) wa[s][h] = *(const i16x4 *)&mw.wa[h][i16][16 * s + 4 * g];
-        if constexpr (WD) wd[s] = *(const i16x8 *)&mw.wd[g >> 1][16 * s + i16][8 * (g & 1)];
+        if constexpr (WD) wd[s] = *(const i16x8 *)&wd_buf[g >> 1][16 * s + i16][8 * (g & 1)];
     }
     wave_lds_sync();
 }
@@ -606,28 +645,29 @@ __device__ __forceinline__ f32x4 mf_map(const i16x4 (&a)[2], const i16x4 (&wa)[2
     return F;
 }
 
-// dL/dF of the L1 feature loss for two packed BF16 map values against the target.
-__device__ __forceinline__ uint32_t l1_grad2(uint32_t f, uint32_t t, float gs) {
-    const float d0 = bf16_to_f32(f & 0xFFFFu) - bf16_to_f32(t & 0xFFFFu);
-    const float d1 = bf16_to_f32(f >> 16) - bf16_to_f32(t >> 16);
-    const float g0 = d0 > 0.f ? gs : (d0 < 0.f ? -gs : 0.f);
-    const float g1 = d1 > 0.f ? gs : (d1 < 0.f ? -gs : 0.f);
-    return pk_bf16(g0, g1);
+// Sign of the L1 feature loss gradient for two packed BF16 map values against the
+// target: -1, 0 or +1 per value, packed as BF16 (the loss scale is applied to the
+// sums).  d = F - F^ is exact; scaling it by 2^140 lifts every nonzero difference
+// of two BF16 values (at least 2^-133) to 2^7 or more before the clamp to [-1, 1].
+__device__ __forceinline__ uint32_t l1_sign2(uint32_t f, uint32_t t) {
+    const float d0 = __uint_as_float(f << 16) - __uint_as_float(t << 16);
+    const float d1 = __uint_as_float(f & 0xFFFF0000u) - __uint_as_float(t & 0xFFFF0000u);
+    const float s0 = __builtin_amdgcn_fmed3f(__builtin_ldexpf(d0, 140), -1.f, 1.f);
+    const float s1 = __builtin_amdgcn_fmed3f(__builtin_ldexpf(d1, 140), -1.f, 1.f);
+    return pk_bf16(s0, s1);
 }
 
 template <int K, int FT>
 __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int D, int U,
                                            const void *__restrict__ feat, uint16_t *__restrict__ F,
-                                           UnionLds<K> &L, Slots<K> &s, unsigned char *dyn) {
+                                           UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t *ft = (uint16_t *)dyn;
-    MfWave &mw = ((MfWave *)(dyn + mf_region0(D, K)))[wave];
-    mf_prologue<K, FT>(L, s, U, D, feat, ft);
+    const SlotTable<K> st = slot_table<K>(dyn, D);
+    MfWaveF &mw = ((MfWaveF *)(dyn + mf_region0(D, K) + mf_slots_bytes(K)))[wave];
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
-    mf_load_ops(ft, U, D, mc, lane, opA, opC);
-    const SlotTable<K> st = slot_table(L);
+    mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
     const int nub = U > 16 ? 2 : 1;
     const int i16 = lane & 15, g = lane >> 4;
     const int x = tg.tx0 + i16;
@@ -654,27 +694,26 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
 }
 
 // Backward of the MFMA path.  L1: dF holds the target map and G = l1_scale
-// sign(F - F^) is formed from the recomputed map; otherwise dF holds dL/dF.
+// sign(F - F^) is formed from the recomputed map (the products take the sign, the
+// sums the scale); otherwise dF holds dL/dF.
 template <int K, int FT, bool L1, int R>
 __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, int D, int U,
                                             const void *__restrict__ feat, const uint16_t *__restrict__ dF,
                                             float gs, float *__restrict__ dfeat, float *__restrict__ dtw,
-                                            UnionLds<K> &L, Slots<K> &s, unsigned char *dyn) {
+                                            UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t *ft = (uint16_t *)dyn;
-    float *sred = (float *)dyn;   // [4][256][K], after the operands are loaded
-    MfWave &mw = ((MfWave *)(dyn + mf_region0(D, K)))[wave];
-    mf_prologue<K, FT>(L, s, U, D, feat, ft);
+    float *sred = (float *)dyn;   // [4][256][K], once the operands are in registers
+    const SlotTable<K> st = slot_table<K>(dyn, D);
+    MfWaveB &mw = ((MfWaveB *)(dyn + mf_region0(D, K) + mf_slots_bytes(K)))[wave];
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
-    mf_load_ops(ft, U, D, mc, lane, opA, opC);
-    __syncthreads();   // staged rows are dead from here on
-    const SlotTable<K> st = slot_table(L);
+    mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
     const int nub = U > 16 ? 2 : 1;
     const int i16 = lane & 15, g = lane >> 4;
     const int x = tg.tx0 + i16;
     const int rows = min(16, H - tg.ty0);
+    const float gscale = L1 ? gs : 1.f;   // the L1 path accumulates sign(F - F^)
 
     f32x4 acc[kCPW][2][2];   // [chunk][channel block][union block]
 #pragma unroll
@@ -684,28 +723,36 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
 #pragma unroll
             for (int v = 0; v < 2; ++v) acc[i][b][v] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    // dL/dF (or the target) of R - 1 rows ahead, in an R-deep register ring;
-    // lane (i16, g) reads channels 8g..8g+7 of each chunk for pixel i16
+    // dL/dF (or the target) of R - 1 rows ahead, in an R-deep register ring; lane
+    // (i16, g) reads channels 8g..8g+7 of each chunk for pixel i16.  The loads carry
+    // no branches: each is a uniform row base plus a per-lane offset fixed for the
+    // tile, where a lane whose pixel or channels lie outside reads the row's first
+    // element (rows past the image read the last row).  Such values meet only zero
+    // weights and zero operands; the L1 gradient is always finite, dL/dF is masked.
     u32x4 tb[R][kCPW];
-    auto fetch = [&](int row, u32x4 (&dst)[kCPW]) {
-        const int y = tg.ty0 + row;
-        const bool pix_on = row < rows && x < W;
-        const long pix = (long)tg.view * W * H + (long)y * W + x;
+    uint32_t loff[kCPW];
+    bool lon[kCPW];
 #pragma unroll
-        for (int i = 0; i < kCPW; ++i) {
-            const int ch = (mc.beg + i) * 32 + 8 * g;
-            dst[i] = (u32x4){0u, 0u, 0u, 0u};
-            if (pix_on && i < mc.n && ch < D) dst[i] = *(const u32x4 *)(dF + pix * D + ch);
-        }
+    for (int i = 0; i < kCPW; ++i) {
+        const int ch = (mc.beg + i) * 32 + 8 * g;
+        lon[i] = x < W && i < mc.n && ch < D;
+        loff[i] = lon[i] ? (uint32_t)(i16 * D + ch) : 0u;
+    }
+    auto fetch = [&](int row, u32x4 (&dst)[kCPW]) {
+        const uint16_t *base = dF + ((long)tg.view * W * H + (long)(tg.ty0 + min(row, rows - 1)) * W + tg.tx0) * D;
+#pragma unroll
+        for (int i = 0; i < kCPW; ++i) dst[i] = *(const u32x4 *)(base + loff[i]);
     };
 #pragma unroll
     for (int r = 0; r < R - 1; ++r) fetch(r, tb[r]);
 
-    for (int row0 = 0; row0 < rows; row0 += R) {
+    // every wave walks all 16 rows and all kCPW chunks: rows past the image and
+    // chunks past D carry zero weights and zero operands
+#pragma unroll 1
+    for (int row0 = 0; row0 < 16; row0 += R) {
 #pragma unroll
         for (int h = 0; h < R; ++h) {
             const int row = row0 + h;
-            if (row >= rows) break;
             fetch(row + R - 1, tb[(h + R - 1) % R]);
             i16x4 wa[2][2];
             i16x8 wd[2];
@@ -713,40 +760,48 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
             for (int i = 0; i < kCPW; ++i) {
-                if (i >= mc.n) break;
+                const u32x4 T = (L1 || (row < rows && lon[i])) ? tb[h][i] : (u32x4){0u, 0u, 0u, 0u};
                 u32x4 G;
                 if constexpr (L1) {
                     const f32x4 F0 = mf_map(opA[i][0], wa, nub);
                     const f32x4 F1 = mf_map(opA[i][1], wa, nub);
-                    G.x = l1_grad2(pk_bf16(F0[0], F0[1]), tb[h][i].x, gs);
-                    G.y = l1_grad2(pk_bf16(F0[2], F0[3]), tb[h][i].y, gs);
-                    G.z = l1_grad2(pk_bf16(F1[0], F1[1]), tb[h][i].z, gs);
-                    G.w = l1_grad2(pk_bf16(F1[2], F1[3]), tb[h][i].w, gs);
+                    u32x4 Fp = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
+                                pk_bf16(F1[2], F1[3])};
+                    __asm__ volatile("" : "+v"(Fp.x), "+v"(Fp.y), "+v"(Fp.z), "+v"(Fp.w));
+                    G.x = l1_sign2(Fp.x, T.x);
+                    G.y = l1_sign2(Fp.y, T.y);
+                    G.z = l1_sign2(Fp.z, T.z);
+                    G.w = l1_sign2(Fp.w, T.w);
                 } else {
-                    G = tb[h][i];
+                    G = T;
                 }
+                // keep G packed: its halves are stored as they are, not re-derived
+                __asm__ volatile("" : "+v"(G.x), "+v"(G.y), "+v"(G.z), "+v"(G.w));
                 // dot products over the chunk's 32 channels
                 sacc[0] = mfma32(opC[i][0], as_op8(G), sacc[0]);
                 if (nub > 1) sacc[1] = mfma32(opC[i][1], as_op8(G), sacc[1]);
                 // G transposed: block b row 4g + r <- this lane's channel 8g + 4b + r
-                mw.gt[0][4 * g + 0][i16] = (uint16_t)(G.x & 0xFFFFu);
-                mw.gt[0][4 * g + 1][i16] = (uint16_t)(G.x >> 16);
-                mw.gt[0][4 * g + 2][i16] = (uint16_t)(G.y & 0xFFFFu);
-                mw.gt[0][4 * g + 3][i16] = (uint16_t)(G.y >> 16);
-                mw.gt[1][4 * g + 0][i16] = (uint16_t)(G.z & 0xFFFFu);
-                mw.gt[1][4 * g + 1][i16] = (uint16_t)(G.z >> 16);
-                mw.gt[1][4 * g + 2][i16] = (uint16_t)(G.w & 0xFFFFu);
-                mw.gt[1][4 * g + 3][i16] = (uint16_t)(G.w >> 16);
-                wave_lds_sync();
-                // B operand [hi pixels; lo pixels] x 16 block rows: G of pixels 8 (g % 2) + j
+                mw.gt[i][0][4 * g + 0][i16] = (uint16_t)(G.x & 0xFFFFu);
+                mw.gt[i][0][4 * g + 1][i16] = (uint16_t)(G.x >> 16);
+                mw.gt[i][0][4 * g + 2][i16] = (uint16_t)(G.y & 0xFFFFu);
+                mw.gt[i][0][4 * g + 3][i16] = (uint16_t)(G.y >> 16);
+                mw.gt[i][1][4 * g + 0][i16] = (uint16_t)(G.z & 0xFFFFu);
+                mw.gt[i][1][4 * g + 1][i16] = (uint16_t)(G.z >> 16);
+                mw.gt[i][1][4 * g + 2][i16] = (uint16_t)(G.w & 0xFFFFu);
+                mw.gt[i][1][4 * g + 3][i16] = (uint16_t)(G.w >> 16);
+            }
+            wave_lds_sync();
+            // gradient rows: B operand [hi pixels; lo pixels] x 16 block rows, i.e. G of
+            // pixels 8 (g % 2) + j
+#pragma unroll
+            for (int i = 0; i < kCPW; ++i)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    const i16x8 g2 = *(const i16x8 *)&mw.gt[b][i16][8 * (g & 1)];
+                    const i16x8 g2 = *(const i16x8 *)&mw.gt[i][b][i16][8 * (g & 1)];
                     acc[i][b][0] = mfma32(wd[0], g2, acc[i][b][0]);
                     if (nub > 1) acc[i][b][1] = mfma32(wd[1], g2, acc[i][b][1]);
                 }
-                wave_lds_sync();
-            }
+            wave_lds_sync();
             // this wave's share of S^T for the row -> its K slots, through LDS
             float *spb = (float *)&mw;   // [kUP][16], over the weight buffers
 #pragma unroll
@@ -757,7 +812,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             const int p = row * 16 + i16;
             for (int k = g; k < K; k += 4) {
                 const int u = st.u[p * K + k];
-                sred[(wave * kTilePix + p) * K + k] = u >= 0 ? spb[u * 16 + i16] : 0.f;
+                sred[(wave * kTilePix + p) * K + k] = u >= 0 ? gscale * spb[u * 16 + i16] : 0.f;
             }
             wave_lds_sync();
         }
@@ -778,7 +833,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     const int ch = (mc.beg + i) * 32 + blk_ch(b, i16);
-                    const float val = acc[i][b][v][r];
+                    const float val = gscale * acc[i][b][v][r];
                     if (ch < D && val != 0.f) unsafeAtomicAdd(dst + ch, val);
                 }
             }
@@ -811,7 +866,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
 template <int K, int FT, int MT, bool STAGED>
 __device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
                                            const void *__restrict__ feat, void *__restrict__ F,
-                                           const Slots<K> &sl, const UnionLds<K> &L,
+                                           const Slots<K> &sl, const UnionLds<K, FT> &L,
                                            const unsigned char *rows, int wave, int lane) {
     constexpr int CPL = TileCfg<K>::CPL;
     const int passes = (D + 64 * CPL - 1) / (64 * CPL);
@@ -872,7 +927,7 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
                                                           const float *__restrict__ tw,
                                                           void *__restrict__ F) {
     extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ UnionLds<K> L;
+    __shared__ UnionLds<K, FT> L;
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
@@ -900,7 +955,7 @@ template <int K, int FT, int MT, bool L1, bool STAGED>
 __device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
                                            const void *__restrict__ feat, const void *__restrict__ dF,
                                            float l1_scale, float *__restrict__ dfeat,
-                                           const Slots<K> &sl, const UnionLds<K> &L,
+                                           const Slots<K> &sl, const UnionLds<K, FT> &L,
                                            const unsigned char *rows, int nw,
                                            float (*sdot)[K], float *xbuf, int wave, int lane) {
     constexpr int CPL = TileCfg<K>::CPL, RA = TileCfg<K>::RA;
@@ -1032,7 +1087,7 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
                                                           float *__restrict__ dtw) {
     constexpr int CPL = TileCfg<K>::CPL;
     extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ UnionLds<K> L;
+    __shared__ UnionLds<K, FT> L;
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
@@ -1221,7 +1276,7 @@ lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
     const size_t rows = (size_t)ucap * D * Bytes<FT>::v;
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
-        lds = MfOk<KK, FT, MT>::v ? std::max(rows, mf_lds_bytes(D, KK)) : rows;                     \
+        lds = MfOk<KK, FT, MT>::v ? std::max(rows, mf_lds_bytes(D, KK, false)) : rows;                     \
         hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(kFB), lds, st, W, H,  \
                            views, D, ucap, feat, scale, ids, tw, F);                                 \
         break;
@@ -1240,7 +1295,7 @@ lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
         lds = kRowBudget + fallback_extra<KK, TileCfg<KK>::CPL>();                                  \
-        if (MfOk<KK, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, KK));                          \
+        if (MfOk<KK, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, KK, true));                          \
         hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, L1>), dim3(grid), dim3(kFB), lds, st, W, \
                            H, views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw);        \
         break;

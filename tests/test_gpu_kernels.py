@@ -350,7 +350,11 @@ def test_fused_l1_matches_unfused(torch, K, fdt, D, spread):
     t1 = render.feature_bwd(dev(ids), dev(w), store, sc8, fdt, "bf16", gF, d1)
     t2 = render.feature_bwd_l1(dev(ids), dev(w), store, sc8, fdt, "bf16", target, scale, d2)
     torch.cuda.synchronize()
-    assert torch.equal(t1, t2)
+    # the fused path sums signs and scales the sums, so values agree to rounding; one
+    # flipped sign would move a pixel's dot product by about a tenth
     assert torch.equal(d1 != 0, d2 != 0)
     rel = ((d1 - d2).norm(dim=1) / d2.norm(dim=1).clamp_min(1e-30)).max().item()
     assert rel <= 1e-6, rel
+    scl = t2.abs().amax(-1, keepdim=True).clamp_min(1e-30)
+    e = ((t1 - t2).abs() / scl).max().item()
+    assert e <= 1e-5, e
