@@ -93,7 +93,7 @@ constexpr int kRowBudget = 32 * 1024;   // LDS bytes for staged rows on the per-
 template <int K> struct TileCfg {
     static constexpr int CPL = K <= 4 ? 8 : (K <= 8 ? 4 : 2);   // channels per lane per pass
     static constexpr int RA = K <= 4 ? 12 : (K <= 8 ? 16 : 24);  // register accumulators per wave
-    static constexpr int HS = 512;                                // union hash slots
+    static constexpr int HS = 256;   // union hash slots: dedups any tile of up to 128 wave-distinct ids
 };
 
 template <int FT> struct Bytes { static constexpr int v = FT == FT_F32 ? 4 : FT == FT_BF16 ? 2 : 1; };
@@ -431,27 +431,37 @@ __device__ __forceinline__ int blk_ch(int b, int m) { return 8 * (m >> 2) + 4 * 
 
 // Per-wave LDS of the MFMA path: the weights of the current row (both kernels),
 // their transpose and G of the row's chunks, transposed (backward only).
+constexpr int kOutPitch = 128 + 8;   // bf16 per staged map row (the pad spreads LDS banks)
 struct MfWaveF {
-    uint16_t wa[2][16][kUP];            // [hi, lo][pixel of the row][union index]
+    union {
+        uint16_t wa[2][16][kUP];        // [hi, lo][pixel of the row][union index]
+        uint16_t out[16][kOutPitch];    // the row's map values for the wave's channels
+    };
 };
 struct MfWaveB {
     uint16_t wa[2][16][kUP];
     uint16_t wd[2][kUP][16];            // [hi, lo][union index][pixel of the row]
     uint16_t gt[kCPW][2][16][16];       // [chunk][channel block][block row][pixel]
 };
-static_assert(sizeof(MfWaveF) == 2048 && sizeof(MfWaveB) == 8192, "MfWave layout");
+static_assert(sizeof(MfWaveF) == 16 * kOutPitch * 2 && sizeof(MfWaveB) == 8192, "MfWave layout");
 
 // Dynamic LDS of the MFMA path: [0, R0) half of the union rows staged as BF16
-// ([16][D]), reused by the per-wave partial dot products [4][256][K] once the
-// operands are in registers; then the slot table (per pixel and slot: union index,
-// Wa weight, Wd weight); then the four per-wave buffers.
+// ([16][D]) while the operands are loaded; then, in the backward, the per-wave
+// partial dot products [4][256][K] in the same place, followed by the slot table (per
+// pixel and slot: union index, Wa weight, Wd weight); in the forward the slot table
+// itself takes region 0.  The four per-wave buffers come last.
 __host__ __device__ inline size_t mf_region0(int D, int K) {
     size_t a = (size_t)16 * D * 2, b = (size_t)4 * kTilePix * K * 4;
     return ((a > b ? a : b) + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t mf_slots_bytes(int K) { return (size_t)3 * kTilePix * K * 4; }
+__host__ __device__ inline size_t mf_slots_at(int D, int K, bool bwd) { return bwd ? mf_region0(D, K) : 0; }
+__host__ __device__ inline size_t mf_waves_at(int D, int K, bool bwd) {
+    const size_t a = mf_region0(D, K), b = mf_slots_bytes(K);
+    return bwd ? a + b : ((a > b ? a : b) + 15) & ~(size_t)15;
+}
 __host__ __device__ inline size_t mf_lds_bytes(int D, int K, bool bwd) {
-    return mf_region0(D, K) + mf_slots_bytes(K) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
+    return mf_waves_at(D, K, bwd) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
 }
 
 template <int K>
@@ -460,18 +470,17 @@ struct SlotTable {
     float *wa, *wd;
 };
 template <int K>
-__device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, int D) {
+__device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, int D, bool bwd) {
     SlotTable<K> st;
-    st.u = (int *)(dyn + mf_region0(D, K));
+    st.u = (int *)(dyn + mf_slots_at(D, K, bwd));
     st.wa = (float *)(st.u + kTilePix * K);
     st.wd = st.wa + kTilePix * K;
     return st;
 }
 
-// Prologue of the MFMA path (all 256 threads; U <= kUP): orders the union by id
-// and writes the slot table.
+// Prologue of the MFMA path (all 256 threads; U <= kUP): orders the union by id.
 template <int K, int FT>
-__device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int U, const SlotTable<K> &st) {
+__device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int U) {
     const int t = threadIdx.x;
     if (t < 128) {   // four threads per member (waves 0 and 1 whole, so the shuffles see every lane)
         const int u = t >> 2, q = t & 3;
@@ -488,12 +497,7 @@ __device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        s.u[k] = s.u[k] >= 0 ? L.rank[s.u[k]] : -1;
-        st.u[t * K + k] = s.u[k];
-        st.wa[t * K + k] = s.u[k] >= 0 ? s.wf[k] : 0.f;
-        st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
-    }
+    for (int k = 0; k < K; ++k) s.u[k] = s.u[k] >= 0 ? L.rank[s.u[k]] : -1;
 }
 
 // Stages union rows 16 h .. 16 h + 15 (those below U) as BF16 into ft = [16][D].
@@ -571,7 +575,7 @@ __device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U,
                                          unsigned char *dyn, const SlotTable<K> &st, const MfChunks &mc, int lane,
                                          i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
     uint16_t *ft = (uint16_t *)dyn;
-    mf_prologue<K, FT>(L, s, U, st);
+    mf_prologue<K, FT>(L, s, U);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         if (h == 1 && U <= 16) {
@@ -588,6 +592,14 @@ __device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U,
         mf_load_ops(ft, U, D, h, mc, lane, opA, opC);
         __syncthreads();
     }
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        st.u[t * K + k] = s.u[k];
+        st.wa[t * K + k] = s.u[k] >= 0 ? s.wf[k] : 0.f;
+        st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
+    }
+    __syncthreads();
 }
 
 // Weights of tile row `row` in operand layout:
@@ -662,8 +674,8 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
                                            const void *__restrict__ feat, uint16_t *__restrict__ F,
                                            UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const SlotTable<K> st = slot_table<K>(dyn, D);
-    MfWaveF &mw = ((MfWaveF *)(dyn + mf_region0(D, K) + mf_slots_bytes(K)))[wave];
+    const SlotTable<K> st = slot_table<K>(dyn, D, false);
+    MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(D, K, false)))[wave];
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
@@ -677,19 +689,29 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
         i16x4 wa[2][2];
         i16x8 wd[2];
         mf_weights<K, false>(row, st, mw, lane, wa, wd);
-        const long pix = (long)tg.view * W * H + (long)y * W + x;
+        // the row's map values go through LDS (over the weights, now in registers)
+        // so that every store instruction writes whole pixel rows: 16 lanes x 16 bytes
+        // per pixel, four pixels per instruction
 #pragma unroll
         for (int i = 0; i < kCPW; ++i) {
             if (i >= mc.n) break;
             const f32x4 F0 = mf_map(opA[i][0], wa, nub);
             const f32x4 F1 = mf_map(opA[i][1], wa, nub);
-            const int ch = (mc.beg + i) * 32 + 8 * g;
-            if (x < W && ch < D) {
-                u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
-                           pk_bf16(F1[2], F1[3])};
-                *(u32x4 *)(F + pix * D + ch) = o;
-            }
+            u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
+                       pk_bf16(F1[2], F1[3])};
+            *(u32x4 *)&mw.out[i16][i * 32 + 8 * g] = o;
         }
+        wave_lds_sync();
+        const long rowpix = (long)tg.view * W * H + (long)y * W + tg.tx0;
+        const int piece = lane & 15;                      // 8 channels each
+        const int ch = mc.beg * 32 + 8 * piece;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int px = 4 * q + (lane >> 4);
+            if (tg.tx0 + px < W && piece < 4 * mc.n && ch < D)
+                *(u32x4 *)(F + (rowpix + px) * D + ch) = *(const u32x4 *)&mw.out[px][8 * piece];
+        }
+        wave_lds_sync();
     }
 }
 
@@ -703,8 +725,8 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
                                             UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *sred = (float *)dyn;   // [4][256][K], once the operands are in registers
-    const SlotTable<K> st = slot_table<K>(dyn, D);
-    MfWaveB &mw = ((MfWaveB *)(dyn + mf_region0(D, K) + mf_slots_bytes(K)))[wave];
+    const SlotTable<K> st = slot_table<K>(dyn, D, true);
+    MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(D, K, true)))[wave];
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
@@ -1272,15 +1294,23 @@ template <int FT, int MT>
 lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
                         const int *ids, const float *tw, void *F, hipStream_t st) {
     unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
-    const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
-    const size_t rows = (size_t)ucap * D * Bytes<FT>::v;
+    const int rb = D * Bytes<FT>::v;
+    // MFMA-capable kernels give the per-pixel path (unions beyond kUP) whatever rows
+    // fit the MFMA path's LDS, so that both paths keep four blocks per CU
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
-        lds = MfOk<KK, FT, MT>::v ? std::max(rows, mf_lds_bytes(D, KK, false)) : rows;                     \
+        if (MfOk<KK, FT, MT>::v) {                                                                   \
+            lds = mf_lds_bytes(D, KK, false);                                                        \
+            ucap = (int)(lds / rb);                                                                  \
+        } else {                                                                                     \
+            ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);                                           \
+            lds = (size_t)ucap * rb;                                                                 \
+        }                                                                                            \
         hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(kFB), lds, st, W, H,  \
                            views, D, ucap, feat, scale, ids, tw, F);                                 \
         break;
     size_t lds = 0;
+    int ucap = 0;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
     return check_launch("feature_render_fwd");
