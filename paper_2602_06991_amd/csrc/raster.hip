@@ -3,7 +3,7 @@
 // pass, Sec. 3.2), and its adjoint replayed back to front from the saved final
 // transmittance.  One 256-thread block per 16x16 tile, one thread per pixel; the
 // tile's depth-sorted Gaussians are staged through LDS in batches (256 forward,
-// 128 backward).
+// 32 backward).
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
@@ -113,7 +113,23 @@ __global__ __launch_bounds__(256) void raster_fwd_kernel(RasterArgs a, float *__
 }
 
 constexpr int kNG = 10;   // per-Gaussian gradient slots: mean2d 2, conic 3, opacity, rgb 3, depth
-constexpr int kRB = 128;  // Gaussians per LDS batch in the backward
+constexpr int kNGP = 12;  // the same, padded to whole 16-byte LDS stores
+constexpr int kRB = 32;   // Gaussians per LDS batch in the backward
+
+// Sums of N values over each row of 16 lanes, returned to every lane of the row
+// (quad_perm 1,0,3,2 and 2,3,0,1, then the 8- and 16-lane mirrors).  Every lane
+// must be active.
+template <int N>
+__device__ __forceinline__ void row_sum_many(float (&v)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0xB1>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x4E>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x141>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x140>(v[q]);
+}
 
 template <int K>
 __global__ __launch_bounds__(256) void raster_bwd_kernel(
@@ -126,7 +142,7 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
     __shared__ float2 s_xy[kRB];
     __shared__ float4 s_co[kRB];
     __shared__ float4 s_cz[kRB];
-    __shared__ float s_part[4][kNG][kRB];
+    __shared__ __align__(16) float s_part[16][kRB][kNGP];   // [pixel row of the tile][Gaussian][slot]
     __shared__ int s_max;
     const int ntiles = a.ntx * a.nty;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -215,36 +231,30 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
                     }
                 }
             }
-            // wave-level reduction of all ten components (every lane takes part)
-            if (__ballot(hit) != 0ull) {
-                float s[kNG];
-                wave_sum_many<kNG>(v, s);
-                if ((t & 63) == 0) {
-#pragma unroll
-                    for (int q = 0; q < kNG; ++q) s_part[wave][q][j] = s[q];
-                }
-            } else if ((t & 63) == 0) {
-#pragma unroll
-                for (int q = 0; q < kNG; ++q) s_part[wave][q][j] = 0.f;
+            // sums over each 16-pixel row of the tile (every lane takes part); the
+            // row's first lane files them, and the 16 row sums meet after the batch
+            if (__ballot(hit) != 0ull) row_sum_many<kNG>(v);
+            if ((t & 15) == 0) {
+                float *dst = s_part[t >> 4][j];
+                *(float4 *)dst = make_float4(v[0], v[1], v[2], v[3]);
+                *(float4 *)(dst + 4) = make_float4(v[4], v[5], v[6], v[7]);
+                *(float2 *)(dst + 8) = make_float2(v[8], v[9]);
             }
         }
         __syncthreads();
-        if (t < cnt) {
-            const int g = s_id[t];
-            float s[kNG];
+        // per Gaussian and slot: the 16 row sums in a fixed order, one atomic
+        for (int o = t; o < cnt * kNG; o += 256) {
+            const int j = o / kNG, q = o - j * kNG;
+            float sum = 0.f;
 #pragma unroll
-            for (int q = 0; q < kNG; ++q)
-                s[q] = (s_part[0][q][t] + s_part[1][q][t]) + (s_part[2][q][t] + s_part[3][q][t]);
-            if (s[0] != 0.f) unsafeAtomicAdd(&g_mean2d[2 * g], s[0]);
-            if (s[1] != 0.f) unsafeAtomicAdd(&g_mean2d[2 * g + 1], s[1]);
-            if (s[2] != 0.f) unsafeAtomicAdd(&g_conic[3 * g], s[2]);
-            if (s[3] != 0.f) unsafeAtomicAdd(&g_conic[3 * g + 1], s[3]);
-            if (s[4] != 0.f) unsafeAtomicAdd(&g_conic[3 * g + 2], s[4]);
-            if (s[9] != 0.f) unsafeAtomicAdd(&g_opac[g], s[9]);
-            if (s[5] != 0.f) unsafeAtomicAdd(&g_rgb[3 * g], s[5]);
-            if (s[6] != 0.f) unsafeAtomicAdd(&g_rgb[3 * g + 1], s[6]);
-            if (s[7] != 0.f) unsafeAtomicAdd(&g_rgb[3 * g + 2], s[7]);
-            if (s[8] != 0.f) unsafeAtomicAdd(&g_depth[g], s[8]);
+            for (int r = 0; r < 16; ++r) sum += s_part[r][j][q];
+            if (sum == 0.f) continue;
+            const int g = s_id[j];
+            float *dst = q < 2 ? &g_mean2d[2 * g + q]
+                       : q < 5 ? &g_conic[3 * g + (q - 2)]
+                       : q < 8 ? &g_rgb[3 * g + (q - 5)]
+                       : q == 8 ? &g_depth[g] : &g_opac[g];
+            unsafeAtomicAdd(dst, sum);
         }
     }
 }
