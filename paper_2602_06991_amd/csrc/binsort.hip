@@ -16,8 +16,8 @@ namespace lgs {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortIpt = 16;
-constexpr int kSortItems = kSortThreads * kSortIpt;   // 4096 items per block
+constexpr int kSortIpt = 4;
+constexpr int kSortItems = kSortThreads * kSortIpt;   // 1024 items per block: several blocks per CU
 constexpr int kScanItems = 4096;
 
 // Exclusive scan of one value per thread over a 256-thread block.
