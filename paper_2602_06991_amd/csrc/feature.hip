@@ -217,7 +217,7 @@ struct UnionLds {
     int hkey[TileCfg<K>::HS];
     int hval[TileCfg<K>::HS];
     int wlist[4][kPixPerWave * K];   // wave-local distinct ids
-    int wmap[4][kPixPerWave * K];    // wave-local index -> tile union index
+    int16_t wmap[4][kPixPerWave * K];   // wave-local index -> tile union index (< 4 * 64 K)
     int uid[4 * kPixPerWave * K];    // tile union index -> Gaussian id
     float uscale[FT == FT_FP8 ? 4 * kPixPerWave * K : 1];  // tile union index -> FP8 row scale
     int nw[4];
@@ -226,7 +226,7 @@ struct UnionLds {
     // kernels order the K dimension of their products identically
     int rank[kUP];       // hash-order union index -> ascending-id index
     int uid2[kUP];       // ascending-id index -> Gaussian id
-    float uscale2[kUP];  // ascending-id index -> FP8 row scale
+    float uscale2[FT == FT_FP8 ? kUP : 1];  // ascending-id index -> FP8 row scale
 };
 
 // Builds the tile union: L.uid[0, U) and, per lane, the slots' union indices.
@@ -299,7 +299,7 @@ __device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H,
             const int g = L.wlist[wave][j];
             uint32_t h = ((uint32_t)g * 2654435761u) & (HS - 1);
             for (int probe = 0; probe < HS && L.hkey[h] != g; ++probe) h = (h + 1) & (HS - 1);
-            L.wmap[wave][j] = L.hval[h];
+            L.wmap[wave][j] = (int16_t)L.hval[h];
         }
     } else {
         // very large unions: concatenate the wave lists (a Gaussian seen by several
@@ -310,7 +310,7 @@ __device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H,
             const int g = L.wlist[wave][j];
             L.uid[off + j] = g;
             if constexpr (FT == FT_FP8) L.uscale[off + j] = scale[g];
-            L.wmap[wave][j] = off + j;
+            L.wmap[wave][j] = (int16_t)(off + j);
         }
         if (t == 0) L.nU = ntot;
         __syncthreads();
@@ -429,36 +429,46 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Channel of block b, row m within a 32-channel chunk.
 __device__ __forceinline__ int blk_ch(int b, int m) { return 8 * (m >> 2) + 4 * b + (m & 3); }
 
-// Per-wave LDS of the MFMA path: the weights of the current row (both kernels),
-// their transpose and G of the row's chunks, transposed (backward only).
-constexpr int kOutPitch = 128 + 8;   // bf16 per staged map row (the pad spreads LDS banks)
-struct MfWaveF {
-    union {
-        uint16_t wa[2][16][kUP];        // [hi, lo][pixel of the row][union index]
-        uint16_t out[16][kOutPitch];    // the row's map values for the wave's channels
-    };
+// Weights of one tile row in operand-ready layout, shared by the block's four waves:
+// a ring of three such buffers lets one row be read while the next is scattered and
+// the one after is cleared, with a single block barrier per row.
+struct MfRingF {
+    uint16_t wa[2][16][kUP];            // [hi, lo][pixel of the row][union index]
 };
-struct MfWaveB {
+struct MfRingB {
     uint16_t wa[2][16][kUP];
     uint16_t wd[2][kUP][16];            // [hi, lo][union index][pixel of the row]
+};
+// Per-wave LDS: the forward's map row for the wave's channels (16-byte columns
+// XOR-swizzled by pixel, so neither the writes nor the reads collide on banks), the
+// backward's G of the row's chunks, transposed.
+struct MfWaveF {
+    uint16_t out[16][128];
+};
+struct MfWaveB {
     uint16_t gt[kCPW][2][16][16];       // [chunk][channel block][block row][pixel]
 };
-static_assert(sizeof(MfWaveF) == 16 * kOutPitch * 2 && sizeof(MfWaveB) == 8192, "MfWave layout");
+static_assert(sizeof(MfRingF) == 2048 && sizeof(MfRingB) == 4096, "ring layout");
+static_assert(sizeof(MfWaveF) == 4096 && sizeof(MfWaveB) == 4096, "wave buffer layout");
 
 // Dynamic LDS of the MFMA path: [0, R0) half of the union rows staged as BF16
 // ([16][D]) while the operands are loaded; then, in the backward, the per-wave
 // partial dot products [4][256][K] in the same place, followed by the slot table (per
 // pixel and slot: union index, Wa weight, Wd weight); in the forward the slot table
-// itself takes region 0.  The four per-wave buffers come last.
+// itself takes region 0.  Then the weight ring and the four per-wave buffers.
+__host__ __device__ inline size_t mf_align(size_t a) { return (a + 15) & ~(size_t)15; }
 __host__ __device__ inline size_t mf_region0(int D, int K) {
     size_t a = (size_t)16 * D * 2, b = (size_t)4 * kTilePix * K * 4;
-    return ((a > b ? a : b) + 15) & ~(size_t)15;
+    return mf_align(a > b ? a : b);
 }
 __host__ __device__ inline size_t mf_slots_bytes(int K) { return (size_t)3 * kTilePix * K * 4; }
 __host__ __device__ inline size_t mf_slots_at(int D, int K, bool bwd) { return bwd ? mf_region0(D, K) : 0; }
-__host__ __device__ inline size_t mf_waves_at(int D, int K, bool bwd) {
+__host__ __device__ inline size_t mf_ring_at(int D, int K, bool bwd) {
     const size_t a = mf_region0(D, K), b = mf_slots_bytes(K);
-    return bwd ? a + b : ((a > b ? a : b) + 15) & ~(size_t)15;
+    return bwd ? a + b : mf_align(a > b ? a : b);
+}
+__host__ __device__ inline size_t mf_waves_at(int D, int K, bool bwd) {
+    return mf_ring_at(D, K, bwd) + 3 * (bwd ? sizeof(MfRingB) : sizeof(MfRingF));
 }
 __host__ __device__ inline size_t mf_lds_bytes(int D, int K, bool bwd) {
     return mf_waves_at(D, K, bwd) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
@@ -602,45 +612,71 @@ __device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U,
     __syncthreads();
 }
 
-// Weights of tile row `row` in operand layout:
-//   wa[s][h]: lane (i16, g) = Wa_h[pixel i16][16 s + 4 g + j], j < 4     (16x16x16 B)
-//   wd[s]:    lane (i16, g) = Wd_{g/2}[pixel 8 (g % 2) + j][16 s + i16]    (16x16x32 A)
-template <int K, bool WD, typename MW>
-__device__ __forceinline__ void mf_weights(int row, const SlotTable<K> &st, MW &mw, int lane,
-                                           i16x4 (&wa)[2][2], i16x8 (&wd)[2]) {
-    // wa, and for WD the wd buffer right after it
-    uint16_t(*wd_buf)[kUP][16] = (uint16_t(*)[kUP][16])((unsigned char *)&mw + sizeof(mw.wa));
-    u32x4 *z = (u32x4 *)&mw;
-    constexpr int nz = (WD ? 2 : 1) * (int)sizeof(mw.wa) / 16;
-    static_assert(nz % 64 == 0, "whole waves of 16-byte stores");
-#pragma unroll
-    for (int j = 0; j < nz; j += 64) z[j + lane] = (u32x4){0u, 0u, 0u, 0u};
-    wave_lds_sync();
-    const int x = lane & 15, kq = lane >> 4, p = row * 16 + x;
-    for (int k = kq; k < K; k += 4) {
+// The weight ring (all 256 threads take part in clearing and scattering).
+template <typename RB>
+__device__ __forceinline__ void ring_clear(RB &rb) {
+    constexpr int n16 = (int)sizeof(RB) / 16;
+    static_assert(n16 <= kFB, "one 16-byte store per thread");
+    if ((int)threadIdx.x < n16) ((u32x4 *)&rb)[threadIdx.x] = (u32x4){0u, 0u, 0u, 0u};
+}
+
+// Scatters tile row `row`'s slots (16 pixels x K) into a cleared ring buffer, each
+// FP32 weight as hi = RNE(w) and lo = RNE(w - hi).
+template <int K, typename RB>
+__device__ __forceinline__ void ring_scatter(int row, const SlotTable<K> &st, RB &rb) {
+    constexpr bool WD = sizeof(RB) == sizeof(MfRingB);
+    const int t = threadIdx.x;
+    if (t < 16 * K) {
+        const int x = t & 15, k = t >> 4, p = row * 16 + x;
         const int u = st.u[p * K + k];
         if (u >= 0) {
             const float a = st.wa[p * K + k];
-            const float ah = bf16_to_f32(bits_bf16(a));
-            mw.wa[0][x][u] = bits_bf16(a);
-            mw.wa[1][x][u] = bits_bf16(a - ah);
+            rb.wa[0][x][u] = bits_bf16(a);
+            rb.wa[1][x][u] = bits_bf16(a - bf16_to_f32(bits_bf16(a)));
             if constexpr (WD) {
                 const float d = st.wd[p * K + k];
-                const float dh = bf16_to_f32(bits_bf16(d));
-                wd_buf[0][u][x] = bits_bf16(d);
-                wd_buf[1][u][x] = bits_bf16(d - dh);
+                MfRingB &rbb = reinterpret_cast<MfRingB &>(rb);
+                rbb.wd[0][u][x] = bits_bf16(d);
+                rbb.wd[1][u][x] = bits_bf16(d - bf16_to_f32(bits_bf16(d)));
             }
         }
     }
-    wave_lds_sync();
+}
+
+// Operands of one row from its ring buffer:
+//   wa[s][h]: lane (i16, g) = Wa_h[pixel i16][16 s + 4 g + j], j < 4     (16x16x16 B)
+//   wd[s]:    lane (i16, g) = Wd_{g/2}[pixel 8 (g % 2) + j][16 s + i16]    (16x16x32 A)
+template <typename RB>
+__device__ __forceinline__ void ring_read(const RB &rb, int lane, i16x4 (&wa)[2][2], i16x8 (&wd)[2]) {
     const int i16 = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) wa[s][h] = *(const i16x4 *)&mw.wa[h][i16][16 * s + 4 * g];
-        if constexpr (WD) wd[s] = *(const i16x8 *)&wd_buf[g >> 1][16 * s + i16][8 * (g & 1)];
+        for (int h = 0; h < 2; ++h) wa[s][h] = *(const i16x4 *)&rb.wa[h][i16][16 * s + 4 * g];
+        if constexpr (sizeof(RB) == sizeof(MfRingB))
+            wd[s] = *(const i16x8 *)&reinterpret_cast<const MfRingB &>(rb).wd[g >> 1][16 * s + i16][8 * (g & 1)];
     }
-    wave_lds_sync();
+}
+
+// Ring schedule: before the rows, buffers 0 and 1 are cleared and row 0 scattered
+// into buffer 0.  At row r, after the block barrier: read buffer r % 3, scatter row
+// r + 1 into buffer (r + 1) % 3 (cleared during row r - 1) and clear buffer
+// (r + 2) % 3 (last read during row r - 1).
+template <int K, typename RB>
+__device__ __forceinline__ void ring_start(RB *ring, const SlotTable<K> &st) {
+    ring_clear(ring[0]);
+    ring_clear(ring[1]);
+    __syncthreads();
+    ring_scatter<K>(0, st, ring[0]);
+}
+template <int K, typename RB>
+__device__ __forceinline__ void ring_row(RB *ring, const SlotTable<K> &st, int row, int lane, i16x4 (&wa)[2][2],
+                                         i16x8 (&wd)[2]) {
+    __syncthreads();
+    const int b = row % 3;
+    ring_read(ring[b], lane, wa, wd);
+    if (row + 1 < 16) ring_scatter<K>(row + 1, st, ring[b == 2 ? 0 : b + 1]);
+    ring_clear(ring[b == 0 ? 2 : b - 1]);
 }
 
 // Map block (chunk i, channel block b) of the current row: lane (i16, g) gets
@@ -675,23 +711,22 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
                                            UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const SlotTable<K> st = slot_table<K>(dyn, D, false);
+    MfRingF *ring = (MfRingF *)(dyn + mf_ring_at(D, K, false));
     MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(D, K, false)))[wave];
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
     mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
+    ring_start<K>(ring, st);
     const int nub = U > 16 ? 2 : 1;
     const int i16 = lane & 15, g = lane >> 4;
-    const int x = tg.tx0 + i16;
-    for (int row = 0; row < 16; ++row) {
-        const int y = tg.ty0 + row;
-        if (y >= H) break;
+    const int rows = min(16, H - tg.ty0);
+    for (int row = 0; row < rows; ++row) {
         i16x4 wa[2][2];
         i16x8 wd[2];
-        mf_weights<K, false>(row, st, mw, lane, wa, wd);
-        // the row's map values go through LDS (over the weights, now in registers)
-        // so that every store instruction writes whole pixel rows: 16 lanes x 16 bytes
-        // per pixel, four pixels per instruction
+        ring_row<K>(ring, st, row, lane, wa, wd);
+        // the row's map values go through LDS so that every store instruction writes
+        // whole pixel rows: 16 lanes x 16 bytes per pixel, four pixels per instruction
 #pragma unroll
         for (int i = 0; i < kCPW; ++i) {
             if (i >= mc.n) break;
@@ -699,17 +734,17 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
             const f32x4 F1 = mf_map(opA[i][1], wa, nub);
             u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
                        pk_bf16(F1[2], F1[3])};
-            *(u32x4 *)&mw.out[i16][i * 32 + 8 * g] = o;
+            *(u32x4 *)&mw.out[i16][8 * ((4 * i + g) ^ i16)] = o;
         }
         wave_lds_sync();
-        const long rowpix = (long)tg.view * W * H + (long)y * W + tg.tx0;
+        const long rowpix = (long)tg.view * W * H + (long)(tg.ty0 + row) * W + tg.tx0;
         const int piece = lane & 15;                      // 8 channels each
         const int ch = mc.beg * 32 + 8 * piece;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int px = 4 * q + (lane >> 4);
             if (tg.tx0 + px < W && piece < 4 * mc.n && ch < D)
-                *(u32x4 *)(F + (rowpix + px) * D + ch) = *(const u32x4 *)&mw.out[px][8 * piece];
+                *(u32x4 *)(F + (rowpix + px) * D + ch) = *(const u32x4 *)&mw.out[px][8 * (piece ^ px)];
         }
         wave_lds_sync();
     }
@@ -726,11 +761,13 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *sred = (float *)dyn;   // [4][256][K], once the operands are in registers
     const SlotTable<K> st = slot_table<K>(dyn, D, true);
+    MfRingB *ring = (MfRingB *)(dyn + mf_ring_at(D, K, true));
     MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(D, K, true)))[wave];
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
     mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
+    ring_start<K>(ring, st);
     const int nub = U > 16 ? 2 : 1;
     const int i16 = lane & 15, g = lane >> 4;
     const int x = tg.tx0 + i16;
@@ -778,7 +815,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             fetch(row + R - 1, tb[(h + R - 1) % R]);
             i16x4 wa[2][2];
             i16x8 wd[2];
-            mf_weights<K, true>(row, st, mw, lane, wa, wd);
+            ring_row<K>(ring, st, row, lane, wa, wd);
             f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
             for (int i = 0; i < kCPW; ++i) {
@@ -825,7 +862,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
                 }
             wave_lds_sync();
             // this wave's share of S^T for the row -> its K slots, through LDS
-            float *spb = (float *)&mw;   // [kUP][16], over the weight buffers
+            float *spb = (float *)&mw;   // [kUP][16], over the G buffer
 #pragma unroll
             for (int v = 0; v < 2; ++v)
 #pragma unroll
