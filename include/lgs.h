@@ -14,7 +14,8 @@
  *    except inside the workspace the caller passes to lgs_bin_sort, and never
  *    frees caller memory.
  *  - Every call is asynchronous on `stream` (it may be NULL, the default stream),
- *    except lgs_bin_sort, which reads the pair count back to the host once.
+ *    except lgs_bin_sort (unless asked not to) and lgs_bin_sort_count, which read the
+ *    pair count back to the host.
  *  - Gradient outputs ACCUMULATE (+=) unless stated; the caller zeroes them.
  *  - Arguments are validated on the host before any launch.  A failing call
  *    returns a negative lgs_status, launches nothing and leaves outputs untouched;
@@ -122,12 +123,26 @@ lgs_status lgs_bin_sort_workspace(int32_t n, int32_t width, int32_t height, int6
  * untouched: grow the buffers and call again.  This call synchronises `stream`
  * once to read the count.  workspace: ws_bytes >= lgs_bin_sort_workspace(...),
  * 256-byte aligned.
+ * n_pairs may be NULL: the call is then fully asynchronous.  The count stays in the
+ * workspace and the launches after the count take it from there (their grids are
+ * sized for max_pairs); if the count exceeds max_pairs the outputs hold only the
+ * first max_pairs pairs and are not a valid binning.  lgs_bin_sort_count reads the
+ * count back later and reports that case.
  */
 lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float *depth,
                         const int32_t *tile_rect, const int32_t *tiles_touched,
                         void *workspace, size_t ws_bytes, int64_t max_pairs,
                         int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
                         hipStream_t stream);
+
+/*
+ * The pair count of the last lgs_bin_sort on this workspace (same n and max_pairs),
+ * for calls made with n_pairs = NULL.  Synchronises `stream`; *n_pairs is a host
+ * pointer.  Returns LGS_ERR_CAPACITY if the count exceeded max_pairs (that call's
+ * outputs are then not valid: grow the buffers and bin again).
+ */
+lgs_status lgs_bin_sort_count(int32_t n, int64_t max_pairs, const void *workspace, int64_t *n_pairs,
+                              hipStream_t stream);
 
 /*
  * Colour/depth/opacity alpha blending (Eq. 1) that records the Top-K (Eq. 2) ids

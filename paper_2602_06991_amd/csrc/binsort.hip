@@ -49,11 +49,17 @@ __global__ __launch_bounds__(256) void depth_keys_kernel(int n, const float *__r
     vals[i] = i;
 }
 
+// The item count of a pass is n, or min(n, *n_dev) when the count lives on the device.
+__device__ __forceinline__ int items_of(int n, const long long *n_dev) {
+    return n_dev ? (int)min((long long)n, *n_dev) : n;
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
-                                                                  int n, int shift, int nb,
-                                                                  int *__restrict__ hist) {
+                                                                  int n, const long long *__restrict__ n_dev,
+                                                                  int shift, int nb, int *__restrict__ hist) {
     __shared__ int h[256];
     int t = threadIdx.x;
+    n = items_of(n, n_dev);
     h[t] = 0;
     __syncthreads();
     long base = (long)blockIdx.x * kSortItems;
@@ -84,9 +90,10 @@ __global__ __launch_bounds__(256) void radix_scan_digits_kernel(int *__restrict_
 }
 
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
-    const uint32_t *__restrict__ kin, const int *__restrict__ vin, int n, int shift, int nb,
-    const int *__restrict__ hist, const int *__restrict__ totals, uint32_t *__restrict__ kout,
+    const uint32_t *__restrict__ kin, const int *__restrict__ vin, int n, const long long *__restrict__ n_dev,
+    int shift, int nb, const int *__restrict__ hist, const int *__restrict__ totals, uint32_t *__restrict__ kout,
     int *__restrict__ vout) {
+    n = items_of(n, n_dev);
     __shared__ int base[256];
     __shared__ int run[256];
     __shared__ int wcnt[4][256];
@@ -201,24 +208,61 @@ __global__ __launch_bounds__(256) void scan_final_kernel(const long long *__rest
     }
 }
 
+// Writes the (tile, id) pairs of 256 consecutive Gaussians (depth order) per block.
+// The block's pairs are dealt out evenly over its threads: pair q belongs to the
+// last Gaussian whose first pair is at or before q (binary search in LDS), so a
+// Gaussian covering hundreds of tiles does not hold up its wave.
 __global__ __launch_bounds__(256) void duplicate_kernel(int n, const int *__restrict__ order,
                                                         const long long *__restrict__ offs,
                                                         const int4 *__restrict__ rect,
                                                         const int *__restrict__ touched, int ntx,
+                                                        long long max_pairs,
                                                         uint32_t *__restrict__ tile_keys,
                                                         int *__restrict__ ids) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    int g = order[s];
-    if (touched[g] <= 0) return;
-    int4 r = rect[g];
-    long o = offs[s];
-    for (int ty = r.y; ty < r.w; ++ty)
-        for (int tx = r.x; tx < r.z; ++tx) {
-            tile_keys[o] = (uint32_t)(ty * ntx + tx);
-            ids[o] = g;
-            ++o;
+    __shared__ int s_start[256];
+    __shared__ int s_g[256];
+    __shared__ int4 s_rect[256];
+    __shared__ long long s_base;
+    __shared__ int s_total;
+    const int t = threadIdx.x;
+    const int s = blockIdx.x * 256 + t;
+    int g = -1, c = 0;
+    long long o = 0;
+    int4 r = make_int4(0, 0, 1, 1);
+    if (s < n) {
+        g = order[s];
+        c = max(touched[g], 0);
+        o = offs[s];
+        if (c > 0) r = rect[g];
+    }
+    if (t == 0) {
+        s_base = o;   // the block's first Gaussian always exists
+        s_total = 0;
+    }
+    __syncthreads();
+    const int start = s < n ? (int)(o - s_base) : 0x7FFFFFFF;
+    s_start[t] = start;
+    s_g[t] = g;
+    s_rect[t] = r;
+    if (s < n) atomicMax(&s_total, start + c);
+    __syncthreads();
+    const int total = s_total;
+    const long long base = s_base;
+    const int lim = (int)min((long long)total, max_pairs - base);   // never past the buffers
+    for (int q = t; q < lim; q += 256) {
+        int lo = 0, hi = 255;   // largest j with s_start[j] <= q
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= q) lo = mid;
+            else hi = mid - 1;
         }
+        const int4 rr = s_rect[lo];
+        const int k = q - s_start[lo];
+        const int rw = rr.z - rr.x;
+        const int ty = rr.y + k / rw, tx = rr.x + k - (k / rw) * rw;
+        tile_keys[base + q] = (uint32_t)(ty * ntx + tx);
+        ids[base + q] = s_g[lo];
+    }
 }
 
 __global__ __launch_bounds__(256) void zero_ranges_kernel(int n2, int *__restrict__ ranges) {
@@ -226,8 +270,10 @@ __global__ __launch_bounds__(256) void zero_ranges_kernel(int n2, int *__restric
     if (i < n2) ranges[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void mark_ranges_kernel(int m, const uint32_t *__restrict__ keys,
+__global__ __launch_bounds__(256) void mark_ranges_kernel(int m, const long long *__restrict__ m_dev,
+                                                          const uint32_t *__restrict__ keys,
                                                           int *__restrict__ ranges) {
+    m = items_of(m, m_dev);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     uint32_t k = keys[i];
@@ -271,13 +317,14 @@ Layout layout_of(long n, long max_pairs) {
     return L;
 }
 
-// One stable LSD pass over bits [shift, shift + 8).
+// One stable LSD pass over bits [shift, shift + 8) of n items (min(n, *n_dev) if
+// n_dev is given: the grid is sized for n).
 lgs_status radix_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int n,
-                      int shift, int *hist, int *totals, hipStream_t st) {
+                      const long long *n_dev, int shift, int *hist, int *totals, hipStream_t st) {
     int nb = (n + kSortItems - 1) / kSortItems;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, n, shift, nb, hist);
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, n, n_dev, shift, nb, hist);
     hipLaunchKernelGGL(radix_scan_digits_kernel, dim3(256), dim3(256), 0, st, hist, nb, totals);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, n, shift,
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, n, n_dev, shift,
                        nb, hist, totals, kout, vout);
     return check_launch("radix pass");
 }
@@ -303,7 +350,6 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
                                    hipStream_t stream) {
     lgs_status st = check_camera(cam);
     if (st) return st;
-    LGS_REQUIRE(n_pairs, LGS_ERR_INVALID_ARG, "n_pairs is NULL");
     LGS_REQUIRE(n >= 0 && max_pairs >= 0 && max_pairs <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG,
                 "lgs_bin_sort: bad sizes");
     LGS_REQUIRE(tile_ranges, LGS_ERR_INVALID_ARG, "tile_ranges is NULL");
@@ -312,7 +358,7 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
     if (n == 0) {
         hipLaunchKernelGGL(zero_ranges_kernel, dim3((2 * T + 255) / 256), dim3(256), 0, stream,
                            2 * T, tile_ranges);
-        *n_pairs = 0;
+        if (n_pairs) *n_pairs = 0;
         return check_launch("bin_sort zero");
     }
     LGS_REQUIRE(depth && tile_rect && tiles_touched && workspace && (sorted_ids || max_pairs == 0),
@@ -337,7 +383,7 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
     for (int pass = 0; pass < 4; ++pass) {
         bool even = (pass & 1) == 0;
         st = radix_pass(even ? dk0 : dk1, even ? dv0 : dv1, even ? dk1 : dk0, even ? dv1 : dv0, n,
-                        8 * pass, hist, totals, stream);
+                        nullptr, 8 * pass, hist, totals, stream);
         if (st) return st;
     }
     // 2. pair offsets in depth order
@@ -349,15 +395,22 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
     hipLaunchKernelGGL(scan_final_kernel, dim3(nbs), dim3(256), 0, stream, cnt, (long)n, sums, offs);
     st = check_launch("bin_sort scan");
     if (st) return st;
-    long long M = 0;
-    st = check_hip(hipMemcpyAsync(&M, total, sizeof(M), hipMemcpyDeviceToHost, stream), "pair count copy");
-    if (st) return st;
-    st = check_hip(hipStreamSynchronize(stream), "pair count sync");
-    if (st) return st;
-    *n_pairs = M;
-    if (M > max_pairs) {
-        set_error("lgs_bin_sort: %lld pairs exceed max_pairs %lld", M, (long long)max_pairs);
-        return LGS_ERR_CAPACITY;
+    // the pair count: read back once (n_pairs given), or left on the device, where the
+    // remaining launches take it from (grids sized for max_pairs)
+    long long M = max_pairs;
+    const long long *M_dev = nullptr;
+    if (n_pairs) {
+        st = check_hip(hipMemcpyAsync(&M, total, sizeof(M), hipMemcpyDeviceToHost, stream), "pair count copy");
+        if (st) return st;
+        st = check_hip(hipStreamSynchronize(stream), "pair count sync");
+        if (st) return st;
+        *n_pairs = M;
+        if (M > max_pairs) {
+            set_error("lgs_bin_sort: %lld pairs exceed max_pairs %lld", M, (long long)max_pairs);
+            return LGS_ERR_CAPACITY;
+        }
+    } else {
+        M_dev = total;
     }
     hipLaunchKernelGGL(zero_ranges_kernel, dim3((2 * T + 255) / 256), dim3(256), 0, stream, 2 * T,
                        tile_ranges);
@@ -373,16 +426,40 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
     uint32_t *kcur = pk0, *knext = pk1;
     int *vcur = (passes % 2 == 0) ? pv0 : pv1, *vnext = (passes % 2 == 0) ? pv1 : pv0;
     hipLaunchKernelGGL(duplicate_kernel, dim3(g1), dim3(256), 0, stream, n, dv0, offs,
-                       (const int4 *)tile_rect, tiles_touched, ntx, kcur, vcur);
+                       (const int4 *)tile_rect, tiles_touched, ntx, (long long)max_pairs, kcur, vcur);
     st = check_launch("bin_sort duplicate");
     if (st) return st;
     for (int pass = 0; pass < passes; ++pass) {
-        st = radix_pass(kcur, vcur, knext, vnext, (int)M, 8 * pass, hist, totals, stream);
+        st = radix_pass(kcur, vcur, knext, vnext, (int)M, M_dev, 8 * pass, hist, totals, stream);
         if (st) return st;
         uint32_t *tk = kcur; kcur = knext; knext = tk;
         int *tv = vcur; vcur = vnext; vnext = tv;
     }
     hipLaunchKernelGGL(mark_ranges_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream,
-                       (int)M, kcur, tile_ranges);
+                       (int)M, M_dev, kcur, tile_ranges);
     return check_launch("bin_sort ranges");
+}
+
+extern "C" lgs_status lgs_bin_sort_count(int32_t n, int64_t max_pairs, const void *workspace, int64_t *n_pairs,
+                                         hipStream_t stream) {
+    LGS_REQUIRE(n_pairs && workspace, LGS_ERR_INVALID_ARG, "lgs_bin_sort_count: NULL pointer");
+    LGS_REQUIRE(n >= 0 && max_pairs >= 0 && max_pairs <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG,
+                "lgs_bin_sort_count: bad sizes");
+    if (n == 0) {
+        *n_pairs = 0;
+        return LGS_OK;
+    }
+    const Layout L = layout_of(n, max_pairs);
+    long long M = 0;
+    lgs_status st = check_hip(hipMemcpyAsync(&M, (const char *)workspace + L.total, sizeof(M),
+                                             hipMemcpyDeviceToHost, stream), "pair count copy");
+    if (st) return st;
+    st = check_hip(hipStreamSynchronize(stream), "pair count sync");
+    if (st) return st;
+    *n_pairs = M;
+    if (M > max_pairs) {
+        set_error("lgs_bin_sort: %lld pairs exceed max_pairs %lld", M, (long long)max_pairs);
+        return LGS_ERR_CAPACITY;
+    }
+    return LGS_OK;
 }

@@ -59,6 +59,7 @@ _SIG = {
     "lgs_bin_sort_workspace": [_I32, _I32, _I32, _I64, ctypes.POINTER(ctypes.c_size_t)],
     "lgs_bin_sort": [_CAM, _I32, _P, _P, _P, _P, ctypes.c_size_t, _I64, _P, _P,
                      ctypes.POINTER(ctypes.c_int64), _P],
+    "lgs_bin_sort_count": [_I32, _I64, _P, ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_rasterize_topk_fwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P],
     "lgs_feature_render_fwd": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
@@ -139,11 +140,22 @@ def lgs_bin_sort_workspace(n, width, height, max_pairs):
 
 
 def lgs_bin_sort(cam, n, depth, tile_rect, tiles_touched, workspace, ws_bytes, max_pairs,
-                 sorted_ids, tile_ranges, stream=None):
-    """Returns (status, n_pairs); LGS_ERR_CAPACITY is returned, not raised."""
+                 sorted_ids, tile_ranges, stream=None, sync=True):
+    """Returns (status, n_pairs); LGS_ERR_CAPACITY is returned, not raised.  With
+    sync=False the C call gets n_pairs = NULL and n_pairs is returned as None."""
     m = ctypes.c_int64(0)
     st = load().lgs_bin_sort(ctypes.byref(cam), n, depth, tile_rect, tiles_touched, workspace,
-                             ws_bytes, max_pairs, sorted_ids, tile_ranges, ctypes.byref(m), stream)
+                             ws_bytes, max_pairs, sorted_ids, tile_ranges,
+                             ctypes.byref(m) if sync else None, stream)
+    if st != LGS_ERR_CAPACITY:
+        _check(st)
+    return st, (m.value if sync else None)
+
+
+def lgs_bin_sort_count(n, max_pairs, workspace, stream=None):
+    """Returns (status, n_pairs); LGS_ERR_CAPACITY is returned, not raised."""
+    m = ctypes.c_int64(0)
+    st = load().lgs_bin_sort_count(n, max_pairs, workspace, ctypes.byref(m), stream)
     if st != LGS_ERR_CAPACITY:
         _check(st)
     return st, m.value

@@ -33,13 +33,21 @@ def _need_cuda(*ts):
 
 
 class Binner:
-    """Reusable workspace and pair buffer for lgs_bin_sort; grows on demand."""
+    """Reusable workspace and pair buffer for lgs_bin_sort; grows on demand.
 
-    def __init__(self, device="cuda"):
+    sync=False keeps the pair count on the device after the first call (which sizes
+    the buffers with a margin): no host round trip per frame, so the host can queue
+    the rest of the frame.  `count()` reads the count of the last call and tells
+    whether it fitted; a call that did not fit must be repeated after `count()` grew
+    the buffers."""
+
+    def __init__(self, device="cuda", sync=True):
         self.device = device
+        self.sync = sync
         self.cap = 0
         self.ws = None
         self.ids = None
+        self.n = 0
 
     def _ensure(self, n, W, H, cap):
         need = lgs.lgs_bin_sort_workspace(n, W, H, cap)
@@ -48,19 +56,37 @@ class Binner:
         if self.ids is None or self.ids.numel() < max(cap, 1):
             self.ids = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
         self.cap = cap
+        self.dims = (W, H)
 
     def __call__(self, cam, n, depth, tile_rect, touched):
         ntiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
         ranges = torch.empty(ntiles * 2, dtype=torch.int32, device=self.device)
+        first = self.cap == 0 or self.n != n
         if self.cap == 0:
             self._ensure(n, cam.width, cam.height, max(4 * n, 1 << 16))
+        self.n = n
+        if not self.sync and not first:
+            lgs.lgs_bin_sort(cam, n, _p(depth), _p(tile_rect), _p(touched), _p(self.ws), self.ws.numel(),
+                             self.cap, _p(self.ids), _p(ranges), _stream(), sync=False)
+            return self.ids, ranges.view(ntiles, 2), None
         while True:
             ws = self.ws
             st, m = lgs.lgs_bin_sort(cam, n, _p(depth), _p(tile_rect), _p(touched), _p(ws),
                                      ws.numel(), self.cap, _p(self.ids), _p(ranges), _stream())
             if st == lgs.LGS_OK:
+                if not self.sync and m * 3 > self.cap * 2:
+                    # room for frames that bring up to half as many pairs again
+                    self._ensure(n, cam.width, cam.height, int(m * 1.5) + 4096)
                 return self.ids[:m], ranges.view(ntiles, 2), m
-            self._ensure(n, cam.width, cam.height, int(m * 1.25) + 4096)
+            self._ensure(n, cam.width, cam.height, int(m * 1.5) + 4096)
+
+    def count(self):
+        """(pair count, fitted) of the last call; grows the buffers if it did not fit."""
+        st, m = lgs.lgs_bin_sort_count(self.n, self.cap, _p(self.ws), _stream())
+        if st != lgs.LGS_OK:
+            self._ensure(self.n, self.dims[0], self.dims[1], int(m * 1.5) + 4096)
+            return m, False
+        return m, True
 
 
 def project(cam, P):

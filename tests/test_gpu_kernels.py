@@ -84,22 +84,29 @@ def test_project_parity(torch, orc, cfg):
     assert np.all(rect[has, 2] * 16 > orect[has, 2]) and np.all(rect[has, 3] * 16 > orect[has, 3])
 
 
-@pytest.mark.parametrize("n,W,H,seed", [(1, 16, 16, 0), (1000, 64, 48, 1), (20000, 640, 480, 2),
-                                        (100000, 1200, 680, 3)])
-def test_bin_sort_matches_lexsort(torch, n, W, H, seed):
-    """Synthetic rects and depth keys (with deliberate ties): the pairs must come out
-    ordered by (tile, depth key, id), exactly as numpy's lexsort orders them."""
-    from paper_2602_06991_amd import lgs, render
+def _synthetic_bins(n, W, H, seed, big):
     rng = np.random.default_rng(seed)
     ntx, nty = (W + 15) // 16, (H + 15) // 16
     tx0 = rng.integers(0, ntx, n)
     ty0 = rng.integers(0, nty, n)
-    tx1 = np.minimum(tx0 + rng.integers(1, 4, n), ntx)
-    ty1 = np.minimum(ty0 + rng.integers(1, 4, n), nty)
+    wide = rng.random(n) < big                             # a few Gaussians cover many tiles
+    tx1 = np.minimum(tx0 + np.where(wide, rng.integers(1, 40, n), rng.integers(1, 4, n)), ntx)
+    ty1 = np.minimum(ty0 + np.where(wide, rng.integers(1, 30, n), rng.integers(1, 4, n)), nty)
     touched = ((tx1 - tx0) * (ty1 - ty0)).astype(np.int32)
     touched[rng.random(n) < 0.2] = 0                       # culled
     depth = rng.choice(rng.uniform(0.3, 9.0, max(n // 3, 1)).astype(np.float32), n)  # many ties
     rect = np.stack([tx0, ty0, tx1, ty1], 1).astype(np.int32)
+    return ntx, nty, tx0, ty0, tx1, ty1, touched, depth, rect
+
+
+@pytest.mark.parametrize("n,W,H,seed,big", [(1, 16, 16, 0, 0.0), (1000, 64, 48, 1, 0.0),
+                                            (20000, 640, 480, 2, 0.0), (100000, 1200, 680, 3, 0.0),
+                                            (50000, 1200, 680, 4, 0.01)])
+def test_bin_sort_matches_lexsort(torch, n, W, H, seed, big):
+    """Synthetic rects and depth keys (with deliberate ties): the pairs must come out
+    ordered by (tile, depth key, id), exactly as numpy's lexsort orders them."""
+    from paper_2602_06991_amd import lgs, render
+    ntx, nty, tx0, ty0, tx1, ty1, touched, depth, rect = _synthetic_bins(n, W, H, seed, big)
     cam = lgs.lgs_camera()
     cam.width, cam.height, cam.fx, cam.fy = W, H, 1.0, 1.0
     tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -125,6 +132,38 @@ def test_bin_sort_matches_lexsort(torch, n, W, H, seed):
     np.testing.assert_array_equal(r[:, 1] - r[:, 0], cnt)
     starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])
     np.testing.assert_array_equal(r[cnt > 0, 0], starts[cnt > 0])
+
+
+def test_bin_sort_without_host_round_trip(torch):
+    """The asynchronous mode (count left on the device) bins exactly as the synchronous
+    one; a buffer that is too small is reported by the count query, and the call stays
+    inside its buffers."""
+    from paper_2602_06991_amd import lgs, render
+    n, W, H = 60000, 1200, 680
+    ntx, nty, tx0, ty0, tx1, ty1, touched, depth, rect = _synthetic_bins(n, W, H, 9, 0.005)
+    cam = lgs.lgs_camera()
+    cam.width, cam.height, cam.fx, cam.fy = W, H, 1.0, 1.0
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (cam, n, tt(depth), tt(rect), tt(touched))
+    ids0, r0, m = render.Binner()(*args)
+    b = render.Binner(sync=False)
+    _, _, m1 = b(*args)                                      # the first call sizes the buffers
+    ids, r, none = b(*args)
+    assert m1 == m and none is None
+    assert b.count() == (m, True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.cpu().numpy(), r0.cpu().numpy())
+    np.testing.assert_array_equal(ids[:m].cpu().numpy(), ids0.cpu().numpy())
+    # too small: the count says so and the next call (after count() grew the buffers) fits
+    b._ensure(n, W, H, m // 2)
+    guard = torch.full((b.cap + 4096,), -7, dtype=torch.int32, device="cuda")
+    b.ids = guard
+    b(*args)
+    assert b.count() == (m, False)
+    assert int(guard[m // 2:].ne(-7).sum()) == 0            # nothing past max_pairs
+    ids, r, _ = b(*args)
+    assert b.count() == (m, True)
+    np.testing.assert_array_equal(r.cpu().numpy(), r0.cpu().numpy())
 
 
 def _oracle_topk(orc, g, cam, K):
