@@ -1,9 +1,9 @@
 // Per-tile alpha blending of colour, depth and opacity (Eq. 1) that keeps each
 // pixel's K largest blending weights in registers (Eq. 2; recorded during the same
 // pass, Sec. 3.2), and its adjoint replayed back to front from the saved final
-// transmittance.  One 256-thread block per 16x16 tile, one thread per pixel; the
-// tile's depth-sorted Gaussians are staged through LDS in batches (256 forward,
-// 32 backward).
+// transmittance.  One block per 16x16 tile: 256 threads and one pixel each in the
+// forward, 128 threads and two pixels each in the adjoint; the tile's depth-sorted
+// Gaussians are staged through LDS in batches (256 forward, 32 backward).
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
@@ -131,8 +131,14 @@ __device__ __forceinline__ void row_sum_many(float (&v)[N]) {
     for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x140>(v[q]);
 }
 
+// The adjoint gives each thread kPPT pixels of the tile, (x, y + j 16 / kPPT), so the
+// per-Gaussian row sums and their LDS traffic serve 16 kPPT pixels per lane row.
+constexpr int kPPT = 2;
+constexpr int kBwdThreads = 256 / kPPT;
+constexpr int kBwdRows = kBwdThreads / 16;   // lane rows of 16 per block
+
 template <int K>
-__global__ __launch_bounds__(256) void raster_bwd_kernel(
+__global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
     RasterArgs a, const float *__restrict__ T_final, const int *__restrict__ n_contrib,
     const int *__restrict__ topk_ids, const float *__restrict__ dL_dtopkw,
     const float *__restrict__ dL_dcolor, const float *__restrict__ dL_ddepth,
@@ -142,46 +148,54 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
     __shared__ float2 s_xy[kRB];
     __shared__ float4 s_co[kRB];
     __shared__ float4 s_cz[kRB];
-    __shared__ __align__(16) float s_part[16][kRB][kNGP];   // [pixel row of the tile][Gaussian][slot]
+    __shared__ __align__(16) float s_part[kBwdRows][kRB][kNGP];   // [lane row][Gaussian][slot]
     __shared__ int s_max;
     const int ntiles = a.ntx * a.nty;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     const int t = threadIdx.x;
-    const int wave = t >> 6;
-    const int px = (tile % a.ntx) * kTile + (t & 15);
-    const int py = (tile / a.ntx) * kTile + (t >> 4);
-    const bool inside = px < a.W && py < a.H;
-    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const int2 rg = a.ranges[tile];
-    const long p = (long)py * a.W + px;
+    const int px = (tile % a.ntx) * kTile + (t & 15);
+    const int py0 = (tile / a.ntx) * kTile + (t >> 4);
 
-    float T = 1.0f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gO = 0.f;
-    int last = 0;
-    int ti[K];
-    float gam[K];
+    // per-pixel state of the thread's kPPT pixels
+    float fy[kPPT], T[kPPT], gC0[kPPT], gC1[kPPT], gC2[kPPT], gD[kPPT], gO[kPPT], A[kPPT];
+    int last[kPPT];
+    int ti[kPPT][K];
+    float gam[kPPT][K];
+    const float fx = (float)px + 0.5f;
+    int lmax = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) { ti[k] = -1; gam[k] = 0.f; }
-    if (inside) {
-        T = T_final[p];
-        last = n_contrib[p];
-        gC0 = dL_dcolor[3 * p];
-        gC1 = dL_dcolor[3 * p + 1];
-        gC2 = dL_dcolor[3 * p + 2];
-        gD = dL_ddepth[p];
-        gO = dL_dalpha ? dL_dalpha[p] : 0.f;
+    for (int h = 0; h < kPPT; ++h) {
+        const int py = py0 + (16 / kPPT) * h;
+        fy[h] = (float)py + 0.5f;
+        T[h] = 1.0f; gC0[h] = gC1[h] = gC2[h] = gD[h] = gO[h] = A[h] = 0.f;
+        last[h] = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            ti[k] = topk_ids[p * K + k];
-            gam[k] = dL_dtopkw ? dL_dtopkw[p * K + k] : 0.f;
+        for (int k = 0; k < K; ++k) { ti[h][k] = -1; gam[h][k] = 0.f; }
+        if (px < a.W && py < a.H) {
+            const long p = (long)py * a.W + px;
+            T[h] = T_final[p];
+            last[h] = n_contrib[p];
+            gC0[h] = dL_dcolor[3 * p];
+            gC1[h] = dL_dcolor[3 * p + 1];
+            gC2[h] = dL_dcolor[3 * p + 2];
+            gD[h] = dL_ddepth[p];
+            gO[h] = dL_dalpha ? dL_dalpha[p] : 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                ti[h][k] = topk_ids[p * K + k];
+                gam[h][k] = dL_dtopkw ? dL_dtopkw[p * K + k] : 0.f;
+            }
         }
     }
     if (t == 0) s_max = 0;
     __syncthreads();
-    atomicMax(&s_max, last);
+#pragma unroll
+    for (int h = 0; h < kPPT; ++h) lmax = max(lmax, last[h]);
+    atomicMax(&s_max, lmax);
     __syncthreads();
     const int maxl = s_max;
-    float A = 0.0f;   // sum over later blended Gaussians of e_j w_j
     for (int hi = maxl; hi > 0; hi -= kRB) {
         const int lo = hi > kRB ? hi - kRB : 0;
         const int cnt = hi - lo;
@@ -199,40 +213,41 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
 #pragma unroll
             for (int q = 0; q < kNG; ++q) v[q] = 0.f;
             bool hit = false;
-            if (lo + j < last) {
-                float2 m = s_xy[j];
-                float4 co = s_co[j];
-                float dx, dy, raw, ex;
-                float alpha = blend_alpha(fx, fy, m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
-                if (alpha >= kAlphaMin) {
-                    hit = true;
-                    const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
-                    T *= r;                         // transmittance in front of this Gaussian
-                    const float w = alpha * T;
-                    const float4 cz = s_cz[j];
-                    const int g = s_id[j];
-                    float e = gC0 * cz.x + gC1 * cz.y + gC2 * cz.z + gD * cz.w + gO;
+            const float2 m = s_xy[j];
+            const float4 co = s_co[j];
 #pragma unroll
-                    for (int k = 0; k < K; ++k) e += (ti[k] == g) ? gam[k] : 0.f;
-                    const float dal = T * e - A * r;
-                    A = fmaf(e, w, A);
-                    v[5] = w * gC0;
-                    v[6] = w * gC1;
-                    v[7] = w * gC2;
-                    v[8] = w * gD;
-                    if (raw <= kAlphaMax) {       // unclamped: alpha = o e^-sigma
-                        const float ds = -alpha * dal;
-                        v[0] = -ds * (co.x * dx + co.y * dy);
-                        v[1] = -ds * (co.y * dx + co.z * dy);
-                        v[2] = ds * 0.5f * dx * dx;
-                        v[3] = ds * dx * dy;
-                        v[4] = ds * 0.5f * dy * dy;
-                        v[9] = dal * ex;
-                    }
+            for (int h = 0; h < kPPT; ++h) {
+                if (lo + j >= last[h]) continue;
+                float dx, dy, raw, ex;
+                const float alpha = blend_alpha(fx, fy[h], m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
+                if (alpha < kAlphaMin) continue;
+                hit = true;
+                const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
+                T[h] *= r;                          // transmittance in front of this Gaussian
+                const float w = alpha * T[h];
+                const float4 cz = s_cz[j];
+                const int g = s_id[j];
+                float e = gC0[h] * cz.x + gC1[h] * cz.y + gC2[h] * cz.z + gD[h] * cz.w + gO[h];
+#pragma unroll
+                for (int k = 0; k < K; ++k) e += (ti[h][k] == g) ? gam[h][k] : 0.f;
+                const float dal = T[h] * e - A[h] * r;
+                A[h] = fmaf(e, w, A[h]);
+                v[5] += w * gC0[h];
+                v[6] += w * gC1[h];
+                v[7] += w * gC2[h];
+                v[8] += w * gD[h];
+                if (raw <= kAlphaMax) {             // unclamped: alpha = o e^-sigma
+                    const float ds = -alpha * dal;
+                    v[0] += -ds * (co.x * dx + co.y * dy);
+                    v[1] += -ds * (co.y * dx + co.z * dy);
+                    v[2] += ds * 0.5f * dx * dx;
+                    v[3] += ds * dx * dy;
+                    v[4] += ds * 0.5f * dy * dy;
+                    v[9] += dal * ex;
                 }
             }
-            // sums over each 16-pixel row of the tile (every lane takes part); the
-            // row's first lane files them, and the 16 row sums meet after the batch
+            // sums over each lane row (16 lanes, 16 kPPT pixels; every lane takes part); the
+            // row's first lane files them, and the row sums meet after the batch
             if (__ballot(hit) != 0ull) row_sum_many<kNG>(v);
             if ((t & 15) == 0) {
                 float *dst = s_part[t >> 4][j];
@@ -242,12 +257,12 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(
             }
         }
         __syncthreads();
-        // per Gaussian and slot: the 16 row sums in a fixed order, one atomic
-        for (int o = t; o < cnt * kNG; o += 256) {
+        // per Gaussian and slot: the row sums in a fixed order, one atomic
+        for (int o = t; o < cnt * kNG; o += kBwdThreads) {
             const int j = o / kNG, q = o - j * kNG;
             float sum = 0.f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) sum += s_part[r][j][q];
+            for (int r = 0; r < kBwdRows; ++r) sum += s_part[r][j][q];
             if (sum == 0.f) continue;
             const int g = s_id[j];
             float *dst = q < 2 ? &g_mean2d[2 * g + q]
@@ -271,7 +286,7 @@ void launch_bwd(RasterArgs a, const float *T_final, const int *n_contrib, const 
                 const float *dL_dtopkw, const float *dL_dcolor, const float *dL_ddepth,
                 const float *dL_dalpha, float *gm, float *gc, float *go, float *grgb, float *gz,
                 hipStream_t st) {
-    hipLaunchKernelGGL(raster_bwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(256), 0,
+    hipLaunchKernelGGL(raster_bwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(kBwdThreads), 0,
                        st, a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha,
                        gm, gc, go, grgb, gz);
 }
