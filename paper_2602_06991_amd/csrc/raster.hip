@@ -1,9 +1,9 @@
 // Per-tile alpha blending of colour, depth and opacity (Eq. 1) that keeps each
 // pixel's K largest blending weights in registers (Eq. 2; recorded during the same
 // pass, Sec. 3.2), and its adjoint replayed back to front from the saved final
-// transmittance.  One block per 16x16 tile: 256 threads and one pixel each in the
-// forward, 128 threads and two pixels each in the adjoint; the tile's depth-sorted
-// Gaussians are staged through LDS in batches (256 forward, 32 backward).
+// transmittance.  One block of 128 threads per 16x16 tile, two pixels per thread
+// (rows y and y + 8); the tile's depth-sorted Gaussians are staged through LDS in
+// batches (256 forward, 32 backward).
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
@@ -37,14 +37,18 @@ __device__ __forceinline__ void topk_insert(float (&tw)[K], int (&ti)[K], float 
     }
 }
 
+// The forward gives each thread two pixels of the tile, (x, y) and (x, y + 8): the
+// Gaussian's LDS records are read once for both.
+constexpr int kFwdThreads = 128;
+
 template <int K>
-__global__ __launch_bounds__(256) void raster_fwd_kernel(RasterArgs a, float *__restrict__ color,
-                                                         float *__restrict__ depth_map,
-                                                         float *__restrict__ alpha_map,
-                                                         float *__restrict__ T_final,
-                                                         int *__restrict__ n_contrib,
-                                                         int *__restrict__ topk_ids,
-                                                         float *__restrict__ topk_w) {
+__global__ __launch_bounds__(kFwdThreads) void raster_fwd_kernel(RasterArgs a, float *__restrict__ color,
+                                                                 float *__restrict__ depth_map,
+                                                                 float *__restrict__ alpha_map,
+                                                                 float *__restrict__ T_final,
+                                                                 int *__restrict__ n_contrib,
+                                                                 int *__restrict__ topk_ids,
+                                                                 float *__restrict__ topk_w) {
     __shared__ int s_id[256];
     __shared__ float2 s_xy[256];
     __shared__ float4 s_co[256];   // conic a, b, c, opacity
@@ -54,61 +58,79 @@ __global__ __launch_bounds__(256) void raster_fwd_kernel(RasterArgs a, float *__
     if (tile >= ntiles) return;
     const int t = threadIdx.x;
     const int px = (tile % a.ntx) * kTile + (t & 15);
-    const int py = (tile / a.ntx) * kTile + (t >> 4);
-    const bool inside = px < a.W && py < a.H;
-    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int py0 = (tile / a.ntx) * kTile + (t >> 4);
+    const float fx = (float)px + 0.5f;
     const int2 rg = a.ranges[tile];
-    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, Dz = 0.f;
-    int last = 0;
-    float tw[K];
-    int ti[K];
+    float fy[2], T[2], C0[2], C1[2], C2[2], Dz[2];
+    int last[2];
+    bool done[2];
+    float tw[2][K];
+    int ti[2][K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) { tw[k] = 0.0f; ti[k] = -1; }
-    bool done = !inside;
+    for (int h = 0; h < 2; ++h) {
+        const int py = py0 + 8 * h;
+        fy[h] = (float)py + 0.5f;
+        T[h] = 1.0f; C0[h] = C1[h] = C2[h] = Dz[h] = 0.f;
+        last[h] = 0;
+        done[h] = !(px < a.W && py < a.H);
+#pragma unroll
+        for (int k = 0; k < K; ++k) { tw[h][k] = 0.0f; ti[h][k] = -1; }
+    }
     for (int base = rg.x; base < rg.y; base += 256) {
-        if (__syncthreads_count(done) == 256) break;
-        int idx = base + t;
-        if (idx < rg.y) {
-            int g = a.sorted_ids[idx];
-            s_id[t] = g;
-            s_xy[t] = a.mean2d[g];
-            s_co[t] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
-            s_cz[t] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[g]);
+        if (__syncthreads_count(done[0] && done[1]) == kFwdThreads) break;
+        for (int idx = base + t; idx < min(base + 256, rg.y); idx += kFwdThreads) {
+            const int g = a.sorted_ids[idx];
+            const int q = idx - base;
+            s_id[q] = g;
+            s_xy[q] = a.mean2d[g];
+            s_co[q] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
+            s_cz[q] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[g]);
         }
         __syncthreads();
         const int cnt = min(256, rg.y - base);
-        for (int j = 0; j < cnt && !done; ++j) {
-            float2 m = s_xy[j];
-            float4 co = s_co[j];
-            float dx, dy, raw, ex;
-            float alpha = blend_alpha(fx, fy, m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
-            if (alpha < kAlphaMin) continue;
-            float nT = T * (1.0f - alpha);
-            if (nT < kTMin) { done = true; break; }
-            float w = alpha * T;
-            float4 cz = s_cz[j];
-            C0 = fmaf(cz.x, w, C0);
-            C1 = fmaf(cz.y, w, C1);
-            C2 = fmaf(cz.z, w, C2);
-            Dz = fmaf(cz.w, w, Dz);
-            T = nT;
-            last = base + j - rg.x + 1;
-            topk_insert<K>(tw, ti, w, s_id[j]);
+        for (int j = 0; j < cnt && !(done[0] && done[1]); ++j) {
+            const float2 m = s_xy[j];
+            const float4 co = s_co[j];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (done[h]) continue;
+                float dx, dy, raw, ex;
+                const float alpha = blend_alpha(fx, fy[h], m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
+                if (alpha < kAlphaMin) continue;
+                const float nT = T[h] * (1.0f - alpha);
+                if (nT < kTMin) {
+                    done[h] = true;
+                    continue;
+                }
+                const float w = alpha * T[h];
+                const float4 cz = s_cz[j];
+                C0[h] = fmaf(cz.x, w, C0[h]);
+                C1[h] = fmaf(cz.y, w, C1[h]);
+                C2[h] = fmaf(cz.z, w, C2[h]);
+                Dz[h] = fmaf(cz.w, w, Dz[h]);
+                T[h] = nT;
+                last[h] = base + j - rg.x + 1;
+                topk_insert<K>(tw[h], ti[h], w, s_id[j]);
+            }
         }
     }
-    if (!inside) return;
-    const long p = (long)py * a.W + px;
-    color[3 * p] = C0;
-    color[3 * p + 1] = C1;
-    color[3 * p + 2] = C2;
-    depth_map[p] = Dz;
-    alpha_map[p] = 1.0f - T;
-    T_final[p] = T;
-    n_contrib[p] = last;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        topk_ids[p * K + k] = ti[k];
-        topk_w[p * K + k] = tw[k];
+    for (int h = 0; h < 2; ++h) {
+        const int py = py0 + 8 * h;
+        if (!(px < a.W && py < a.H)) continue;
+        const long p = (long)py * a.W + px;
+        color[3 * p] = C0[h];
+        color[3 * p + 1] = C1[h];
+        color[3 * p + 2] = C2[h];
+        depth_map[p] = Dz[h];
+        alpha_map[p] = 1.0f - T[h];
+        T_final[p] = T[h];
+        n_contrib[p] = last[h];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            topk_ids[p * K + k] = ti[h][k];
+            topk_w[p * K + k] = tw[h][k];
+        }
     }
 }
 
@@ -277,7 +299,7 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
 template <int K>
 void launch_fwd(RasterArgs a, float *color, float *depth_map, float *alpha_map, float *T_final,
                 int *n_contrib, int *topk_ids, float *topk_w, hipStream_t st) {
-    hipLaunchKernelGGL(raster_fwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(256), 0,
+    hipLaunchKernelGGL(raster_fwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(kFwdThreads), 0,
                        st, a, color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w);
 }
 
