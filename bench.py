@@ -6,9 +6,12 @@ table stored in BF16 (FP32 accumulation) and, for comparison, the plain FP32 for
 
 One step = one pass of the whole hot path over one frame:
   quantize the FP32 master features to the storage format (BF16 form only),
-  project -> bin + sort -> blend with Top-K -> feature render,
+  project -> bin + sort -> blend with Top-K,
   L1 loss gradients of colour and depth against a target frame,
-  zero the gradient buffers, feature adjoint fused with the feature L1 loss gradient
+  zero the gradient buffers,
+  feature render + its adjoint under the feature L1 loss, in one pass that stores the
+  map and differentiates it (--feature-path separate: the render, then the adjoint
+  with the loss gradient formed inside it, as two launches),
   -> blend adjoint -> projection adjoint.
 All inputs are resident in HBM before timing starts.
 
@@ -43,6 +46,8 @@ def parse():
     ap.add_argument("--sweep", action="store_true", help="also time K = 1 and 8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bf16,f32")
+    ap.add_argument("--feature-path", choices=("fused", "separate"), default="fused",
+                    help="feature render and adjoint in one launch (fused) or two")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy three times (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -52,8 +57,9 @@ def parse():
 class Step:
     """All buffers of one frame's forward + backward, reused across steps."""
 
-    def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form):
+    def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form, fused=True):
         self.t, self.render, self.lgs = torch, render, lgs
+        self.fused = fused
         self.P, self.target, self.cam, self.K, self.form = scene_dev, target, cam, K, form
         self.map = "f32" if form == "f32" else "bf16"
         self.binner = render.Binner(sync=False)   # no host round trip inside the step
@@ -88,8 +94,9 @@ class Step:
         self._mark("bin_sort")
         fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges)
         self._mark("rasterize_topk_fwd")
-        F = r.feature_fwd(fw["ids"], fw["w"], store, scale, self.form, self.map)
-        self._mark("feature_render_fwd")
+        if not self.fused:
+            F = r.feature_fwd(fw["ids"], fw["w"], store, scale, self.form, self.map)
+            self._mark("feature_render_fwd")
         tC, tD, tF = self.target
         gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
         gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
@@ -104,18 +111,23 @@ class Step:
         if self.kmarks is not None:
             ka = self.t.cuda.Event(enable_timing=True)
             ka.record()
-        dtw = r.feature_bwd_l1(fw["ids"], fw["w"], store, scale, self.form, self.map, tF,
-                               1.0 / (self.npix * self.d), self.dfeat)
+        fscale = 1.0 / (self.npix * self.d)
+        if self.fused:
+            F, dtw = r.feature_fwd_bwd_l1(fw["ids"], fw["w"], store, scale, self.form, self.map, tF, fscale,
+                                          self.dfeat)
+        else:
+            dtw = r.feature_bwd_l1(fw["ids"], fw["w"], store, scale, self.form, self.map, tF, fscale,
+                                   self.dfeat)
         if self.kmarks is not None:
             kb = self.t.cuda.Event(enable_timing=True)
             kb.record()
             self.kmarks.append((ka, kb))
-        self._mark("feature_render_bwd")
+        self._mark("feature_render_fwd_bwd" if self.fused else "feature_render_bwd")
         r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg)
         self._mark("rasterize_topk_bwd")
         r.project_bwd(c, P, self.sg, self.pg)
         self._mark("project_bwd")
-        self.last = dict(fw=fw, pairs=m, F=F)
+        self.last = dict(fw=fw, pairs=m, F=F, store=store, scale=scale)
 
 
 def time_steps(torch, step, steps, warmup):
@@ -184,9 +196,44 @@ def tile_union_stats(ids, W, H):
 
 
 def feature_bytes(npix, K, D, U, s_map, s_f, fp8):
-    fwd = npix * D * s_map + 8 * npix * K + U * D * s_f + (4 * U if fp8 else 0)
-    bwd = npix * D * s_map + 12 * npix * K + U * D * (s_f + 4) + (4 * U if fp8 else 0)
-    return fwd, bwd
+    """Algorithmic HBM bytes of the feature render, of its L1 adjoint, and of both in
+    one pass (map written and target read; ids and w read once, dL/dw written; the
+    union's rows read and their gradient rows written; FP8 row scales)."""
+    sc = 4 * U if fp8 else 0
+    fwd = npix * D * s_map + 8 * npix * K + U * D * s_f + sc
+    bwd = npix * D * s_map + 12 * npix * K + U * D * (s_f + 4) + sc
+    both = 2 * npix * D * s_map + 12 * npix * K + U * D * (s_f + 4) + sc
+    return fwd, bwd, both
+
+
+def feature_ms(phases):
+    if "feature_render_fwd_bwd" in phases:
+        return phases["feature_render_fwd_bwd"]
+    return phases["feature_render_fwd"] + phases["feature_render_bwd"]
+
+
+def separate_feature_ms(torch, render, fw, store, scale, form, mp, target, d, n, reps=10):
+    """The render and the L1 adjoint as two launches (for comparison with the one-pass
+    kernel), each timed alone with HIP events over `reps` launches."""
+    dfeat = torch.zeros(n, d, device="cuda")
+    fs = 1.0 / (fw["ids"].shape[0] * fw["ids"].shape[1] * d)
+    runs = {"feature_render_fwd": lambda: render.feature_fwd(fw["ids"], fw["w"], store, scale, form, mp),
+            "feature_render_bwd_l1": lambda: render.feature_bwd_l1(fw["ids"], fw["w"], store, scale, form, mp,
+                                                                   target, fs, dfeat)}
+    out = {}
+    for name, fn in runs.items():
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = round(a.elapsed_time(b) / reps, 4)
+    del dfeat
+    return out
 
 
 def cpu_baseline(scene, K, form):
@@ -257,7 +304,8 @@ def main():
         tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp)
         target = (tfw["C"].clone(), tfw["D"].clone(), tF.clone())
         del tproj, tb, tids, tranges, tfw, tstore, tscale, tF
-        step = Step(torch, render, lgs, P, target, cam, K, form)
+        fused = args.feature_path == "fused"
+        step = Step(torch, render, lgs, P, target, cam, K, form, fused)
         ms, phases, kern_ms = time_steps(torch, step, args.steps, args.warmup)
         pairs, fitted = step.binner.count()
         assert fitted, "pair buffer overflowed during timing"
@@ -267,9 +315,11 @@ def main():
         npix = cam.width * cam.height
         s_map = 4 if mp == "f32" else 2
         s_f = {"f32": 4, "bf16": 2, "fp8": 1}[form]
-        bf, bb = feature_bytes(npix, K, cfg["D"], U, s_map, s_f, form == "fp8")
+        bf, bb, b2 = feature_bytes(npix, K, cfg["D"], U, s_map, s_f, form == "fp8")
+        sep = separate_feature_ms(torch, render, fw, step.last["store"], step.last["scale"], form, mp,
+                                  target[2], cfg["D"], P["feat"].shape[0])
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
-                             bytes_fwd=bf, bytes_bwd=bb,
+                             bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
                              tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
         print(f"# {form}: {ms:.3f} ms/step, U={U}, pairs={step.last['pairs']}, phases "
               + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()), file=sys.stderr, flush=True)
@@ -288,28 +338,29 @@ def main():
                 tstore, tscale = render.quantize(PT["feat"], form)
                 tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp)
                 step = Step(torch, render, lgs, P, (tfw["C"].clone(), tfw["D"].clone(), tF.clone()), cam,
-                            k2, form)
+                            k2, form, args.feature_path == "fused")
                 ms, ph, _ = time_steps(torch, step, max(5, args.steps // 2), 2)
                 assert step.binner.count()[1], "pair buffer overflowed during timing"
-                sweep[f"K{k2}_{form}"] = dict(ms_per_frame=round(ms, 4),
-                                              feature_fwd_bwd_ms=round(ph["feature_render_fwd"] +
-                                                                       ph["feature_render_bwd"], 4))
+                sweep[f"K{k2}_{form}"] = dict(ms_per_frame=round(ms, 4), feature_fwd_bwd_ms=round(feature_ms(ph), 4))
                 del step
                 torch.cuda.empty_cache()
 
     main_form = forms[0]
     R = results[main_form]
     ph = R["phases"]
-    # dominant kernel of the feature path (HBM-bound): the feature adjoint, timed by the
-    # HIP events around it inside the timed steps
-    kern = "feature_render_bwd"
-    kbytes = R["bytes_bwd"]
+    # dominant kernel of the feature path (HBM-bound): the one-pass render + adjoint (or
+    # the adjoint alone with --feature-path separate), timed by the HIP events around it
+    # inside the timed steps
+    mode = 2 if R["fused"] else 1
+    kern = "feature_render_fwd_bwd_l1" if R["fused"] else "feature_render_bwd_l1"
+    kbytes = R["bytes_both"] if R["fused"] else R["bytes_bwd"]
     achieved = kbytes / (R["kern_ms"] * 1e-3) / 1e9
-    kname = f"feature_bwd_kernel<{K}, 1, 1, true>" if main_form == "bf16" else f"feature_bwd_kernel<{K}, 0, 0, true>"
+    ft = {"bf16": "1, 1", "f32": "0, 0", "fp8": "2, 1"}[main_form]
+    kname = f"feature_bwd_kernel<{K}, {ft}, {mode}>"
     t = counter_traffic(kname, args.config == 2 and K == 4 and main_form == "bf16")
     traffic = None if t is None else t["total"]
-    feat_ms = ph["feature_render_fwd"] + ph["feature_render_bwd"]
-    feat_gbs = (R["bytes_fwd"] + R["bytes_bwd"]) / (feat_ms * 1e-3) / 1e9
+    feat_ms = feature_ms(ph)
+    feat_gbs = (R["bytes_both"] if R["fused"] else R["bytes_fwd"] + R["bytes_bwd"]) / (feat_ms * 1e-3) / 1e9
     line = {
         "metric": "Top-K feature render fwd+bwd ms/frame + HBM GB/s, BF16 vs FP32, D=512, 1 GPU",
         "value": round(R["ms"], 4),
@@ -330,9 +381,10 @@ def main():
         "feature_fwd_bwd_ms": round(feat_ms, 4),
         "feature_fwd_bwd_GBps": round(feat_gbs, 1),
         "feature_fwd_bwd_hbm_frac": round(feat_gbs / HBM_PEAK_GBS, 4),
+        "feature_path": args.feature_path,
         "forms": {k: {"ms_per_frame": round(v["ms"], 4),
-                      "feature_fwd_bwd_ms": round(v["phases"]["feature_render_fwd"] +
-                                                  v["phases"]["feature_render_bwd"], 4),
+                      "feature_fwd_bwd_ms": round(feature_ms(v["phases"]), 4),
+                      "separate_launches_ms": v["separate"],
                       "phases_ms": {p: round(x, 4) for p, x in v["phases"].items()},
                       "U": v["U"], "pairs": v["pairs"], "tile_union": v["tile_union"]}
                   for k, v in results.items()},
@@ -341,9 +393,7 @@ def main():
                      "traffic": traffic,
                      "traffic_read_write": None if t is None else [t["read"], t["write"]],
                      "algorithmic_bytes": int(kbytes),
-                     "avg_ms": round(R["kern_ms"], 4),
-                     "note": "the blend adjoint (rasterize_topk_bwd) takes about as long; it is "
-                             "bound by per-pair VALU work, not HBM"},
+                     "avg_ms": round(R["kern_ms"], 4)},
     }
     if sweep:
         line["k_sweep"] = sweep

@@ -206,6 +206,25 @@ lgs_status lgs_feature_render_bwd_l1(int32_t width, int32_t height, int32_t view
                                      hipStream_t stream);
 
 /*
+ * The feature render (Eq. 3-4) and its adjoint under the L1 feature loss of Eq. 9
+ * in one pass over the Top-K records.  The outputs equal those of
+ * lgs_feature_render_fwd followed by lgs_feature_render_bwd_l1 on the same inputs:
+ * F is bit-identical to the forward's map, dL_dtopkw and the accumulated dL_dfeat
+ * are those of the L1 adjoint.  The map is computed once and is both stored and
+ * compared with the target, so one launch does the work of two.
+ * Out: F[n_pix*d] (map_dt, overwritten), dL_dfeat[n*d] (FP32, accumulated),
+ *      dL_dtopkw[n_pix*k] (overwritten).  In: F_target[n_pix*d] (map_dt).
+ * Same dtype and layout rules as the forward; F and F_target are 16-byte aligned and
+ * must not overlap (INVALID_ARG otherwise).
+ */
+lgs_status lgs_feature_render_fwd_bwd_l1(int32_t width, int32_t height, int32_t views, int32_t k,
+                                         int32_t d, lgs_dtype feat_dt, const void *feat,
+                                         const float *feat_scale, const int32_t *topk_ids,
+                                         const float *topk_w, lgs_dtype map_dt, void *F,
+                                         const void *F_target, float scale, float *dL_dfeat,
+                                         float *dL_dtopkw, hipStream_t stream);
+
+/*
  * Adjoint of the blend (Eq. 1) including the Top-K weight path, replayed back to
  * front per pixel from T_final and n_contrib.  dL_dalpha and dL_dtopkw may be NULL.
  * Accumulates per-Gaussian screen-space gradients:

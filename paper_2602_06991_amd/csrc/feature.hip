@@ -752,12 +752,15 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
 
 // Backward of the MFMA path.  L1: dF holds the target map and G = l1_scale
 // sign(F - F^) is formed from the recomputed map (the products take the sign, the
-// sums the scale); otherwise dF holds dL/dF.
-template <int K, int FT, bool L1, int R>
+// sums the scale); otherwise dF holds dL/dF.  SF (with L1): the map is also stored
+// to Fo, so one pass renders and differentiates.
+template <int K, int FT, bool L1, bool SF, int R>
 __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, int D, int U,
                                             const void *__restrict__ feat, const uint16_t *__restrict__ dF,
                                             float gs, float *__restrict__ dfeat, float *__restrict__ dtw,
-                                            UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
+                                            uint16_t *__restrict__ Fo, UnionLds<K, FT> &L, Slots<K> &s,
+                                            unsigned char *dyn) {
+    static_assert(L1 || !SF, "the map is stored only on the L1 path");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float *sred = (float *)dyn;   // [4][256][K], once the operands are in registers
     const SlotTable<K> st = slot_table<K>(dyn, D, true);
@@ -797,8 +800,9 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
         lon[i] = x < W && i < mc.n && ch < D;
         loff[i] = lon[i] ? (uint32_t)(i16 * D + ch) : 0u;
     }
+    auto row_at = [&](int row) { return ((long)tg.view * W * H + (long)(tg.ty0 + row) * W + tg.tx0) * D; };
     auto fetch = [&](int row, u32x4 (&dst)[kCPW]) {
-        const uint16_t *base = dF + ((long)tg.view * W * H + (long)(tg.ty0 + min(row, rows - 1)) * W + tg.tx0) * D;
+        const uint16_t *base = dF + row_at(min(row, rows - 1));
 #pragma unroll
         for (int i = 0; i < kCPW; ++i) dst[i] = *(const u32x4 *)(base + loff[i]);
     };
@@ -827,6 +831,9 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
                     u32x4 Fp = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
                                 pk_bf16(F1[2], F1[3])};
                     __asm__ volatile("" : "+v"(Fp.x), "+v"(Fp.y), "+v"(Fp.z), "+v"(Fp.w));
+                    // the stored map: the target's layout, so the same per-lane offsets
+                    if constexpr (SF)
+                        if (row < rows && lon[i]) *(u32x4 *)(Fo + row_at(row) + loff[i]) = Fp;
                     G.x = l1_sign2(Fp.x, T.x);
                     G.y = l1_sign2(Fp.y, T.y);
                     G.z = l1_sign2(Fp.z, T.z);
@@ -1010,10 +1017,10 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
 
 // The wave's pixels for one channel pass after another.  STAGED: every union row of
 // the tile is in LDS, so the only global traffic in the loop is dL/dF (or the target).
-template <int K, int FT, int MT, bool L1, bool STAGED>
+template <int K, int FT, int MT, bool L1, bool SF, bool STAGED>
 __device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
                                            const void *__restrict__ feat, const void *__restrict__ dF,
-                                           float l1_scale, float *__restrict__ dfeat,
+                                           float l1_scale, float *__restrict__ dfeat, void *__restrict__ Fo,
                                            const Slots<K> &sl, const UnionLds<K, FT> &L,
                                            const unsigned char *rows, int nw,
                                            float (*sdot)[K], float *xbuf, int wave, int lane) {
@@ -1048,6 +1055,16 @@ __device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int
 #pragma unroll
             for (int j = 0; j < CPL; ++j) cur[j] = nxt[j];
             if (i + 1 < kPixPerWave) fetch(i + 1, nxt);
+            if constexpr (SF) {
+                // pixels without contributors still get their (zero) map entries
+                const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
+                if (x < W && y < H && !(rdlane(sl.W, i) > 0.f) && lane_on) {
+                    float z[CPL];
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) z[j] = 0.f;
+                    storec<MT, CPL>(Fo, ((long)tg.view * W * H + (long)y * W + x) * D + c0, z);
+                }
+            }
             if (!want(i)) continue;
             int wl[K];
             float wp[K], v[K][CPL];
@@ -1082,11 +1099,16 @@ __device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int
 #pragma unroll
                     for (int j = 0; j < CPL; ++j) Fv[j] = fmaf(wf, v[k][j], Fv[j]);
                 }
+                float fm[CPL];
 #pragma unroll
                 for (int j = 0; j < CPL; ++j) {
-                    const float fm = MT == MT_F32 ? Fv[j] : bf16_to_f32(f32_to_bf16(Fv[j]));
-                    const float d = lane_on ? fm - cur[j] : 0.f;
+                    fm[j] = MT == MT_F32 ? Fv[j] : bf16_to_f32(f32_to_bf16(Fv[j]));
+                    const float d = lane_on ? fm[j] - cur[j] : 0.f;
                     G[j] = d > 0.f ? gs : (d < 0.f ? -gs : 0.f);
+                }
+                if constexpr (SF) {
+                    const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
+                    if (lane_on) storec<MT, CPL>(Fo, ((long)tg.view * W * H + (long)y * W + x) * D + c0, fm);
                 }
             } else {
 #pragma unroll
@@ -1126,16 +1148,17 @@ __device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int
     }
 }
 
-// L1 = false: dF holds dL/dF (map dtype).  L1 = true: dF holds the target map F^ and
+// MODE 0: dF holds dL/dF (map dtype).  MODE 1: dF holds the target map F^ and
 // dL/dF = l1_scale * sign(F - F^) is formed on the fly from F recomputed exactly as
-// the forward kernel computes and rounds it.
+// the forward kernel computes and rounds it.  MODE 2: as 1, and that F is stored to
+// Fo, bit-identical to the forward kernel's map (render and adjoint in one pass).
 constexpr int kRing = 1;   // rows of dL/dF in flight on the MFMA path, besides the one in use
 
 template <int K, int CPL>
 constexpr size_t fallback_extra() { return (size_t)4 * kPixPerWave * K * 4 + (size_t)4 * 64 * CPL * 4; }
 
 // Two blocks per CU: registers are capped at 256 per lane.
-template <int K, int FT, int MT, bool L1>
+template <int K, int FT, int MT, int MODE>
 __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int views, int D, int ucap,
                                                           const void *__restrict__ feat,
                                                           const float *__restrict__ scale,
@@ -1143,8 +1166,9 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
                                                           const float *__restrict__ tw,
                                                           const void *__restrict__ dF, float l1_scale,
                                                           float *__restrict__ dfeat,
-                                                          float *__restrict__ dtw) {
+                                                          float *__restrict__ dtw, void *__restrict__ Fo) {
     constexpr int CPL = TileCfg<K>::CPL;
+    constexpr bool L1 = MODE >= 1, SF = MODE == 2;
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ UnionLds<K, FT> L;
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
@@ -1158,8 +1182,8 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
     if constexpr (MfOk<K, FT, MT>::v) {
         if (U <= kUP && D <= 128 * kCPW) {
             const float gs = bf16_to_f32(f32_to_bf16(l1_scale));
-            mf_backward<K, FT, L1, kRing + 1>(tg, W, H, D, U, feat, (const uint16_t *)dF, gs, dfeat, dtw, L,
-                                              sl, dyn);
+            mf_backward<K, FT, L1, SF, kRing + 1>(tg, W, H, D, U, feat, (const uint16_t *)dF, gs, dfeat, dtw,
+                                                  (uint16_t *)Fo, L, sl, dyn);
             return;
         }
     }
@@ -1171,11 +1195,11 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
 #pragma unroll
     for (int k = 0; k < K; ++k) s_dot[wave][lane][k] = 0.f;
     if (U >= 1 && U <= ucap)
-        bwd_pixels<K, FT, MT, L1, true>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, dyn, nw,
-                                       s_dot[wave], xbuf, wave, lane);
+        bwd_pixels<K, FT, MT, L1, SF, true>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
+                                           s_dot[wave], xbuf, wave, lane);
     else
-        bwd_pixels<K, FT, MT, L1, false>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, sl, L, dyn, nw,
-                                        s_dot[wave], xbuf, wave, lane);
+        bwd_pixels<K, FT, MT, L1, SF, false>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
+                                            s_dot[wave], xbuf, wave, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     // gamma_k = (g_k - sum_j w'_j g_j) / W for the lane's own pixel
@@ -1353,18 +1377,18 @@ lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
     return check_launch("feature_render_fwd");
 }
 
-template <int FT, int MT, bool L1>
+template <int FT, int MT, int MODE>
 lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
                         const int *ids, const float *tw, const void *dF, float l1_scale, float *dfeat,
-                        float *dtw, hipStream_t st) {
+                        float *dtw, void *Fo, hipStream_t st) {
     unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
     const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
         lds = kRowBudget + fallback_extra<KK, TileCfg<KK>::CPL>();                                  \
         if (MfOk<KK, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, KK, true));                          \
-        hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, L1>), dim3(grid), dim3(kFB), lds, st, W, \
-                           H, views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw);        \
+        hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, MODE>), dim3(grid), dim3(kFB), lds, st, W, \
+                           H, views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw, Fo);    \
         break;
     size_t lds = 0;
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
@@ -1372,17 +1396,17 @@ lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
     return check_launch("feature_render_bwd");
 }
 
-template <bool L1>
+template <int MODE>
 lgs_status bwd_entry(int32_t width, int32_t height, int32_t views, int32_t k, int32_t d, lgs_dtype feat_dt,
                      const void *feat, const float *feat_scale, const int32_t *topk_ids, const float *topk_w,
                      lgs_dtype map_dt, const void *dF, float l1_scale, float *dL_dfeat, float *dL_dtopkw,
-                     hipStream_t stream) {
-#define ARGS k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dF, l1_scale, dL_dfeat, dL_dtopkw, stream
-    if (feat_dt == LGS_F32) return bwd_dispatch<FT_F32, MT_F32, L1>(ARGS);
-    if (feat_dt == LGS_BF16 && map_dt == LGS_BF16) return bwd_dispatch<FT_BF16, MT_BF16, L1>(ARGS);
-    if (feat_dt == LGS_BF16) return bwd_dispatch<FT_BF16, MT_F32, L1>(ARGS);
-    if (map_dt == LGS_BF16) return bwd_dispatch<FT_FP8, MT_BF16, L1>(ARGS);
-    return bwd_dispatch<FT_FP8, MT_F32, L1>(ARGS);
+                     void *Fo, hipStream_t stream) {
+#define ARGS k, width, height, views, d, feat, feat_scale, topk_ids, topk_w, dF, l1_scale, dL_dfeat, dL_dtopkw, Fo, stream
+    if (feat_dt == LGS_F32) return bwd_dispatch<FT_F32, MT_F32, MODE>(ARGS);
+    if (feat_dt == LGS_BF16 && map_dt == LGS_BF16) return bwd_dispatch<FT_BF16, MT_BF16, MODE>(ARGS);
+    if (feat_dt == LGS_BF16) return bwd_dispatch<FT_BF16, MT_F32, MODE>(ARGS);
+    if (map_dt == LGS_BF16) return bwd_dispatch<FT_FP8, MT_BF16, MODE>(ARGS);
+    return bwd_dispatch<FT_FP8, MT_F32, MODE>(ARGS);
 #undef ARGS
 }
 
@@ -1433,8 +1457,8 @@ extern "C" lgs_status lgs_feature_render_bwd(int32_t width, int32_t height, int3
     LGS_REQUIRE(topk_ids && topk_w && dL_dF && dL_dfeat && dL_dtopkw, LGS_ERR_INVALID_ARG,
                 "lgs_feature_render_bwd: NULL pointer");
     LGS_REQUIRE(aligned16(dL_dF), LGS_ERR_INVALID_ARG, "dL_dF must be 16-byte aligned");
-    return bwd_entry<false>(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w, map_dt,
-                            dL_dF, 0.0f, dL_dfeat, dL_dtopkw, stream);
+    return bwd_entry<0>(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w, map_dt,
+                        dL_dF, 0.0f, dL_dfeat, dL_dtopkw, nullptr, stream);
 }
 
 extern "C" lgs_status lgs_feature_render_bwd_l1(int32_t width, int32_t height, int32_t views, int32_t k,
@@ -1448,8 +1472,27 @@ extern "C" lgs_status lgs_feature_render_bwd_l1(int32_t width, int32_t height, i
     LGS_REQUIRE(topk_ids && topk_w && F_target && dL_dfeat && dL_dtopkw, LGS_ERR_INVALID_ARG,
                 "lgs_feature_render_bwd_l1: NULL pointer");
     LGS_REQUIRE(aligned16(F_target), LGS_ERR_INVALID_ARG, "F_target must be 16-byte aligned");
-    return bwd_entry<true>(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w, map_dt,
-                           F_target, scale, dL_dfeat, dL_dtopkw, stream);
+    return bwd_entry<1>(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w, map_dt,
+                        F_target, scale, dL_dfeat, dL_dtopkw, nullptr, stream);
+}
+
+extern "C" lgs_status lgs_feature_render_fwd_bwd_l1(int32_t width, int32_t height, int32_t views, int32_t k,
+                                                    int32_t d, lgs_dtype feat_dt, const void *feat,
+                                                    const float *feat_scale, const int32_t *topk_ids,
+                                                    const float *topk_w, lgs_dtype map_dt, void *F,
+                                                    const void *F_target, float scale, float *dL_dfeat,
+                                                    float *dL_dtopkw, hipStream_t stream) {
+    lgs_status st = check_feature_args(width, height, views, k, d, feat_dt, feat, feat_scale, map_dt);
+    if (st) return st;
+    LGS_REQUIRE(topk_ids && topk_w && F && F_target && dL_dfeat && dL_dtopkw, LGS_ERR_INVALID_ARG,
+                "lgs_feature_render_fwd_bwd_l1: NULL pointer");
+    LGS_REQUIRE(aligned16(F) && aligned16(F_target), LGS_ERR_INVALID_ARG,
+                "F and F_target must be 16-byte aligned");
+    const size_t map_bytes = (size_t)width * height * views * d * (map_dt == LGS_F32 ? 4 : 2);
+    const char *a = (const char *)F, *b = (const char *)F_target;
+    LGS_REQUIRE(a + map_bytes <= b || b + map_bytes <= a, LGS_ERR_INVALID_ARG, "F and F_target overlap");
+    return bwd_entry<2>(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids, topk_w, map_dt,
+                        F_target, scale, dL_dfeat, dL_dtopkw, F, stream);
 }
 
 extern "C" lgs_status lgs_quantize_features(int32_t n, int32_t d, const float *src, lgs_dtype dst_dt,

@@ -68,6 +68,8 @@ _SIG = {
                                ctypes.c_int, _P, _P, _P, _P],
     "lgs_feature_render_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                   ctypes.c_int, _P, _F, _P, _P, _P],
+    "lgs_feature_render_fwd_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
+                                      ctypes.c_int, _P, _P, _F, _P, _P, _P],
     "lgs_rasterize_topk_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -188,6 +190,13 @@ def lgs_feature_render_bwd_l1(width, height, views, k, d, feat_dt, feat, feat_sc
     return _check(load().lgs_feature_render_bwd_l1(width, height, views, k, d, feat_dt, feat, feat_scale,
                                                    topk_ids, topk_w, map_dt, F_target, scale, dL_dfeat,
                                                    dL_dtopkw, stream))
+
+
+def lgs_feature_render_fwd_bwd_l1(width, height, views, k, d, feat_dt, feat, feat_scale, topk_ids,
+                                  topk_w, map_dt, F, F_target, scale, dL_dfeat, dL_dtopkw, stream=None):
+    return _check(load().lgs_feature_render_fwd_bwd_l1(width, height, views, k, d, feat_dt, feat,
+                                                       feat_scale, topk_ids, topk_w, map_dt, F, F_target,
+                                                       scale, dL_dfeat, dL_dtopkw, stream))
 
 
 def lgs_rasterize_topk_bwd(cam, k, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,

@@ -175,6 +175,22 @@ def feature_bwd_l1(ids, w, feat_store, feat_scale, feat_dtype, map_dtype, F_targ
     return dtw
 
 
+def feature_fwd_bwd_l1(ids, w, feat_store, feat_scale, feat_dtype, map_dtype, F_target, scale, dfeat,
+                       views=1):
+    """The feature render and its L1 adjoint in one pass: returns (F, dL/dw), the same
+    as feature_fwd followed by feature_bwd_l1."""
+    K = ids.shape[-1]
+    Hs, W = ids.shape[0], ids.shape[1]
+    d = feat_store.shape[1]
+    F = torch.empty(Hs, W, d, dtype=_TORCH_MAP[map_dtype], device=ids.device)
+    dtw = torch.empty(Hs, W, K, device=ids.device)
+    _need_cuda(ids, w, feat_store, feat_scale, F_target, dfeat)
+    lgs.lgs_feature_render_fwd_bwd_l1(W, Hs // views, views, K, d, lgs.DTYPES[feat_dtype], _p(feat_store),
+                                      _p(feat_scale), _p(ids), _p(w), lgs.DTYPES[map_dtype], _p(F),
+                                      _p(F_target), float(scale), _p(dfeat), _p(dtw), _stream())
+    return F, dtw
+
+
 def rasterize_bwd(cam, K, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads):
     lgs.lgs_rasterize_topk_bwd(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(fwd["T"]),

@@ -80,6 +80,18 @@ def test_unsupported_k_d_and_dtypes():
         lgs.lgs_feature_render_bwd(16, 16, 1, 3, 16, lgs.LGS_BF16, FAKE, None, FAKE, FAKE, lgs.LGS_BF16, FAKE,
                                    None, FAKE)
     assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    # the one-pass render + L1 adjoint: map and target must not overlap, nor be NULL
+    fused = lambda F, T: lgs.lgs_feature_render_fwd_bwd_l1(16, 16, 1, 4, 16, lgs.LGS_BF16, FAKE, None, FAKE,
+                                                           FAKE, lgs.LGS_BF16, F, T, 1.0, FAKE, FAKE)
+    for F, T in ((FAKE, FAKE), (FAKE, FAKE + 16 * 16 * 16 * 2 - 16), (FAKE + 4096, FAKE), (None, FAKE),
+                 (FAKE, FAKE + 8)):
+        with pytest.raises(lgs.LgsError) as e:
+            fused(F, T)
+        assert e.value.status == lgs.LGS_ERR_INVALID_ARG, (F, T)
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_feature_render_fwd_bwd_l1(16, 16, 1, 4, 16, lgs.LGS_F32, FAKE, None, FAKE, FAKE, lgs.LGS_BF16,
+                                          FAKE, FAKE + 65536, 1.0, FAKE, FAKE)
+    assert e.value.status == lgs.LGS_ERR_UNSUPPORTED
     with pytest.raises(lgs.LgsError) as e:
         lgs.lgs_quantize_features(10, 16, FAKE, lgs.LGS_F32, FAKE, None)
     assert e.value.status == lgs.LGS_ERR_UNSUPPORTED

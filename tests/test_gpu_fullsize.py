@@ -76,7 +76,44 @@ def test_benchmark_frame(torch, orc, form):
     tol = 1e-4 if mdt == "f32" else 1e-2
     log(f"feature map ({form}): max normwise err {err.max():.3g}, mean {err.mean():.3g}")
     assert err.max() <= tol
-    del F, Fo
+
+    # the benchmark's one-pass render + L1 adjoint: the target is kept clear of the
+    # oracle's map on unflagged pixels and equals the GPU's own map on flagged ones
+    # (sign 0 there, matching the oracle's masked upstream gradient)
+    rng = np.random.default_rng(5)
+    P, D = cam.W * cam.H, g.d
+    delta = rng.choice([-1.0, 1.0], (P, D)) * (0.02 + 0.05 * np.abs(Fo.reshape(P, D)))
+    That = (Fo.reshape(P, D) + delta).astype(np.float32)
+    del delta
+    tmap = torch.float32 if mdt == "f32" else torch.bfloat16
+    T_dev = torch.from_numpy(That).cuda().to(tmap)
+    del That
+    flat_ok = torch.from_numpy(ok.reshape(-1)).cuda()
+    T_dev = torch.where(flat_ok[:, None], T_dev, F.reshape(P, D)).reshape(cam.H, cam.W, D).contiguous()
+    T_m = T_dev.reshape(P, D).float().cpu().numpy().astype(np.float64)
+    fs = 1.0 / (P * D)
+    d1 = torch.zeros(g.n, D, device="cuda")
+    F1, t1 = render.feature_fwd_bwd_l1(state["fw"]["ids"], state["fw"]["w"], store, scale, form, mdt, T_dev,
+                                       fs, d1)
+    torch.cuda.synchronize()
+    assert torch.equal(F1, F)                      # the stored map is the forward's, bit for bit
+    gs = fs if mdt == "f32" else float(torch.tensor(fs).to(torch.bfloat16).float())
+    gF1 = gs * np.sign(Fo.reshape(P, D) - T_m) * ok.reshape(-1, 1)
+    del T_m
+    d_feat, d_w = orc.feature_backward(r["ids"], r["w"].astype(np.float32).astype(np.float64), f64,
+                                       gF1.reshape(cam.H, cam.W, D))
+    del gF1
+    df = d1.cpu().numpy()
+    touched = np.abs(d_feat).sum(1) > 0
+    e = normwise(df[touched], d_feat[touched], 1e-12)
+    gam = t1.cpu().numpy()[ok]
+    dw = d_w[ok]
+    eg = (np.abs(gam - dw) / (np.abs(dw).max(-1, keepdims=True) + 1e-12)).max()
+    log(f"one-pass render + L1 adjoint ({form}): gradient rows max normwise err {e.max():.3g}, "
+        f"dL/dw max err {eg:.3g}")
+    assert e.max() <= 1e-4 and eg <= 1e-4
+    assert np.all(df[~touched] == 0)
+    del F, Fo, F1, d1, df, d_feat, d_w, T_dev
 
     # the whole adjoint, upstream gradients zeroed on flagged pixels on both sides
     gC, gD, gO, gF = random_upstream(11, cam.W * cam.H, g.d)

@@ -397,3 +397,73 @@ def test_fused_l1_matches_unfused(torch, K, fdt, D, spread):
     scl = t2.abs().amax(-1, keepdim=True).clamp_min(1e-30)
     e = ((t1 - t2).abs() / scl).max().item()
     assert e <= 1e-5, e
+
+
+@pytest.mark.parametrize("K,fdt,mdt,views,H,W,D,spread", [
+    (4, "bf16", "bf16", 1, 40, 53, 512, 24),       # MFMA path, ragged tiles
+    (8, "fp8", "bf16", 2, 33, 40, 768, 30),        # FP8 rows, unions up to 32, two views
+    (4, "bf16", "bf16", 1, 48, 48, 256, 20000),    # unions beyond 32: per-pixel path in the same launch
+    (3, "bf16", "f32", 1, 20, 36, 200, 14),        # FP32 map, channel tail
+    (4, "f32", "f32", 1, 37, 53, 64, 40),          # FP32 form
+    (16, "bf16", "bf16", 1, 32, 32, 128, 300)])    # K beyond the MFMA path
+def test_one_pass_render_and_l1_adjoint(torch, orc, K, fdt, mdt, views, H, W, D, spread):
+    """lgs_feature_render_fwd_bwd_l1 against the two separate launches (the map bit for
+    bit, dL/dw bit for bit, dL/df to summation order) on a target with exact ties and
+    one-ulp gaps, and against the oracle on a target kept clear of the map."""
+    from paper_2602_06991_amd import render
+    rng = np.random.default_rng(13 * K + D + views)
+    n = 30000
+    feat = rng.standard_normal((n, D)).astype(np.float32)
+    ids, w = _synthetic_topk(rng, views, H, W, K, n, spread)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    store, sc8 = render.quantize(dev(feat), fdt)
+    ids_d, w_d = dev(ids), dev(w)
+    scale = 1.0 / (views * H * W * D)
+    F1 = render.feature_fwd(ids_d, w_d, store, sc8, fdt, mdt, views=views)
+    ibits = torch.int16 if mdt == "bf16" else torch.int32
+    bits = F1.view(ibits).clone()
+    pick = torch.from_numpy(rng.integers(0, 3, tuple(bits.shape))).cuda()
+    step = torch.from_numpy(rng.choice([-1, 1], tuple(bits.shape))).cuda().to(ibits)
+    rnd = torch.from_numpy(rng.standard_normal(tuple(bits.shape)).astype(np.float32)).cuda().to(F1.dtype)
+    # one-ulp neighbours of nonzero values only (a step off +0 would make a NaN)
+    near = torch.where((pick == 1) & (F1 != 0), bits + step, bits).view(F1.dtype)
+    target = torch.where(pick == 2, rnd, near).contiguous()
+    for _ in range(2):   # twice: everything but the order of the dL/df atomics repeats exactly
+        d1 = torch.zeros(n, D, device="cuda")
+        d2 = torch.zeros(n, D, device="cuda")
+        t1 = render.feature_bwd_l1(ids_d, w_d, store, sc8, fdt, mdt, target, scale, d1, views=views)
+        F2, t2 = render.feature_fwd_bwd_l1(ids_d, w_d, store, sc8, fdt, mdt, target, scale, d2, views=views)
+        torch.cuda.synchronize()
+        assert torch.equal(F2.view(ibits), F1.view(ibits))
+        assert torch.equal(t2, t1)
+        assert torch.equal(d1 != 0, d2 != 0)
+        rel = ((d1 - d2).norm(dim=1) / d2.norm(dim=1).clamp_min(1e-30)).max().item()
+        assert rel <= 1e-6, rel
+
+    # against the oracle, with the target well clear of the map
+    if fdt == "f32":
+        f64 = feat.astype(np.float64)
+    elif fdt == "bf16":
+        f64 = orc.bf16_to_f64(orc.bf16_bits(feat)).reshape(feat.shape)
+    else:
+        c, s = orc.fp8_quantize(feat)
+        f64 = orc.fp8_dequant(c, s)
+    Fo = orc.feature(ids, w.astype(np.float64), f64)
+    delta = rng.choice([-1.0, 1.0], Fo.shape) * (0.02 + 0.05 * np.abs(Fo))
+    tmap = torch.float32 if mdt == "f32" else torch.bfloat16
+    T_dev = dev((Fo + delta).astype(np.float32)).to(tmap)
+    T_m = T_dev.float().cpu().numpy().astype(np.float64)
+    d3 = torch.zeros(n, D, device="cuda")
+    F3, t3 = render.feature_fwd_bwd_l1(ids_d, w_d, store, sc8, fdt, mdt, T_dev, scale, d3, views=views)
+    torch.cuda.synchronize()
+    err = normwise(F3.float().cpu().numpy().astype(np.float64), Fo, 1e-2)
+    assert err.max() <= (1e-4 if mdt == "f32" else 1e-2), err.max()
+    gs = scale if mdt == "f32" else float(torch.tensor(scale).to(torch.bfloat16).float())
+    d_feat, d_w = orc.feature_backward(ids, w.astype(np.float64), f64, gs * np.sign(Fo - T_m))
+    df = d3.cpu().numpy()
+    touched = np.abs(d_feat).sum(1) > 0
+    e = normwise(df[touched], d_feat[touched], 1e-12)
+    assert e.max() <= 1e-4, e.max()
+    assert np.all(df[~touched] == 0)
+    scl = np.abs(d_w).max(-1, keepdims=True) + 1e-12
+    assert (np.abs(t3.cpu().numpy() - d_w) / scl).max() <= 1e-4
