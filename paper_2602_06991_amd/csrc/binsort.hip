@@ -249,19 +249,29 @@ __global__ __launch_bounds__(256) void duplicate_kernel(int n, const int *__rest
     const int total = s_total;
     const long long base = s_base;
     const int lim = (int)min((long long)total, max_pairs - base);   // never past the buffers
-    for (int q = t; q < lim; q += 256) {
-        int lo = 0, hi = 255;   // largest j with s_start[j] <= q
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_start[mid] <= q) lo = mid;
-            else hi = mid - 1;
+    // four pairs per thread and round, their owner searches interleaved (eight
+    // fixed steps each: the largest j with s_start[j] <= q; s_start[0] = 0)
+    constexpr int kU = 4;
+    for (int q0 = t; q0 < lim; q0 += kU * 256) {
+        int lo[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) lo[u] = 0;
+#pragma unroll
+        for (int step = 128; step > 0; step >>= 1)
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (s_start[lo[u] + step] <= q0 + u * 256) lo[u] += step;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int q = q0 + u * 256;
+            if (q >= lim) break;
+            const int4 rr = s_rect[lo[u]];
+            const int k = q - s_start[lo[u]];
+            const int rw = rr.z - rr.x;
+            const int ty = rr.y + k / rw, tx = rr.x + k - (k / rw) * rw;
+            tile_keys[base + q] = (uint32_t)(ty * ntx + tx);
+            ids[base + q] = s_g[lo[u]];
         }
-        const int4 rr = s_rect[lo];
-        const int k = q - s_start[lo];
-        const int rw = rr.z - rr.x;
-        const int ty = rr.y + k / rw, tx = rr.x + k - (k / rw) * rw;
-        tile_keys[base + q] = (uint32_t)(ty * ntx + tx);
-        ids[base + q] = s_g[lo];
     }
 }
 
@@ -270,13 +280,16 @@ __global__ __launch_bounds__(256) void zero_ranges_kernel(int n2, int *__restric
     if (i < n2) ranges[i] = 0;
 }
 
+// Run boundaries of the sorted tile keys; keys outside [0, T) (a caller's box past the
+// tile grid) mark nothing.
 __global__ __launch_bounds__(256) void mark_ranges_kernel(int m, const long long *__restrict__ m_dev,
-                                                          const uint32_t *__restrict__ keys,
+                                                          const uint32_t *__restrict__ keys, uint32_t T,
                                                           int *__restrict__ ranges) {
     m = items_of(m, m_dev);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     uint32_t k = keys[i];
+    if (k >= T) return;
     if (i == 0 || keys[i - 1] != k) ranges[2 * k] = i;
     if (i == m - 1 || keys[i + 1] != k) ranges[2 * k + 1] = i + 1;
 }
@@ -436,7 +449,7 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
         int *tv = vcur; vcur = vnext; vnext = tv;
     }
     hipLaunchKernelGGL(mark_ranges_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream,
-                       (int)M, M_dev, kcur, tile_ranges);
+                       (int)M, M_dev, kcur, (uint32_t)T, tile_ranges);
     return check_launch("bin_sort ranges");
 }
 
