@@ -127,7 +127,7 @@ class Step:
         self._mark("rasterize_topk_bwd")
         r.project_bwd(c, P, self.sg, self.pg)
         self._mark("project_bwd")
-        self.last = dict(fw=fw, pairs=m, F=F, store=store, scale=scale)
+        self.last = dict(fw=fw, pairs=m, F=F, store=store, scale=scale, proj=proj, ids=ids, ranges=ranges)
 
 
 def time_steps(torch, step, steps, warmup):
@@ -180,6 +180,30 @@ def counter_traffic(kernel, workload_ok):
             if f[0] == sha and f[1] == kernel:
                 return dict(read=int(f[2]), write=int(f[3]), total=int(f[2]) + int(f[3]))
     return None
+
+
+def timed(torch, fn, reps=10):
+    """Average ms of `fn` over `reps` launches after two warm-ups, by HIP events."""
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def copy_bandwidth(torch, nbytes):
+    """GB/s of a plain device-to-device copy of `nbytes` (nbytes read and nbytes
+    written): the achievable streaming rate, reported beside the 8 TB/s peak."""
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(torch, lambda: dst.copy_(src))
+    del src, dst
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
 
 
 def tile_union_stats(ids, W, H):
@@ -318,8 +342,16 @@ def main():
         bf, bb, b2 = feature_bytes(npix, K, cfg["D"], U, s_map, s_f, form == "fp8")
         sep = separate_feature_ms(torch, render, fw, step.last["store"], step.last["scale"], form, mp,
                                   target[2], cfg["D"], P["feat"].shape[0])
+        # the pruning statistics of Sec. 3.3 (run every few hundred iterations, not per step)
+        cnt = torch.zeros(P["feat"].shape[0], dtype=torch.int32, device="cuda")
+        mxw = torch.zeros(P["feat"].shape[0], device="cuda")
+        st = step.last
+        prune_ms = timed(torch, lambda: render.prune_stats(cam, K, st["proj"], st["ids"], st["ranges"], fw, cnt,
+                                                           mxw))
+        del cnt, mxw
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
                              bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
+                             prune_ms=prune_ms,
                              tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
         print(f"# {form}: {ms:.3f} ms/step, U={U}, pairs={step.last['pairs']}, phases "
               + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()), file=sys.stderr, flush=True)
@@ -382,9 +414,14 @@ def main():
         "feature_fwd_bwd_GBps": round(feat_gbs, 1),
         "feature_fwd_bwd_hbm_frac": round(feat_gbs / HBM_PEAK_GBS, 4),
         "feature_path": args.feature_path,
+        "achievable_copy_GBps": copy_bandwidth(torch, cfg["W"] * cfg["H"] * cfg["D"] * 2),   # a BF16 map
         "forms": {k: {"ms_per_frame": round(v["ms"], 4),
                       "feature_fwd_bwd_ms": round(feature_ms(v["phases"]), 4),
                       "separate_launches_ms": v["separate"],
+                      "fwd_ms_per_frame": round(v["phases"]["project_fwd"] + v["phases"]["bin_sort"] +
+                                                v["phases"]["rasterize_topk_fwd"] +
+                                                v["separate"]["feature_render_fwd"], 4),
+                      "prune_stats_ms": round(v["prune_ms"], 4),
                       "phases_ms": {p: round(x, 4) for p, x in v["phases"].items()},
                       "U": v["U"], "pairs": v["pairs"], "tile_union": v["tile_union"]}
                   for k, v in results.items()},

@@ -256,6 +256,24 @@ lgs_status lgs_project_bwd(const lgs_camera *cam, int32_t n,
                            float *dL_dopacity_logits, hipStream_t stream);
 
 /*
+ * Statistics of the semantic-geometric consistency pruning (Sec. 3.3, Eq. 5) for one
+ * view, from that view's forward outputs (same geometry inputs, n_contrib and
+ * topk_ids of lgs_rasterize_topk_fwd with the same k):
+ *   topk_count[g] += number of pixels whose Top-K list holds Gaussian g (its Top-K
+ *                    participation);
+ *   max_w[g] = max(max_w[g], w) over every pixel where g is blended, w = alpha T its
+ *              blending weight (the geometric importance S_g of Eq. 5).
+ * Both accumulate over calls, so calling once per keyframe gives the counts and maxima
+ * over all keyframes; the caller zeroes them first (max_w entries must be >= 0).
+ * The weights are recomputed with the forward's own arithmetic and equal its weights
+ * bit for bit.  topk_count[n] int32, max_w[n] FP32 (4-byte aligned).
+ */
+lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const float *mean2d, const float *conic,
+                           const float *opacity, const int32_t *sorted_ids, const int32_t *tile_ranges,
+                           const int32_t *n_contrib, const int32_t *topk_ids, int32_t *topk_count,
+                           float *max_w, hipStream_t stream);
+
+/*
  * Storage quantization of the feature table (the precision forms of the renderer):
  * dst_dt = BF16: round-to-nearest-even; dst_dt = FP8_E4M3: per row, scale
  * s = 2^floor(log2(amax / 224)) (s = 1 for an all-zero row) so x / s is exact and

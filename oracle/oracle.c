@@ -452,6 +452,67 @@ int orc_render(int n, const float *means, const float *ls, const float *q, const
     return err;
 }
 
+/*
+ * Pruning statistics of Sec. 3.3 for one view, accumulated into the caller's arrays:
+ *   count[g] += number of pixels whose Top-K list (Eq. 2) holds g;
+ *   maxw[g] = max(maxw[g], w) over every pixel where g is blended (Eq. 5's S_g: the
+ *   largest blending weight alpha T the Gaussian reaches).
+ * Each thread keeps its own arrays; they are merged after the pixel loop.
+ */
+int orc_prune_stats(int n, const float *means, const float *ls, const float *q, const float *opl,
+                    const float *rgb, const float *cam, int W, int H, int K, int *count, double *maxw)
+{
+    if (K < 1 || K > 63) return -2;
+    cam_t c;
+    cam_from(cam, W, H, &c);
+    proj_t *P = project_all(&c, n, means, ls, q, opl, rgb);
+    if (!P) return -1;
+    bins_t b;
+    if (make_bins(P, n, W, H, 0, &b)) { free(P); return -1; }
+    int cap = max_list_len(&b) + 1;
+    int err = 0;
+#pragma omp parallel
+    {
+        blend_t *bl = (blend_t *)malloc(sizeof(blend_t) * (size_t)cap);
+        int *cnt = (int *)calloc((size_t)(n > 0 ? n : 1), sizeof(int));
+        double *mw = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+        int ids[64];
+        double ws[64];
+        if (!bl || !cnt || !mw) {
+#pragma omp atomic write
+            err = -1;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (long pix = 0; pix < (long)W * H; ++pix) {
+            if (!bl || !cnt || !mw) continue;
+            int x = (int)(pix % W), y = (int)(pix / W);
+            int t = (y / ORC_TILE) * b.ntx + x / ORC_TILE;
+            pix_t o;
+            blend_pixel(P, rgb, b.list + b.start[t], b.start[t + 1] - b.start[t], x, y, 1, bl, &o);
+            for (int i = 0; i < o.n; ++i)
+                if (bl[i].w > mw[bl[i].id]) mw[bl[i].id] = bl[i].w;
+            double mk;
+            topk_of(bl, o.n, K, ids, ws, NULL, &mk);
+            for (int k = 0; k < K; ++k)
+                if (ids[k] >= 0) cnt[ids[k]] += 1;
+        }
+#pragma omp critical
+        {
+            if (cnt && mw)
+                for (int g = 0; g < n; ++g) {
+                    count[g] += cnt[g];
+                    if (mw[g] > maxw[g]) maxw[g] = mw[g];
+                }
+        }
+        free(bl);
+        free(cnt);
+        free(mw);
+    }
+    free_bins(&b);
+    free(P);
+    return err;
+}
+
 /* Eq. 3-4: F[p] = sum_k (w_k / W) f_{id_k}, W = sum_k w_k, F = 0 where W = 0. */
 int orc_feature(long n_pix, int K, int D, const int *ids, const double *w, const double *feat,
                 double *F)

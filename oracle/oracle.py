@@ -42,6 +42,7 @@ def lib():
         L.orc_project.argtypes = [I, P, P, P, P, P, P, I, I, P, P, P, P, P, P, P, P]
         L.orc_render.argtypes = [I, P, P, P, P, P, P, I, I, I, I, P, P, P, P, P, P, P, P, P]
         L.orc_feature.argtypes = [Lg, I, I, P, P, P, P]
+        L.orc_prune_stats.argtypes = [I, P, P, P, P, P, P, I, I, I, P, P]
         L.orc_backward.argtypes = [I, P, P, P, P, P, P, I, I, I, I, P, P, P, P, P,
                                    P, P, P, P, P, P, P, P, P, P, P]
         L.orc_bf16_from_f32.argtypes = [Lg, P, P]
@@ -55,7 +56,7 @@ def lib():
         L.orc_feature_backward.argtypes = [Lg, I, I, I, P, P, P, P, P, P]
         for f in (L.orc_project, L.orc_render, L.orc_feature, L.orc_backward,
                   L.orc_bf16_from_f32, L.orc_fp8_quantize, L.orc_e4m3_table, L.orc_num_threads,
-                  L.orc_topk_select, L.orc_feature_backward):
+                  L.orc_topk_select, L.orc_feature_backward, L.orc_prune_stats):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -118,6 +119,20 @@ def render(g, cam, K, brute=False):
         raise RuntimeError(f"orc_render failed: {rc}")
     assert P == out["D"].size
     return out
+
+
+def prune_stats(g, cam, K, count=None, maxw=None):
+    """Sec. 3.3 statistics of one view (Eq. 5), accumulated into count (int32 [n],
+    Top-K participation) and maxw (float64 [n], the largest blending weight)."""
+    n = g.means.shape[0]
+    count = np.zeros(n, np.int32) if count is None else count
+    maxw = np.zeros(n) if maxw is None else maxw
+    geo = _geom(g)
+    rc = lib().orc_prune_stats(n, *[_p(a) for a in geo], _p(cam_array(cam)), cam.W, cam.H, int(K), _p(count),
+                               _p(maxw))
+    if rc:
+        raise RuntimeError(f"orc_prune_stats failed: {rc}")
+    return count, maxw
 
 
 def feature(ids, w, feat64):

@@ -296,6 +296,100 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
     }
 }
 
+// Pruning statistics of Sec. 3.3 for one view: every pixel adds one to the Top-K
+// count of each Gaussian in its Top-K list, and every blended (pixel, Gaussian) pair
+// raises that Gaussian's score S_i = max w (Eq. 5) to its weight.  The blend is replayed
+// front to back up to n_contrib with the forward's own arithmetic, so each weight is
+// bit-identical to the one the forward blended.  Per Gaussian the block takes a wave
+// maximum (weights are >= 0, so the FP32 bits order like integers) and issues one
+// atomic max per wave; the counts are gathered per wave and id first as well, so a
+// Gaussian in many lists does not take one atomic per pixel.
+template <int K>
+__global__ __launch_bounds__(kFwdThreads) void prune_stats_kernel(RasterArgs a, const int *__restrict__ n_contrib,
+                                                                  const int *__restrict__ topk_ids,
+                                                                  int *__restrict__ topk_count,
+                                                                  float *__restrict__ max_w) {
+    __shared__ int s_id[256];
+    __shared__ float2 s_xy[256];
+    __shared__ float4 s_co[256];
+    __shared__ int s_max;
+    const int ntiles = a.ntx * a.nty;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int t = threadIdx.x, lane = t & 63;
+    const int px = (tile % a.ntx) * kTile + (t & 15);
+    const int py0 = (tile / a.ntx) * kTile + (t >> 4);
+    const float fx = (float)px + 0.5f;
+    const int2 rg = a.ranges[tile];
+    float fy[2], T[2];
+    int last[2];
+    if (t == 0) s_max = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int py = py0 + 8 * h;
+        const bool valid = px < a.W && py < a.H;
+        const long p = (long)py * a.W + px;
+        fy[h] = (float)py + 0.5f;
+        T[h] = 1.0f;
+        last[h] = valid ? n_contrib[p] : 0;
+        for (int k = 0; k < K; ++k) {
+            int id = valid ? topk_ids[p * K + k] : -1;
+            // one atomic per distinct id of the wave (the loop is uniform over the wave)
+            while (true) {
+                const uint64_t pend = __ballot(id >= 0);
+                if (pend == 0ull) break;
+                const int src = (int)__builtin_ctzll(pend);
+                const int g = __builtin_amdgcn_readlane(id, src);
+                const uint64_t same = __ballot(id == g);
+                if (lane == src) atomicAdd(&topk_count[g], (int)__popcll(same));
+                if (id == g) id = -1;
+            }
+        }
+    }
+    __syncthreads();
+    atomicMax(&s_max, max(last[0], last[1]));
+    __syncthreads();
+    const int maxl = s_max;
+    for (int base = 0; base < maxl; base += 256) {
+        const int cnt = min(256, maxl - base);
+        __syncthreads();
+        for (int q = t; q < cnt; q += kFwdThreads) {
+            const int g = a.sorted_ids[rg.x + base + q];
+            s_id[q] = g;
+            s_xy[q] = a.mean2d[g];
+            s_co[q] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const float2 m = s_xy[j];
+            const float4 co = s_co[j];
+            float wm = 0.f;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (base + j >= last[h]) continue;
+                float dx, dy, raw, ex;
+                const float alpha = blend_alpha(fx, fy[h], m.x, m.y, co.x, co.y, co.z, co.w, dx, dy, raw, ex);
+                if (alpha < kAlphaMin) continue;
+                const float w = alpha * T[h];
+                T[h] = T[h] * (1.0f - alpha);
+                wm = fmaxf(wm, w);
+            }
+            // every lane takes part in the reduction
+            if (__ballot(wm > 0.f) == 0ull) continue;
+            wm = fmaxf(wm, dpp_mov<0xB1>(wm));
+            wm = fmaxf(wm, dpp_mov<0x4E>(wm));
+            wm = fmaxf(wm, dpp_mov<0x141>(wm));
+            wm = fmaxf(wm, dpp_mov<0x140>(wm));
+            const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wm), 0));
+            const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wm), 16));
+            const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wm), 32));
+            const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wm), 48));
+            const float wmax = fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+            if (lane == 0 && wmax > 0.f) atomicMax((int *)max_w + s_id[j], __float_as_int(wmax));
+        }
+    }
+}
+
 template <int K>
 void launch_fwd(RasterArgs a, float *color, float *depth_map, float *alpha_map, float *T_final,
                 int *n_contrib, int *topk_ids, float *topk_w, hipStream_t st) {
@@ -311,6 +405,12 @@ void launch_bwd(RasterArgs a, const float *T_final, const int *n_contrib, const 
     hipLaunchKernelGGL(raster_bwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(kBwdThreads), 0,
                        st, a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha,
                        gm, gc, go, grgb, gz);
+}
+
+template <int K>
+void launch_prune(RasterArgs a, const int *n_contrib, const int *topk_ids, int *count, float *max_w, hipStream_t st) {
+    hipLaunchKernelGGL(prune_stats_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(kFwdThreads), 0, st,
+                       a, n_contrib, topk_ids, count, max_w);
 }
 
 #define LGS_K_SWITCH(k, CALL)            \
@@ -379,4 +479,26 @@ extern "C" lgs_status lgs_rasterize_topk_bwd(
     LGS_K_SWITCH(k, CALL_BWD)
 #undef CALL_BWD
     return check_launch("rasterize_topk_bwd");
+}
+
+extern "C" lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const float *mean2d, const float *conic,
+                                      const float *opacity, const int32_t *sorted_ids,
+                                      const int32_t *tile_ranges, const int32_t *n_contrib,
+                                      const int32_t *topk_ids, int32_t *topk_count, float *max_w,
+                                      hipStream_t stream) {
+    lgs_status st = check_camera(cam);
+    if (st) return st;
+    LGS_REQUIRE(k_supported(k), LGS_ERR_UNSUPPORTED, "K = %d is not compiled", k);
+    LGS_REQUIRE(mean2d && conic && opacity && sorted_ids && tile_ranges && n_contrib && topk_ids && topk_count &&
+                    max_w,
+                LGS_ERR_INVALID_ARG, "lgs_prune_stats: NULL pointer");
+    LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && ((uintptr_t)tile_ranges & 7u) == 0 && ((uintptr_t)max_w & 3u) == 0,
+                LGS_ERR_INVALID_ARG, "mean2d and tile_ranges must be 8-byte aligned, max_w 4-byte aligned");
+    RasterArgs a{cam->width, cam->height, tiles_x(cam->width), tiles_y(cam->height),
+                 (const float2 *)mean2d, conic, opacity, nullptr, nullptr, sorted_ids,
+                 (const int2 *)tile_ranges};
+#define CALL_PRUNE(KK) launch_prune<KK>(a, n_contrib, topk_ids, topk_count, max_w, stream)
+    LGS_K_SWITCH(k, CALL_PRUNE)
+#undef CALL_PRUNE
+    return check_launch("prune_stats");
 }

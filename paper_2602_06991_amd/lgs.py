@@ -68,6 +68,7 @@ _SIG = {
                                ctypes.c_int, _P, _P, _P, _P],
     "lgs_feature_render_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                   ctypes.c_int, _P, _F, _P, _P, _P],
+    "lgs_prune_stats": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_feature_render_fwd_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                       ctypes.c_int, _P, _P, _F, _P, _P, _P],
     "lgs_rasterize_topk_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -197,6 +198,12 @@ def lgs_feature_render_fwd_bwd_l1(width, height, views, k, d, feat_dt, feat, fea
     return _check(load().lgs_feature_render_fwd_bwd_l1(width, height, views, k, d, feat_dt, feat,
                                                        feat_scale, topk_ids, topk_w, map_dt, F, F_target,
                                                        scale, dL_dfeat, dL_dtopkw, stream))
+
+
+def lgs_prune_stats(cam, k, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib, topk_ids, topk_count,
+                    max_w, stream=None):
+    return _check(load().lgs_prune_stats(ctypes.byref(cam), k, mean2d, conic, opacity, sorted_ids, tile_ranges,
+                                         n_contrib, topk_ids, topk_count, max_w, stream))
 
 
 def lgs_rasterize_topk_bwd(cam, k, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,

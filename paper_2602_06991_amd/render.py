@@ -119,6 +119,14 @@ def rasterize(cam, K, proj, rgb, sorted_ids, ranges):
     return out
 
 
+def prune_stats(cam, K, proj, sorted_ids, ranges, fwd, topk_count, max_w):
+    """Sec. 3.3 statistics of one view, accumulated: Top-K participation counts
+    (int32 [N]) and the maximum blending weight S (FP32 [N], Eq. 5)."""
+    _need_cuda(topk_count, max_w)
+    lgs.lgs_prune_stats(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]), _p(sorted_ids),
+                        _p(ranges), _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(topk_count), _p(max_w), _stream())
+
+
 def quantize(feat, dtype):
     """FP32 [N,D] -> storage (bf16 tensor, or (uint8 codes, f32 scale) for fp8)."""
     n, d = feat.shape

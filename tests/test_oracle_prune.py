@@ -1,0 +1,69 @@
+"""Pins of the oracle's pruning statistics (Sec. 3.3, Eq. 5): Top-K participation
+counts and the largest blending weight S_g of every Gaussian."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2602_06991_amd.scenegen import Gaussians, identity_camera, make_scene, make_tiny
+
+
+def _gs(means, log_scales, quats, opls, rgbs, feats):
+    f = lambda a: np.ascontiguousarray(np.array(a, np.float32))
+    return Gaussians(f(means), f(log_scales), f(quats), f(opls), f(rgbs), f(feats))
+
+
+@pytest.mark.parametrize("opl", [0.3, 2.0, 6.0])
+def test_single_gaussian_peak_weight(orc, opl):
+    # mean2D on the centre of pixel (8, 8): there sigma = 0, so the largest weight the
+    # Gaussian reaches is its clamped opacity min(0.99, o); it is counted at every
+    # pixel where it is blended (the only candidate, so always in the Top-K)
+    cam = identity_camera(16, 16, f=16.0)
+    z = 2.0
+    g = _gs([[0.5 / 16 * z, 0.5 / 16 * z, z]], [np.log([0.08, 0.05, 0.05])], [[1, 0, 0, 0]], [opl],
+            [[1, 1, 1]], [[1, 0]])
+    np.testing.assert_allclose(orc.project(g, cam)["mean2d"], [[8.5, 8.5]], atol=1e-12)
+    o = 1.0 / (1.0 + math.exp(-float(np.float32(opl))))
+    count, maxw = orc.prune_stats(g, cam, 4)
+    assert maxw[0] == pytest.approx(min(0.99, o), rel=1e-15)
+    r = orc.render(g, cam, 4)
+    assert count[0] == int((r["O"] > 0).sum()) > 1
+
+
+@pytest.mark.parametrize("K", [1, 4, 8])
+def test_counts_are_topk_memberships(orc, K):
+    sc = make_scene(0)
+    g, cam = sc.gaussians, sc.cameras[0]
+    count, _ = orc.prune_stats(g, cam, K)
+    r = orc.render(g, cam, K)
+    ids = r["ids"].reshape(-1)
+    assert count.sum() == int((ids >= 0).sum())
+    np.testing.assert_array_equal(count, np.bincount(ids[ids >= 0], minlength=g.n))
+    assert count.max() <= cam.W * cam.H
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_peak_weight_is_the_largest_blended_weight(orc, seed):
+    # with K above every pixel's blended count the Top-K lists hold every blended
+    # Gaussian and its weight, so S_g is the largest listed weight of g
+    g, cam = make_tiny(seed, n=[30, 50, 64][seed], W=40, H=32, scale=(-2.3, 0.7))
+    r = orc.render(g, cam, 63)
+    assert r["nblend"].max() < 63
+    _, maxw = orc.prune_stats(g, cam, 4)
+    ids, w = r["ids"].reshape(-1), r["w"].reshape(-1)
+    want = np.zeros(g.n)
+    np.maximum.at(want, ids[ids >= 0], w[ids >= 0])
+    np.testing.assert_array_equal(maxw, want)
+    assert (want > 0).sum() > g.n // 2
+
+
+def test_statistics_accumulate_over_views(orc):
+    sc = make_scene(3, N=20000, W=96, H=64)
+    g = sc.gaussians
+    c1, m1 = orc.prune_stats(g, sc.cameras[0], 4)
+    c2, m2 = orc.prune_stats(g, sc.cameras[1], 4)
+    c, m = orc.prune_stats(g, sc.cameras[0], 4)
+    orc.prune_stats(g, sc.cameras[1], 4, c, m)
+    np.testing.assert_array_equal(c, c1 + c2)
+    np.testing.assert_array_equal(m, np.maximum(m1, m2))
+    assert np.all((m > 0) >= (c > 0))      # a Top-K member is blended somewhere
