@@ -348,10 +348,14 @@ def main():
         st = step.last
         prune_ms = timed(torch, lambda: render.prune_stats(cam, K, st["proj"], st["ids"], st["ranges"], fw, cnt,
                                                            mxw))
-        del cnt, mxw
+        # and the Eq. 6 survival draw over the Gaussians never in a Top-K list, keeping half
+        gen = torch.Generator(device="cuda").manual_seed(5)
+        expo = torch.empty(P["feat"].shape[0], device="cuda").exponential_(generator=gen)
+        select_ms = timed(torch, lambda: render.prune_select(cnt, mxw, 1, expo, 0.5))
+        del cnt, mxw, expo
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
                              bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
-                             prune_ms=prune_ms,
+                             prune_ms=prune_ms, select_ms=select_ms,
                              tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
         print(f"# {form}: {ms:.3f} ms/step, U={U}, pairs={step.last['pairs']}, phases "
               + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()), file=sys.stderr, flush=True)
@@ -422,6 +426,7 @@ def main():
                                                 v["phases"]["rasterize_topk_fwd"] +
                                                 v["separate"]["feature_render_fwd"], 4),
                       "prune_stats_ms": round(v["prune_ms"], 4),
+                      "prune_select_ms": round(v["select_ms"], 4),
                       "phases_ms": {p: round(x, 4) for p, x in v["phases"].items()},
                       "U": v["U"], "pairs": v["pairs"], "tile_union": v["tile_union"]}
                   for k, v in results.items()},

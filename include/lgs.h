@@ -274,6 +274,29 @@ lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const float *mean2d
                            float *max_w, hipStream_t stream);
 
 /*
+ * Workspace bytes of lgs_prune_select for n Gaussians.  *bytes is a host pointer.
+ */
+lgs_status lgs_prune_select_workspace(int32_t n, size_t *bytes);
+
+/*
+ * Survival sampling of the consistency pruning (Sec. 3.3, Eq. 6).  The candidate set
+ * G_prune is every Gaussian with topk_count[i] < count_below (low Top-K participation);
+ * of its c members, m = floor(keep_ratio * c) (computed in FP64) survive, drawn
+ * without replacement with probabilities proportional to S_i = max_w[i]: with the
+ * caller's exponential variates expo[i] (E_i >= 0, i.i.d. Exp(1) for a fair draw) the
+ * survivors are the m candidates with the smallest key E_i / S_i (divided in FP64,
+ * rounded once to FP32; +inf when S_i = 0), equal keys taken in index order.  The first survivor is then
+ * candidate i with probability S_i / sum_j S_j, which is Eq. 6.
+ * Out: survive[n] (uint8, overwritten): 1 for every non-candidate and every drawn
+ * candidate, 0 for the candidates to remove.  workspace: ws_bytes >=
+ * lgs_prune_select_workspace(n), 256-byte aligned.  keep_ratio in [0, 1]; the paper
+ * keeps half (0.5).  Asynchronous: the whole draw runs on the device.
+ */
+lgs_status lgs_prune_select(int32_t n, const int32_t *topk_count, const float *max_w, int32_t count_below,
+                            const float *expo, float keep_ratio, void *workspace, size_t ws_bytes,
+                            uint8_t *survive, hipStream_t stream);
+
+/*
  * Storage quantization of the feature table (the precision forms of the renderer):
  * dst_dt = BF16: round-to-nearest-even; dst_dt = FP8_E4M3: per row, scale
  * s = 2^floor(log2(amax / 224)) (s = 1 for an all-zero row) so x / s is exact and

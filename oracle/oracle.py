@@ -7,6 +7,7 @@ the HIP library.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -133,6 +134,31 @@ def prune_stats(g, cam, K, count=None, maxw=None):
     if rc:
         raise RuntimeError(f"orc_prune_stats failed: {rc}")
     return count, maxw
+
+
+def prune_select(count, maxw, count_below, expo, keep_ratio):
+    """Survival draw of the consistency pruning (Sec. 3.3, Eq. 6), from its definition:
+    candidates are the Gaussians with count < count_below; m = floor(keep_ratio * c)
+    of the c candidates survive, drawn without replacement with weights S = maxw by
+    exponential keys E / S (E the given Exp(1) variates; FP64 quotient rounded to
+    FP32; +inf where S = 0), the m smallest keys surviving, ties in index order.
+    Returns uint8 [n]: 1 keep, 0 remove."""
+    count = np.asarray(count)
+    n = count.shape[0]
+    cand = count < count_below
+    c = int(cand.sum())
+    m = int(math.floor(float(np.float32(keep_ratio)) * c))
+    e = np.asarray(expo, np.float32).astype(np.float64)
+    s = np.asarray(maxw, np.float32).astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        q = (e / np.where(s > 0, s, 1.0)).astype(np.float32)
+    key = np.where(s > 0, q.view(np.uint32), np.uint32(0x7F800000))
+    idx = np.nonzero(cand)[0]
+    order = idx[np.lexsort((idx, key[idx]))]
+    survive = np.ones(n, np.uint8)
+    survive[cand] = 0
+    survive[order[:m]] = 1
+    return survive
 
 
 def feature(ids, w, feat64):

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblgs.so")
-SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "feature.hip"]
+SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "feature.hip", "prune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

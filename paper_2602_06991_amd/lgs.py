@@ -69,6 +69,8 @@ _SIG = {
     "lgs_feature_render_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                   ctypes.c_int, _P, _F, _P, _P, _P],
     "lgs_prune_stats": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_prune_select_workspace": [_I32, ctypes.POINTER(ctypes.c_size_t)],
+    "lgs_prune_select": [_I32, _P, _P, _I32, _P, _F, _P, ctypes.c_size_t, _P, _P],
     "lgs_feature_render_fwd_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                       ctypes.c_int, _P, _P, _F, _P, _P, _P],
     "lgs_rasterize_topk_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -204,6 +206,18 @@ def lgs_prune_stats(cam, k, mean2d, conic, opacity, sorted_ids, tile_ranges, n_c
                     max_w, stream=None):
     return _check(load().lgs_prune_stats(ctypes.byref(cam), k, mean2d, conic, opacity, sorted_ids, tile_ranges,
                                          n_contrib, topk_ids, topk_count, max_w, stream))
+
+
+def lgs_prune_select_workspace(n):
+    b = ctypes.c_size_t(0)
+    _check(load().lgs_prune_select_workspace(n, ctypes.byref(b)))
+    return b.value
+
+
+def lgs_prune_select(n, topk_count, max_w, count_below, expo, keep_ratio, workspace, ws_bytes, survive,
+                     stream=None):
+    return _check(load().lgs_prune_select(n, topk_count, max_w, count_below, expo, keep_ratio, workspace,
+                                          ws_bytes, survive, stream))
 
 
 def lgs_rasterize_topk_bwd(cam, k, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,

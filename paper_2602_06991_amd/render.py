@@ -127,6 +127,19 @@ def prune_stats(cam, K, proj, sorted_ids, ranges, fwd, topk_count, max_w):
                         _p(ranges), _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(topk_count), _p(max_w), _stream())
 
 
+def prune_select(topk_count, max_w, count_below, expo, keep_ratio=0.5):
+    """Eq. 6 survival draw over the candidates topk_count < count_below: returns a
+    uint8 [N] mask, 1 = keep.  expo: the caller's Exp(1) variates, FP32 [N]."""
+    n = topk_count.shape[0]
+    _need_cuda(topk_count, max_w, expo)
+    need = lgs.lgs_prune_select_workspace(n)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=topk_count.device)
+    survive = torch.empty(n, dtype=torch.uint8, device=topk_count.device)
+    lgs.lgs_prune_select(n, _p(topk_count), _p(max_w), int(count_below), _p(expo), float(keep_ratio), _p(ws),
+                         ws.numel(), _p(survive), _stream())
+    return survive
+
+
 def quantize(feat, dtype):
     """FP32 [N,D] -> storage (bf16 tensor, or (uint8 codes, f32 scale) for fp8)."""
     n, d = feat.shape

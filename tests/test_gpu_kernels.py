@@ -467,3 +467,22 @@ def test_one_pass_render_and_l1_adjoint(torch, orc, K, fdt, mdt, views, H, W, D,
     assert np.all(df[~touched] == 0)
     scl = np.abs(d_w).max(-1, keepdims=True) + 1e-12
     assert (np.abs(t3.cpu().numpy() - d_w) / scl).max() <= 1e-4
+
+
+@pytest.mark.parametrize("n,below,ratio,seed", [(1, 1, 0.5, 0), (1000, 3, 0.5, 1), (300000, 4, 0.5, 2),
+                                                 (300000, 2, 0.0, 3), (300000, 5, 1.0, 4), (70001, 100, 0.37, 5)])
+def test_prune_select_matches_oracle(torch, orc, n, below, ratio, seed):
+    """The Eq. 6 survival draw on seeded inputs (counts, importances with zeros and
+    exact key ties, exponential variates): the survive mask bit for bit."""
+    from paper_2602_06991_amd import render
+    rng = np.random.default_rng(seed)
+    count = rng.integers(0, 8, n).astype(np.int32)
+    S = np.where(rng.random(n) < 0.1, 0.0, rng.choice([0.25, 0.5, 1.0, 0.3], n) * rng.random(n) ** 2)
+    S = np.where(rng.random(n) < 0.3, 0.5, S).astype(np.float32)
+    E = np.where(rng.random(n) < 0.3, 1.0, rng.exponential(size=n)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    got = render.prune_select(dev(count), dev(S), below, dev(E), ratio).cpu().numpy()
+    want = orc.prune_select(count, S, below, E, ratio)
+    cand = count < below
+    print(f"n={n}: candidates {cand.sum()}, survivors among them {want[cand].sum()}", flush=True)
+    np.testing.assert_array_equal(got, want)

@@ -67,3 +67,44 @@ def test_statistics_accumulate_over_views(orc):
     np.testing.assert_array_equal(c, c1 + c2)
     np.testing.assert_array_equal(m, np.maximum(m1, m2))
     assert np.all((m > 0) >= (c > 0))      # a Top-K member is blended somewhere
+
+
+def test_first_survivor_follows_eq6(orc):
+    # one survivor out of four candidates: over many draws candidate i is picked with
+    # probability S_i / sum S (Eq. 6); two non-candidates always survive
+    S = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 0.5], np.float32)
+    count = np.array([0, 1, 0, 2, 9, 9], np.int32)
+    rng = np.random.default_rng(42)
+    trials = 40000
+    hits = np.zeros(6)
+    for _ in range(trials):
+        s = orc.prune_select(count, S, 3, rng.exponential(size=6).astype(np.float32), 0.25)
+        assert s[4] == 1 and s[5] == 1 and s[:4].sum() == 1
+        hits += s
+    p = S[:4] / S[:4].sum()
+    sd = np.sqrt(p * (1 - p) / trials)
+    assert np.all(np.abs(hits[:4] / trials - p) <= 4 * sd), (hits[:4] / trials, p)
+
+
+def test_survivors_hold_the_smallest_keys(orc):
+    rng = np.random.default_rng(7)
+    n = 5000
+    count = rng.integers(0, 6, n).astype(np.int32)
+    S = rng.choice([0.0, 0.25, 0.5, 1.0], n).astype(np.float32)      # zeros and many ties
+    E = rng.choice([0.5, 1.0, 2.0], n).astype(np.float32)
+    for ratio in (0.0, 0.3, 0.5, 1.0):
+        s = orc.prune_select(count, S, 3, E, ratio)
+        cand = count < 3
+        assert np.all(s[~cand] == 1)
+        assert s[cand].sum() == int(np.floor(np.float64(np.float32(ratio)) * cand.sum()))
+        key = np.where(S > 0, E / np.where(S > 0, S, 1), np.inf)
+        kept, gone = cand & (s == 1), cand & (s == 0)
+        if kept.any() and gone.any():
+            assert key[kept].max() <= key[gone].min()
+            kt = key[kept].max()
+            # at the threshold key the kept ones come first in index order
+            at = np.nonzero(cand & (key == kt))[0]
+            assert np.all(np.diff(s[at].astype(int)) <= 0)
+        # a zero-importance candidate goes before any positive one
+        if gone.any() and (S[kept] == 0).any():
+            assert np.all(S[gone] == 0)
