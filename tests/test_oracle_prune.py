@@ -108,3 +108,12 @@ def test_survivors_hold_the_smallest_keys(orc):
         # a zero-importance candidate goes before any positive one
         if gone.any() and (S[kept] == 0).any():
             assert np.all(S[gone] == 0)
+
+
+def test_survivor_count_rounds_down(orc):
+    # 5 candidates at ratio 0.75: 3.75 -> 3 survivors (the share is rounded down)
+    count = np.array([0, 0, 0, 0, 0, 7, 7], np.int32)
+    S = np.ones(7, np.float32)
+    E = np.arange(1, 8, dtype=np.float32)
+    s = orc.prune_select(count, S, 1, E, 0.75)
+    np.testing.assert_array_equal(s, [1, 1, 1, 0, 0, 1, 1])
