@@ -17,7 +17,10 @@ All inputs are resident in HBM before timing starts.
 
 Prints one JSON line (metric, value = BF16 fwd+bwd ms per frame, roofline of the
 dominant feature kernel from live HIP-event timings, and the FP64 oracle's CPU time
-for one full frame of the same workload).
+for one full frame of the same workload).  Per form it also reports: the forward
+alone, the render and the L1 adjoint as two separate launches, a geometry-only step
+(the hybrid schedule's geometry iterations: no feature passes), the pruning
+statistics and the survival draw; and once the achievable copy bandwidth.
 """
 from __future__ import annotations
 
@@ -57,9 +60,10 @@ def parse():
 class Step:
     """All buffers of one frame's forward + backward, reused across steps."""
 
-    def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form, fused=True):
+    def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form, fused=True, geometry_only=False):
         self.t, self.render, self.lgs = torch, render, lgs
         self.fused = fused
+        self.geometry_only = geometry_only   # the hybrid schedule's geometry iterations (Sec. 3.4)
         self.P, self.target, self.cam, self.K, self.form = scene_dev, target, cam, K, form
         self.map = "f32" if form == "f32" else "bf16"
         self.binner = render.Binner(sync=False)   # no host round trip inside the step
@@ -83,7 +87,9 @@ class Step:
     def __call__(self):
         r, P, c = self.render, self.P, self.cam
         self._mark("start")
-        if self.form == "f32":
+        if self.geometry_only:
+            store, scale = None, None
+        elif self.form == "f32":
             store, scale = P["feat"], None
         else:
             store, scale = r.quantize(P["feat"], self.form)
@@ -94,14 +100,16 @@ class Step:
         self._mark("bin_sort")
         fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges)
         self._mark("rasterize_topk_fwd")
-        if not self.fused:
+        F = None
+        if not self.fused and not self.geometry_only:
             F = r.feature_fwd(fw["ids"], fw["w"], store, scale, self.form, self.map)
             self._mark("feature_render_fwd")
         tC, tD, tF = self.target
         gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
         gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
         self._mark("l1_grad")
-        self.dfeat.zero_()
+        if not self.geometry_only:
+            self.dfeat.zero_()
         for v in self.sg.values():
             v.zero_()
         for v in self.pg.values():
@@ -112,7 +120,9 @@ class Step:
             ka = self.t.cuda.Event(enable_timing=True)
             ka.record()
         fscale = 1.0 / (self.npix * self.d)
-        if self.fused:
+        if self.geometry_only:
+            dtw = None
+        elif self.fused:
             F, dtw = r.feature_fwd_bwd_l1(fw["ids"], fw["w"], store, scale, self.form, self.map, tF, fscale,
                                           self.dfeat)
         else:
@@ -122,7 +132,8 @@ class Step:
             kb = self.t.cuda.Event(enable_timing=True)
             kb.record()
             self.kmarks.append((ka, kb))
-        self._mark("feature_render_fwd_bwd" if self.fused else "feature_render_bwd")
+        if not self.geometry_only:
+            self._mark("feature_render_fwd_bwd" if self.fused else "feature_render_bwd")
         r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg)
         self._mark("rasterize_topk_bwd")
         r.project_bwd(c, P, self.sg, self.pg)
@@ -348,6 +359,11 @@ def main():
         st = step.last
         prune_ms = timed(torch, lambda: render.prune_stats(cam, K, st["proj"], st["ids"], st["ranges"], fw, cnt,
                                                            mxw))
+        # the hybrid schedule's geometry-only iterations: no feature passes, no gamma term
+        geo = Step(torch, render, lgs, P, target, cam, K, form, fused, geometry_only=True)
+        geo_ms, _, _ = time_steps(torch, geo, args.steps, args.warmup)
+        assert geo.binner.count()[1], "pair buffer overflowed during timing"
+        del geo
         # and the Eq. 6 survival draw over the Gaussians never in a Top-K list, keeping half
         gen = torch.Generator(device="cuda").manual_seed(5)
         expo = torch.empty(P["feat"].shape[0], device="cuda").exponential_(generator=gen)
@@ -355,7 +371,7 @@ def main():
         del cnt, mxw, expo
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
                              bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
-                             prune_ms=prune_ms, select_ms=select_ms,
+                             prune_ms=prune_ms, select_ms=select_ms, geo_ms=geo_ms,
                              tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
         print(f"# {form}: {ms:.3f} ms/step, U={U}, pairs={step.last['pairs']}, phases "
               + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()), file=sys.stderr, flush=True)
@@ -425,6 +441,7 @@ def main():
                       "fwd_ms_per_frame": round(v["phases"]["project_fwd"] + v["phases"]["bin_sort"] +
                                                 v["phases"]["rasterize_topk_fwd"] +
                                                 v["separate"]["feature_render_fwd"], 4),
+                      "geometry_only_ms_per_frame": round(v["geo_ms"], 4),
                       "prune_stats_ms": round(v["prune_ms"], 4),
                       "prune_select_ms": round(v["select_ms"], 4),
                       "phases_ms": {p: round(x, 4) for p, x in v["phases"].items()},
