@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--K", type=int, default=4)
-    ap.add_argument("--sweep", action="store_true", help="also time K = 1 and 8")
+    ap.add_argument("--no-sweep", dest="sweep", action="store_false", help="skip the K = 1 and 8 steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bf16,f32")
     ap.add_argument("--feature-path", choices=("fused", "separate"), default="fused",
@@ -161,7 +161,7 @@ def time_steps(torch, step, steps, warmup):
     total_ms = t0.elapsed_time(t1)
     kern = [a.elapsed_time(b) for a, b in step.kmarks]
     step.kmarks = None
-    phases = {}
+    phases, per_step = {}, []
     for _ in range(steps):
         step.events = []
         step()
@@ -169,8 +169,11 @@ def time_steps(torch, step, steps, warmup):
         ev = step.events
         for (_, a), (name, b) in zip(ev[:-1], ev[1:]):
             phases.setdefault(name, []).append(a.elapsed_time(b))
+        per_step.append(ev[0][1].elapsed_time(ev[-1][1]))
     step.events = None
-    return total_ms / steps, {k: float(np.median(v)) for k, v in phases.items()}, float(np.mean(kern))
+    # spread of single steps (from the pass with per-phase events, so a few us higher)
+    dist = {f"p{q}": round(float(np.percentile(per_step, q)), 4) for q in (10, 50, 90)}
+    return total_ms / steps, {k: float(np.median(v)) for k, v in phases.items()}, float(np.mean(kern)), dist
 
 
 def counter_traffic(kernel, workload_ok):
@@ -341,7 +344,7 @@ def main():
         del tproj, tb, tids, tranges, tfw, tstore, tscale, tF
         fused = args.feature_path == "fused"
         step = Step(torch, render, lgs, P, target, cam, K, form, fused)
-        ms, phases, kern_ms = time_steps(torch, step, args.steps, args.warmup)
+        ms, phases, kern_ms, dist = time_steps(torch, step, args.steps, args.warmup)
         pairs, fitted = step.binner.count()
         assert fitted, "pair buffer overflowed during timing"
         step.last["pairs"] = pairs
@@ -361,7 +364,7 @@ def main():
                                                            mxw))
         # the hybrid schedule's geometry-only iterations: no feature passes, no gamma term
         geo = Step(torch, render, lgs, P, target, cam, K, form, fused, geometry_only=True)
-        geo_ms, _, _ = time_steps(torch, geo, args.steps, args.warmup)
+        geo_ms, _, _, _ = time_steps(torch, geo, args.steps, args.warmup)
         assert geo.binner.count()[1], "pair buffer overflowed during timing"
         del geo
         # and the Eq. 6 survival draw over the Gaussians never in a Top-K list, keeping half
@@ -371,7 +374,7 @@ def main():
         del cnt, mxw, expo
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
                              bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
-                             prune_ms=prune_ms, select_ms=select_ms, geo_ms=geo_ms,
+                             prune_ms=prune_ms, select_ms=select_ms, geo_ms=geo_ms, dist=dist,
                              tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
         print(f"# {form}: {ms:.3f} ms/step, U={U}, pairs={step.last['pairs']}, phases "
               + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()), file=sys.stderr, flush=True)
@@ -391,7 +394,7 @@ def main():
                 tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp)
                 step = Step(torch, render, lgs, P, (tfw["C"].clone(), tfw["D"].clone(), tF.clone()), cam,
                             k2, form, args.feature_path == "fused")
-                ms, ph, _ = time_steps(torch, step, max(5, args.steps // 2), 2)
+                ms, ph, _, _ = time_steps(torch, step, max(5, args.steps // 2), 2)
                 assert step.binner.count()[1], "pair buffer overflowed during timing"
                 sweep[f"K{k2}_{form}"] = dict(ms_per_frame=round(ms, 4), feature_fwd_bwd_ms=round(feature_ms(ph), 4))
                 del step
@@ -441,6 +444,11 @@ def main():
                       "fwd_ms_per_frame": round(v["phases"]["project_fwd"] + v["phases"]["bin_sort"] +
                                                 v["phases"]["rasterize_topk_fwd"] +
                                                 v["separate"]["feature_render_fwd"], 4),
+                      "step_ms_percentiles": v["dist"],
+                      # the render's own fwd+bwd: without the storage quantization of the
+                      # master features and the caller's gradient zeroing
+                      "ms_per_frame_excl_quantize_zeroing": round(sum(x for p, x in v["phases"].items()
+                                                                      if p not in ("quantize", "zero_grads")), 4),
                       "geometry_only_ms_per_frame": round(v["geo_ms"], 4),
                       "prune_stats_ms": round(v["prune_ms"], 4),
                       "prune_select_ms": round(v["select_ms"], 4),
