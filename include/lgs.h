@@ -10,9 +10,9 @@
  * Conventions shared by every entry point
  *  - Pointers are DEVICE pointers unless marked (host).  Arrays are row-major and
  *    contiguous.  Per-pixel arrays are indexed p = y * width + x ("pixel-major").
- *  - The caller owns every buffer.  The library never allocates device memory
- *    except inside the workspace the caller passes to lgs_bin_sort, and never
- *    frees caller memory.
+ *  - The caller owns every buffer.  The library never allocates device memory (its
+ *    scratch lives in the workspaces the caller passes to lgs_bin_sort and
+ *    lgs_prune_select) and never frees caller memory.
  *  - Every call is asynchronous on `stream` (it may be NULL, the default stream),
  *    except lgs_bin_sort (unless asked not to) and lgs_bin_sort_count, which read the
  *    pair count back to the host.
