@@ -452,39 +452,56 @@ static_assert(sizeof(MfRingF) == 2048 && sizeof(MfRingB) == 4096, "ring layout")
 static_assert(sizeof(MfWaveF) == 4096 && sizeof(MfWaveB) == 4096, "wave buffer layout");
 
 // Dynamic LDS of the MFMA path: [0, R0) half of the union rows staged as BF16
-// ([16][D]) while the operands are loaded; then, in the backward, the per-wave
-// partial dot products [4][256][K] in the same place, followed by the slot table (per
-// pixel and slot: union index, Wa weight, Wd weight); in the forward the slot table
-// itself takes region 0.  Then the weight ring and the four per-wave buffers.
+// ([16][D]) while the operands are loaded; then, in the backward, the waves' partial
+// dot products in the same place, followed by the slot table (per pixel and slot:
+// union index, Wa weight, Wd weight); in the forward the slot table itself takes
+// region 0.  Then the weight ring and the four per-wave buffers.  Up to K = 4 the
+// partial dot products are kept for the whole tile ([4][256][K]) and the slot table
+// holds 32-bit indices and both weights.  Above K = 4, to stay at two blocks per CU,
+// the partials of the last two rows ([2][4][16][K]) are summed row by row into the
+// tile's dot products ([256][K]), and the slot table holds 16-bit indices and, without
+// FP8 row scales (Wa = Wd), one weight.
 __host__ __device__ inline size_t mf_align(size_t a) { return (a + 15) & ~(size_t)15; }
+__host__ __device__ constexpr bool mf_compact(int K) { return K > 4; }
 __host__ __device__ inline size_t mf_region0(int D, int K) {
-    size_t a = (size_t)16 * D * 2, b = (size_t)4 * kTilePix * K * 4;
+    size_t a = (size_t)16 * D * 2;
+    size_t b = mf_compact(K) ? (size_t)(2 * 4 * 16 + kTilePix) * K * 4 : (size_t)4 * kTilePix * K * 4;
     return mf_align(a > b ? a : b);
 }
-__host__ __device__ inline size_t mf_slots_bytes(int K) { return (size_t)3 * kTilePix * K * 4; }
+__host__ __device__ inline size_t mf_slots_bytes(int K, bool fp8) {
+    if (!mf_compact(K)) return (size_t)3 * kTilePix * K * 4;
+    return mf_align((size_t)kTilePix * K * (2 + 4 * (fp8 ? 2 : 1)));
+}
 __host__ __device__ inline size_t mf_slots_at(int D, int K, bool bwd) { return bwd ? mf_region0(D, K) : 0; }
-__host__ __device__ inline size_t mf_ring_at(int D, int K, bool bwd) {
-    const size_t a = mf_region0(D, K), b = mf_slots_bytes(K);
+__host__ __device__ inline size_t mf_ring_at(int D, int K, bool bwd, bool fp8) {
+    const size_t a = mf_region0(D, K), b = mf_slots_bytes(K, fp8);
     return bwd ? a + b : mf_align(a > b ? a : b);
 }
-__host__ __device__ inline size_t mf_waves_at(int D, int K, bool bwd) {
-    return mf_ring_at(D, K, bwd) + 3 * (bwd ? sizeof(MfRingB) : sizeof(MfRingF));
+__host__ __device__ inline size_t mf_waves_at(int D, int K, bool bwd, bool fp8) {
+    return mf_ring_at(D, K, bwd, fp8) + 3 * (bwd ? sizeof(MfRingB) : sizeof(MfRingF));
 }
-__host__ __device__ inline size_t mf_lds_bytes(int D, int K, bool bwd) {
-    return mf_waves_at(D, K, bwd) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
+__host__ __device__ inline size_t mf_lds_bytes(int D, int K, bool bwd, bool fp8) {
+    return mf_waves_at(D, K, bwd, fp8) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
 }
 
 template <int K>
 struct SlotTable {
-    int *u;
+    typename std::conditional<mf_compact(K), int16_t, int>::type *u;
     float *wa, *wd;
 };
-template <int K>
+template <int K, bool FP8>
 __device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, int D, bool bwd) {
     SlotTable<K> st;
-    st.u = (int *)(dyn + mf_slots_at(D, K, bwd));
-    st.wa = (float *)(st.u + kTilePix * K);
-    st.wd = st.wa + kTilePix * K;
+    float *w = (float *)(dyn + mf_slots_at(D, K, bwd));
+    if constexpr (mf_compact(K)) {
+        st.wa = w;
+        st.wd = FP8 ? w + kTilePix * K : w;
+        st.u = (int16_t *)(w + kTilePix * K * (FP8 ? 2 : 1));
+    } else {
+        st.u = (int *)w;
+        st.wa = w + kTilePix * K;
+        st.wd = st.wa + kTilePix * K;
+    }
     return st;
 }
 
@@ -607,7 +624,7 @@ __device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U,
     for (int k = 0; k < K; ++k) {
         st.u[t * K + k] = s.u[k];
         st.wa[t * K + k] = s.u[k] >= 0 ? s.wf[k] : 0.f;
-        st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
+        if constexpr (FT == FT_FP8 || !mf_compact(K)) st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
     }
     __syncthreads();
 }
@@ -710,9 +727,9 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
                                            const void *__restrict__ feat, uint16_t *__restrict__ F,
                                            UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const SlotTable<K> st = slot_table<K>(dyn, D, false);
-    MfRingF *ring = (MfRingF *)(dyn + mf_ring_at(D, K, false));
-    MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(D, K, false)))[wave];
+    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, D, false);
+    MfRingF *ring = (MfRingF *)(dyn + mf_ring_at(D, K, false, FT == FT_FP8));
+    MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(D, K, false, FT == FT_FP8)))[wave];
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
@@ -762,10 +779,27 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
                                             unsigned char *dyn) {
     static_assert(L1 || !SF, "the map is stored only on the L1 path");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float *sred = (float *)dyn;   // [4][256][K], once the operands are in registers
-    const SlotTable<K> st = slot_table<K>(dyn, D, true);
-    MfRingB *ring = (MfRingB *)(dyn + mf_ring_at(D, K, true));
-    MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(D, K, true)))[wave];
+    // once the operands are in registers: the waves' partial dot products, [4][256][K]
+    // (K <= 4), or those of the last two rows [2][4][16][K] and the tile's sums [256][K]
+    constexpr bool RS = mf_compact(K);
+    float *sred = (float *)dyn;
+    float *sring = (float *)dyn;
+    float *gsum = sring + 2 * 4 * 16 * K;
+    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, D, true);
+    MfRingB *ring = (MfRingB *)(dyn + mf_ring_at(D, K, true, FT == FT_FP8));
+    MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(D, K, true, FT == FT_FP8)))[wave];
+    // row r's four partials meet after the barrier of row r + 1, in a fixed order
+    auto sum_row = [&](int r) {
+        const int t = threadIdx.x;
+        if (t < 16 * K) {
+            const int i = t & 15, k = t >> 4;
+            const float *b = sring + (size_t)(r & 1) * 4 * 16 * K;
+            float v = b[(0 * 16 + i) * K + k] + b[(1 * 16 + i) * K + k];
+            v += b[(2 * 16 + i) * K + k];
+            v += b[(3 * 16 + i) * K + k];
+            gsum[(r * 16 + i) * K + k] = v;
+        }
+    };
     const MfChunks mc = mf_chunks(D, wave);
     i16x4 opA[kCPW][2][2];
     i16x8 opC[kCPW][2];
@@ -820,6 +854,8 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             i16x4 wa[2][2];
             i16x8 wd[2];
             ring_row<K>(ring, st, row, lane, wa, wd);
+            if constexpr (RS)
+                if (row > 0) sum_row(row - 1);
             f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
             for (int i = 0; i < kCPW; ++i) {
@@ -878,10 +914,16 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             const int p = row * 16 + i16;
             for (int k = g; k < K; k += 4) {
                 const int u = st.u[p * K + k];
-                sred[(wave * kTilePix + p) * K + k] = u >= 0 ? gscale * spb[u * 16 + i16] : 0.f;
+                const float val = u >= 0 ? gscale * spb[u * 16 + i16] : 0.f;
+                if constexpr (RS) sring[(((row & 1) * 4 + wave) * 16 + i16) * K + k] = val;
+                else sred[(wave * kTilePix + p) * K + k] = val;
             }
             wave_lds_sync();
         }
+    }
+    if constexpr (RS) {
+        __syncthreads();
+        sum_row(15);
     }
 
     // gradient rows: lane (i16, g) holds dFt[16 v + 4 g + r][chunk + blk_ch(b, i16)]
@@ -914,9 +956,14 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
     float gk[K], mean = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        float v = sred[(0 * kTilePix + t) * K + k] + sred[(1 * kTilePix + t) * K + k];
-        v += sred[(2 * kTilePix + t) * K + k];
-        v += sred[(3 * kTilePix + t) * K + k];
+        float v;
+        if constexpr (RS) {
+            v = gsum[t * K + k];
+        } else {
+            v = sred[(0 * kTilePix + t) * K + k] + sred[(1 * kTilePix + t) * K + k];
+            v += sred[(2 * kTilePix + t) * K + k];
+            v += sred[(3 * kTilePix + t) * K + k];
+        }
         if constexpr (FT == FT_FP8) v *= s.u[k] >= 0 ? L.uscale2[s.u[k]] : 0.f;
         gk[k] = s.u[k] >= 0 ? v : 0.f;
         mean = fmaf(s.wp[k], gk[k], mean);
@@ -1361,7 +1408,7 @@ lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
         if (MfOk<KK, FT, MT>::v) {                                                                   \
-            lds = mf_lds_bytes(D, KK, false);                                                        \
+            lds = mf_lds_bytes(D, KK, false, FT == FT_FP8);                                          \
             ucap = (int)(lds / rb);                                                                  \
         } else {                                                                                     \
             ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);                                           \
@@ -1386,7 +1433,7 @@ lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat,
 #define CALL(KK)                                                                                     \
     case KK:                                                                                         \
         lds = kRowBudget + fallback_extra<KK, TileCfg<KK>::CPL>();                                  \
-        if (MfOk<KK, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, KK, true));                          \
+        if (MfOk<KK, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, KK, true, FT == FT_FP8));           \
         hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, MODE>), dim3(grid), dim3(kFB), lds, st, W, \
                            H, views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw, Fo);    \
         break;
