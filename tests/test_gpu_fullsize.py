@@ -10,7 +10,8 @@
 
 The oracle always renders its own Top-K; upstream gradients are seeded draws (the
 large per-pixel maps are drawn on the device with a seeded generator and only the
-sampled rows travel to the host)."""
+sampled rows travel to the host).  On the multi-view workloads the one-pass render +
+L1 adjoint is also checked against the two separate launches over all views."""
 import time
 
 import numpy as np
@@ -206,6 +207,23 @@ def _sampled_feature_parity(torch, orc, g, ids, w, views, form, seed, n_rows):
     outside = rng.integers(0, g.n, 4000)
     outside = outside[~np.isin(outside, union)]
     assert float(dfeat[torch.from_numpy(outside).cuda()].abs().max()) == 0.0
+    del dfeat, dtw
+
+    # the one-pass render + L1 adjoint over the same views (the drawn map as the
+    # target): its map and dL/dw equal the two separate launches' bit for bit
+    fs = 1.0 / (P * D)
+    d1 = torch.zeros(g.n, D, device="cuda")
+    t1 = render.feature_bwd_l1(ids_dev, w_dev, store, scale, form, "bf16", gF, fs, d1, views=views)
+    d2 = torch.zeros(g.n, D, device="cuda")
+    F2, t2 = render.feature_fwd_bwd_l1(ids_dev, w_dev, store, scale, form, "bf16", gF, fs, d2, views=views)
+    torch.cuda.synchronize()
+    assert torch.equal(F2, F)
+    assert torch.equal(t2, t1)
+    rows_t = torch.from_numpy(union).cuda()
+    a, b = d1[rows_t], d2[rows_t]
+    rel = ((a - b).norm(dim=1) / b.norm(dim=1).clamp_min(1e-30)).max().item()
+    log(f"one-pass render + L1 adjoint over {views} views: map and dL/dw identical, dL/df rows rel {rel:.2e}")
+    assert rel <= 1e-6
 
 
 @pytest.mark.timeout(500)
