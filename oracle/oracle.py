@@ -263,9 +263,21 @@ def fp8_dequant(codes, scale):
     return e4m3_table()[codes] * np.asarray(scale, np.float64)[:, None]
 
 
-def flagged(margins, eps_skip=1e-3, eps_clamp=1e-3, eps_T=1e-3, eps_topk=1e-3):
+# Decision-margin threshold of the parity tests: 4x the largest FP32 relative error
+# of a selected blending weight measured at 640x480 (5.2e-5).
+FLAG_EPS = 2.5e-4
+
+
+def flagged(margins, eps_skip=FLAG_EPS, eps_clamp=FLAG_EPS, eps_T=FLAG_EPS, eps_topk=FLAG_EPS):
     """Pixels whose alpha-skip, alpha-clamp, T-floor or Top-K rank decision came within
     the given relative distance of its threshold."""
     m = np.asarray(margins)
     return ((m[..., 0] < eps_skip) | (m[..., 1] < eps_clamp) | (m[..., 2] < eps_T) |
             (m[..., 3] < eps_topk))
+
+
+def blend_flagged(margins, eps=FLAG_EPS):
+    """Pixels where the blend itself (skip, clamp or T-floor) came within eps of a
+    threshold, so C, D and O may legitimately differ by one Gaussian's share."""
+    m = np.asarray(margins)
+    return (m[..., 0] < eps) | (m[..., 1] < eps) | (m[..., 2] < eps)
