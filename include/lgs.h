@@ -281,11 +281,12 @@ lgs_status lgs_prune_select_workspace(int32_t n, size_t *bytes);
 /*
  * Survival sampling of the consistency pruning (Sec. 3.3, Eq. 6).  The candidate set
  * G_prune is every Gaussian with topk_count[i] < count_below (low Top-K participation);
- * of its c members, m = floor(keep_ratio * c) (computed in FP64) survive, drawn
- * without replacement with probabilities proportional to S_i = max_w[i]: with the
- * caller's exponential variates expo[i] (E_i >= 0, i.i.d. Exp(1) for a fair draw) the
- * survivors are the m candidates with the smallest key E_i / S_i (divided in FP64,
- * rounded once to FP32; +inf when S_i = 0), equal keys taken in index order.  The first survivor is then
+ * of its c members, m = floor(keep_ratio * c) (the exact product, taken in integer
+ * arithmetic) survive, drawn without replacement with probabilities proportional to
+ * S_i = max_w[i]: with the caller's exponential variates expo[i] (E_i >= 0, i.i.d.
+ * Exp(1) for a fair draw) the survivors are the m candidates with the smallest key
+ * E_i / S_i (the correctly rounded FP32 quotient; +inf when S_i = 0), equal keys taken
+ * in index order.  The first survivor is then
  * candidate i with probability S_i / sum_j S_j, which is Eq. 6.
  * Out: survive[n] (uint8, overwritten): 1 for every non-candidate and every drawn
  * candidate, 0 for the candidates to remove.  workspace: ws_bytes >=

@@ -7,8 +7,8 @@ the HIP library.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
+from fractions import Fraction
 import subprocess
 
 import numpy as np
@@ -139,15 +139,17 @@ def prune_stats(g, cam, K, count=None, maxw=None):
 def prune_select(count, maxw, count_below, expo, keep_ratio):
     """Survival draw of the consistency pruning (Sec. 3.3, Eq. 6), from its definition:
     candidates are the Gaussians with count < count_below; m = floor(keep_ratio * c)
-    of the c candidates survive, drawn without replacement with weights S = maxw by
-    exponential keys E / S (E the given Exp(1) variates; FP64 quotient rounded to
-    FP32; +inf where S = 0), the m smallest keys surviving, ties in index order.
+    (the exact product of the FP32 ratio and c) of the c candidates survive, drawn
+    without replacement with weights S = maxw by exponential keys E / S (E the given
+    Exp(1) variates; the quotient correctly rounded to FP32, here an FP64 quotient
+    rounded once more, which gives the same bits since 53 >= 2*24 + 2; +inf where
+    S = 0), the m smallest keys surviving, ties in index order.
     Returns uint8 [n]: 1 keep, 0 remove."""
     count = np.asarray(count)
     n = count.shape[0]
     cand = count < count_below
     c = int(cand.sum())
-    m = int(math.floor(float(np.float32(keep_ratio)) * c))
+    m = int((Fraction(float(np.float32(keep_ratio))) * c).__floor__())
     e = np.asarray(expo, np.float32).astype(np.float64)
     s = np.asarray(maxw, np.float32).astype(np.float64)
     with np.errstate(divide="ignore", invalid="ignore"):

@@ -20,6 +20,9 @@ FLAGS = [
     # the blend's alpha must come out bit-identical in the forward and backward
     # kernels, so no floating-point contraction except the explicit fmaf calls
     "-ffp-contract=off",
+    # FP32 division and square root correctly rounded (hipcc's default, stated here
+    # because the survival draw's keys rely on it)
+    "-fhip-fp32-correctly-rounded-divide-sqrt",
     # packed FP32 instructions stay off
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

@@ -24,10 +24,11 @@ constexpr uint32_t kInfKey = 0x7F800000u;
 // candidates holding that prefix still survive; then the digit histogram [256]
 constexpr int kStCand = 0, kStM = 1, kStPrefix = 2, kStLeft = 3, kStHist = 4, kStWords = kStHist + 256;
 
-// The quotient is formed in FP64 (IEEE division) and rounded once to FP32, so every
-// implementation that follows this rule gets the same key bits.
+// The key is the correctly rounded FP32 quotient e / s (IEEE division, which hipcc
+// emits for FP32 '/' by default and the build requests explicitly), so every
+// implementation that rounds the exact quotient once to FP32 gets the same key bits.
 __device__ __forceinline__ uint32_t sel_key(float e, float s) {
-    return s > 0.f ? __float_as_uint((float)((double)e / (double)s)) : kInfKey;
+    return s > 0.f ? __float_as_uint(e / s) : kInfKey;
 }
 
 __global__ __launch_bounds__(256) void sel_reset_kernel(int *__restrict__ st) {
@@ -46,10 +47,13 @@ __global__ __launch_bounds__(256) void sel_count_kernel(int n, const int *__rest
     if (threadIdx.x == 0 && s) atomicAdd(&st[kStCand], s);
 }
 
-// m = floor(keep_ratio * candidates), in FP64
-__global__ void sel_setup_kernel(double keep_ratio, int *__restrict__ st) {
+// m = floor(keep_ratio * candidates), exactly: keep_ratio = sig 2^-sh with an integer
+// significand sig < 2^24 and sh >= 23 (keep_ratio <= 1), so the product is the 64-bit
+// integer sig * c shifted right by sh (c < 2^31, the product < 2^55).
+__global__ void sel_setup_kernel(uint32_t sig, int sh, int *__restrict__ st) {
     if (threadIdx.x != 0) return;
-    const int m = (int)floor(keep_ratio * (double)st[kStCand]);
+    const unsigned long long prod = (unsigned long long)sig * (unsigned long long)(uint32_t)st[kStCand];
+    const int m = sh >= 64 ? 0 : (int)(prod >> sh);
     st[kStM] = m;
     st[kStLeft] = m;
     st[kStPrefix] = 0;
@@ -227,10 +231,16 @@ extern "C" lgs_status lgs_prune_select(int32_t n, const int32_t *topk_count, con
     LGS_REQUIRE(((uintptr_t)workspace & 255u) == 0, LGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     int *st = (int *)((char *)workspace + L.state);
     int *ties = (int *)((char *)workspace + L.ties);
+    // keep_ratio = sig 2^-sh exactly (a normal float is (2^23 + mantissa) 2^(e - 150), a
+    // subnormal one mantissa 2^-149)
+    const uint32_t bits = __builtin_bit_cast(uint32_t, keep_ratio);
+    const uint32_t ex = (bits >> 23) & 0xFFu, man = bits & 0x7FFFFFu;
+    const uint32_t sig = ex ? (man | 0x800000u) : man;
+    const int sh = ex ? 150 - (int)ex : 149;
     const unsigned g = sel_grid(n);
     hipLaunchKernelGGL(sel_reset_kernel, dim3(1), dim3(256), 0, stream, st);
     hipLaunchKernelGGL(sel_count_kernel, dim3(g), dim3(256), 0, stream, n, topk_count, count_below, st);
-    hipLaunchKernelGGL(sel_setup_kernel, dim3(1), dim3(64), 0, stream, (double)keep_ratio, st);
+    hipLaunchKernelGGL(sel_setup_kernel, dim3(1), dim3(64), 0, stream, sig, sh, st);
     for (int shift = 24; shift >= 0; shift -= 8) {
         hipLaunchKernelGGL(sel_hist_kernel, dim3(g), dim3(256), 0, stream, n, topk_count, count_below, max_w, expo,
                            shift, st);

@@ -1,7 +1,11 @@
 """Parity at the workloads' full sizes, in the launch configuration the benchmark times.
 
-* 1200x680 px, 500k Gaussians, D = 512, K = 4 (the benchmark frame), BF16 and FP32
-  forms: the whole frame, forward and the whole adjoint, against the oracle.
+* 1200x680 px, 500k Gaussians, D = 512, K = 1, 4 and 8 (the benchmark frame and its K
+  sweep), BF16 and FP32 forms: the whole frame, forward and the whole adjoint, against
+  the oracle.
+* 8 views of 640x480, 1M Gaussians (pitched keyframes), and one 1200x680 view of 3M
+  Gaussians at K = 8: projection, binning, blend + Top-K on every pixel, and the
+  geometry adjoint, against the oracle.
 * 8 views of 640x480, 1M Gaussians, D = 512, K = 4, BF16: the feature kernels over
   the stacked views in one launch, Top-K taken from the oracle's render of each
   view; sampled pixels and sampled gradient rows against the oracle.
@@ -17,7 +21,7 @@ import time
 import numpy as np
 import pytest
 
-from gpu_util import FLAG_EPS, gpu_forward, normwise, rel_close
+from gpu_util import check_forward, gpu_forward, normwise
 from paper_2602_06991_amd.scenegen import make_scene, random_upstream
 
 pytestmark = pytest.mark.gpu
@@ -47,25 +51,29 @@ def _stored(orc, feat, form):
     return orc.fp8_dequant(codes, s)
 
 
-@pytest.mark.timeout(400)
-@pytest.mark.parametrize("form", ["bf16", "f32"])
-def test_benchmark_frame(torch, orc, form):
-    from paper_2602_06991_amd import render
-    from test_gpu_render import _gpu_backward, _group_err
+@pytest.fixture(scope="module")
+def frame_scene():
     t0 = time.time()
     sc = make_scene(2)
-    g, cam, K = sc.gaussians, sc.cameras[0], 4
+    log(f"scene {sc.cameras[0].W}x{sc.cameras[0].H} N={sc.gaussians.n} D={sc.gaussians.d} "
+        f"in {time.time() - t0:.1f}s")
+    return sc
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("form,K", [("bf16", 4), ("f32", 4), ("bf16", 1), ("bf16", 8), ("f32", 1),
+                                    ("f32", 8)])
+def test_benchmark_frame(torch, orc, frame_scene, form, K):
+    """The benchmark frame at every K of its sweep, in the launch configuration the
+    benchmark times (the one-pass feature kernel included)."""
+    from paper_2602_06991_amd import render
+    from test_gpu_render import _gpu_backward, _group_err
+    g, cam = frame_scene.gaussians, frame_scene.cameras[0]
     mdt = "f32" if form == "f32" else "bf16"
-    log(f"scene {cam.W}x{cam.H} N={g.n} D={g.d} in {time.time() - t0:.1f}s")
     out, state = gpu_forward(g, cam, K)
     r = orc.render(g, cam, K)
-    fl = orc.flagged(r["margins"], **FLAG_EPS)
+    fl, bfl, ids_eq = check_forward(orc, g, cam, K, out, r, f"{cam.W}x{cam.H}")
     ok = ~fl
-    ids_eq = np.all(out["ids"] == r["ids"], -1)
-    log(f"forward: flagged {fl.mean():.4%}, id mismatches on unflagged pixels {np.sum(~ids_eq & ok)}")
-    assert np.all(ids_eq[ok])
-    for k, floor in (("C", 1e-2), ("D", 1e-2), ("O", 1e-2)):
-        assert np.all(rel_close(out[k][ok], r[k][ok], 1e-4, floor)), k
 
     # feature map from the GPU's own Top-K (the benchmark's launch), on unflagged pixels
     f64 = _stored(orc, g.feat, form)
@@ -226,25 +234,98 @@ def _sampled_feature_parity(torch, orc, g, ids, w, views, form, seed, n_rows):
     assert rel <= 1e-6
 
 
-@pytest.mark.timeout(500)
-def test_eight_views_bf16(torch, orc):
+@pytest.fixture(scope="module")
+def scene3():
     t0 = time.time()
     sc = make_scene(3)
+    log(f"scene {len(sc.cameras)} views {sc.cameras[0].W}x{sc.cameras[0].H} N={sc.gaussians.n} "
+        f"D={sc.gaussians.d} in {time.time() - t0:.1f}s")
+    return sc
+
+
+@pytest.fixture(scope="module")
+def scene4():
+    t0 = time.time()
+    sc = make_scene(4)
+    log(f"scene {len(sc.cameras)} views {sc.cameras[0].W}x{sc.cameras[0].H} N={sc.gaussians.n} "
+        f"D={sc.gaussians.d} in {time.time() - t0:.1f}s")
+    return sc
+
+
+def _geometry_adjoint(torch, orc, g, cam, K, state, ok, seed, feat_form, with_feature):
+    """The whole adjoint of one view against the oracle's, upstream gradients zeroed on
+    flagged pixels on both sides; the feature term (through the Top-K weights) only when
+    with_feature (the oracle then needs the dense FP64 feature table)."""
+    from test_gpu_render import _gpu_backward, _group_err
+    H, W = cam.H, cam.W
+    gC, gD, gO, gF = random_upstream(seed, W * H, g.d if with_feature else 8)
+    m = ok.reshape(-1).astype(np.float32)
+    gC *= m[:, None]; gD *= m; gO *= m; gF *= m[:, None]
+    if with_feature:
+        gF = torch.from_numpy(gF).to(torch.bfloat16).float().numpy()
+        f64 = _stored(orc, g.feat, feat_form)
+    else:
+        gF = np.zeros((W * H, g.d), np.float32)
+        f64 = np.zeros((g.n, 8))
+    gpu = _gpu_backward(torch, state, K, gC.reshape(H, W, 3), gD.reshape(H, W), gO.reshape(H, W),
+                        gF.reshape(H, W, g.d), fdt=feat_form, mdt="bf16")
+    b = orc.backward(g, cam, K, f64, gC, gD, gO, gF.astype(np.float64) if with_feature else None)
+    pairs = [("s_mean2d", "d_mean2d"), ("s_conic", "d_conic"), ("s_opacity", "d_opac"),
+             ("s_rgb", "d_rgb"), ("s_depth", "d_z"), ("p_means", "d_means"),
+             ("p_log_scales", "d_log_scales"), ("p_quats", "d_quats"),
+             ("p_opacity_logits", "d_opacity_logits")] + ([("dfeat", "d_feat")] if with_feature else [])
+    # FP32 geometry gradients: 1e-3; with the BF16 feature term: 1e-2
+    tol = 1e-2 if with_feature else 1e-3
+    msg = []
+    for a, o in pairs:
+        fro, worst = _group_err(gpu[a], b[o])
+        msg.append(f"{a} {fro:.1e}/{worst:.1e}")
+        assert fro <= tol and worst <= tol, (a, fro, worst)
+    log("adjoint (fro/worst): " + ", ".join(msg))
+
+
+@pytest.mark.timeout(600)
+def test_geometry_path_eight_pitched_views(torch, orc, scene3):
+    """Projection, binning, blend + Top-K of all 8 keyframes of the 640x480 / 1M
+    workload (random positions, yaw and +-15 degree pitch), every pixel against the
+    oracle; the whole adjoint (BF16 features, feature term included) of two of them."""
+    g, K = scene3.gaussians, 4
+    for v, cam in enumerate(scene3.cameras):
+        out, state = gpu_forward(g, cam, K)
+        r = orc.render(g, cam, K)
+        fl, _, _ = check_forward(orc, g, cam, K, out, r, f"view {v}")
+        if v in (0, 5):
+            _geometry_adjoint(torch, orc, g, cam, K, state, ~fl, 20 + v, "bf16", True)
+        del out, state, r
+
+
+@pytest.mark.timeout(600)
+def test_geometry_path_large_view(torch, orc, scene4):
+    """One 1200x680 view of the 3M-Gaussian workload (K = 8): every pixel of the blend
+    and Top-K against the oracle, and the geometry adjoint of colour, depth and opacity."""
+    g, K = scene4.gaussians, 8
+    cam = scene4.cameras[1]
+    out, state = gpu_forward(g, cam, K)
+    r = orc.render(g, cam, K)
+    fl, _, _ = check_forward(orc, g, cam, K, out, r, "3M view 1")
+    _geometry_adjoint(torch, orc, g, cam, K, state, ~fl, 31, "fp8", False)
+
+
+@pytest.mark.timeout(500)
+def test_eight_views_bf16(torch, orc, scene3):
+    t0 = time.time()
+    sc = scene3
     g, K = sc.gaussians, 4
-    log(f"scene {len(sc.cameras)} views {sc.cameras[0].W}x{sc.cameras[0].H} N={g.n} D={g.d} "
-        f"in {time.time() - t0:.1f}s")
     ids, w = _oracle_topk(orc, g, sc.cameras, K)
     log(f"oracle Top-K of {len(sc.cameras)} views in {time.time() - t0:.1f}s")
     _sampled_feature_parity(torch, orc, g, ids, w, len(sc.cameras), "bf16", 3, 3000)
 
 
 @pytest.mark.timeout(600)
-def test_four_views_fp8_d768_k8(torch, orc):
+def test_four_views_fp8_d768_k8(torch, orc, scene4):
     t0 = time.time()
-    sc = make_scene(4)
+    sc = scene4
     g, K = sc.gaussians, 8
-    log(f"scene {len(sc.cameras)} views {sc.cameras[0].W}x{sc.cameras[0].H} N={g.n} D={g.d} "
-        f"in {time.time() - t0:.1f}s")
     ids, w = _oracle_topk(orc, g, sc.cameras, K)
     log(f"oracle Top-K of {len(sc.cameras)} views in {time.time() - t0:.1f}s")
     _sampled_feature_parity(torch, orc, g, ids, w, len(sc.cameras), "fp8", 4, 800)

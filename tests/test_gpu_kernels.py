@@ -401,7 +401,9 @@ def test_fused_l1_matches_unfused(torch, K, fdt, D, spread):
 
 @pytest.mark.parametrize("K,fdt,mdt,views,H,W,D,spread", [
     (4, "bf16", "bf16", 1, 40, 53, 512, 24),       # MFMA path, ragged tiles
-    (8, "fp8", "bf16", 2, 33, 40, 768, 30),        # FP8 rows, unions up to 32, two views
+    (8, "fp8", "bf16", 2, 33, 40, 768, 30),        # FP8 rows, D = 768 (per-pixel path), two views
+    (8, "bf16", "bf16", 1, 40, 53, 512, 24),       # K = 8 MFMA path (compact slot table), unions <= 32
+    (8, "fp8", "bf16", 1, 40, 40, 512, 30),        # K = 8 MFMA path with FP8 row scales
     (4, "bf16", "bf16", 1, 48, 48, 256, 20000),    # unions beyond 32: per-pixel path in the same launch
     (3, "bf16", "f32", 1, 20, 36, 200, 14),        # FP32 map, channel tail
     (4, "f32", "f32", 1, 37, 53, 64, 40),          # FP32 form

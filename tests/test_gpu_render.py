@@ -2,13 +2,14 @@
 feature render, and the whole adjoint) against the oracle on seeded scenes.
 
 Top-K ids must match bit-exactly on every pixel whose decisions the oracle did
-not flag as within rounding distance of a threshold; values match within the
-FP32 tolerance there.  For gradients the upstream gradients of flagged pixels
-are zeroed on both sides."""
+not flag as within rounding distance of a threshold, the flagged share is bounded,
+values match within the FP32 tolerance wherever the blend decisions were clear, and
+a flagged pixel whose ids differ must hold an admissible answer (gpu_util.check_forward).
+For gradients the upstream gradients of flagged pixels are zeroed on both sides."""
 import numpy as np
 import pytest
 
-from gpu_util import FLAG_EPS, dev_params, gpu_forward, normwise, rel_close
+from gpu_util import FLAG_EPS, check_forward, dev_params, gpu_forward
 from paper_2602_06991_amd.scenegen import make_scene, make_tiny, random_upstream
 
 pytestmark = pytest.mark.gpu
@@ -42,26 +43,14 @@ def test_forward_parity(torch, orc, name, K):
     g, cam = _scene(name)
     out, _ = gpu_forward(g, cam, K)
     r = orc.render(g, cam, K)
-    fl = orc.flagged(r["margins"], **FLAG_EPS)
-    ok = ~fl
-    ids_eq = np.all(out["ids"] == r["ids"], -1)
-    print(f"{name} K={K}: flagged {fl.mean():.4%}, id mismatches unflagged {np.sum(~ids_eq & ok)}, "
-          f"flagged {np.sum(~ids_eq & fl)}; mean blended {r['nblend'].mean():.1f}")
+    fl, bfl, ids_eq = check_forward(orc, g, cam, K, out, r, name)
     # FP32 error scale of the decisions: weights of the selected slots on unflagged pixels
-    sel = ok[..., None] & (r["ids"] >= 0)
+    sel = (~fl)[..., None] & (r["ids"] >= 0)
     werr = np.abs(out["w"] / np.where(sel, r["w"], 1) - 1)[sel]
     mm = ~ids_eq
     mmin = r["margins"][mm].min(-1) if mm.any() else np.array([np.inf])
     print(f"   max rel err of selected w {werr.max() if werr.size else 0:.3g}; "
           f"largest decision margin among mismatching pixels {mmin.max():.3g}")
-    assert np.all(ids_eq[ok])
-    assert np.all(rel_close(out["C"][ok], r["C"][ok], 1e-4, 1e-2))
-    assert np.all(rel_close(out["D"][ok], r["D"][ok], 1e-4, 1e-2))
-    assert np.all(rel_close(out["O"][ok], r["O"][ok], 1e-4, 1e-2))
-    assert np.all(rel_close(out["w"][ok], r["w"][ok], 1e-4, 1e-6))
-    # flagged pixels still hold a valid answer: K distinct ids or padding
-    s = np.sort(out["ids"], -1)
-    assert np.all((s[..., 1:] != s[..., :-1]) | (s[..., 1:] == -1))
 
 
 def test_forward_is_deterministic(torch):

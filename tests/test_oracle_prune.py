@@ -117,3 +117,15 @@ def test_survivor_count_rounds_down(orc):
     E = np.arange(1, 8, dtype=np.float32)
     s = orc.prune_select(count, S, 1, E, 0.75)
     np.testing.assert_array_equal(s, [1, 1, 1, 0, 0, 1, 1])
+
+
+def test_survivor_count_uses_the_fp32_ratio_exactly(orc):
+    # the ratio is the FP32 value the caller passes: FP32 0.7 is 0.699999988..., so 10
+    # candidates keep floor(6.99999988) = 6, not 7; FP32 0.3 is 0.300000012..., so 10
+    # keep 3
+    count = np.zeros(10, np.int32)
+    S = np.ones(10, np.float32)
+    E = np.arange(1, 11, dtype=np.float32)
+    assert orc.prune_select(count, S, 1, E, 0.7).sum() == 6
+    assert orc.prune_select(count, S, 1, E, 0.3).sum() == 3
+    assert orc.prune_select(count, S, 1, E, 1.0).sum() == 10
