@@ -145,6 +145,26 @@ lgs_status lgs_bin_sort_count(int32_t n, int64_t max_pairs, const void *workspac
                               hipStream_t stream);
 
 /*
+ * Allocation-free variant of lgs_bin_sort, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same binning and outputs, with the workspace in a static device array
+ * of the library (64 MiB per GPU, held from the library's load on that GPU until the
+ * process ends) instead of caller memory.  It calls no allocator.
+ * Limit: the workspace lgs_bin_sort_workspace(n, width, height, max_pairs) would report
+ * must fit in 64 MiB (about 32 n + 12 max_pairs bytes), else INVALID_ARG before any
+ * launch.  *n_pairs (host) is required: the call synchronises `stream` once to read
+ * the pair count, and returns LGS_ERR_CAPACITY with *n_pairs set to the need (outputs
+ * untouched) when it exceeds max_pairs.  Every call on one GPU shares that GPU's array
+ * and overwrites it; calls that overlap on one GPU (other host threads, other streams)
+ * race and must be serialised by the caller.  Nothing in the array needs to start at
+ * zero: every word a call reads is written by that call first.
+ */
+lgs_status lgs_bin_sort_noalloc(const lgs_camera *cam, int32_t n, const float *depth,
+                                const int32_t *tile_rect, const int32_t *tiles_touched,
+                                int64_t max_pairs, int32_t *sorted_ids, int32_t *tile_ranges,
+                                int64_t *n_pairs, hipStream_t stream);
+
+/*
  * Colour/depth/opacity alpha blending (Eq. 1) that records the Top-K (Eq. 2) ids
  * and weights of every pixel during the same pass (Sec. 3.2, implementation).
  * In:  the projection outputs, rgb[n*3], and the lgs_bin_sort outputs.

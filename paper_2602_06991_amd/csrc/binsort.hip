@@ -12,6 +12,8 @@
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
+#include <mutex>
+
 namespace lgs {
 namespace {
 
@@ -356,11 +358,13 @@ extern "C" lgs_status lgs_bin_sort_workspace(int32_t n, int32_t width, int32_t h
     return LGS_OK;
 }
 
-extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float *depth,
-                                   const int32_t *tile_rect, const int32_t *tiles_touched,
-                                   void *workspace, size_t ws_bytes, int64_t max_pairs,
-                                   int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
-                                   hipStream_t stream) {
+namespace lgs {
+namespace {
+
+// The binning of lgs_bin_sort over the workspace `workspace` (ws_bytes usable bytes).
+lgs_status bin_sort_on(const lgs_camera *cam, int32_t n, const float *depth, const int32_t *tile_rect,
+                       const int32_t *tiles_touched, void *workspace, size_t ws_bytes, int64_t max_pairs,
+                       int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs, hipStream_t stream) {
     lgs_status st = check_camera(cam);
     if (st) return st;
     LGS_REQUIRE(n >= 0 && max_pairs >= 0 && max_pairs <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG,
@@ -453,6 +457,18 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
     return check_launch("bin_sort ranges");
 }
 
+}  // namespace
+}  // namespace lgs
+
+extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float *depth,
+                                   const int32_t *tile_rect, const int32_t *tiles_touched,
+                                   void *workspace, size_t ws_bytes, int64_t max_pairs,
+                                   int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
+                                   hipStream_t stream) {
+    return bin_sort_on(cam, n, depth, tile_rect, tiles_touched, workspace, ws_bytes, max_pairs, sorted_ids,
+                       tile_ranges, n_pairs, stream);
+}
+
 extern "C" lgs_status lgs_bin_sort_count(int32_t n, int64_t max_pairs, const void *workspace, int64_t *n_pairs,
                                          hipStream_t stream) {
     LGS_REQUIRE(n_pairs && workspace, LGS_ERR_INVALID_ARG, "lgs_bin_sort_count: NULL pointer");
@@ -475,4 +491,66 @@ extern "C" lgs_status lgs_bin_sort_count(int32_t n, int64_t max_pairs, const voi
         return LGS_ERR_CAPACITY;
     }
     return LGS_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free variant
+//
+// lgs_bin_sort_noalloc bins exactly as lgs_bin_sort, with its workspace in a static
+// device array instead of caller memory.  Each GPU the library runs on holds its own
+// copy of the array from the module's load until the process ends.  In host code the
+// array's name is only a host-side stand-in, never a device address: the device address
+// is looked up once per device with hipGetSymbolAddress and used from then on.
+
+namespace lgs {
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;   // 64 MiB per GPU
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first call per
+// device (with that device current) and kept.
+lgs_status scratch_of_current_device(void **out) {
+    int dev = -1;
+    lgs_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    LGS_REQUIRE(dev >= 0 && dev < kMaxDevices, LGS_ERR_INVALID_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        st = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (st) return st;
+        LGS_REQUIRE(p != nullptr, LGS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LGS_OK;
+}
+
+}  // namespace
+}  // namespace lgs
+
+extern "C" lgs_status lgs_bin_sort_noalloc(const lgs_camera *cam, int32_t n, const float *depth,
+                                           const int32_t *tile_rect, const int32_t *tiles_touched,
+                                           int64_t max_pairs, int32_t *sorted_ids, int32_t *tile_ranges,
+                                           int64_t *n_pairs, hipStream_t stream) {
+    lgs_status st = check_camera(cam);
+    if (st) return st;
+    LGS_REQUIRE(n_pairs, LGS_ERR_INVALID_ARG, "lgs_bin_sort_noalloc: n_pairs (host) is required");
+    LGS_REQUIRE(n >= 0 && max_pairs >= 0 && max_pairs <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG,
+                "lgs_bin_sort_noalloc: bad sizes");
+    const size_t need = layout_of(n, max_pairs).bytes;
+    LGS_REQUIRE(need <= kScratchBytes, LGS_ERR_INVALID_ARG,
+                "lgs_bin_sort_noalloc: n = %d with max_pairs = %lld needs %zu bytes of scratch; the static "
+                "scratch holds %zu (use lgs_bin_sort with a workspace)",
+                n, (long long)max_pairs, need, kScratchBytes);
+    void *ws = nullptr;
+    st = scratch_of_current_device(&ws);
+    if (st) return st;
+    return bin_sort_on(cam, n, depth, tile_rect, tiles_touched, ws, kScratchBytes, max_pairs, sorted_ids,
+                       tile_ranges, n_pairs, stream);
 }

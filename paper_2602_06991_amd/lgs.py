@@ -60,6 +60,7 @@ _SIG = {
     "lgs_bin_sort": [_CAM, _I32, _P, _P, _P, _P, ctypes.c_size_t, _I64, _P, _P,
                      ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_bin_sort_count": [_I32, _I64, _P, ctypes.POINTER(ctypes.c_int64), _P],
+    "lgs_bin_sort_noalloc": [_CAM, _I32, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_rasterize_topk_fwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P],
     "lgs_feature_render_fwd": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
@@ -161,6 +162,17 @@ def lgs_bin_sort_count(n, max_pairs, workspace, stream=None):
     """Returns (status, n_pairs); LGS_ERR_CAPACITY is returned, not raised."""
     m = ctypes.c_int64(0)
     st = load().lgs_bin_sort_count(n, max_pairs, workspace, ctypes.byref(m), stream)
+    if st != LGS_ERR_CAPACITY:
+        _check(st)
+    return st, m.value
+
+
+def lgs_bin_sort_noalloc(cam, n, depth, tile_rect, tiles_touched, max_pairs, sorted_ids, tile_ranges,
+                         stream=None):
+    """Returns (status, n_pairs); LGS_ERR_CAPACITY is returned, not raised."""
+    m = ctypes.c_int64(0)
+    st = load().lgs_bin_sort_noalloc(ctypes.byref(cam), n, depth, tile_rect, tiles_touched, max_pairs,
+                                     sorted_ids, tile_ranges, ctypes.byref(m), stream)
     if st != LGS_ERR_CAPACITY:
         _check(st)
     return st, m.value
