@@ -1,1268 +1,14 @@
-// Top-K feature rendering (Eq. 3-4, Sec. 3.2) and its adjoint, the storage
-// quantizers of the feature table, the L1 loss gradient and the Top-K union count.
-//
-// Forward: one wave per pixel; each lane owns 8 consecutive channels and reads the
-// K gathered feature rows with 128-bit loads (FP32: two), accumulating in FP32 and
-// writing the map row once with non-temporal 128-bit stores.  Since K is fixed,
-// every pixel costs the same: the paper's fixed thread allocation (Sec. 3.2).
-//
-// Backward: one block per 16x16 tile.  The block first builds the union of the
-// tile's Top-K ids in an LDS hash table and, for every distinct Gaussian, the list
-// of (pixel, slot) entries that selected it.  It then walks the channels in chunks
-// of 32: the tile's dL/dF chunk is staged in LDS once, each pixel accumulates its K
-// dot products from it, and each distinct Gaussian's gradient row chunk is summed
-// in registers over its list and added to global memory with one coalesced atomic
-// per channel - U_t atomics per channel per tile instead of 256 K.
+// Entry points of the Top-K feature render (Eq. 3-4, Sec. 3.2) and its adjoint, which
+// dispatch to the per-K launches (feature_k*.hip), plus the storage quantizers of the
+// feature table, the L1 loss gradient and the Top-K union count.
 #include <algorithm>
-#include <type_traits>
 
+#include "feature_launch.hpp"
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
 namespace lgs {
 namespace {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-enum { FT_F32 = 0, FT_BF16 = 1, FT_FP8 = 2 };
-enum { MT_F32 = 0, MT_BF16 = 1 };
-
-// Load 8 consecutive feature values of row `row` starting at channel c.
-template <int FT>
-__device__ __forceinline__ void load8(const void *feat, long row, int D, int c, float (&v)[8]) {
-    if constexpr (FT == FT_F32) {
-        const f32x4 *p = (const f32x4 *)((const float *)feat + row * D + c);
-        f32x4 a = p[0], b = p[1];
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-    } else if constexpr (FT == FT_BF16) {
-        u32x4 a = *(const u32x4 *)((const uint16_t *)feat + row * D + c);
-        v[0] = bf16_to_f32(a.x & 0xFFFFu); v[1] = bf16_to_f32(a.x >> 16);
-        v[2] = bf16_to_f32(a.y & 0xFFFFu); v[3] = bf16_to_f32(a.y >> 16);
-        v[4] = bf16_to_f32(a.z & 0xFFFFu); v[5] = bf16_to_f32(a.z >> 16);
-        v[6] = bf16_to_f32(a.w & 0xFFFFu); v[7] = bf16_to_f32(a.w >> 16);
-    } else {
-        u32x2 a = *(const u32x2 *)((const uint8_t *)feat + row * D + c);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            v[i] = e4m3_to_f32((a.x >> (8 * i)) & 0xFFu);
-            v[4 + i] = e4m3_to_f32((a.y >> (8 * i)) & 0xFFu);
-        }
-    }
-}
-
-template <int MT>
-__device__ __forceinline__ void store8(void *F, long row, int D, int c, const float (&v)[8]) {
-    if constexpr (MT == MT_F32) {
-        f32x4 *p = (f32x4 *)((float *)F + row * D + c);
-        f32x4 a = {v[0], v[1], v[2], v[3]}, b = {v[4], v[5], v[6], v[7]};
-        __builtin_nontemporal_store(a, p);
-        __builtin_nontemporal_store(b, p + 1);
-    } else {
-        u32x4 a;
-        a.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
-        a.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
-        a.z = (uint32_t)f32_to_bf16(v[4]) | ((uint32_t)f32_to_bf16(v[5]) << 16);
-        a.w = (uint32_t)f32_to_bf16(v[6]) | ((uint32_t)f32_to_bf16(v[7]) << 16);
-        __builtin_nontemporal_store(a, (u32x4 *)((uint16_t *)F + row * D + c));
-    }
-}
-
-// ---------------------------------------------------------------- tile union
-
-// Both feature kernels give one 16x16 tile to a 256-thread block.  Wave w owns the
-// tile's rows 4w..4w+3 (64 pixels) and streams them one pixel at a time with lanes
-// across channels (CPL consecutive channels per lane per pass).
-//
-// Prologue: lane i loads the Top-K slots of the wave's pixel i.  The wave lists its
-// distinct Gaussian ids with a ballot loop (one iteration per distinct id, no
-// contention), the four wave lists merge through a small LDS hash table into the
-// tile's union, and the union's feature rows are staged once into LDS (at most
-// `ucap` of them; rare larger unions read the rest from global memory).  The forward
-// then builds each pixel's row from LDS and writes it; the backward adds w'_k dL/dF
-// into per-wave register accumulators indexed by the wave-local id index, and adds
-// each accumulator to dL/df once, with coalesced atomics.
-constexpr int kFB = 256;          // threads per feature block
-constexpr int kPixPerWave = 64;
-constexpr int kUP = 32;           // union rows the MFMA path holds (two 16-row blocks)
-constexpr int kCPW = 4;           // 32-channel chunks per wave on the MFMA path (D <= 512)
-constexpr int kRowBudget = 32 * 1024;   // LDS bytes for staged rows on the per-pixel path
-
-template <int K> struct TileCfg {
-    static constexpr int CPL = K <= 4 ? 8 : (K <= 8 ? 4 : 2);   // channels per lane per pass
-    static constexpr int RA = K <= 4 ? 12 : (K <= 8 ? 16 : 24);  // register accumulators per wave
-    static constexpr int HS = 256;   // union hash slots: dedups any tile of up to 128 wave-distinct ids
-};
-
-template <int FT> struct Bytes { static constexpr int v = FT == FT_F32 ? 4 : FT == FT_BF16 ? 2 : 1; };
-
-// CPL consecutive values (storage format FT) starting at element index `at`.
-template <int FT, int CPL>
-__device__ __forceinline__ void loadc(const void *__restrict__ base, long at, float (&v)[CPL]) {
-    if constexpr (FT == FT_F32) {
-        const float *p = (const float *)base + at;
-        if constexpr (CPL == 8) {
-            f32x4 a = ((const f32x4 *)p)[0], b = ((const f32x4 *)p)[1];
-            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-        } else if constexpr (CPL == 4) {
-            f32x4 a = *(const f32x4 *)p;
-            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        } else {
-            typedef float f32x2 __attribute__((ext_vector_type(2)));
-            f32x2 a = *(const f32x2 *)p;
-            v[0] = a.x; v[1] = a.y;
-        }
-    } else if constexpr (FT == FT_BF16) {
-        const uint16_t *p = (const uint16_t *)base + at;
-        if constexpr (CPL == 8) {
-            u32x4 a = *(const u32x4 *)p;
-            uint32_t w4[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { v[2 * i] = bf16_to_f32(w4[i] & 0xFFFFu); v[2 * i + 1] = bf16_to_f32(w4[i] >> 16); }
-        } else if constexpr (CPL == 4) {
-            u32x2 a = *(const u32x2 *)p;
-            v[0] = bf16_to_f32(a.x & 0xFFFFu); v[1] = bf16_to_f32(a.x >> 16);
-            v[2] = bf16_to_f32(a.y & 0xFFFFu); v[3] = bf16_to_f32(a.y >> 16);
-        } else {
-            uint32_t a = *(const uint32_t *)p;
-            v[0] = bf16_to_f32(a & 0xFFFFu); v[1] = bf16_to_f32(a >> 16);
-        }
-    } else {
-        const uint8_t *p = (const uint8_t *)base + at;
-        if constexpr (CPL == 8) {
-            u32x2 a = *(const u32x2 *)p;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { v[i] = e4m3_to_f32((a.x >> (8 * i)) & 0xFFu); v[4 + i] = e4m3_to_f32((a.y >> (8 * i)) & 0xFFu); }
-        } else if constexpr (CPL == 4) {
-            uint32_t a = *(const uint32_t *)p;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = e4m3_to_f32((a >> (8 * i)) & 0xFFu);
-        } else {
-            uint32_t a = *(const uint16_t *)p;
-            v[0] = e4m3_to_f32(a & 0xFFu); v[1] = e4m3_to_f32(a >> 8);
-        }
-    }
-}
-
-template <int MT, int CPL>
-__device__ __forceinline__ void storec(void *__restrict__ base, long at, const float (&v)[CPL]) {
-    if constexpr (MT == MT_F32) {
-        float *p = (float *)base + at;
-        if constexpr (CPL == 8) {
-            f32x4 a = {v[0], v[1], v[2], v[3]}, b = {v[4], v[5], v[6], v[7]};
-            __builtin_nontemporal_store(a, (f32x4 *)p);
-            __builtin_nontemporal_store(b, (f32x4 *)p + 1);
-        } else if constexpr (CPL == 4) {
-            f32x4 a = {v[0], v[1], v[2], v[3]};
-            __builtin_nontemporal_store(a, (f32x4 *)p);
-        } else {
-            typedef float f32x2 __attribute__((ext_vector_type(2)));
-            f32x2 a = {v[0], v[1]};
-            __builtin_nontemporal_store(a, (f32x2 *)p);
-        }
-    } else {
-        uint16_t *p = (uint16_t *)base + at;
-        uint32_t w[CPL / 2];
-#pragma unroll
-        for (int i = 0; i < CPL / 2; ++i)
-            w[i] = (uint32_t)f32_to_bf16(v[2 * i]) | ((uint32_t)f32_to_bf16(v[2 * i + 1]) << 16);
-        if constexpr (CPL == 8) {
-            u32x4 a = {w[0], w[1], w[2], w[3]};
-            __builtin_nontemporal_store(a, (u32x4 *)p);
-        } else if constexpr (CPL == 4) {
-            u32x2 a = {w[0], w[1]};
-            __builtin_nontemporal_store(a, (u32x2 *)p);
-        } else {
-            __builtin_nontemporal_store(w[0], (uint32_t *)p);
-        }
-    }
-}
-
-__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ float rdlane(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-struct TileGeom {
-    int view, tx0, ty0;
-};
-
-__device__ __forceinline__ TileGeom tile_geom(int tile, int W, int H) {
-    const int ntx = (W + kTile - 1) / kTile, nty = (H + kTile - 1) / kTile;
-    TileGeom g;
-    g.view = tile / (ntx * nty);
-    int tv = tile - g.view * ntx * nty;
-    g.tx0 = (tv % ntx) * kTile;
-    g.ty0 = (tv / ntx) * kTile;
-    return g;
-}
-
-// Per-lane state after the prologue: the lane's pixel slots and, for each slot, the
-// wave-local index of its Gaussian.
-template <int K>
-struct Slots {
-    int id[K];
-    int wl[K];     // wave-local index of the slot's Gaussian (-1: empty)
-    int u[K];      // tile union index (-1: empty)
-    float wp[K];   // renormalised weight w'_k
-    float wf[K];   // weight applied to the stored row: w'_k, times the row scale for FP8
-    float W;
-};
-
-// LDS shared by both kernels (static part; staged rows are dynamic LDS).
-template <int K, int FT>
-struct UnionLds {
-    int hkey[TileCfg<K>::HS];
-    int hval[TileCfg<K>::HS];
-    int wlist[4][kPixPerWave * K];   // wave-local distinct ids
-    int16_t wmap[4][kPixPerWave * K];   // wave-local index -> tile union index (< 4 * 64 K)
-    int uid[4 * kPixPerWave * K];    // tile union index -> Gaussian id
-    float uscale[FT == FT_FP8 ? 4 * kPixPerWave * K : 1];  // tile union index -> FP8 row scale
-    int nw[4];
-    int nU;
-    // MFMA path (U <= kUP): the union in ascending id order, so both feature
-    // kernels order the K dimension of their products identically
-    int rank[kUP];       // hash-order union index -> ascending-id index
-    int uid2[kUP];       // ascending-id index -> Gaussian id
-    float uscale2[FT == FT_FP8 ? kUP : 1];  // ascending-id index -> FP8 row scale
-};
-
-// Builds the tile union: L.uid[0, U) and, per lane, the slots' union indices.
-// Returns the wave's number of distinct ids.
-template <int K, int FT>
-__device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H,
-                                          const int *__restrict__ ids, const float *__restrict__ tw,
-                                          const float *__restrict__ scale, UnionLds<K, FT> &L,
-                                          Slots<K> &s, int &U) {
-    constexpr int HS = TileCfg<K>::HS;
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int x = tg.tx0 + (lane & 15), y = tg.ty0 + wave * 4 + (lane >> 4);
-    const bool valid = x < W && y < H;
-    const long p = (long)tg.view * W * H + (long)y * W + x;
-    float wv[K];
-    s.W = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        s.id[k] = valid ? ids[p * K + k] : -1;
-        wv[k] = valid ? tw[p * K + k] : 0.f;
-        s.W += wv[k];
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        s.wp[k] = (s.W > 0.f && s.id[k] >= 0) ? wv[k] / s.W : 0.f;
-        if (!(s.W > 0.f)) s.id[k] = -1;
-        s.wl[k] = -1;
-    }
-    for (int h = t; h < HS; h += kFB) L.hkey[h] = -1;
-    if (t == 0) L.nU = 0;
-    // distinct ids of the wave: each iteration takes the first pending slot's id and
-    // resolves every slot of every lane that holds it
-    int nw = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        while (true) {
-            const uint64_t m = __ballot(s.wl[k] < 0 && s.id[k] >= 0);
-            if (m == 0ull) break;
-            const int lid = rdlane(s.id[k], (int)__builtin_ctzll(m));
-#pragma unroll
-            for (int k2 = k; k2 < K; ++k2) s.wl[k2] = (s.id[k2] == lid) ? nw : s.wl[k2];
-            if (lane == 0) L.wlist[wave][nw] = lid;
-            ++nw;
-        }
-    }
-    if (lane == 0) L.nw[wave] = nw;
-    __syncthreads();
-    const int ntot = L.nw[0] + L.nw[1] + L.nw[2] + L.nw[3];
-    if (ntot <= HS / 2) {
-        // merge the four lists through the hash table (at most half full, so every
-        // probe sequence ends): one dense index per distinct id
-        for (int j = lane; j < nw; j += 64) {
-            const int g = L.wlist[wave][j];
-            uint32_t h = ((uint32_t)g * 2654435761u) & (HS - 1);
-            for (int probe = 0; probe < HS; ++probe) {
-                const int prev = atomicCAS(&L.hkey[h], -1, g);
-                if (prev == -1) {
-                    const int u = atomicAdd(&L.nU, 1);
-                    L.uid[u] = g;
-                    if constexpr (FT == FT_FP8) L.uscale[u] = scale[g];
-                    L.hval[h] = u;
-                    break;
-                }
-                if (prev == g) break;
-                h = (h + 1) & (HS - 1);
-            }
-        }
-        __syncthreads();
-        for (int j = lane; j < nw; j += 64) {
-            const int g = L.wlist[wave][j];
-            uint32_t h = ((uint32_t)g * 2654435761u) & (HS - 1);
-            for (int probe = 0; probe < HS && L.hkey[h] != g; ++probe) h = (h + 1) & (HS - 1);
-            L.wmap[wave][j] = (int16_t)L.hval[h];
-        }
-    } else {
-        // very large unions: concatenate the wave lists (a Gaussian seen by several
-        // waves gets several rows; only the staging budget notices)
-        int off = 0;
-        for (int w2 = 0; w2 < wave; ++w2) off += L.nw[w2];
-        for (int j = lane; j < nw; j += 64) {
-            const int g = L.wlist[wave][j];
-            L.uid[off + j] = g;
-            if constexpr (FT == FT_FP8) L.uscale[off + j] = scale[g];
-            L.wmap[wave][j] = (int16_t)(off + j);
-        }
-        if (t == 0) L.nU = ntot;
-        __syncthreads();
-    }
-    U = L.nU;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        s.u[k] = s.wl[k] >= 0 ? L.wmap[wave][s.wl[k]] : -1;
-        s.wf[k] = s.wp[k];
-        if constexpr (FT == FT_FP8) s.wf[k] = s.u[k] >= 0 ? s.wp[k] * L.uscale[s.u[k]] : 0.f;
-    }
-    __syncthreads();   // wmap has been read: its space may be reused
-    return nw;
-}
-
-// Stages the first min(U, ucap) union rows in their storage format into `rows`:
-// 16-byte pieces (8-byte for FP8 rows).
-template <int K, int FT>
-__device__ __forceinline__ void stage_rows(const UnionLds<K, FT> &L, int U, int D, int ucap,
-                                           const void *__restrict__ feat, unsigned char *rows) {
-    typedef typename std::conditional<FT == FT_FP8, u32x2, u32x4>::type piece;
-    const int t = threadIdx.x;
-    const int nr = min(U, ucap);
-    const int rb = D * Bytes<FT>::v;
-    const int chunks = rb / (int)sizeof(piece);
-    for (int q = t; q < nr * chunks; q += kFB) {
-        const int r = q / chunks, c = q - r * chunks;
-        const piece *src = (const piece *)((const unsigned char *)feat + (long)L.uid[r] * rb) + c;
-        ((piece *)(rows + (long)r * rb))[c] = *src;
-    }
-    __syncthreads();
-}
-
-// CPL values of union row u from LDS (staged) or global memory.
-template <int FT, int CPL>
-__device__ __forceinline__ void urow(const unsigned char *rows, int ucap, const int *uid, int u,
-                                     const void *__restrict__ feat, int D, int c0, float (&v)[CPL]) {
-    if (u < ucap) loadc<FT, CPL>(rows, (long)u * D + c0, v);
-    else loadc<FT, CPL>(feat, (long)uid[u] * D + c0, v);
-}
-
-template <int CPL>
-__device__ __forceinline__ void flush_row(const float (&a)[CPL], int g, int D, int pass_c0, int lane,
-                                          float *__restrict__ dfeat, float *xbuf) {
-    // transpose through wave-private LDS so each atomic instruction covers 64
-    // consecutive channels
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) xbuf[lane * CPL + j] = a[j];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    float *dst = dfeat + (long)g * D + pass_c0;
-    const int span = min(64 * CPL, D - pass_c0);
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        const int c = j * 64 + lane;
-        const float v = xbuf[c];
-        if (c < span && v != 0.f) unsafeAtomicAdd(&dst[c], v);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// ---------------------------------------------------------------- MFMA tile path
-//
-// Tiles whose Top-K union has at most kUP Gaussians (BF16 or FP8 storage, BF16 map)
-// run both feature kernels as dense per-tile products on the matrix cores:
-//   F^T[c][p]  = sum_u Ft[u][c] Wa[p][u]         the feature map (Eq. 4), and its L1 recompute
-//   S^T[u][p] += sum_c Ft[u][c] G[p][c]          the dot products g_k = <dL/dF, f_k>
-//   dFt[u][c] += sum_p Wd[p][u] G[p][c]          the feature gradient rows sum_p w'_k dL/dF
-// Ft holds the union's stored rows (FP8 codes widened to BF16, exactly), Wa the
-// renormalised weights w'_k (times the FP8 row scale), Wd the weights w'_k; each is
-// zero outside the pixel's K slots.  An FP32 weight w enters as two BF16 terms
-// hi = RNE(w), lo = RNE(w - hi), i.e. with 16 significant bits, and every product is
-// exact in the FP32 accumulator.
-//
-// Operand layouts (lane l = 16 g + i): v_mfma_f32_16x16x16_bf16 takes A[i][4g..4g+3]
-// and B[4g..4g+3][i]; v_mfma_f32_16x16x32_bf16 takes A[i][8g..8g+7] and
-// B[8g..8g+7][i]; both return D[4g..4g+3][i].
-//
-// Work split: wave w owns a contiguous range of 32-channel chunks for all 256
-// pixels of the tile, so its Ft operands stay in registers for the whole tile and
-// its gradient rows are complete when the tile ends (one atomic per element and
-// tile).  The tile's 16 pixel rows are the MFMA column blocks, processed in turn;
-// per row the weights are scattered into a per-wave LDS buffer and read back in
-// operand layout.  Within a chunk, channel block b (of two) row m stands for
-// channel 8 (m / 4) + 4 b + m % 4, so that after both blocks lane (i, g) holds the
-// eight consecutive channels 8g..8g+7 of pixel i: one 16-byte access per lane.
-// Partial dot products of the four waves meet in LDS and are summed in a fixed
-// order, so dL/dw is deterministic.
-
-typedef short i16x4 __attribute__((ext_vector_type(4)));
-typedef short i16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-
-// Two floats to packed BF16, round to nearest even (v_cvt_pk_bf16_f32).
-__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
-    bf16x2_t r = {(__bf16)a, (__bf16)b};
-    return __builtin_bit_cast(uint32_t, r);
-}
-__device__ __forceinline__ uint16_t bits_bf16(float a) { return __builtin_bit_cast(uint16_t, (__bf16)a); }
-__device__ __forceinline__ i16x4 as_op4(u32x2 v) { return __builtin_bit_cast(i16x4, v); }
-__device__ __forceinline__ i16x8 as_op8(u32x4 v) { return __builtin_bit_cast(i16x8, v); }
-__device__ __forceinline__ f32x4 mfma16(i16x4 a, i16x4 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma32(i16x8 a, i16x8 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(__bf16 __attribute__((ext_vector_type(8))), a),
-                                                   __builtin_bit_cast(__bf16 __attribute__((ext_vector_type(8))), b),
-                                                   c, 0, 0, 0);
-}
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-// Channel of block b, row m within a 32-channel chunk.
-__device__ __forceinline__ int blk_ch(int b, int m) { return 8 * (m >> 2) + 4 * b + (m & 3); }
-
-// Weights of one tile row in operand-ready layout, shared by the block's four waves:
-// a ring of three such buffers lets one row be read while the next is scattered and
-// the one after is cleared, with a single block barrier per row.
-struct MfRingF {
-    uint16_t wa[2][16][kUP];            // [hi, lo][pixel of the row][union index]
-};
-struct MfRingB {
-    uint16_t wa[2][16][kUP];
-    uint16_t wd[2][kUP][16];            // [hi, lo][union index][pixel of the row]
-};
-// Per-wave LDS: the forward's map row for the wave's channels (16-byte columns
-// XOR-swizzled by pixel, so neither the writes nor the reads collide on banks), the
-// backward's G of the row's chunks, transposed.
-struct MfWaveF {
-    uint16_t out[16][128];
-};
-struct MfWaveB {
-    uint16_t gt[kCPW][2][16][16];       // [chunk][channel block][block row][pixel]
-};
-static_assert(sizeof(MfRingF) == 2048 && sizeof(MfRingB) == 4096, "ring layout");
-static_assert(sizeof(MfWaveF) == 4096 && sizeof(MfWaveB) == 4096, "wave buffer layout");
-
-// Dynamic LDS of the MFMA path: [0, R0) half of the union rows staged as BF16
-// ([16][D]) while the operands are loaded; then, in the backward, the waves' partial
-// dot products in the same place, followed by the slot table (per pixel and slot:
-// union index, Wa weight, Wd weight); in the forward the slot table itself takes
-// region 0.  Then the weight ring and the four per-wave buffers.  Up to K = 4 the
-// partial dot products are kept for the whole tile ([4][256][K]) and the slot table
-// holds 32-bit indices and both weights.  Above K = 4, to stay at two blocks per CU,
-// the partials of the last two rows ([2][4][16][K]) are summed row by row into the
-// tile's dot products ([256][K]), and the slot table holds 16-bit indices and, without
-// FP8 row scales (Wa = Wd), one weight.
-__host__ __device__ inline size_t mf_align(size_t a) { return (a + 15) & ~(size_t)15; }
-__host__ __device__ constexpr bool mf_compact(int K) { return K > 4; }
-__host__ __device__ inline size_t mf_region0(int D, int K) {
-    size_t a = (size_t)16 * D * 2;
-    size_t b = mf_compact(K) ? (size_t)(2 * 4 * 16 + kTilePix) * K * 4 : (size_t)4 * kTilePix * K * 4;
-    return mf_align(a > b ? a : b);
-}
-__host__ __device__ inline size_t mf_slots_bytes(int K, bool fp8) {
-    if (!mf_compact(K)) return (size_t)3 * kTilePix * K * 4;
-    return mf_align((size_t)kTilePix * K * (2 + 4 * (fp8 ? 2 : 1)));
-}
-__host__ __device__ inline size_t mf_slots_at(int D, int K, bool bwd) { return bwd ? mf_region0(D, K) : 0; }
-__host__ __device__ inline size_t mf_ring_at(int D, int K, bool bwd, bool fp8) {
-    const size_t a = mf_region0(D, K), b = mf_slots_bytes(K, fp8);
-    return bwd ? a + b : mf_align(a > b ? a : b);
-}
-__host__ __device__ inline size_t mf_waves_at(int D, int K, bool bwd, bool fp8) {
-    return mf_ring_at(D, K, bwd, fp8) + 3 * (bwd ? sizeof(MfRingB) : sizeof(MfRingF));
-}
-__host__ __device__ inline size_t mf_lds_bytes(int D, int K, bool bwd, bool fp8) {
-    return mf_waves_at(D, K, bwd, fp8) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
-}
-
-template <int K>
-struct SlotTable {
-    typename std::conditional<mf_compact(K), int16_t, int>::type *u;
-    float *wa, *wd;
-};
-template <int K, bool FP8>
-__device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, int D, bool bwd) {
-    SlotTable<K> st;
-    float *w = (float *)(dyn + mf_slots_at(D, K, bwd));
-    if constexpr (mf_compact(K)) {
-        st.wa = w;
-        st.wd = FP8 ? w + kTilePix * K : w;
-        st.u = (int16_t *)(w + kTilePix * K * (FP8 ? 2 : 1));
-    } else {
-        st.u = (int *)w;
-        st.wa = w + kTilePix * K;
-        st.wd = st.wa + kTilePix * K;
-    }
-    return st;
-}
-
-// Prologue of the MFMA path (all 256 threads; U <= kUP): orders the union by id.
-template <int K, int FT>
-__device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int U) {
-    const int t = threadIdx.x;
-    if (t < 128) {   // four threads per member (waves 0 and 1 whole, so the shuffles see every lane)
-        const int u = t >> 2, q = t & 3;
-        const int g = u < U ? L.uid[u] : 0;
-        int r = 0;
-        for (int v = q; v < U; v += 4) r += L.uid[v] < g ? 1 : 0;   // ids are distinct
-        r += __shfl_xor(r, 1);
-        r += __shfl_xor(r, 2);
-        if (u < U && q == 0) {
-            L.rank[u] = r;
-            L.uid2[r] = g;
-            if constexpr (FT == FT_FP8) L.uscale2[r] = L.uscale[u];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) s.u[k] = s.u[k] >= 0 ? L.rank[s.u[k]] : -1;
-}
-
-// Stages union rows 16 h .. 16 h + 15 (those below U) as BF16 into ft = [16][D].
-template <int K, int FT>
-__device__ __forceinline__ void mf_stage_half(const UnionLds<K, FT> &L, int U, int D, int h,
-                                              const void *__restrict__ feat, uint16_t *ft) {
-    const int c8 = D >> 3;
-    const int nr = min(16, U - 16 * h);
-    for (int q = threadIdx.x; q < nr * c8; q += kFB) {
-        const int r = q / c8, c = (q - r * c8) * 8;
-        const long src = (long)L.uid2[16 * h + r] * D + c;
-        u32x4 o;
-        if constexpr (FT == FT_BF16) {
-            o = *(const u32x4 *)((const uint16_t *)feat + src);
-        } else {
-            const u32x2 a = *(const u32x2 *)((const uint8_t *)feat + src);
-            float v[8];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                v[i] = e4m3_to_f32((a.x >> (8 * i)) & 0xFFu);
-                v[4 + i] = e4m3_to_f32((a.y >> (8 * i)) & 0xFFu);
-            }
-            o.x = pk_bf16(v[0], v[1]); o.y = pk_bf16(v[2], v[3]);
-            o.z = pk_bf16(v[4], v[5]); o.w = pk_bf16(v[6], v[7]);
-        }
-        *(u32x4 *)(ft + (long)r * D + c) = o;
-    }
-}
-
-// The wave's chunks: [beg, beg + n) of the ceil(D / 32) chunks.
-struct MfChunks {
-    int beg, n;
-};
-__device__ __forceinline__ MfChunks mf_chunks(int D, int wave) {
-    const int nch = (D + 31) >> 5, cpw = (nch + 3) >> 2;
-    MfChunks m;
-    m.beg = wave * cpw;
-    m.n = max(0, min(cpw, nch - m.beg));
-    return m;
-}
-
-// Register operands of union block h (rows 16 h .. 16 h + 15, staged in ft), zero
-// outside the union and past D:
-//   opA[i][b][h]: lane (i16, g) = Ft[16 h + 4 g + j][chunk + blk_ch(b, i16)], j < 4
-//   opC[i][h]:    lane (i16, g) = Ft[16 h + i16][chunk + 8 g + j], j < 8
-__device__ __forceinline__ void mf_load_ops(const uint16_t *ft, int U, int D, int h, const MfChunks &mc,
-                                            int lane, i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
-    const int i16 = lane & 15, g = lane >> 4;
-    const int nr = U - 16 * h;   // staged rows of this block
-#pragma unroll
-    for (int i = 0; i < kCPW; ++i) {
-        const int c0 = (mc.beg + i) * 32;
-        const bool on = i < mc.n;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            i16x4 a;
-            const int ch = c0 + blk_ch(b, i16);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = 4 * g + j;
-                a[j] = (on && r < nr && ch < D) ? (short)ft[r * D + ch] : (short)0;
-            }
-            opA[i][b][h] = a;
-        }
-        const int ch = c0 + 8 * g;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (on && i16 < nr && ch < D) v = *(const u32x4 *)(ft + i16 * D + ch);
-        opC[i][h] = as_op8(v);
-    }
-}
-
-// Prologue and operands of the MFMA path; on return region 0 is free.
-template <int K, int FT>
-__device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U, int D, const void *__restrict__ feat,
-                                         unsigned char *dyn, const SlotTable<K> &st, const MfChunks &mc, int lane,
-                                         i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
-    uint16_t *ft = (uint16_t *)dyn;
-    mf_prologue<K, FT>(L, s, U);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h == 1 && U <= 16) {
-#pragma unroll
-            for (int i = 0; i < kCPW; ++i) {
-                opA[i][0][1] = (i16x4){0, 0, 0, 0};
-                opA[i][1][1] = (i16x4){0, 0, 0, 0};
-                opC[i][1] = (i16x8){0, 0, 0, 0, 0, 0, 0, 0};
-            }
-            break;
-        }
-        mf_stage_half<K, FT>(L, U, D, h, feat, ft);
-        __syncthreads();
-        mf_load_ops(ft, U, D, h, mc, lane, opA, opC);
-        __syncthreads();
-    }
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        st.u[t * K + k] = s.u[k];
-        st.wa[t * K + k] = s.u[k] >= 0 ? s.wf[k] : 0.f;
-        if constexpr (FT == FT_FP8 || !mf_compact(K)) st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
-    }
-    __syncthreads();
-}
-
-// The weight ring (all 256 threads take part in clearing and scattering).
-template <typename RB>
-__device__ __forceinline__ void ring_clear(RB &rb) {
-    constexpr int n16 = (int)sizeof(RB) / 16;
-    static_assert(n16 <= kFB, "one 16-byte store per thread");
-    if ((int)threadIdx.x < n16) ((u32x4 *)&rb)[threadIdx.x] = (u32x4){0u, 0u, 0u, 0u};
-}
-
-// Scatters tile row `row`'s slots (16 pixels x K) into a cleared ring buffer, each
-// FP32 weight as hi = RNE(w) and lo = RNE(w - hi).
-template <int K, typename RB>
-__device__ __forceinline__ void ring_scatter(int row, const SlotTable<K> &st, RB &rb) {
-    constexpr bool WD = sizeof(RB) == sizeof(MfRingB);
-    const int t = threadIdx.x;
-    if (t < 16 * K) {
-        const int x = t & 15, k = t >> 4, p = row * 16 + x;
-        const int u = st.u[p * K + k];
-        if (u >= 0) {
-            const float a = st.wa[p * K + k];
-            rb.wa[0][x][u] = bits_bf16(a);
-            rb.wa[1][x][u] = bits_bf16(a - bf16_to_f32(bits_bf16(a)));
-            if constexpr (WD) {
-                const float d = st.wd[p * K + k];
-                MfRingB &rbb = reinterpret_cast<MfRingB &>(rb);
-                rbb.wd[0][u][x] = bits_bf16(d);
-                rbb.wd[1][u][x] = bits_bf16(d - bf16_to_f32(bits_bf16(d)));
-            }
-        }
-    }
-}
-
-// Operands of one row from its ring buffer:
-//   wa[s][h]: lane (i16, g) = Wa_h[pixel i16][16 s + 4 g + j], j < 4     (16x16x16 B)
-//   wd[s]:    lane (i16, g) = Wd_{g/2}[pixel 8 (g % 2) + j][16 s + i16]    (16x16x32 A)
-template <typename RB>
-__device__ __forceinline__ void ring_read(const RB &rb, int lane, i16x4 (&wa)[2][2], i16x8 (&wd)[2]) {
-    const int i16 = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) wa[s][h] = *(const i16x4 *)&rb.wa[h][i16][16 * s + 4 * g];
-        if constexpr (sizeof(RB) == sizeof(MfRingB))
-            wd[s] = *(const i16x8 *)&reinterpret_cast<const MfRingB &>(rb).wd[g >> 1][16 * s + i16][8 * (g & 1)];
-    }
-}
-
-// Ring schedule: before the rows, buffers 0 and 1 are cleared and row 0 scattered
-// into buffer 0.  At row r, after the block barrier: read buffer r % 3, scatter row
-// r + 1 into buffer (r + 1) % 3 (cleared during row r - 1) and clear buffer
-// (r + 2) % 3 (last read during row r - 1).
-template <int K, typename RB>
-__device__ __forceinline__ void ring_start(RB *ring, const SlotTable<K> &st) {
-    ring_clear(ring[0]);
-    ring_clear(ring[1]);
-    __syncthreads();
-    ring_scatter<K>(0, st, ring[0]);
-}
-template <int K, typename RB>
-__device__ __forceinline__ void ring_row(RB *ring, const SlotTable<K> &st, int row, int lane, i16x4 (&wa)[2][2],
-                                         i16x8 (&wd)[2]) {
-    __syncthreads();
-    const int b = row % 3;
-    ring_read(ring[b], lane, wa, wd);
-    if (row + 1 < 16) ring_scatter<K>(row + 1, st, ring[b == 2 ? 0 : b + 1]);
-    ring_clear(ring[b == 0 ? 2 : b - 1]);
-}
-
-// Map block (chunk i, channel block b) of the current row: lane (i16, g) gets
-// F[pixel i16][chunk + 8 g + 4 b + r], r < 4.  Forward and backward run this same
-// sequence, so the recomputed map is bit-identical to the stored one.
-__device__ __forceinline__ f32x4 mf_map(const i16x4 (&a)[2], const i16x4 (&wa)[2][2], int nub) {
-    f32x4 F = {0.f, 0.f, 0.f, 0.f};
-    F = mfma16(a[0], wa[0][0], F);
-    F = mfma16(a[0], wa[0][1], F);
-    if (nub > 1) {
-        F = mfma16(a[1], wa[1][0], F);
-        F = mfma16(a[1], wa[1][1], F);
-    }
-    return F;
-}
-
-// Sign of the L1 feature loss gradient for two packed BF16 map values against the
-// target: -1, 0 or +1 per value, packed as BF16 (the loss scale is applied to the
-// sums).  d = F - F^ is exact; scaling it by 2^140 lifts every nonzero difference
-// of two BF16 values (at least 2^-133) to 2^7 or more before the clamp to [-1, 1].
-__device__ __forceinline__ uint32_t l1_sign2(uint32_t f, uint32_t t) {
-    const float d0 = __uint_as_float(f << 16) - __uint_as_float(t << 16);
-    const float d1 = __uint_as_float(f & 0xFFFF0000u) - __uint_as_float(t & 0xFFFF0000u);
-    const float s0 = __builtin_amdgcn_fmed3f(__builtin_ldexpf(d0, 140), -1.f, 1.f);
-    const float s1 = __builtin_amdgcn_fmed3f(__builtin_ldexpf(d1, 140), -1.f, 1.f);
-    return pk_bf16(s0, s1);
-}
-
-template <int K, int FT>
-__device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int D, int U,
-                                           const void *__restrict__ feat, uint16_t *__restrict__ F,
-                                           UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, D, false);
-    MfRingF *ring = (MfRingF *)(dyn + mf_ring_at(D, K, false, FT == FT_FP8));
-    MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(D, K, false, FT == FT_FP8)))[wave];
-    const MfChunks mc = mf_chunks(D, wave);
-    i16x4 opA[kCPW][2][2];
-    i16x8 opC[kCPW][2];
-    mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
-    ring_start<K>(ring, st);
-    const int nub = U > 16 ? 2 : 1;
-    const int i16 = lane & 15, g = lane >> 4;
-    const int rows = min(16, H - tg.ty0);
-    for (int row = 0; row < rows; ++row) {
-        i16x4 wa[2][2];
-        i16x8 wd[2];
-        ring_row<K>(ring, st, row, lane, wa, wd);
-        // the row's map values go through LDS so that every store instruction writes
-        // whole pixel rows: 16 lanes x 16 bytes per pixel, four pixels per instruction
-#pragma unroll
-        for (int i = 0; i < kCPW; ++i) {
-            if (i >= mc.n) break;
-            const f32x4 F0 = mf_map(opA[i][0], wa, nub);
-            const f32x4 F1 = mf_map(opA[i][1], wa, nub);
-            u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
-                       pk_bf16(F1[2], F1[3])};
-            *(u32x4 *)&mw.out[i16][8 * ((4 * i + g) ^ i16)] = o;
-        }
-        wave_lds_sync();
-        const long rowpix = (long)tg.view * W * H + (long)(tg.ty0 + row) * W + tg.tx0;
-        const int piece = lane & 15;                      // 8 channels each
-        const int ch = mc.beg * 32 + 8 * piece;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int px = 4 * q + (lane >> 4);
-            if (tg.tx0 + px < W && piece < 4 * mc.n && ch < D)
-                *(u32x4 *)(F + (rowpix + px) * D + ch) = *(const u32x4 *)&mw.out[px][8 * (piece ^ px)];
-        }
-        wave_lds_sync();
-    }
-}
-
-// Backward of the MFMA path.  L1: dF holds the target map and G = l1_scale
-// sign(F - F^) is formed from the recomputed map (the products take the sign, the
-// sums the scale); otherwise dF holds dL/dF.  SF (with L1): the map is also stored
-// to Fo, so one pass renders and differentiates.
-template <int K, int FT, bool L1, bool SF, int R>
-__device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, int D, int U,
-                                            const void *__restrict__ feat, const uint16_t *__restrict__ dF,
-                                            float gs, float *__restrict__ dfeat, float *__restrict__ dtw,
-                                            uint16_t *__restrict__ Fo, UnionLds<K, FT> &L, Slots<K> &s,
-                                            unsigned char *dyn) {
-    static_assert(L1 || !SF, "the map is stored only on the L1 path");
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // once the operands are in registers: the waves' partial dot products, [4][256][K]
-    // (K <= 4), or those of the last two rows [2][4][16][K] and the tile's sums [256][K]
-    constexpr bool RS = mf_compact(K);
-    float *sred = (float *)dyn;
-    float *sring = (float *)dyn;
-    float *gsum = sring + 2 * 4 * 16 * K;
-    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, D, true);
-    MfRingB *ring = (MfRingB *)(dyn + mf_ring_at(D, K, true, FT == FT_FP8));
-    MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(D, K, true, FT == FT_FP8)))[wave];
-    // row r's four partials meet after the barrier of row r + 1, in a fixed order
-    auto sum_row = [&](int r) {
-        const int t = threadIdx.x;
-        if (t < 16 * K) {
-            const int i = t & 15, k = t >> 4;
-            const float *b = sring + (size_t)(r & 1) * 4 * 16 * K;
-            float v = b[(0 * 16 + i) * K + k] + b[(1 * 16 + i) * K + k];
-            v += b[(2 * 16 + i) * K + k];
-            v += b[(3 * 16 + i) * K + k];
-            gsum[(r * 16 + i) * K + k] = v;
-        }
-    };
-    const MfChunks mc = mf_chunks(D, wave);
-    i16x4 opA[kCPW][2][2];
-    i16x8 opC[kCPW][2];
-    mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
-    ring_start<K>(ring, st);
-    const int nub = U > 16 ? 2 : 1;
-    const int i16 = lane & 15, g = lane >> 4;
-    const int x = tg.tx0 + i16;
-    const int rows = min(16, H - tg.ty0);
-    const float gscale = L1 ? gs : 1.f;   // the L1 path accumulates sign(F - F^)
-
-    f32x4 acc[kCPW][2][2];   // [chunk][channel block][union block]
-#pragma unroll
-    for (int i = 0; i < kCPW; ++i)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int v = 0; v < 2; ++v) acc[i][b][v] = (f32x4){0.f, 0.f, 0.f, 0.f};
-
-    // dL/dF (or the target) of R - 1 rows ahead, in an R-deep register ring; lane
-    // (i16, g) reads channels 8g..8g+7 of each chunk for pixel i16.  The loads carry
-    // no branches: each is a uniform row base plus a per-lane offset fixed for the
-    // tile, where a lane whose pixel or channels lie outside reads the row's first
-    // element (rows past the image read the last row).  Such values meet only zero
-    // weights and zero operands; the L1 gradient is always finite, dL/dF is masked.
-    u32x4 tb[R][kCPW];
-    uint32_t loff[kCPW];
-    bool lon[kCPW];
-#pragma unroll
-    for (int i = 0; i < kCPW; ++i) {
-        const int ch = (mc.beg + i) * 32 + 8 * g;
-        lon[i] = x < W && i < mc.n && ch < D;
-        loff[i] = lon[i] ? (uint32_t)(i16 * D + ch) : 0u;
-    }
-    auto row_at = [&](int row) { return ((long)tg.view * W * H + (long)(tg.ty0 + row) * W + tg.tx0) * D; };
-    auto fetch = [&](int row, u32x4 (&dst)[kCPW]) {
-        const uint16_t *base = dF + row_at(min(row, rows - 1));
-#pragma unroll
-        for (int i = 0; i < kCPW; ++i) dst[i] = *(const u32x4 *)(base + loff[i]);
-    };
-#pragma unroll
-    for (int r = 0; r < R - 1; ++r) fetch(r, tb[r]);
-
-    // every wave walks all 16 rows and all kCPW chunks: rows past the image and
-    // chunks past D carry zero weights and zero operands
-#pragma unroll 1
-    for (int row0 = 0; row0 < 16; row0 += R) {
-#pragma unroll
-        for (int h = 0; h < R; ++h) {
-            const int row = row0 + h;
-            fetch(row + R - 1, tb[(h + R - 1) % R]);
-            i16x4 wa[2][2];
-            i16x8 wd[2];
-            ring_row<K>(ring, st, row, lane, wa, wd);
-            if constexpr (RS)
-                if (row > 0) sum_row(row - 1);
-            f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-            for (int i = 0; i < kCPW; ++i) {
-                const u32x4 T = (L1 || (row < rows && lon[i])) ? tb[h][i] : (u32x4){0u, 0u, 0u, 0u};
-                u32x4 G;
-                if constexpr (L1) {
-                    const f32x4 F0 = mf_map(opA[i][0], wa, nub);
-                    const f32x4 F1 = mf_map(opA[i][1], wa, nub);
-                    u32x4 Fp = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
-                                pk_bf16(F1[2], F1[3])};
-                    __asm__ volatile("" : "+v"(Fp.x), "+v"(Fp.y), "+v"(Fp.z), "+v"(Fp.w));
-                    // the stored map: the target's layout, so the same per-lane offsets
-                    if constexpr (SF)
-                        if (row < rows && lon[i]) *(u32x4 *)(Fo + row_at(row) + loff[i]) = Fp;
-                    G.x = l1_sign2(Fp.x, T.x);
-                    G.y = l1_sign2(Fp.y, T.y);
-                    G.z = l1_sign2(Fp.z, T.z);
-                    G.w = l1_sign2(Fp.w, T.w);
-                } else {
-                    G = T;
-                }
-                // keep G packed: its halves are stored as they are, not re-derived
-                __asm__ volatile("" : "+v"(G.x), "+v"(G.y), "+v"(G.z), "+v"(G.w));
-                // dot products over the chunk's 32 channels
-                sacc[0] = mfma32(opC[i][0], as_op8(G), sacc[0]);
-                if (nub > 1) sacc[1] = mfma32(opC[i][1], as_op8(G), sacc[1]);
-                // G transposed: block b row 4g + r <- this lane's channel 8g + 4b + r
-                mw.gt[i][0][4 * g + 0][i16] = (uint16_t)(G.x & 0xFFFFu);
-                mw.gt[i][0][4 * g + 1][i16] = (uint16_t)(G.x >> 16);
-                mw.gt[i][0][4 * g + 2][i16] = (uint16_t)(G.y & 0xFFFFu);
-                mw.gt[i][0][4 * g + 3][i16] = (uint16_t)(G.y >> 16);
-                mw.gt[i][1][4 * g + 0][i16] = (uint16_t)(G.z & 0xFFFFu);
-                mw.gt[i][1][4 * g + 1][i16] = (uint16_t)(G.z >> 16);
-                mw.gt[i][1][4 * g + 2][i16] = (uint16_t)(G.w & 0xFFFFu);
-                mw.gt[i][1][4 * g + 3][i16] = (uint16_t)(G.w >> 16);
-            }
-            wave_lds_sync();
-            // gradient rows: B operand [hi pixels; lo pixels] x 16 block rows, i.e. G of
-            // pixels 8 (g % 2) + j
-#pragma unroll
-            for (int i = 0; i < kCPW; ++i)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const i16x8 g2 = *(const i16x8 *)&mw.gt[i][b][i16][8 * (g & 1)];
-                    acc[i][b][0] = mfma32(wd[0], g2, acc[i][b][0]);
-                    if (nub > 1) acc[i][b][1] = mfma32(wd[1], g2, acc[i][b][1]);
-                }
-            wave_lds_sync();
-            // this wave's share of S^T for the row -> its K slots, through LDS
-            float *spb = (float *)&mw;   // [kUP][16], over the G buffer
-#pragma unroll
-            for (int v = 0; v < 2; ++v)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) spb[(16 * v + 4 * g + r) * 16 + i16] = sacc[v][r];
-            wave_lds_sync();
-            const int p = row * 16 + i16;
-            for (int k = g; k < K; k += 4) {
-                const int u = st.u[p * K + k];
-                const float val = u >= 0 ? gscale * spb[u * 16 + i16] : 0.f;
-                if constexpr (RS) sring[(((row & 1) * 4 + wave) * 16 + i16) * K + k] = val;
-                else sred[(wave * kTilePix + p) * K + k] = val;
-            }
-            wave_lds_sync();
-        }
-    }
-    if constexpr (RS) {
-        __syncthreads();
-        sum_row(15);
-    }
-
-    // gradient rows: lane (i16, g) holds dFt[16 v + 4 g + r][chunk + blk_ch(b, i16)]
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        if (v >= nub) break;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int u = 16 * v + 4 * g + r;
-            if (u >= U) continue;
-            float *dst = dfeat + (long)L.uid2[u] * D;
-#pragma unroll
-            for (int i = 0; i < kCPW; ++i) {
-                if (i >= mc.n) break;
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int ch = (mc.beg + i) * 32 + blk_ch(b, i16);
-                    const float val = gscale * acc[i][b][v][r];
-                    if (ch < D && val != 0.f) unsafeAtomicAdd(dst + ch, val);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // gamma_k = (g_k - sum_j w'_j g_j) / W for the thread's own pixel
-    const int t = threadIdx.x;
-    const int px = tg.tx0 + (t & 15), py = tg.ty0 + (t >> 4);
-    if (px >= W || py >= H) return;
-    const long p = (long)tg.view * W * H + (long)py * W + px;
-    float gk[K], mean = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        float v;
-        if constexpr (RS) {
-            v = gsum[t * K + k];
-        } else {
-            v = sred[(0 * kTilePix + t) * K + k] + sred[(1 * kTilePix + t) * K + k];
-            v += sred[(2 * kTilePix + t) * K + k];
-            v += sred[(3 * kTilePix + t) * K + k];
-        }
-        if constexpr (FT == FT_FP8) v *= s.u[k] >= 0 ? L.uscale2[s.u[k]] : 0.f;
-        gk[k] = s.u[k] >= 0 ? v : 0.f;
-        mean = fmaf(s.wp[k], gk[k], mean);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) dtw[p * K + k] = s.u[k] >= 0 ? (gk[k] - mean) / s.W : 0.f;
-}
-
-// ---------------------------------------------------------------- forward
-
-// The wave's pixels.  STAGED: every union row of the tile is in LDS, so the loop
-// issues no global loads at all and its stores never have to be waited for.
-template <int K, int FT, int MT, bool STAGED>
-__device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
-                                           const void *__restrict__ feat, void *__restrict__ F,
-                                           const Slots<K> &sl, const UnionLds<K, FT> &L,
-                                           const unsigned char *rows, int wave, int lane) {
-    constexpr int CPL = TileCfg<K>::CPL;
-    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
-    for (int pass = 0; pass < passes; ++pass) {
-        const int c0 = pass * 64 * CPL + lane * CPL;
-        const bool lane_on = c0 < D;
-        for (int i = 0; i < kPixPerWave; ++i) {
-            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
-            if (x >= W || y >= H) continue;
-            const long p = (long)tg.view * W * H + (long)y * W + x;
-            float out[CPL];
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) out[j] = 0.f;
-            if constexpr (STAGED) {
-                // branch-free: an empty slot reads row 0 with weight 0, a lane past D
-                // reads channel 0 and stores nothing; all K reads issue together
-                const int cc = lane_on ? c0 : 0;
-                float v[K][CPL];
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int u = rdlane(sl.u[k], i);
-                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * D + cc, v[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float wf = rdlane(sl.wf[k], i);
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) out[j] = fmaf(wf, v[k][j], out[j]);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int u = rdlane(sl.u[k], i);
-                    if (u < 0 || !lane_on) continue;
-                    const float wf = rdlane(sl.wf[k], i);
-                    float v[CPL];
-                    urow<FT, CPL>(rows, ucap, L.uid, u, feat, D, c0, v);
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) out[j] = fmaf(wf, v[j], out[j]);
-                }
-            }
-            if (lane_on) storec<MT, CPL>(F, p * D + c0, out);
-        }
-    }
-}
-
-// Tiles take the MFMA path when the storage / map formats allow it and the union fits.
-template <int K, int FT, int MT>
-struct MfOk {
-    static constexpr bool v = (FT == FT_BF16 || FT == FT_FP8) && MT == MT_BF16 && K <= 8;
-};
-
-template <int K, int FT, int MT>
-__global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int views, int D, int ucap,
-                                                          const void *__restrict__ feat,
-                                                          const float *__restrict__ scale,
-                                                          const int *__restrict__ ids,
-                                                          const float *__restrict__ tw,
-                                                          void *__restrict__ F) {
-    extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ UnionLds<K, FT> L;
-    const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const TileGeom tg = tile_geom(tile, W, H);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    Slots<K> sl;
-    int U;
-    tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
-    if constexpr (MfOk<K, FT, MT>::v) {
-        if (U <= kUP && D <= 128 * kCPW) {
-            mf_forward<K, FT>(tg, W, H, D, U, feat, (uint16_t *)F, L, sl, dyn);
-            return;
-        }
-    }
-    stage_rows<K, FT>(L, U, D, ucap, feat, dyn);
-    if (U >= 1 && U <= ucap) fwd_pixels<K, FT, MT, true>(tg, W, H, D, ucap, feat, F, sl, L, dyn, wave, lane);
-    else fwd_pixels<K, FT, MT, false>(tg, W, H, D, ucap, feat, F, sl, L, dyn, wave, lane);
-}
-
-// ---------------------------------------------------------------- backward
-
-// The wave's pixels for one channel pass after another.  STAGED: every union row of
-// the tile is in LDS, so the only global traffic in the loop is dL/dF (or the target).
-template <int K, int FT, int MT, bool L1, bool SF, bool STAGED>
-__device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
-                                           const void *__restrict__ feat, const void *__restrict__ dF,
-                                           float l1_scale, float *__restrict__ dfeat, void *__restrict__ Fo,
-                                           const Slots<K> &sl, const UnionLds<K, FT> &L,
-                                           const unsigned char *rows, int nw,
-                                           float (*sdot)[K], float *xbuf, int wave, int lane) {
-    constexpr int CPL = TileCfg<K>::CPL, RA = TileCfg<K>::RA;
-    const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
-    constexpr int MS = MT == MT_F32 ? FT_F32 : FT_BF16;
-    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
-    for (int pass = 0; pass < passes; ++pass) {
-        const int c0 = pass * 64 * CPL + lane * CPL;
-        const bool lane_on = c0 < D;
-        float acc[RA][CPL];
-#pragma unroll
-        for (int r = 0; r < RA; ++r)
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) acc[r][j] = 0.f;
-        // dL/dF (or the target) one pixel ahead of its use
-        auto want = [&](int i) {
-            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
-            return x < W && y < H && rdlane(sl.W, i) > 0.f;
-        };
-        auto fetch = [&](int i, float (&dst)[CPL]) {
-            const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) dst[j] = 0.f;
-            if (want(i) && lane_on)
-                loadc<MS, CPL>(dF, ((long)tg.view * W * H + (long)y * W + x) * D + c0, dst);
-        };
-        float nxt[CPL];
-        fetch(0, nxt);
-        for (int i = 0; i < kPixPerWave; ++i) {
-            float cur[CPL];
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) cur[j] = nxt[j];
-            if (i + 1 < kPixPerWave) fetch(i + 1, nxt);
-            if constexpr (SF) {
-                // pixels without contributors still get their (zero) map entries
-                const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
-                if (x < W && y < H && !(rdlane(sl.W, i) > 0.f) && lane_on) {
-                    float z[CPL];
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) z[j] = 0.f;
-                    storec<MT, CPL>(Fo, ((long)tg.view * W * H + (long)y * W + x) * D + c0, z);
-                }
-            }
-            if (!want(i)) continue;
-            int wl[K];
-            float wp[K], v[K][CPL];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                wl[k] = rdlane(sl.wl[k], i);
-                wp[k] = rdlane(sl.wp[k], i);
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) v[k][j] = 0.f;
-                const int u = rdlane(sl.u[k], i);
-                if constexpr (STAGED) {
-                    // branch-free (see the forward); empty slots carry weight 0 and
-                    // their dot product is never used
-                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * D + (lane_on ? c0 : 0), v[k]);
-                    if (!lane_on) {
-#pragma unroll
-                        for (int j = 0; j < CPL; ++j) v[k][j] = 0.f;
-                    }
-                } else if (u >= 0 && lane_on) {
-                    urow<FT, CPL>(rows, ucap, L.uid, u, feat, D, c0, v[k]);
-                }
-            }
-            float G[CPL];
-            if constexpr (L1) {
-                float Fv[CPL];
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) Fv[j] = 0.f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (wl[k] < 0) continue;
-                    const float wf = rdlane(sl.wf[k], i);
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) Fv[j] = fmaf(wf, v[k][j], Fv[j]);
-                }
-                float fm[CPL];
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) {
-                    fm[j] = MT == MT_F32 ? Fv[j] : bf16_to_f32(f32_to_bf16(Fv[j]));
-                    const float d = lane_on ? fm[j] - cur[j] : 0.f;
-                    G[j] = d > 0.f ? gs : (d < 0.f ? -gs : 0.f);
-                }
-                if constexpr (SF) {
-                    const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
-                    if (lane_on) storec<MT, CPL>(Fo, ((long)tg.view * W * H + (long)y * W + x) * D + c0, fm);
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) G[j] = cur[j];
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                float part = 0.f;
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) part = fmaf(G[j], v[k][j], part);
-                if constexpr (FT == FT_FP8) {
-                    const int u = rdlane(sl.u[k], i);
-                    part *= (u >= 0 ? L.uscale[u] : 0.f);
-                }
-                const float g = wave_sum(part);
-                if (lane == 0) sdot[i][k] += g;
-                if (wl[k] < 0) continue;
-                if (wl[k] < RA) {
-#pragma unroll
-                    for (int r = 0; r < RA; ++r) {
-                        if (r != wl[k]) continue;
-#pragma unroll
-                        for (int j = 0; j < CPL; ++j) acc[r][j] = fmaf(wp[k], G[j], acc[r][j]);
-                    }
-                } else {
-                    // beyond the register accumulators: straight to global memory
-                    float a[CPL];
-#pragma unroll
-                    for (int j = 0; j < CPL; ++j) a[j] = wp[k] * G[j];
-                    flush_row<CPL>(a, L.wlist[wave][wl[k]], D, pass * 64 * CPL, lane, dfeat, xbuf);
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RA; ++r)
-            if (r < nw) flush_row<CPL>(acc[r], L.wlist[wave][r], D, pass * 64 * CPL, lane, dfeat, xbuf);
-    }
-}
-
-// MODE 0: dF holds dL/dF (map dtype).  MODE 1: dF holds the target map F^ and
-// dL/dF = l1_scale * sign(F - F^) is formed on the fly from F recomputed exactly as
-// the forward kernel computes and rounds it.  MODE 2: as 1, and that F is stored to
-// Fo, bit-identical to the forward kernel's map (render and adjoint in one pass).
-constexpr int kRing = 1;   // rows of dL/dF in flight on the MFMA path, besides the one in use
-
-template <int K, int CPL>
-constexpr size_t fallback_extra() { return (size_t)4 * kPixPerWave * K * 4 + (size_t)4 * 64 * CPL * 4; }
-
-// Two blocks per CU: registers are capped at 256 per lane.
-template <int K, int FT, int MT, int MODE>
-__global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int views, int D, int ucap,
-                                                          const void *__restrict__ feat,
-                                                          const float *__restrict__ scale,
-                                                          const int *__restrict__ ids,
-                                                          const float *__restrict__ tw,
-                                                          const void *__restrict__ dF, float l1_scale,
-                                                          float *__restrict__ dfeat,
-                                                          float *__restrict__ dtw, void *__restrict__ Fo) {
-    constexpr int CPL = TileCfg<K>::CPL;
-    constexpr bool L1 = MODE >= 1, SF = MODE == 2;
-    extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ UnionLds<K, FT> L;
-    const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const TileGeom tg = tile_geom(tile, W, H);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    Slots<K> sl;
-    int U;
-    const int nw = tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
-    if constexpr (MfOk<K, FT, MT>::v) {
-        if (U <= kUP && D <= 128 * kCPW) {
-            const float gs = bf16_to_f32(f32_to_bf16(l1_scale));
-            mf_backward<K, FT, L1, SF, kRing + 1>(tg, W, H, D, U, feat, (const uint16_t *)dF, gs, dfeat, dtw,
-                                                  (uint16_t *)Fo, L, sl, dyn);
-            return;
-        }
-    }
-    // per-pixel path: staged rows, then the dot products and the transpose buffers
-    float(*s_dot)[kPixPerWave][K] = (float(*)[kPixPerWave][K])(dyn + kRowBudget);
-    float(*s_x)[64 * CPL] = (float(*)[64 * CPL])(dyn + kRowBudget + (size_t)4 * kPixPerWave * K * 4);
-    float *xbuf = s_x[wave];
-    stage_rows<K, FT>(L, U, D, ucap, feat, dyn);
-#pragma unroll
-    for (int k = 0; k < K; ++k) s_dot[wave][lane][k] = 0.f;
-    if (U >= 1 && U <= ucap)
-        bwd_pixels<K, FT, MT, L1, SF, true>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
-                                           s_dot[wave], xbuf, wave, lane);
-    else
-        bwd_pixels<K, FT, MT, L1, SF, false>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
-                                            s_dot[wave], xbuf, wave, lane);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // gamma_k = (g_k - sum_j w'_j g_j) / W for the lane's own pixel
-    const int x = tg.tx0 + (lane & 15), y = tg.ty0 + wave * 4 + (lane >> 4);
-    if (x >= W || y >= H) return;
-    const long p = (long)tg.view * W * H + (long)y * W + x;
-    float g[K], mean = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        g[k] = s_dot[wave][lane][k];
-        mean = fmaf(sl.wp[k], g[k], mean);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        dtw[p * K + k] = (sl.W > 0.f && sl.id[k] >= 0) ? (g[k] - mean) / sl.W : 0.f;
-}
 
 // ---------------------------------------------------------------- quantize, L1, union
 
@@ -1394,53 +140,29 @@ __global__ __launch_bounds__(256) void union_sum_kernel(int n, int *__restrict__
 
 // ---------------------------------------------------------------- dispatch
 
-// Staged union rows per block: as many as fit in `budget` bytes (at least 0).
-inline int pick_ucap(int D, int sf, int budget) { return budget / (D * sf); }
-
-
 template <int FT, int MT>
 lgs_status fwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
                         const int *ids, const float *tw, void *F, hipStream_t st) {
-    unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
-    const int rb = D * Bytes<FT>::v;
-    // MFMA-capable kernels give the per-pixel path (unions beyond kUP) whatever rows
-    // fit the MFMA path's LDS, so that both paths keep four blocks per CU
-#define CALL(KK)                                                                                     \
-    case KK:                                                                                         \
-        if (MfOk<KK, FT, MT>::v) {                                                                   \
-            lds = mf_lds_bytes(D, KK, false, FT == FT_FP8);                                          \
-            ucap = (int)(lds / rb);                                                                  \
-        } else {                                                                                     \
-            ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);                                           \
-            lds = (size_t)ucap * rb;                                                                 \
-        }                                                                                            \
-        hipLaunchKernelGGL((feature_fwd_kernel<KK, FT, MT>), dim3(grid), dim3(kFB), lds, st, W, H,  \
-                           views, D, ucap, feat, scale, ids, tw, F);                                 \
-        break;
-    size_t lds = 0;
-    int ucap = 0;
+#define CALL(KK) \
+    case KK: return feature_fwd_launch<KK, FT, MT>(W, H, views, D, feat, scale, ids, tw, F, st);
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
-    return check_launch("feature_render_fwd");
+    set_error("K = %d is not compiled", k);
+    return LGS_ERR_UNSUPPORTED;
 }
 
 template <int FT, int MT, int MODE>
 lgs_status bwd_dispatch(int k, int W, int H, int views, int D, const void *feat, const float *scale,
                         const int *ids, const float *tw, const void *dF, float l1_scale, float *dfeat,
                         float *dtw, void *Fo, hipStream_t st) {
-    unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
-    const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
-#define CALL(KK)                                                                                     \
-    case KK:                                                                                         \
-        lds = kRowBudget + fallback_extra<KK, TileCfg<KK>::CPL>();                                  \
-        if (MfOk<KK, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, KK, true, FT == FT_FP8));           \
-        hipLaunchKernelGGL((feature_bwd_kernel<KK, FT, MT, MODE>), dim3(grid), dim3(kFB), lds, st, W, \
-                           H, views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw, Fo);    \
-        break;
-    size_t lds = 0;
+#define CALL(KK)                                                                                        \
+    case KK:                                                                                            \
+        return feature_bwd_launch<KK, FT, MT, MODE>(W, H, views, D, feat, scale, ids, tw, dF, l1_scale, \
+                                                    dfeat, dtw, Fo, st);
     switch (k) { CALL(1) CALL(2) CALL(3) CALL(4) CALL(5) CALL(8) CALL(10) CALL(16) }
 #undef CALL
-    return check_launch("feature_render_bwd");
+    set_error("K = %d is not compiled", k);
+    return LGS_ERR_UNSUPPORTED;
 }
 
 template <int MODE>

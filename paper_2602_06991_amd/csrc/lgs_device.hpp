@@ -8,6 +8,10 @@
 
 namespace lgs {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 constexpr int kTile = 16;
 constexpr int kTilePix = kTile * kTile;   // 256 pixels = one 256-thread block
 constexpr int kWave = 64;
