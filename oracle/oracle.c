@@ -453,6 +453,52 @@ int orc_render(int n, const float *means, const float *ls, const float *q, const
 }
 
 /*
+ * Vanilla feature render (the alpha-blended feature field that Top-K rendering replaces,
+ * Sec. 3.2 and Tab. 4): the D-channel feature blended exactly as the colour of Eq. 1,
+ * over every blended Gaussian, F[p*D + ch] = sum_i w_i feat[id_i*D + ch], with the
+ * weights w_i = alpha_i T_i of the same blend.  feat[n*D] holds FP64 features.
+ */
+int orc_vanilla_feature(int n, const float *means, const float *ls, const float *q, const float *opl,
+                        const float *rgb, const float *cam, int W, int H, int D, const double *feat,
+                        double *F)
+{
+    cam_t c;
+    cam_from(cam, W, H, &c);
+    proj_t *P = project_all(&c, n, means, ls, q, opl, rgb);
+    if (!P) return -1;
+    bins_t b;
+    if (make_bins(P, n, W, H, 0, &b)) { free(P); return -1; }
+    int cap = max_list_len(&b) + 1;
+    int err = 0;
+#pragma omp parallel
+    {
+        blend_t *bl = (blend_t *)malloc(sizeof(blend_t) * (size_t)cap);
+        if (!bl) {
+#pragma omp atomic write
+            err = -1;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (long pix = 0; pix < (long)W * H; ++pix) {
+            if (!bl) continue;
+            int x = (int)(pix % W), y = (int)(pix / W);
+            int t = (y / ORC_TILE) * b.ntx + x / ORC_TILE;
+            pix_t o;
+            blend_pixel(P, rgb, b.list + b.start[t], b.start[t + 1] - b.start[t], x, y, 1, bl, &o);
+            double *out = F + pix * D;
+            for (int ch = 0; ch < D; ++ch) out[ch] = 0;
+            for (int i = 0; i < o.n; ++i) {
+                const double *f = feat + (long)bl[i].id * D;
+                for (int ch = 0; ch < D; ++ch) out[ch] += bl[i].w * f[ch];
+            }
+        }
+        free(bl);
+    }
+    free_bins(&b);
+    free(P);
+    return err;
+}
+
+/*
  * Pruning statistics of Sec. 3.3 for one view, accumulated into the caller's arrays:
  *   count[g] += number of pixels whose Top-K list (Eq. 2) holds g;
  *   maxw[g] = max(maxw[g], w) over every pixel where g is blended (Eq. 5's S_g: the
@@ -578,7 +624,17 @@ enum { G_MX, G_MY, G_CA, G_CB, G_CC, G_OP, G_R, G_G, G_B, G_Z, G_NS };
  *   d_mean2d[2n], d_conic[3n] (a, b, c of sigma = a dx^2/2 + b dx dy + c dy^2/2),
  *   d_opac[n], d_rgb[3n], d_z[n]  (all may be NULL),
  * the per-slot Top-K weight gradient d_topkw[P*K] (may be NULL),
- * and the parameter gradients d_means[3n], d_ls[3n], d_q[4n], d_opl[n], d_feat[n*D].
+ * the parameter gradients d_means[3n], d_ls[3n], d_q[4n], d_opl[n], d_feat[n*D],
+ * With vanilla != 0 the upstream gF is that of the vanilla feature render
+ * (orc_vanilla_feature) instead of the Top-K one: every blended Gaussian then receives
+ * the feature term, d_feat[id_i] += w_i gF and e_i += <gF, f_i>, and d_topkw is zero.
+ * Also the camera-pose gradients (both may be NULL):
+ *   d_Rt[12]: partial derivatives with respect to the 12 entries of the world->camera
+ *             [R|t] (row-major 3x4), each entry taken as an independent variable;
+ *   d_pose[6]: the gradient with respect to a pose increment xi = (rho, phi) applied on
+ *             the left, [R|t] <- exp(xi^) [R|t], i.e. R <- (I + [phi]x) R and
+ *             t <- (I + [phi]x) t + rho to first order (the rendering-loss pose
+ *             refinement of Sec. 4.1): rho first, then phi.
  */
 int orc_backward(int n, const float *means, const float *ls, const float *q, const float *opl,
                  const float *rgb, const float *cam, int W, int H, int K, int D,
@@ -586,7 +642,8 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
                  const double *gF,
                  double *d_mean2d, double *d_conic, double *d_opac, double *d_rgb, double *d_z,
                  double *d_topkw,
-                 double *d_means, double *d_ls, double *d_q, double *d_opl, double *d_feat)
+                 double *d_means, double *d_ls, double *d_q, double *d_opl, double *d_feat,
+                 double *d_Rt, double *d_pose, int vanilla)
 {
     if (K < 1 || K > 63) return -2;
     cam_t c;
@@ -605,7 +662,11 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
     /* per pixel Top-K ids and normalized weights, for the feature scatter below */
     int *tk_id = (int *)malloc(sizeof(int) * (size_t)NP * K);
     double *tk_wp = (double *)malloc(sizeof(double) * (size_t)NP * K);
-    if (!acc || !tk_id || !tk_wp) { free(acc); free(tk_id); free(tk_wp); free_bins(&b); free(P); return -1; }
+    /* blended count per pixel, for the vanilla feature gradient */
+    int *nbl = vanilla ? (int *)malloc(sizeof(int) * (size_t)NP) : NULL;
+    if (!acc || !tk_id || !tk_wp || (vanilla && !nbl)) {
+        free(acc); free(tk_id); free(tk_wp); free(nbl); free_bins(&b); free(P); return -1;
+    }
     int err = 0;
 #pragma omp parallel
     {
@@ -640,7 +701,8 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
                 tk_id[pix * K + k] = -1;
                 tk_wp[pix * K + k] = 0;
             }
-            if (Wsum > 0) {
+            if (nbl) nbl[pix] = o.n;
+            if (Wsum > 0 && !vanilla) {
                 for (int k = 0; k < K; ++k) {
                     if (ids[k] < 0) continue;
                     double s = 0;
@@ -665,6 +727,12 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
             }
             for (int k = 0; k < K; ++k)
                 if (pos[k] >= 0) e[pos[k]] += gam[k];
+            if (vanilla && gF)   /* the feature blended like the colour: e_i += <gF, f_i> */
+                for (int i = 0; i < o.n; ++i) {
+                    double sdot = 0;
+                    for (int ch = 0; ch < D; ++ch) sdot += gF[pix * D + ch] * feat[(long)bl[i].id * D + ch];
+                    e[i] += sdot;
+                }
             /* back to front: dL/dalpha_i = T_i e_i - (sum_{j>i} e_j w_j) / (1 - alpha_i) */
             double A = 0;
             for (int i = o.n - 1; i >= 0; --i) {
@@ -691,14 +759,53 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
         free(bl);
         free(e);
     }
-    if (err) { free(acc); free(tk_id); free(tk_wp); free_bins(&b); free(P); return err; }
+    if (err) { free(acc); free(tk_id); free(tk_wp); free(nbl); free_bins(&b); free(P); return err; }
     /* reduce the per-thread slots */
     for (int t = 1; t < nthr; ++t) {
         double *src = acc + (size_t)t * (size_t)n * G_NS;
         for (size_t i = 0; i < (size_t)n * G_NS; ++i) acc[i] += src[i];
     }
+    /* feature gradient, vanilla: dL/df_i += w_i gF over every blended (pixel, Gaussian);
+       the blended lists are replayed into CSR form, then channels are split over threads */
+    if (d_feat && vanilla) {
+        memset(d_feat, 0, sizeof(double) * (size_t)n * D);
+        long *off = (long *)malloc(sizeof(long) * (size_t)(NP + 1));
+        off[0] = 0;
+        for (long pix = 0; pix < NP; ++pix) off[pix + 1] = off[pix] + nbl[pix];
+        int *pid = (int *)malloc(sizeof(int) * (size_t)(off[NP] > 0 ? off[NP] : 1));
+        double *pw = (double *)malloc(sizeof(double) * (size_t)(off[NP] > 0 ? off[NP] : 1));
+        if (gF && pid && pw) {
+#pragma omp parallel
+            {
+                blend_t *bl = (blend_t *)malloc(sizeof(blend_t) * (size_t)cap);
+#pragma omp for schedule(dynamic, 64)
+                for (long pix = 0; pix < NP; ++pix) {
+                    int x = (int)(pix % W), y = (int)(pix / W);
+                    int t = (y / ORC_TILE) * b.ntx + x / ORC_TILE;
+                    pix_t o;
+                    blend_pixel(P, rgb, b.list + b.start[t], b.start[t + 1] - b.start[t], x, y, 1, bl, &o);
+                    for (int i = 0; i < o.n; ++i) {
+                        pid[off[pix] + i] = bl[i].id;
+                        pw[off[pix] + i] = bl[i].w;
+                    }
+                }
+                free(bl);
+            }
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int c0 = 0; c0 < D; c0 += 8) {
+                int c1 = c0 + 8 < D ? c0 + 8 : D;
+                for (long pix = 0; pix < NP; ++pix)
+                    for (long j = off[pix]; j < off[pix + 1]; ++j) {
+                        double *dst = d_feat + (long)pid[j] * D;
+                        const double *src = gF + pix * D;
+                        for (int ch = c0; ch < c1; ++ch) dst[ch] += pw[j] * src[ch];
+                    }
+            }
+        }
+        free(off); free(pid); free(pw);
+    }
     /* feature gradient: dL/df_k += w'_k gF */
-    if (d_feat) {
+    if (d_feat && !vanilla) {
         memset(d_feat, 0, sizeof(double) * (size_t)n * D);
         if (gF)
             for (long pix = 0; pix < NP; ++pix)
@@ -713,9 +820,11 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
     }
     free(tk_id);
     free(tk_wp);
+    free(nbl);
 
     /* chain rule, per Gaussian */
-#pragma omp parallel for schedule(static)
+    double rt[12] = {0};
+#pragma omp parallel for schedule(static) reduction(+ : rt[:12])
     for (int g = 0; g < n; ++g) {
         const double *a = acc + (size_t)g * G_NS;
         const proj_t *p = &P[g];
@@ -787,6 +896,18 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
             /* t = Rcam mu + tcam */
             for (int j = 0; j < 3; ++j)
                 dmu[j] = c.R[0][j] * dt[0] + c.R[1][j] * dt[1] + c.R[2][j] * dt[2];
+            /* the camera's own entries: t_i = sum_j R_ij mu_j + tcam_i gives dR_ij += dt_i mu_j
+               and dtcam_i += dt_i; Tm = J Rcam gives dRcam = J^T dTm, with J (2x3) as
+               projected: J00 = fx/tz, J02 = -fx xc/tz, J11 = fy/tz, J12 = -fy yc/tz, where
+               xc, yc are the (clamped) ratios tx/tz, ty/tz */
+            double xc = p->clampx ? (tx / tz < 0 ? -p->limx : p->limx) : tx / tz;
+            double yc = p->clampy ? (ty / tz < 0 ? -p->limy : p->limy) : ty / tz;
+            double Jm[2][3] = {{fx / tz, 0, -fx * xc / tz}, {0, fy / tz, -fy * yc / tz}};
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j)
+                    rt[4 * i + j] += dt[i] * (double)means[3 * g + j] + Jm[0][i] * dTm[0][j] + Jm[1][i] * dTm[1][j];
+                rt[4 * i + 3] += dt[i];
+            }
             /* Sig = M M^T with M = Rq diag(s): dM = 2 dSig M (dSig symmetric) */
             double M[3][3], dM[3][3];
             for (int i = 0; i < 3; ++i)
@@ -829,6 +950,37 @@ int orc_backward(int n, const float *means, const float *ls, const float *q, con
         if (d_q)
             for (int i = 0; i < 4; ++i) d_q[4 * g + i] = dq[i];
         if (d_opl) d_opl[g] = dop;
+    }
+    if (d_Rt)
+        for (int i = 0; i < 12; ++i) d_Rt[i] = rt[i];
+    if (d_pose) {
+        /* rho: t <- t + rho, so dL/drho = dL/dt.  phi: dR = [phi]x R and dt = phi x t, so
+           dL = sum_ij GR_ij ([phi]x R)_ij + Gt . (phi x t), with GR, Gt the partials above */
+        double GR[3][3], Gt[3], M[3][3];
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) GR[i][j] = rt[4 * i + j];
+            Gt[i] = rt[4 * i + 3];
+        }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0;
+                for (int k = 0; k < 3; ++k) s += c.R[i][k] * GR[j][k];
+                M[i][j] = s;   /* (R GR^T)_ij */
+            }
+        /* sum_ij GR_ij (S R)_ij = sum_ik S_ik M_ki for S = [phi]x = [[0, -pz, py],
+           [pz, 0, -px], [-py, px, 0]]: collecting px, py, pz gives the three lines below */
+        double dphi[3];
+        dphi[0] = M[1][2] - M[2][1];
+        dphi[1] = M[2][0] - M[0][2];
+        dphi[2] = M[0][1] - M[1][0];
+        /* phi . (t x Gt) */
+        dphi[0] += c.t[1] * Gt[2] - c.t[2] * Gt[1];
+        dphi[1] += c.t[2] * Gt[0] - c.t[0] * Gt[2];
+        dphi[2] += c.t[0] * Gt[1] - c.t[1] * Gt[0];
+        for (int i = 0; i < 3; ++i) {
+            d_pose[i] = Gt[i];
+            d_pose[3 + i] = dphi[i];
+        }
     }
     free(acc);
     free_bins(&b);
@@ -940,6 +1092,18 @@ int orc_num_threads(void)
 #ifdef _OPENMP
     return omp_get_max_threads();
 #else
+    return 1;
+#endif
+}
+
+/* Sets the OpenMP thread count of later calls; returns the count now in effect. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
     return 1;
 #endif
 }

@@ -45,7 +45,10 @@ def lib():
         L.orc_feature.argtypes = [Lg, I, I, P, P, P, P]
         L.orc_prune_stats.argtypes = [I, P, P, P, P, P, P, I, I, I, P, P]
         L.orc_backward.argtypes = [I, P, P, P, P, P, P, I, I, I, I, P, P, P, P, P,
-                                   P, P, P, P, P, P, P, P, P, P, P]
+                                   P, P, P, P, P, P, P, P, P, P, P, P, P, I]
+        L.orc_vanilla_feature.argtypes = [I, P, P, P, P, P, P, I, I, I, P, P]
+        L.orc_set_threads.argtypes = [I]
+        L.orc_set_threads.restype = ctypes.c_int
         L.orc_bf16_from_f32.argtypes = [Lg, P, P]
         L.orc_bf16_value.argtypes = [ctypes.c_uint16]
         L.orc_bf16_value.restype = ctypes.c_double
@@ -57,7 +60,7 @@ def lib():
         L.orc_feature_backward.argtypes = [Lg, I, I, I, P, P, P, P, P, P]
         for f in (L.orc_project, L.orc_render, L.orc_feature, L.orc_backward,
                   L.orc_bf16_from_f32, L.orc_fp8_quantize, L.orc_e4m3_table, L.orc_num_threads,
-                  L.orc_topk_select, L.orc_feature_backward, L.orc_prune_stats):
+                  L.orc_topk_select, L.orc_feature_backward, L.orc_prune_stats, L.orc_vanilla_feature):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -86,6 +89,11 @@ def _geom(g):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    """OpenMP threads of later oracle calls (the bench's CPU baseline times 1 and all)."""
+    return lib().orc_set_threads(int(n))
 
 
 def project(g, cam):
@@ -196,8 +204,12 @@ def feature_backward(ids, w, feat64, gF):
     return d_feat, d_w
 
 
-def backward(g, cam, K, feat64, gC=None, gD=None, gO=None, gF=None):
-    """Exact adjoint of render + feature for the given upstream gradients."""
+def backward(g, cam, K, feat64, gC=None, gD=None, gO=None, gF=None, vanilla=False):
+    """Exact adjoint of render + feature for the given upstream gradients, including
+    the camera-pose gradients d_Rt (the 12 entries of [R|t]) and d_pose (rho, phi of
+    a left increment exp(xi^) [R|t], Sec. 4.1's rendering-loss pose refinement).
+    vanilla=True: gF is the upstream gradient of the vanilla feature render
+    (vanilla_feature) instead of the Top-K one."""
     n = g.means.shape[0]
     W, H = cam.W, cam.H
     P = W * H
@@ -206,7 +218,8 @@ def backward(g, cam, K, feat64, gC=None, gD=None, gO=None, gF=None):
     out = dict(d_mean2d=np.zeros((n, 2)), d_conic=np.zeros((n, 3)), d_opac=np.zeros(n),
                d_rgb=np.zeros((n, 3)), d_z=np.zeros(n), d_topkw=np.zeros((H, W, K)),
                d_means=np.zeros((n, 3)), d_log_scales=np.zeros((n, 3)), d_quats=np.zeros((n, 4)),
-               d_opacity_logits=np.zeros(n), d_feat=np.zeros((n, D)))
+               d_opacity_logits=np.zeros(n), d_feat=np.zeros((n, D)), d_Rt=np.zeros(12),
+               d_pose=np.zeros(6))
     ups = [_f64(None if a is None else np.asarray(a).reshape(-1)) for a in (gC, gD, gO, gF)]
     for a, m in zip(ups, (3, 1, 1, D)):
         assert a is None or a.size == P * m
@@ -217,10 +230,25 @@ def backward(g, cam, K, feat64, gC=None, gD=None, gO=None, gF=None):
                             _p(out["d_mean2d"]), _p(out["d_conic"]), _p(out["d_opac"]),
                             _p(out["d_rgb"]), _p(out["d_z"]), _p(out["d_topkw"]),
                             _p(out["d_means"]), _p(out["d_log_scales"]), _p(out["d_quats"]),
-                            _p(out["d_opacity_logits"]), _p(out["d_feat"]))
+                            _p(out["d_opacity_logits"]), _p(out["d_feat"]), _p(out["d_Rt"]),
+                            _p(out["d_pose"]), int(bool(vanilla)))
     if rc:
         raise RuntimeError(f"orc_backward failed: {rc}")
     return out
+
+
+def vanilla_feature(g, cam, feat64):
+    """The vanilla alpha-blended feature map (Eq. 1 with the D-channel feature in place
+    of the colour, over every blended Gaussian): [H, W, D] in FP64."""
+    n = g.means.shape[0]
+    feat64 = _f64(feat64)
+    D = feat64.shape[1]
+    F = np.zeros((cam.H, cam.W, D))
+    rc = lib().orc_vanilla_feature(n, *[_p(a) for a in _geom(g)], _p(cam_array(cam)), cam.W, cam.H, D,
+                                   _p(feat64), _p(F))
+    if rc:
+        raise RuntimeError(f"orc_vanilla_feature failed: {rc}")
+    return F
 
 
 def topk_select(w, R):
