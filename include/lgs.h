@@ -245,6 +245,40 @@ lgs_status lgs_feature_render_fwd_bwd_l1(int32_t width, int32_t height, int32_t 
                                          float *dL_dtopkw, hipStream_t stream);
 
 /*
+ * Vanilla feature render, the comparison path of Top-K rendering (Sec. 3.2, Tab. 4):
+ * the D-channel feature blended exactly as the colour of Eq. 1 over EVERY blended
+ * Gaussian, F[p] = sum_i w_i f_i with the blend's weights w_i = alpha_i T_i (no
+ * renormalisation, no Top-K).  One view.  In: the projection and binning outputs and
+ * the n_contrib of lgs_rasterize_topk_fwd on the same inputs (the blend is replayed
+ * with the forward's arithmetic up to n_contrib, so the weights are the forward's bit
+ * for bit); feat[n*d] BF16, or FP8 codes with feat_scale[n].  Out: F[P*d] BF16 (FP32
+ * accumulation, one rounding), P = width * height.  d a positive multiple of 8, feat
+ * and F 16-byte aligned.  Errors: UNSUPPORTED for FP32 storage or an FP32 map.
+ */
+lgs_status lgs_feature_render_vanilla_fwd(const lgs_camera *cam, const float *mean2d, const float *conic,
+                                          const float *opacity, const int32_t *sorted_ids,
+                                          const int32_t *tile_ranges, const int32_t *n_contrib, int32_t d,
+                                          lgs_dtype feat_dt, const void *feat, const float *feat_scale,
+                                          lgs_dtype map_dt, void *F, hipStream_t stream);
+
+/*
+ * Adjoint of the vanilla feature render for a given dL_dF[P*d] (BF16): accumulates
+ *   dL_dfeat[id_i] += w_i dL/dF[p]                     (FP32, per Gaussian row),
+ * and the feature term of the blend adjoint, with e_i = <dL/dF[p], f_i>,
+ *   dL/dalpha_i = T_i e_i - (sum_{j>i} w_j e_j) / (1 - alpha_i),
+ * carried to dL_dmean2d[n*2], dL_dconic[n*3], dL_dopacity[n] (+=, the same screen-space
+ * gradients lgs_rasterize_topk_bwd accumulates for colour and depth, so calling both
+ * gives the whole adjoint).  T_final and n_contrib from lgs_rasterize_topk_fwd.
+ */
+lgs_status lgs_feature_render_vanilla_bwd(const lgs_camera *cam, const float *mean2d, const float *conic,
+                                          const float *opacity, const int32_t *sorted_ids,
+                                          const int32_t *tile_ranges, const float *T_final,
+                                          const int32_t *n_contrib, int32_t d, lgs_dtype feat_dt,
+                                          const void *feat, const float *feat_scale, lgs_dtype map_dt,
+                                          const void *dL_dF, float *dL_dfeat, float *dL_dmean2d,
+                                          float *dL_dconic, float *dL_dopacity, hipStream_t stream);
+
+/*
  * Adjoint of the blend (Eq. 1) including the Top-K weight path, replayed back to
  * front per pixel from T_final and n_contrib.  dL_dalpha and dL_dtopkw may be NULL.
  * Accumulates per-Gaussian screen-space gradients:
@@ -274,6 +308,104 @@ lgs_status lgs_project_bwd(const lgs_camera *cam, int32_t n,
                            const float *dL_dopacity, const float *dL_ddepth_g,
                            float *dL_dmeans, float *dL_dlog_scales, float *dL_dquats,
                            float *dL_dopacity_logits, hipStream_t stream);
+
+/*
+ * Camera-pose gradient of the rendering loss, for the rendering-loss pose refinement
+ * of the mapping step (Sec. 4.1), together with (optionally) the parameter gradients
+ * of lgs_project_bwd from the same screen-space gradients.  The pose is perturbed on
+ * the left, [R|t] <- exp(xi^) [R|t] with xi = (rho, phi): to first order
+ * R <- (I + [phi]x) R and t <- (I + [phi]x) t + rho.  Accumulates
+ *   dL_dpose[6] += (dL/drho, dL/dphi)  (FP32, device; one block sum per component and
+ *                                       block, added with atomics: the summation order
+ *                                       varies from run to run),
+ * and, when dL_dmeans, dL_dlog_scales, dL_dquats and dL_dopacity_logits are all given,
+ * the same parameter gradients as lgs_project_bwd (all four NULL: pose only).
+ * Culled Gaussians contribute nothing.  Errors: INVALID_ARG for a NULL dL_dpose or
+ * input, or a partial set of parameter-gradient outputs.
+ */
+lgs_status lgs_project_bwd_pose(const lgs_camera *cam, int32_t n,
+                                const float *means, const float *log_scales, const float *quats,
+                                const float *opacity_logits, const float *rgb,
+                                const float *dL_dmean2d, const float *dL_dconic,
+                                const float *dL_dopacity, const float *dL_ddepth_g,
+                                float *dL_dmeans, float *dL_dlog_scales, float *dL_dquats,
+                                float *dL_dopacity_logits, float *dL_dpose, hipStream_t stream);
+
+/*
+ * Batched views (Sec. 3.4: one mapping step renders several keyframes of the same
+ * size).  The geometry calls below take `views` cameras (a host array, at most 16, all
+ * of one width x height) and run every view in one launch.  Layout:
+ *  - a projected RECORD is (view, Gaussian): record v*n + g holds Gaussian g seen from
+ *    view v, so mean2d[views*n*2], conic[views*n*3], depth[views*n], opacity[views*n],
+ *    tile_rect[views*n*4], tiles_touched[views*n] and the screen-space gradients
+ *    dL_dmean2d, dL_dconic, dL_dopacity, dL_ddepth_g are all record-indexed;
+ *  - tiles of view v are tiles v*T ... (v+1)*T - 1 (T = tiles of one view), so
+ *    tile_ranges has views*T*2 entries and sorted_ids holds record indices ordered by
+ *    (view, tile, depth key, Gaussian id): the binning sorts the view into the key;
+ *  - per-pixel arrays stack the views: pixel p of view v is entry v*width*height + p;
+ *  - per-Gaussian arrays (rgb, dL_drgb, the parameter gradients, Top-K ids) are
+ *    indexed by Gaussian and accumulate over the views.
+ * Each call with views = 1 equals its single-view counterpart bit for bit (the
+ * single-view calls are this case).  Errors: INVALID_ARG for views outside [1, 16],
+ * cameras of different sizes, or more than 2^31 - 1 records.
+ */
+lgs_status lgs_project_fwd_views(const lgs_camera *cams, int32_t views, int32_t n,
+                                 const float *means, const float *log_scales, const float *quats,
+                                 const float *opacity_logits, const float *rgb,
+                                 float *mean2d, float *conic, float *depth, float *opacity,
+                                 int32_t *tile_rect, int32_t *tiles_touched, hipStream_t stream);
+
+/* Binning of views*n records (workspace: lgs_bin_sort_workspace(views * n, ...); for
+ * lgs_bin_sort_count pass views * n as n).  Same count and capacity rules as
+ * lgs_bin_sort. */
+lgs_status lgs_bin_sort_views(const lgs_camera *cams, int32_t views, int32_t n, const float *depth,
+                              const int32_t *tile_rect, const int32_t *tiles_touched,
+                              void *workspace, size_t ws_bytes, int64_t max_pairs,
+                              int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
+                              hipStream_t stream);
+
+/* Blend + Top-K of every view; n is the Gaussian count (records per view). */
+lgs_status lgs_rasterize_topk_fwd_views(const lgs_camera *cams, int32_t views, int32_t k, int32_t n,
+                                        const float *mean2d, const float *conic, const float *opacity,
+                                        const float *rgb, const float *depth,
+                                        const int32_t *sorted_ids, const int32_t *tile_ranges,
+                                        float *color, float *depth_map, float *alpha_map,
+                                        float *T_final, int32_t *n_contrib,
+                                        int32_t *topk_ids, float *topk_w, hipStream_t stream);
+
+/* Blend adjoint of every view: record-indexed screen-space gradients, per-Gaussian
+ * dL_drgb summed over the views (all accumulated). */
+lgs_status lgs_rasterize_topk_bwd_views(const lgs_camera *cams, int32_t views, int32_t k, int32_t n,
+                                        const float *mean2d, const float *conic, const float *opacity,
+                                        const float *rgb, const float *depth,
+                                        const int32_t *sorted_ids, const int32_t *tile_ranges,
+                                        const float *T_final, const int32_t *n_contrib,
+                                        const int32_t *topk_ids, const float *topk_w,
+                                        const float *dL_dcolor, const float *dL_ddepth,
+                                        const float *dL_dalpha, const float *dL_dtopkw,
+                                        float *dL_dmean2d, float *dL_dconic, float *dL_dopacity,
+                                        float *dL_drgb, float *dL_ddepth_g, hipStream_t stream);
+
+/* Projection adjoint of every view: the parameter gradients summed over the views (one
+ * thread per Gaussian adds its views in order and writes once: deterministic), and,
+ * if dL_dpose is given, each view's camera-pose gradient into dL_dpose[views*6] (as
+ * lgs_project_bwd_pose).  The four parameter-gradient outputs are given together or
+ * all NULL; at least one output is required. */
+lgs_status lgs_project_bwd_views(const lgs_camera *cams, int32_t views, int32_t n,
+                                 const float *means, const float *log_scales, const float *quats,
+                                 const float *opacity_logits, const float *rgb,
+                                 const float *dL_dmean2d, const float *dL_dconic,
+                                 const float *dL_dopacity, const float *dL_ddepth_g,
+                                 float *dL_dmeans, float *dL_dlog_scales, float *dL_dquats,
+                                 float *dL_dopacity_logits, float *dL_dpose, hipStream_t stream);
+
+/* Pruning statistics over every view of a batched forward, accumulated as in
+ * lgs_prune_stats. */
+lgs_status lgs_prune_stats_views(const lgs_camera *cams, int32_t views, int32_t k, int32_t n,
+                                 const float *mean2d, const float *conic, const float *opacity,
+                                 const int32_t *sorted_ids, const int32_t *tile_ranges,
+                                 const int32_t *n_contrib, const int32_t *topk_ids, int32_t *topk_count,
+                                 float *max_w, hipStream_t stream);
 
 /*
  * Statistics of the semantic-geometric consistency pruning (Sec. 3.3, Eq. 5) for one

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblgs.so")
-SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "feature.hip", "prune.hip",
+SOURCES = ["api.hip", "project.hip", "binsort.hip", "raster.hip", "feature.hip", "prune.hip", "vanilla.hip",
            *(f"feature_k{k}.hip" for k in (1, 2, 3, 4, 5, 8, 10, 16))]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -214,11 +214,13 @@ __global__ __launch_bounds__(256) void scan_final_kernel(const long long *__rest
 // The block's pairs are dealt out evenly over its threads: pair q belongs to the
 // last Gaussian whose first pair is at or before q (binary search in LDS), so a
 // Gaussian covering hundreds of tiles does not hold up its wave.
+// Records of several views are binned together: record r belongs to view r / n_view,
+// whose tiles take keys view * T + tile, so one stable sort orders (view, tile).
 __global__ __launch_bounds__(256) void duplicate_kernel(int n, const int *__restrict__ order,
                                                         const long long *__restrict__ offs,
                                                         const int4 *__restrict__ rect,
                                                         const int *__restrict__ touched, int ntx,
-                                                        long long max_pairs,
+                                                        int n_view, int T, long long max_pairs,
                                                         uint32_t *__restrict__ tile_keys,
                                                         int *__restrict__ ids) {
     __shared__ int s_start[256];
@@ -271,8 +273,9 @@ __global__ __launch_bounds__(256) void duplicate_kernel(int n, const int *__rest
             const int k = q - s_start[lo[u]];
             const int rw = rr.z - rr.x;
             const int ty = rr.y + k / rw, tx = rr.x + k - (k / rw) * rw;
-            tile_keys[base + q] = (uint32_t)(ty * ntx + tx);
-            ids[base + q] = s_g[lo[u]];
+            const int r = s_g[lo[u]];
+            tile_keys[base + q] = (uint32_t)((r / n_view) * T + ty * ntx + tx);
+            ids[base + q] = r;
         }
     }
 }
@@ -361,17 +364,23 @@ extern "C" lgs_status lgs_bin_sort_workspace(int32_t n, int32_t width, int32_t h
 namespace lgs {
 namespace {
 
-// The binning of lgs_bin_sort over the workspace `workspace` (ws_bytes usable bytes).
-lgs_status bin_sort_on(const lgs_camera *cam, int32_t n, const float *depth, const int32_t *tile_rect,
-                       const int32_t *tiles_touched, void *workspace, size_t ws_bytes, int64_t max_pairs,
-                       int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs, hipStream_t stream) {
+// The binning of lgs_bin_sort over the workspace `workspace` (ws_bytes usable bytes),
+// for `views` views of n_view records each (views * n_view = n records, view-major).
+lgs_status bin_sort_on(const lgs_camera *cam, int32_t views, int32_t n_view, const float *depth,
+                       const int32_t *tile_rect, const int32_t *tiles_touched, void *workspace, size_t ws_bytes,
+                       int64_t max_pairs, int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
+                       hipStream_t stream) {
     lgs_status st = check_camera(cam);
     if (st) return st;
-    LGS_REQUIRE(n >= 0 && max_pairs >= 0 && max_pairs <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG,
-                "lgs_bin_sort: bad sizes");
+    LGS_REQUIRE(views >= 1 && n_view >= 0 && (long long)views * n_view <= 0x7FFFFFFF && max_pairs >= 0 &&
+                    max_pairs <= 0x7FFFFFFF,
+                LGS_ERR_INVALID_ARG, "lgs_bin_sort: bad sizes");
     LGS_REQUIRE(tile_ranges, LGS_ERR_INVALID_ARG, "tile_ranges is NULL");
+    const int n = views * n_view;
     const int ntx = tiles_x(cam->width), nty = tiles_y(cam->height);
-    const int T = ntx * nty;
+    const int T1 = ntx * nty;                 // tiles of one view
+    LGS_REQUIRE((long long)views * T1 <= (1LL << 29), LGS_ERR_INVALID_ARG, "too many tiles");
+    const int T = views * T1;                 // tiles of all views
     if (n == 0) {
         hipLaunchKernelGGL(zero_ranges_kernel, dim3((2 * T + 255) / 256), dim3(256), 0, stream,
                            2 * T, tile_ranges);
@@ -443,7 +452,8 @@ lgs_status bin_sort_on(const lgs_camera *cam, int32_t n, const float *depth, con
     uint32_t *kcur = pk0, *knext = pk1;
     int *vcur = (passes % 2 == 0) ? pv0 : pv1, *vnext = (passes % 2 == 0) ? pv1 : pv0;
     hipLaunchKernelGGL(duplicate_kernel, dim3(g1), dim3(256), 0, stream, n, dv0, offs,
-                       (const int4 *)tile_rect, tiles_touched, ntx, (long long)max_pairs, kcur, vcur);
+                       (const int4 *)tile_rect, tiles_touched, ntx, n_view > 0 ? n_view : 1, T1,
+                       (long long)max_pairs, kcur, vcur);
     st = check_launch("bin_sort duplicate");
     if (st) return st;
     for (int pass = 0; pass < passes; ++pass) {
@@ -465,7 +475,19 @@ extern "C" lgs_status lgs_bin_sort(const lgs_camera *cam, int32_t n, const float
                                    void *workspace, size_t ws_bytes, int64_t max_pairs,
                                    int32_t *sorted_ids, int32_t *tile_ranges, int64_t *n_pairs,
                                    hipStream_t stream) {
-    return bin_sort_on(cam, n, depth, tile_rect, tiles_touched, workspace, ws_bytes, max_pairs, sorted_ids,
+    return bin_sort_on(cam, 1, n, depth, tile_rect, tiles_touched, workspace, ws_bytes, max_pairs, sorted_ids,
+                       tile_ranges, n_pairs, stream);
+}
+
+extern "C" lgs_status lgs_bin_sort_views(const lgs_camera *cams, int32_t views, int32_t n, const float *depth,
+                                         const int32_t *tile_rect, const int32_t *tiles_touched, void *workspace,
+                                         size_t ws_bytes, int64_t max_pairs, int32_t *sorted_ids,
+                                         int32_t *tile_ranges, int64_t *n_pairs, hipStream_t stream) {
+    LGS_REQUIRE(cams && views >= 1, LGS_ERR_INVALID_ARG, "lgs_bin_sort_views: no cameras");
+    for (int v = 1; v < views; ++v)
+        LGS_REQUIRE(cams[v].width == cams[0].width && cams[v].height == cams[0].height, LGS_ERR_INVALID_ARG,
+                    "batched views share the image size");
+    return bin_sort_on(cams, views, n, depth, tile_rect, tiles_touched, workspace, ws_bytes, max_pairs, sorted_ids,
                        tile_ranges, n_pairs, stream);
 }
 
@@ -551,6 +573,6 @@ extern "C" lgs_status lgs_bin_sort_noalloc(const lgs_camera *cam, int32_t n, con
     void *ws = nullptr;
     st = scratch_of_current_device(&ws);
     if (st) return st;
-    return bin_sort_on(cam, n, depth, tile_rect, tiles_touched, ws, kScratchBytes, max_pairs, sorted_ids,
+    return bin_sort_on(cam, 1, n, depth, tile_rect, tiles_touched, ws, kScratchBytes, max_pairs, sorted_ids,
                        tile_ranges, n_pairs, stream);
 }

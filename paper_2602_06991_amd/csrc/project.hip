@@ -1,6 +1,8 @@
 // Projection of 3D Gaussians to screen-space splats (Sec. 3.1, the EWA splat of the
 // 3DGS rasterizer the paper follows) and its adjoint.  One thread per Gaussian;
 // FP32 throughout, with the depth key as an explicit fused chain.
+#include <algorithm>
+
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
@@ -13,6 +15,12 @@ struct CamDev {
     float fx, fy, cx, cy;
     int W, H;
     float limx, limy;   // guard band: 1.3x the half field of view (tan)
+};
+
+// The cameras of one batched call (views share the image size), passed by value.
+constexpr int kMaxViews = 16;
+struct CamSet {
+    CamDev c[kMaxViews];
 };
 
 CamDev make_cam(const lgs_camera *c) {
@@ -36,6 +44,7 @@ struct Splat {
     float Rq[9];         // rotation of the unit quaternion
     float Sg[6];         // 3D covariance xx xy xz yy yz zz
     float T[6];          // J R, 2x3 row-major
+    float j00, j02, j11, j12;   // the nonzero entries of the Jacobian J
     float A, B, C;       // Sigma2D
     float ca, cb, cc;    // conic
     float mx, my, o;
@@ -96,6 +105,7 @@ __device__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means
     float yt = fminf(fmaxf(ry, -c.limy), c.limy) * z;
     float j00 = c.fx / z, j02 = -c.fx * xt / (z * z);
     float j11 = c.fy / z, j12 = -c.fy * yt / (z * z);
+    s.j00 = j00; s.j02 = j02; s.j11 = j11; s.j12 = j12;
     for (int j = 0; j < 3; ++j) {
         s.T[j] = j00 * c.R[j] + j02 * c.R[6 + j];
         s.T[3 + j] = j11 * c.R[3 + j] + j12 * c.R[6 + j];
@@ -122,30 +132,33 @@ __device__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means
     return true;
 }
 
+
 __global__ __launch_bounds__(256) void project_fwd_kernel(
-    CamDev c, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
+    CamSet cs, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
     const float *__restrict__ quats, const float *__restrict__ opacity_logits,
     const float *__restrict__ rgb, float2 *__restrict__ mean2d, float *__restrict__ conic,
     float *__restrict__ depth, float *__restrict__ opacity, int4 *__restrict__ tile_rect,
     int *__restrict__ tiles_touched) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
+    const CamDev &c = cs.c[blockIdx.y];
+    const long r = (long)blockIdx.y * n + g;   // the record of (view, Gaussian)
     Splat s;
     if (!splat_of(c, g, means, log_scales, quats, opacity_logits, rgb, s)) {
-        mean2d[g] = make_float2(0.f, 0.f);
-        conic[3 * g] = conic[3 * g + 1] = conic[3 * g + 2] = 0.f;
-        depth[g] = 0.f;
-        opacity[g] = 0.f;
-        tile_rect[g] = make_int4(0, 0, 0, 0);
-        tiles_touched[g] = 0;
+        mean2d[r] = make_float2(0.f, 0.f);
+        conic[3 * r] = conic[3 * r + 1] = conic[3 * r + 2] = 0.f;
+        depth[r] = 0.f;
+        opacity[r] = 0.f;
+        tile_rect[r] = make_int4(0, 0, 0, 0);
+        tiles_touched[r] = 0;
         return;
     }
-    mean2d[g] = make_float2(s.mx, s.my);
-    conic[3 * g] = s.ca;
-    conic[3 * g + 1] = s.cb;
-    conic[3 * g + 2] = s.cc;
-    depth[g] = s.t[2];
-    opacity[g] = s.o;
+    mean2d[r] = make_float2(s.mx, s.my);
+    conic[3 * r] = s.ca;
+    conic[3 * r + 1] = s.cb;
+    conic[3 * r + 2] = s.cc;
+    depth[r] = s.t[2];
+    opacity[r] = s.o;
     // support {alpha >= 1/255} is the ellipse d^T Sigma2D^-1 d <= 2 ln(255 o); its box
     // has half extents sqrt(2 ln(255 o) A), sqrt(2 ln(255 o) C); pad by a pixel
     float lvl = fmaxf(2.0f * logf(255.0f * s.o), 0.0f);
@@ -157,30 +170,61 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(
     fx1 = fminf(fx1, (float)(c.W - 1));
     fy1 = fminf(fy1, (float)(c.H - 1));
     if (!(fx1 >= fx0) || !(fy1 >= fy0)) {
-        tile_rect[g] = make_int4(0, 0, 0, 0);
-        tiles_touched[g] = 0;
+        tile_rect[r] = make_int4(0, 0, 0, 0);
+        tiles_touched[r] = 0;
         return;
     }
     int tx0 = (int)fx0 / kTile, tx1 = (int)fx1 / kTile + 1;
     int ty0 = (int)fy0 / kTile, ty1 = (int)fy1 / kTile + 1;
-    tile_rect[g] = make_int4(tx0, ty0, tx1, ty1);
-    tiles_touched[g] = (tx1 - tx0) * (ty1 - ty0);
+    tile_rect[r] = make_int4(tx0, ty0, tx1, ty1);
+    tiles_touched[r] = (tx1 - tx0) * (ty1 - ty0);
 }
 
-__global__ __launch_bounds__(256) void project_bwd_kernel(
-    CamDev c, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
-    const float *__restrict__ quats, const float *__restrict__ opacity_logits,
-    const float *__restrict__ rgb, const float *__restrict__ d_mean2d,
-    const float *__restrict__ d_conic, const float *__restrict__ d_opac,
-    const float *__restrict__ d_depth, float *__restrict__ d_means, float *__restrict__ d_ls,
-    float *__restrict__ d_quats, float *__restrict__ d_opl) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    Splat s;
-    if (!splat_of(c, g, means, log_scales, quats, opacity_logits, rgb, s)) return;
-    float gmx = d_mean2d[2 * g], gmy = d_mean2d[2 * g + 1];
-    float ga = d_conic[3 * g], gb = d_conic[3 * g + 1], gc = d_conic[3 * g + 2];
-    float go = d_opac[g], gz = d_depth[g];
+// Per-Gaussian share of the camera-pose gradient for a left increment exp(xi^) [R|t],
+// xi = (rho, phi): the view-space mean moves by rho + phi x t and the rotation by
+// [phi]x R.  rho gets dL/dt; phi gets t x dL/dt (the mean) plus, from T = J R, the
+// vector (M12 - M21, M20 - M02, M01 - M10) of M = R dT^T J.
+__device__ __forceinline__ void pose_share(const CamDev &c, const Splat &s, const float (&dT)[6], float dtx,
+                                           float dty, float dtz, float (&out)[6]) {
+    out[0] = dtx;
+    out[1] = dty;
+    out[2] = dtz;
+    const float tx = s.t[0], ty = s.t[1], tz = s.t[2];
+    out[3] = ty * dtz - tz * dty;
+    out[4] = tz * dtx - tx * dtz;
+    out[5] = tx * dty - ty * dtx;
+    // N = dT^T J (3x3): J rows (j00, 0, j02) and (0, j11, j12)
+    float N[9];
+    for (int a = 0; a < 3; ++a) {
+        N[3 * a + 0] = dT[a] * s.j00;
+        N[3 * a + 1] = dT[3 + a] * s.j11;
+        N[3 * a + 2] = dT[a] * s.j02 + dT[3 + a] * s.j12;
+    }
+    float M[9];   // R N
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            M[3 * i + j] = c.R[3 * i] * N[j] + c.R[3 * i + 1] * N[3 + j] + c.R[3 * i + 2] * N[6 + j];
+    out[3] += M[5] - M[7];
+    out[4] += M[6] - M[2];
+    out[5] += M[1] - M[3];
+}
+
+// Parameter gradients of one Gaussian in one view (rec: its record in the screen-space
+// gradient arrays).
+struct ParamGrad {
+    float mu[3], ls[3], q[4], opl;
+};
+
+// The adjoint of splat_of for one record.  PARAMS: the parameter gradients into pg;
+// POSE: this record's share of the camera-pose gradient into pose.
+template <bool PARAMS, bool POSE>
+__device__ __forceinline__ void project_bwd_one(const CamDev &c, long rec, const Splat &s,
+                                                const float *__restrict__ d_mean2d, const float *__restrict__ d_conic,
+                                                const float *__restrict__ d_opac, const float *__restrict__ d_depth,
+                                                ParamGrad &pg, float (&pose)[6]) {
+    float gmx = d_mean2d[2 * rec], gmy = d_mean2d[2 * rec + 1];
+    float ga = d_conic[3 * rec], gb = d_conic[3 * rec + 1], gc = d_conic[3 * rec + 2];
+    float go = d_opac[rec], gz = d_depth[rec];
 
     // conic -> Sigma2D: dSigma2D = -Q G Q with G = [[ga, gb/2], [gb/2, gc]]
     float a = s.ca, b = s.cb, cq = s.cc;
@@ -235,9 +279,14 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
     dty += gmy * c.fy * iz;
     dtz -= (gmx * c.fx * tx + gmy * c.fy * ty) * iz2;
     dtz += gz;
+    if constexpr (POSE) {
+        float sh[6];
+        pose_share(c, s, dT, dtx, dty, dtz, sh);
+        for (int q = 0; q < 6; ++q) pose[q] += sh[q];
+    }
+    if constexpr (!PARAMS) return;
     // t = R mu + t_cam
-    for (int j = 0; j < 3; ++j)
-        d_means[3 * g + j] += c.R[j] * dtx + c.R[3 + j] * dty + c.R[6 + j] * dtz;
+    for (int j = 0; j < 3; ++j) pg.mu[j] = c.R[j] * dtx + c.R[3 + j] * dty + c.R[6 + j] * dtz;
     // Sigma = M M^T, M = Rq diag(s): dM = (dS + dS^T) M
     float M[9];
     for (int i = 0; i < 3; ++i)
@@ -251,7 +300,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
             ds += dM * s.Rq[3 * i + j];
             dR[3 * i + j] = dM * s.s[j];
         }
-        d_ls[3 * g + j] += ds * s.s[j];
+        pg.ls[j] = ds * s.s[j];
     }
     // rotation matrix of the unit quaternion (w, x, y, z)
     float w = s.qn[0], x = s.qn[1], y = s.qn[2], zq = s.qn[3];
@@ -264,11 +313,98 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
                       2.f * zq * (dR[0] + dR[4]));
     float dot = dw * w + dx * x + dy * y + dz * zq;
     float il = 1.0f / s.qlen;
-    d_quats[4 * g] += (dw - w * dot) * il;
-    d_quats[4 * g + 1] += (dx - x * dot) * il;
-    d_quats[4 * g + 2] += (dy - y * dot) * il;
-    d_quats[4 * g + 3] += (dz - zq * dot) * il;
-    d_opl[g] += go * s.o * (1.0f - s.o);
+    pg.q[0] = (dw - w * dot) * il;
+    pg.q[1] = (dx - x * dot) * il;
+    pg.q[2] = (dy - y * dot) * il;
+    pg.q[3] = (dz - zq * dot) * il;
+    pg.opl = go * s.o * (1.0f - s.o);
+}
+
+
+// Parameter gradients summed over the views, one thread per Gaussian: the views'
+// shares are added in view order and the sum goes to memory once (deterministic).
+__global__ __launch_bounds__(256) void project_bwd_kernel(
+    CamSet cs, int views, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
+    const float *__restrict__ quats, const float *__restrict__ opacity_logits,
+    const float *__restrict__ rgb, const float *__restrict__ d_mean2d,
+    const float *__restrict__ d_conic, const float *__restrict__ d_opac,
+    const float *__restrict__ d_depth, float *__restrict__ d_means, float *__restrict__ d_ls,
+    float *__restrict__ d_quats, float *__restrict__ d_opl) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    ParamGrad acc = {};
+    bool any = false;
+    float unused[6];
+    for (int v = 0; v < views; ++v) {
+        Splat s;
+        if (!splat_of(cs.c[v], g, means, log_scales, quats, opacity_logits, rgb, s)) continue;
+        ParamGrad pg;
+        project_bwd_one<true, false>(cs.c[v], (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, pg, unused);
+        if (!any) {
+            acc = pg;
+            any = true;
+            continue;
+        }
+        for (int j = 0; j < 3; ++j) acc.mu[j] += pg.mu[j];
+        for (int j = 0; j < 3; ++j) acc.ls[j] += pg.ls[j];
+        for (int j = 0; j < 4; ++j) acc.q[j] += pg.q[j];
+        acc.opl += pg.opl;
+    }
+    if (!any) return;
+    for (int j = 0; j < 3; ++j) d_means[3 * g + j] += acc.mu[j];
+    for (int j = 0; j < 3; ++j) d_ls[3 * g + j] += acc.ls[j];
+    for (int j = 0; j < 4; ++j) d_quats[4 * g + j] += acc.q[j];
+    d_opl[g] += acc.opl;
+}
+
+constexpr int kPoseBlocks = 512;   // blocks per view of the pose reduction: at most this many atomics per component
+
+// Camera-pose gradient of every view (blockIdx.y): a block sum per component, one
+// atomic per block; the grid strides over the Gaussians.
+__global__ __launch_bounds__(256) void project_pose_kernel(
+    CamSet cs, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
+    const float *__restrict__ quats, const float *__restrict__ opacity_logits,
+    const float *__restrict__ rgb, const float *__restrict__ d_mean2d,
+    const float *__restrict__ d_conic, const float *__restrict__ d_opac,
+    const float *__restrict__ d_depth, float *__restrict__ d_pose) {
+    const int v = blockIdx.y;
+    const CamDev &c = cs.c[v];
+    float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+        Splat s;
+        if (!splat_of(c, g, means, log_scales, quats, opacity_logits, rgb, s)) continue;
+        ParamGrad unused;
+        float sh[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        project_bwd_one<false, true>(c, (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, unused, sh);
+        for (int q = 0; q < 6; ++q) pose[q] += sh[q];
+    }
+    __shared__ float part[4][6];
+    float sum[6];
+    wave_sum_many<6>(pose, sum);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 6; ++q) part[wave][q] = sum[q];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const float val = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+        if (val != 0.f) unsafeAtomicAdd(&d_pose[6 * v + threadIdx.x], val);
+    }
+}
+
+// Host-side set of cameras; all views must share the image size.
+lgs_status make_camset(const lgs_camera *cams, int views, CamSet &cs) {
+    LGS_REQUIRE(cams, LGS_ERR_INVALID_ARG, "camera array is NULL");
+    LGS_REQUIRE(views >= 1 && views <= kMaxViews, LGS_ERR_INVALID_ARG, "views = %d outside [1, %d]", views,
+                kMaxViews);
+    for (int v = 0; v < views; ++v) {
+        lgs_status st = check_camera(&cams[v]);
+        if (st) return st;
+        LGS_REQUIRE(cams[v].width == cams[0].width && cams[v].height == cams[0].height, LGS_ERR_INVALID_ARG,
+                    "view %d has size %dx%d, view 0 %dx%d: batched views share the image size", v, cams[v].width,
+                    cams[v].height, cams[0].width, cams[0].height);
+        cs.c[v] = make_cam(&cams[v]);
+    }
+    return LGS_OK;
 }
 
 }  // namespace
@@ -276,13 +412,13 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
 
 using namespace lgs;
 
-extern "C" lgs_status lgs_project_fwd(const lgs_camera *cam, int32_t n, const float *means,
-                                      const float *log_scales, const float *quats,
-                                      const float *opacity_logits, const float *rgb,
-                                      float *mean2d, float *conic, float *depth, float *opacity,
-                                      int32_t *tile_rect, int32_t *tiles_touched,
-                                      hipStream_t stream) {
-    lgs_status st = check_camera(cam);
+extern "C" lgs_status lgs_project_fwd_views(const lgs_camera *cams, int32_t views, int32_t n, const float *means,
+                                            const float *log_scales, const float *quats,
+                                            const float *opacity_logits, const float *rgb, float *mean2d,
+                                            float *conic, float *depth, float *opacity, int32_t *tile_rect,
+                                            int32_t *tiles_touched, hipStream_t stream) {
+    CamSet cs;
+    lgs_status st = make_camset(cams, views, cs);
     if (st) return st;
     LGS_REQUIRE(n >= 0, LGS_ERR_INVALID_ARG, "n must be >= 0");
     if (n == 0) return LGS_OK;
@@ -291,11 +427,52 @@ extern "C" lgs_status lgs_project_fwd(const lgs_camera *cam, int32_t n, const fl
                 LGS_ERR_INVALID_ARG, "lgs_project_fwd: NULL pointer");
     LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && aligned16(tile_rect), LGS_ERR_INVALID_ARG,
                 "lgs_project_fwd: mean2d must be 8-byte and tile_rect 16-byte aligned");
-    CamDev c = make_cam(cam);
-    hipLaunchKernelGGL(project_fwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, c, n, means,
-                       log_scales, quats, opacity_logits, rgb, (float2 *)mean2d, conic, depth,
-                       opacity, (int4 *)tile_rect, tiles_touched);
+    hipLaunchKernelGGL(project_fwd_kernel, dim3((n + 255) / 256, views), dim3(256), 0, stream, cs, n, means,
+                       log_scales, quats, opacity_logits, rgb, (float2 *)mean2d, conic, depth, opacity,
+                       (int4 *)tile_rect, tiles_touched);
     return check_launch("project_fwd");
+}
+
+extern "C" lgs_status lgs_project_fwd(const lgs_camera *cam, int32_t n, const float *means,
+                                      const float *log_scales, const float *quats,
+                                      const float *opacity_logits, const float *rgb,
+                                      float *mean2d, float *conic, float *depth, float *opacity,
+                                      int32_t *tile_rect, int32_t *tiles_touched,
+                                      hipStream_t stream) {
+    return lgs_project_fwd_views(cam, 1, n, means, log_scales, quats, opacity_logits, rgb, mean2d, conic, depth,
+                                 opacity, tile_rect, tiles_touched, stream);
+}
+
+extern "C" lgs_status lgs_project_bwd_views(const lgs_camera *cams, int32_t views, int32_t n, const float *means,
+                                            const float *log_scales, const float *quats,
+                                            const float *opacity_logits, const float *rgb,
+                                            const float *dL_dmean2d, const float *dL_dconic,
+                                            const float *dL_dopacity, const float *dL_ddepth_g, float *dL_dmeans,
+                                            float *dL_dlog_scales, float *dL_dquats, float *dL_dopacity_logits,
+                                            float *dL_dpose, hipStream_t stream) {
+    CamSet cs;
+    lgs_status st = make_camset(cams, views, cs);
+    if (st) return st;
+    LGS_REQUIRE(n >= 0, LGS_ERR_INVALID_ARG, "n must be >= 0");
+    const int nparams = (dL_dmeans != nullptr) + (dL_dlog_scales != nullptr) + (dL_dquats != nullptr) +
+                        (dL_dopacity_logits != nullptr);
+    LGS_REQUIRE(nparams == 0 || nparams == 4, LGS_ERR_INVALID_ARG,
+                "lgs_project_bwd: the four parameter gradients are given together or not at all");
+    LGS_REQUIRE(nparams == 4 || dL_dpose, LGS_ERR_INVALID_ARG, "lgs_project_bwd: no output");
+    if (n == 0) return LGS_OK;
+    LGS_REQUIRE(means && log_scales && quats && opacity_logits && rgb && dL_dmean2d && dL_dconic && dL_dopacity &&
+                    dL_ddepth_g,
+                LGS_ERR_INVALID_ARG, "lgs_project_bwd: NULL input");
+    if (nparams)
+        hipLaunchKernelGGL(project_bwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, cs, views, n, means,
+                           log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic, dL_dopacity, dL_ddepth_g,
+                           dL_dmeans, dL_dlog_scales, dL_dquats, dL_dopacity_logits);
+    if (dL_dpose) {
+        const unsigned gx = (unsigned)std::min<long>((n + 255) / 256, kPoseBlocks);
+        hipLaunchKernelGGL(project_pose_kernel, dim3(gx, views), dim3(256), 0, stream, cs, n, means, log_scales,
+                           quats, opacity_logits, rgb, dL_dmean2d, dL_dconic, dL_dopacity, dL_ddepth_g, dL_dpose);
+    }
+    return check_launch("project_bwd");
 }
 
 extern "C" lgs_status lgs_project_bwd(const lgs_camera *cam, int32_t n, const float *means,
@@ -305,17 +482,22 @@ extern "C" lgs_status lgs_project_bwd(const lgs_camera *cam, int32_t n, const fl
                                       const float *dL_dopacity, const float *dL_ddepth_g,
                                       float *dL_dmeans, float *dL_dlog_scales, float *dL_dquats,
                                       float *dL_dopacity_logits, hipStream_t stream) {
-    lgs_status st = check_camera(cam);
-    if (st) return st;
-    LGS_REQUIRE(n >= 0, LGS_ERR_INVALID_ARG, "n must be >= 0");
-    if (n == 0) return LGS_OK;
-    LGS_REQUIRE(means && log_scales && quats && opacity_logits && rgb && dL_dmean2d && dL_dconic &&
-                    dL_dopacity && dL_ddepth_g && dL_dmeans && dL_dlog_scales && dL_dquats &&
-                    dL_dopacity_logits,
-                LGS_ERR_INVALID_ARG, "lgs_project_bwd: NULL pointer");
-    CamDev c = make_cam(cam);
-    hipLaunchKernelGGL(project_bwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, c, n, means,
-                       log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic, dL_dopacity,
-                       dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats, dL_dopacity_logits);
-    return check_launch("project_bwd");
+    LGS_REQUIRE(n <= 0 || (dL_dmeans && dL_dlog_scales && dL_dquats && dL_dopacity_logits), LGS_ERR_INVALID_ARG,
+                "lgs_project_bwd: NULL pointer");
+    return lgs_project_bwd_views(cam, 1, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,
+                                 dL_dopacity, dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats,
+                                 dL_dopacity_logits, nullptr, stream);
+}
+
+extern "C" lgs_status lgs_project_bwd_pose(const lgs_camera *cam, int32_t n, const float *means,
+                                           const float *log_scales, const float *quats,
+                                           const float *opacity_logits, const float *rgb,
+                                           const float *dL_dmean2d, const float *dL_dconic,
+                                           const float *dL_dopacity, const float *dL_ddepth_g,
+                                           float *dL_dmeans, float *dL_dlog_scales, float *dL_dquats,
+                                           float *dL_dopacity_logits, float *dL_dpose, hipStream_t stream) {
+    LGS_REQUIRE(dL_dpose, LGS_ERR_INVALID_ARG, "lgs_project_bwd_pose: dL_dpose is NULL");
+    return lgs_project_bwd_views(cam, 1, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,
+                                 dL_dopacity, dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats,
+                                 dL_dopacity_logits, dL_dpose, stream);
 }

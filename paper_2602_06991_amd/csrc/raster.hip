@@ -10,8 +10,12 @@
 namespace lgs {
 namespace {
 
+// Views are batched: the tiles of view v are tiles v*ntx*nty ... of the grid, its
+// pixels v*W*H ... of the per-pixel arrays, and its projected records (mean2d, conic,
+// opacity, depth) are records v*n ... ; the sorted lists hold record indices, the
+// Top-K lists and colours Gaussian ids (record - v*n).
 struct RasterArgs {
-    int W, H, ntx, nty;
+    int W, H, ntx, nty, views, n;
     const float2 *mean2d;
     const float *conic;
     const float *opacity;
@@ -20,6 +24,25 @@ struct RasterArgs {
     const int *sorted_ids;
     const int2 *ranges;
 };
+
+struct TilePos {
+    int view, tile, x0, y0;   // view, tile index over all views, first pixel column / row
+    long pix0;                // first pixel of the view in the per-pixel arrays
+    int rec0;                 // first record of the view
+};
+
+__device__ __forceinline__ TilePos tile_pos(const RasterArgs &a, int tile) {
+    const int per = a.ntx * a.nty;
+    TilePos t;
+    t.view = tile / per;
+    const int lt = tile - t.view * per;
+    t.tile = tile;
+    t.x0 = (lt % a.ntx) * kTile;
+    t.y0 = (lt / a.ntx) * kTile;
+    t.pix0 = (long)t.view * a.W * a.H;
+    t.rec0 = t.view * a.n;
+    return t;
+}
 
 template <int K>
 __device__ __forceinline__ void topk_insert(float (&tw)[K], int (&ti)[K], float w, int id) {
@@ -53,12 +76,13 @@ __global__ __launch_bounds__(kFwdThreads) void raster_fwd_kernel(RasterArgs a, f
     __shared__ float2 s_xy[256];
     __shared__ float4 s_co[256];   // conic a, b, c, opacity
     __shared__ float4 s_cz[256];   // r, g, b, depth
-    const int ntiles = a.ntx * a.nty;
+    const int ntiles = a.ntx * a.nty * a.views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
+    const TilePos tp = tile_pos(a, tile);
     const int t = threadIdx.x;
-    const int px = (tile % a.ntx) * kTile + (t & 15);
-    const int py0 = (tile / a.ntx) * kTile + (t >> 4);
+    const int px = tp.x0 + (t & 15);
+    const int py0 = tp.y0 + (t >> 4);
     const float fx = (float)px + 0.5f;
     const int2 rg = a.ranges[tile];
     float fy[2], T[2], C0[2], C1[2], C2[2], Dz[2];
@@ -79,12 +103,13 @@ __global__ __launch_bounds__(kFwdThreads) void raster_fwd_kernel(RasterArgs a, f
     for (int base = rg.x; base < rg.y; base += 256) {
         if (__syncthreads_count(done[0] && done[1]) == kFwdThreads) break;
         for (int idx = base + t; idx < min(base + 256, rg.y); idx += kFwdThreads) {
-            const int g = a.sorted_ids[idx];
+            const int r = a.sorted_ids[idx];
+            const int g = r - tp.rec0;
             const int q = idx - base;
             s_id[q] = g;
-            s_xy[q] = a.mean2d[g];
-            s_co[q] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
-            s_cz[q] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[g]);
+            s_xy[q] = a.mean2d[r];
+            s_co[q] = make_float4(a.conic[3 * r], a.conic[3 * r + 1], a.conic[3 * r + 2], a.opacity[r]);
+            s_cz[q] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[r]);
         }
         __syncthreads();
         const int cnt = min(256, rg.y - base);
@@ -118,7 +143,7 @@ __global__ __launch_bounds__(kFwdThreads) void raster_fwd_kernel(RasterArgs a, f
     for (int h = 0; h < 2; ++h) {
         const int py = py0 + 8 * h;
         if (!(px < a.W && py < a.H)) continue;
-        const long p = (long)py * a.W + px;
+        const long p = tp.pix0 + (long)py * a.W + px;
         color[3 * p] = C0[h];
         color[3 * p + 1] = C1[h];
         color[3 * p + 2] = C2[h];
@@ -172,13 +197,14 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
     __shared__ float4 s_cz[kRB];
     __shared__ __align__(16) float s_part[kBwdRows][kRB][kNGP];   // [lane row][Gaussian][slot]
     __shared__ int s_max;
-    const int ntiles = a.ntx * a.nty;
+    const int ntiles = a.ntx * a.nty * a.views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
+    const TilePos tp = tile_pos(a, tile);
     const int t = threadIdx.x;
     const int2 rg = a.ranges[tile];
-    const int px = (tile % a.ntx) * kTile + (t & 15);
-    const int py0 = (tile / a.ntx) * kTile + (t >> 4);
+    const int px = tp.x0 + (t & 15);
+    const int py0 = tp.y0 + (t >> 4);
 
     // per-pixel state of the thread's kPPT pixels
     float fy[kPPT], T[kPPT], gC0[kPPT], gC1[kPPT], gC2[kPPT], gD[kPPT], gO[kPPT], A[kPPT];
@@ -196,7 +222,7 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
 #pragma unroll
         for (int k = 0; k < K; ++k) { ti[h][k] = -1; gam[h][k] = 0.f; }
         if (px < a.W && py < a.H) {
-            const long p = (long)py * a.W + px;
+            const long p = tp.pix0 + (long)py * a.W + px;
             T[h] = T_final[p];
             last[h] = n_contrib[p];
             gC0[h] = dL_dcolor[3 * p];
@@ -223,11 +249,12 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
         const int cnt = hi - lo;
         __syncthreads();
         if (t < cnt) {
-            int g = a.sorted_ids[rg.x + lo + t];
+            const int r = a.sorted_ids[rg.x + lo + t];
+            const int g = r - tp.rec0;
             s_id[t] = g;
-            s_xy[t] = a.mean2d[g];
-            s_co[t] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
-            s_cz[t] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[g]);
+            s_xy[t] = a.mean2d[r];
+            s_co[t] = make_float4(a.conic[3 * r], a.conic[3 * r + 1], a.conic[3 * r + 2], a.opacity[r]);
+            s_cz[t] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], a.depth[r]);
         }
         __syncthreads();
         for (int j = cnt - 1; j >= 0; --j) {
@@ -286,11 +313,12 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
 #pragma unroll
             for (int r = 0; r < kBwdRows; ++r) sum += s_part[r][j][q];
             if (sum == 0.f) continue;
-            const int g = s_id[j];
-            float *dst = q < 2 ? &g_mean2d[2 * g + q]
-                       : q < 5 ? &g_conic[3 * g + (q - 2)]
+            const int g = s_id[j];          // Gaussian (colour) and record (screen-space) index
+            const long r = (long)tp.rec0 + g;
+            float *dst = q < 2 ? &g_mean2d[2 * r + q]
+                       : q < 5 ? &g_conic[3 * r + (q - 2)]
                        : q < 8 ? &g_rgb[3 * g + (q - 5)]
-                       : q == 8 ? &g_depth[g] : &g_opac[g];
+                       : q == 8 ? &g_depth[r] : &g_opac[r];
             unsafeAtomicAdd(dst, sum);
         }
     }
@@ -313,12 +341,13 @@ __global__ __launch_bounds__(kFwdThreads) void prune_stats_kernel(RasterArgs a, 
     __shared__ float2 s_xy[256];
     __shared__ float4 s_co[256];
     __shared__ int s_max;
-    const int ntiles = a.ntx * a.nty;
+    const int ntiles = a.ntx * a.nty * a.views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
+    const TilePos tp = tile_pos(a, tile);
     const int t = threadIdx.x, lane = t & 63;
-    const int px = (tile % a.ntx) * kTile + (t & 15);
-    const int py0 = (tile / a.ntx) * kTile + (t >> 4);
+    const int px = tp.x0 + (t & 15);
+    const int py0 = tp.y0 + (t >> 4);
     const float fx = (float)px + 0.5f;
     const int2 rg = a.ranges[tile];
     float fy[2], T[2];
@@ -328,7 +357,7 @@ __global__ __launch_bounds__(kFwdThreads) void prune_stats_kernel(RasterArgs a, 
     for (int h = 0; h < 2; ++h) {
         const int py = py0 + 8 * h;
         const bool valid = px < a.W && py < a.H;
-        const long p = (long)py * a.W + px;
+        const long p = tp.pix0 + (long)py * a.W + px;
         fy[h] = (float)py + 0.5f;
         T[h] = 1.0f;
         last[h] = valid ? n_contrib[p] : 0;
@@ -354,10 +383,10 @@ __global__ __launch_bounds__(kFwdThreads) void prune_stats_kernel(RasterArgs a, 
         const int cnt = min(256, maxl - base);
         __syncthreads();
         for (int q = t; q < cnt; q += kFwdThreads) {
-            const int g = a.sorted_ids[rg.x + base + q];
-            s_id[q] = g;
-            s_xy[q] = a.mean2d[g];
-            s_co[q] = make_float4(a.conic[3 * g], a.conic[3 * g + 1], a.conic[3 * g + 2], a.opacity[g]);
+            const int r = a.sorted_ids[rg.x + base + q];
+            s_id[q] = r - tp.rec0;
+            s_xy[q] = a.mean2d[r];
+            s_co[q] = make_float4(a.conic[3 * r], a.conic[3 * r + 1], a.conic[3 * r + 2], a.opacity[r]);
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
@@ -393,7 +422,7 @@ __global__ __launch_bounds__(kFwdThreads) void prune_stats_kernel(RasterArgs a, 
 template <int K>
 void launch_fwd(RasterArgs a, float *color, float *depth_map, float *alpha_map, float *T_final,
                 int *n_contrib, int *topk_ids, float *topk_w, hipStream_t st) {
-    hipLaunchKernelGGL(raster_fwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(kFwdThreads), 0,
+    hipLaunchKernelGGL(raster_fwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty * a.views)), dim3(kFwdThreads), 0,
                        st, a, color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w);
 }
 
@@ -402,14 +431,14 @@ void launch_bwd(RasterArgs a, const float *T_final, const int *n_contrib, const 
                 const float *dL_dtopkw, const float *dL_dcolor, const float *dL_ddepth,
                 const float *dL_dalpha, float *gm, float *gc, float *go, float *grgb, float *gz,
                 hipStream_t st) {
-    hipLaunchKernelGGL(raster_bwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(kBwdThreads), 0,
+    hipLaunchKernelGGL(raster_bwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty * a.views)), dim3(kBwdThreads), 0,
                        st, a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha,
                        gm, gc, go, grgb, gz);
 }
 
 template <int K>
 void launch_prune(RasterArgs a, const int *n_contrib, const int *topk_ids, int *count, float *max_w, hipStream_t st) {
-    hipLaunchKernelGGL(prune_stats_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty)), dim3(kFwdThreads), 0, st,
+    hipLaunchKernelGGL(prune_stats_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty * a.views)), dim3(kFwdThreads), 0, st,
                        a, n_contrib, topk_ids, count, max_w);
 }
 
@@ -425,10 +454,58 @@ void launch_prune(RasterArgs a, const int *n_contrib, const int *topk_ids, int *
     case 16: CALL(16); break;            \
     }
 
+// Checks the batched cameras (one image size) and fills the geometry part of RasterArgs.
+lgs_status raster_args(const lgs_camera *cams, int views, int n, RasterArgs &a) {
+    LGS_REQUIRE(cams, LGS_ERR_INVALID_ARG, "camera array is NULL");
+    LGS_REQUIRE(views >= 1 && n >= 0, LGS_ERR_INVALID_ARG, "views = %d, n = %d", views, n);
+    for (int v = 0; v < views; ++v) {
+        lgs_status st = check_camera(&cams[v]);
+        if (st) return st;
+        LGS_REQUIRE(cams[v].width == cams[0].width && cams[v].height == cams[0].height, LGS_ERR_INVALID_ARG,
+                    "batched views share the image size");
+    }
+    LGS_REQUIRE((long long)views * n <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG, "too many records");
+    a.W = cams[0].width;
+    a.H = cams[0].height;
+    a.ntx = tiles_x(a.W);
+    a.nty = tiles_y(a.H);
+    a.views = views;
+    a.n = n;
+    return LGS_OK;
+}
+
 }  // namespace
 }  // namespace lgs
 
 using namespace lgs;
+
+extern "C" lgs_status lgs_rasterize_topk_fwd_views(const lgs_camera *cams, int32_t views, int32_t k, int32_t n,
+                                                   const float *mean2d, const float *conic, const float *opacity,
+                                                   const float *rgb, const float *depth, const int32_t *sorted_ids,
+                                                   const int32_t *tile_ranges, float *color, float *depth_map,
+                                                   float *alpha_map, float *T_final, int32_t *n_contrib,
+                                                   int32_t *topk_ids, float *topk_w, hipStream_t stream) {
+    RasterArgs a;
+    lgs_status st = raster_args(cams, views, n, a);
+    if (st) return st;
+    LGS_REQUIRE(k_supported(k), LGS_ERR_UNSUPPORTED, "K = %d is not compiled", k);
+    LGS_REQUIRE(mean2d && conic && opacity && rgb && depth && sorted_ids && tile_ranges && color &&
+                    depth_map && alpha_map && T_final && n_contrib && topk_ids && topk_w,
+                LGS_ERR_INVALID_ARG, "lgs_rasterize_topk_fwd: NULL pointer");
+    LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && ((uintptr_t)tile_ranges & 7u) == 0,
+                LGS_ERR_INVALID_ARG, "mean2d and tile_ranges must be 8-byte aligned");
+    a.mean2d = (const float2 *)mean2d;
+    a.conic = conic;
+    a.opacity = opacity;
+    a.rgb = rgb;
+    a.depth = depth;
+    a.sorted_ids = sorted_ids;
+    a.ranges = (const int2 *)tile_ranges;
+#define CALL_FWD(KK) launch_fwd<KK>(a, color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w, stream)
+    LGS_K_SWITCH(k, CALL_FWD)
+#undef CALL_FWD
+    return check_launch("rasterize_topk_fwd");
+}
 
 extern "C" lgs_status lgs_rasterize_topk_fwd(const lgs_camera *cam, int32_t k, const float *mean2d,
                                              const float *conic, const float *opacity,
@@ -437,21 +514,42 @@ extern "C" lgs_status lgs_rasterize_topk_fwd(const lgs_camera *cam, int32_t k, c
                                              float *color, float *depth_map, float *alpha_map,
                                              float *T_final, int32_t *n_contrib, int32_t *topk_ids,
                                              float *topk_w, hipStream_t stream) {
-    lgs_status st = check_camera(cam);
+    // one view: the record of Gaussian g is g (n only splits views)
+    return lgs_rasterize_topk_fwd_views(cam, 1, k, 0x7FFFFFFF, mean2d, conic, opacity, rgb, depth, sorted_ids,
+                                        tile_ranges, color, depth_map, alpha_map, T_final, n_contrib, topk_ids,
+                                        topk_w, stream);
+}
+
+extern "C" lgs_status lgs_rasterize_topk_bwd_views(
+    const lgs_camera *cams, int32_t views, int32_t k, int32_t n, const float *mean2d, const float *conic,
+    const float *opacity, const float *rgb, const float *depth, const int32_t *sorted_ids,
+    const int32_t *tile_ranges, const float *T_final, const int32_t *n_contrib, const int32_t *topk_ids,
+    const float *topk_w, const float *dL_dcolor, const float *dL_ddepth, const float *dL_dalpha,
+    const float *dL_dtopkw, float *dL_dmean2d, float *dL_dconic, float *dL_dopacity, float *dL_drgb,
+    float *dL_ddepth_g, hipStream_t stream) {
+    RasterArgs a;
+    lgs_status st = raster_args(cams, views, n, a);
     if (st) return st;
     LGS_REQUIRE(k_supported(k), LGS_ERR_UNSUPPORTED, "K = %d is not compiled", k);
-    LGS_REQUIRE(mean2d && conic && opacity && rgb && depth && sorted_ids && tile_ranges && color &&
-                    depth_map && alpha_map && T_final && n_contrib && topk_ids && topk_w,
-                LGS_ERR_INVALID_ARG, "lgs_rasterize_topk_fwd: NULL pointer");
+    LGS_REQUIRE(mean2d && conic && opacity && rgb && depth && sorted_ids && tile_ranges && T_final &&
+                    n_contrib && topk_ids && topk_w && dL_dcolor && dL_ddepth && dL_dmean2d &&
+                    dL_dconic && dL_dopacity && dL_drgb && dL_ddepth_g,
+                LGS_ERR_INVALID_ARG, "lgs_rasterize_topk_bwd: NULL pointer");
     LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && ((uintptr_t)tile_ranges & 7u) == 0,
                 LGS_ERR_INVALID_ARG, "mean2d and tile_ranges must be 8-byte aligned");
-    RasterArgs a{cam->width, cam->height, tiles_x(cam->width), tiles_y(cam->height),
-                 (const float2 *)mean2d, conic, opacity, rgb, depth, sorted_ids,
-                 (const int2 *)tile_ranges};
-#define CALL_FWD(KK) launch_fwd<KK>(a, color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w, stream)
-    LGS_K_SWITCH(k, CALL_FWD)
-#undef CALL_FWD
-    return check_launch("rasterize_topk_fwd");
+    a.mean2d = (const float2 *)mean2d;
+    a.conic = conic;
+    a.opacity = opacity;
+    a.rgb = rgb;
+    a.depth = depth;
+    a.sorted_ids = sorted_ids;
+    a.ranges = (const int2 *)tile_ranges;
+#define CALL_BWD(KK)                                                                             \
+    launch_bwd<KK>(a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha, \
+                   dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream)
+    LGS_K_SWITCH(k, CALL_BWD)
+#undef CALL_BWD
+    return check_launch("rasterize_topk_bwd");
 }
 
 extern "C" lgs_status lgs_rasterize_topk_bwd(
@@ -461,32 +559,19 @@ extern "C" lgs_status lgs_rasterize_topk_bwd(
     const float *dL_dcolor, const float *dL_ddepth, const float *dL_dalpha, const float *dL_dtopkw,
     float *dL_dmean2d, float *dL_dconic, float *dL_dopacity, float *dL_drgb, float *dL_ddepth_g,
     hipStream_t stream) {
-    lgs_status st = check_camera(cam);
-    if (st) return st;
-    LGS_REQUIRE(k_supported(k), LGS_ERR_UNSUPPORTED, "K = %d is not compiled", k);
-    LGS_REQUIRE(mean2d && conic && opacity && rgb && depth && sorted_ids && tile_ranges && T_final &&
-                    n_contrib && topk_ids && topk_w && dL_dcolor && dL_ddepth && dL_dmean2d &&
-                    dL_dconic && dL_dopacity && dL_drgb && dL_ddepth_g,
-                LGS_ERR_INVALID_ARG, "lgs_rasterize_topk_bwd: NULL pointer");
-    LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && ((uintptr_t)tile_ranges & 7u) == 0,
-                LGS_ERR_INVALID_ARG, "mean2d and tile_ranges must be 8-byte aligned");
-    RasterArgs a{cam->width, cam->height, tiles_x(cam->width), tiles_y(cam->height),
-                 (const float2 *)mean2d, conic, opacity, rgb, depth, sorted_ids,
-                 (const int2 *)tile_ranges};
-#define CALL_BWD(KK)                                                                             \
-    launch_bwd<KK>(a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha, \
-                   dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream)
-    LGS_K_SWITCH(k, CALL_BWD)
-#undef CALL_BWD
-    return check_launch("rasterize_topk_bwd");
+    return lgs_rasterize_topk_bwd_views(cam, 1, k, 0x7FFFFFFF, mean2d, conic, opacity, rgb, depth, sorted_ids,
+                                        tile_ranges, T_final, n_contrib, topk_ids, topk_w, dL_dcolor, dL_ddepth,
+                                        dL_dalpha, dL_dtopkw, dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb,
+                                        dL_ddepth_g, stream);
 }
 
-extern "C" lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const float *mean2d, const float *conic,
-                                      const float *opacity, const int32_t *sorted_ids,
-                                      const int32_t *tile_ranges, const int32_t *n_contrib,
-                                      const int32_t *topk_ids, int32_t *topk_count, float *max_w,
-                                      hipStream_t stream) {
-    lgs_status st = check_camera(cam);
+extern "C" lgs_status lgs_prune_stats_views(const lgs_camera *cams, int32_t views, int32_t k, int32_t n,
+                                            const float *mean2d, const float *conic, const float *opacity,
+                                            const int32_t *sorted_ids, const int32_t *tile_ranges,
+                                            const int32_t *n_contrib, const int32_t *topk_ids, int32_t *topk_count,
+                                            float *max_w, hipStream_t stream) {
+    RasterArgs a;
+    lgs_status st = raster_args(cams, views, n, a);
     if (st) return st;
     LGS_REQUIRE(k_supported(k), LGS_ERR_UNSUPPORTED, "K = %d is not compiled", k);
     LGS_REQUIRE(mean2d && conic && opacity && sorted_ids && tile_ranges && n_contrib && topk_ids && topk_count &&
@@ -494,11 +579,24 @@ extern "C" lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const fl
                 LGS_ERR_INVALID_ARG, "lgs_prune_stats: NULL pointer");
     LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && ((uintptr_t)tile_ranges & 7u) == 0 && ((uintptr_t)max_w & 3u) == 0,
                 LGS_ERR_INVALID_ARG, "mean2d and tile_ranges must be 8-byte aligned, max_w 4-byte aligned");
-    RasterArgs a{cam->width, cam->height, tiles_x(cam->width), tiles_y(cam->height),
-                 (const float2 *)mean2d, conic, opacity, nullptr, nullptr, sorted_ids,
-                 (const int2 *)tile_ranges};
+    a.mean2d = (const float2 *)mean2d;
+    a.conic = conic;
+    a.opacity = opacity;
+    a.rgb = nullptr;
+    a.depth = nullptr;
+    a.sorted_ids = sorted_ids;
+    a.ranges = (const int2 *)tile_ranges;
 #define CALL_PRUNE(KK) launch_prune<KK>(a, n_contrib, topk_ids, topk_count, max_w, stream)
     LGS_K_SWITCH(k, CALL_PRUNE)
 #undef CALL_PRUNE
     return check_launch("prune_stats");
+}
+
+extern "C" lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const float *mean2d, const float *conic,
+                                      const float *opacity, const int32_t *sorted_ids,
+                                      const int32_t *tile_ranges, const int32_t *n_contrib,
+                                      const int32_t *topk_ids, int32_t *topk_count, float *max_w,
+                                      hipStream_t stream) {
+    return lgs_prune_stats_views(cam, 1, k, 0x7FFFFFFF, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib,
+                                 topk_ids, topk_count, max_w, stream);
 }

@@ -77,6 +77,20 @@ _SIG = {
     "lgs_rasterize_topk_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_project_fwd_views": [_CAM, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_bin_sort_views": [_CAM, _I32, _I32, _P, _P, _P, _P, ctypes.c_size_t, _I64, _P, _P,
+                           ctypes.POINTER(ctypes.c_int64), _P],
+    "lgs_rasterize_topk_fwd_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                     _P, _P, _P],
+    "lgs_rasterize_topk_bwd_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                     _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_project_bwd_views": [_CAM, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_prune_stats_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_feature_render_vanilla_fwd": [_CAM, _P, _P, _P, _P, _P, _P, _I32, ctypes.c_int, _P, _P, ctypes.c_int,
+                                       _P, _P],
+    "lgs_feature_render_vanilla_bwd": [_CAM, _P, _P, _P, _P, _P, _P, _P, _I32, ctypes.c_int, _P, _P,
+                                       ctypes.c_int, _P, _P, _P, _P, _P, _P],
+    "lgs_project_bwd_pose": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_quantize_features": [_I32, _I32, _P, ctypes.c_int, _P, _P, _P],
     "lgs_l1_grad": [_I64, ctypes.c_int, _P, _P, _F, _P, _P],
     "lgs_union_count": [_I64, _I32, _I32, _P, _P, ctypes.POINTER(ctypes.c_int64), _P],
@@ -250,6 +264,86 @@ def lgs_project_bwd(cam, n, means, log_scales, quats, opacity_logits, rgb, dL_dm
                                          opacity_logits, rgb, dL_dmean2d, dL_dconic, dL_dopacity,
                                          dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats,
                                          dL_dopacity_logits, stream))
+
+
+def lgs_project_bwd_pose(cam, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,
+                         dL_dopacity, dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats, dL_dopacity_logits,
+                         dL_dpose, stream=None):
+    return _check(load().lgs_project_bwd_pose(ctypes.byref(cam), n, means, log_scales, quats, opacity_logits,
+                                              rgb, dL_dmean2d, dL_dconic, dL_dopacity, dL_ddepth_g, dL_dmeans,
+                                              dL_dlog_scales, dL_dquats, dL_dopacity_logits, dL_dpose, stream))
+
+
+def lgs_feature_render_vanilla_fwd(cam, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib, d, feat_dt,
+                                   feat, feat_scale, map_dt, F, stream=None):
+    return _check(load().lgs_feature_render_vanilla_fwd(ctypes.byref(cam), mean2d, conic, opacity, sorted_ids,
+                                                        tile_ranges, n_contrib, d, feat_dt, feat, feat_scale, map_dt,
+                                                        F, stream))
+
+
+def lgs_feature_render_vanilla_bwd(cam, mean2d, conic, opacity, sorted_ids, tile_ranges, T_final, n_contrib, d,
+                                   feat_dt, feat, feat_scale, map_dt, dL_dF, dL_dfeat, dL_dmean2d, dL_dconic,
+                                   dL_dopacity, stream=None):
+    return _check(load().lgs_feature_render_vanilla_bwd(ctypes.byref(cam), mean2d, conic, opacity, sorted_ids,
+                                                        tile_ranges, T_final, n_contrib, d, feat_dt, feat, feat_scale,
+                                                        map_dt, dL_dF, dL_dfeat, dL_dmean2d, dL_dconic, dL_dopacity,
+                                                        stream))
+
+
+def camera_array(cams):
+    """A ctypes array of lgs_camera (the host array the *_views calls take)."""
+    arr = (lgs_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c
+    return arr
+
+
+def lgs_project_fwd_views(cams, views, n, means, log_scales, quats, opacity_logits, rgb, mean2d, conic, depth,
+                          opacity, tile_rect, tiles_touched, stream=None):
+    return _check(load().lgs_project_fwd_views(cams, views, n, means, log_scales, quats, opacity_logits, rgb, mean2d,
+                                               conic, depth, opacity, tile_rect, tiles_touched, stream))
+
+
+def lgs_bin_sort_views(cams, views, n, depth, tile_rect, tiles_touched, workspace, ws_bytes, max_pairs,
+                       sorted_ids, tile_ranges, stream=None, sync=True):
+    """As lgs_bin_sort; returns (status, n_pairs), LGS_ERR_CAPACITY returned, not raised."""
+    m = ctypes.c_int64(0)
+    st = load().lgs_bin_sort_views(cams, views, n, depth, tile_rect, tiles_touched, workspace, ws_bytes, max_pairs,
+                                   sorted_ids, tile_ranges, ctypes.byref(m) if sync else None, stream)
+    if st != LGS_ERR_CAPACITY:
+        _check(st)
+    return st, (m.value if sync else None)
+
+
+def lgs_rasterize_topk_fwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,
+                                 color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w, stream=None):
+    return _check(load().lgs_rasterize_topk_fwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth,
+                                                      sorted_ids, tile_ranges, color, depth_map, alpha_map,
+                                                      T_final, n_contrib, topk_ids, topk_w, stream))
+
+
+def lgs_rasterize_topk_bwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,
+                                 T_final, n_contrib, topk_ids, topk_w, dL_dcolor, dL_ddepth, dL_dalpha, dL_dtopkw,
+                                 dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream=None):
+    return _check(load().lgs_rasterize_topk_bwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth,
+                                                      sorted_ids, tile_ranges, T_final, n_contrib, topk_ids,
+                                                      topk_w, dL_dcolor, dL_ddepth, dL_dalpha, dL_dtopkw,
+                                                      dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g,
+                                                      stream))
+
+
+def lgs_project_bwd_views(cams, views, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,
+                          dL_dopacity, dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats, dL_dopacity_logits,
+                          dL_dpose, stream=None):
+    return _check(load().lgs_project_bwd_views(cams, views, n, means, log_scales, quats, opacity_logits, rgb,
+                                               dL_dmean2d, dL_dconic, dL_dopacity, dL_ddepth_g, dL_dmeans,
+                                               dL_dlog_scales, dL_dquats, dL_dopacity_logits, dL_dpose, stream))
+
+
+def lgs_prune_stats_views(cams, views, k, n, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib, topk_ids,
+                          topk_count, max_w, stream=None):
+    return _check(load().lgs_prune_stats_views(cams, views, k, n, mean2d, conic, opacity, sorted_ids, tile_ranges,
+                                               n_contrib, topk_ids, topk_count, max_w, stream))
 
 
 def lgs_quantize_features(n, d, src, dst_dt, dst, dst_scale, stream=None):

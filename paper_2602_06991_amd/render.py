@@ -6,8 +6,10 @@ path in liblgs.so (see lgs.py for the C ABI).
 
 `params` is a dict of CUDA tensors: means[N,3], log_scales[N,3], quats[N,4],
 opacity_logits[N], rgb[N,3] and feat[N,D] (FP32 master copy).  For BF16 / FP8
-storage, call ``r.set_features(feat)`` after each update of the master copy to
-refresh the quantized table the kernels read.
+storage the kernels read a quantized copy of the master table; render() quantizes
+it again whenever the master tensor changed since the copy was made (a different
+tensor, or an in-place update, which advances the tensor's version counter), so a
+stale copy is never rendered.  ``r.set_features(feat)`` refreshes it explicitly.
 """
 from __future__ import annotations
 
@@ -58,27 +60,39 @@ class Binner:
         self.cap = cap
         self.dims = (W, H)
 
-    def __call__(self, cam, n, depth, tile_rect, touched):
-        ntiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    def __call__(self, cam, n, depth, tile_rect, touched, views=1):
+        """Bins n Gaussians of one view, or, with views > 1, the views * n records of a
+        batched projection (cam: the camera array of the views)."""
+        c0 = cam[0] if views > 1 else cam
+        ntiles = ((c0.width + 15) // 16) * ((c0.height + 15) // 16) * views
         ranges = torch.empty(ntiles * 2, dtype=torch.int32, device=self.device)
-        first = self.cap == 0 or self.n != n
+        rec = n * views
+        first = self.cap == 0 or self.n != rec
         if self.cap == 0:
-            self._ensure(n, cam.width, cam.height, max(4 * n, 1 << 16))
-        self.n = n
+            self._ensure(rec, c0.width, c0.height, max(4 * rec, 1 << 16))
+        self.n = rec
+
+        def call(ws, sync):
+            if views > 1:
+                return lgs.lgs_bin_sort_views(cam, views, n, _p(depth), _p(tile_rect), _p(touched), _p(ws),
+                                              ws.numel(), self.cap, _p(self.ids), _p(ranges), _stream(), sync=sync)
+            return lgs.lgs_bin_sort(cam, n, _p(depth), _p(tile_rect), _p(touched), _p(ws), ws.numel(), self.cap,
+                                    _p(self.ids), _p(ranges), _stream(), sync=sync)
+
         if not self.sync and not first:
-            lgs.lgs_bin_sort(cam, n, _p(depth), _p(tile_rect), _p(touched), _p(self.ws), self.ws.numel(),
-                             self.cap, _p(self.ids), _p(ranges), _stream(), sync=False)
+            call(self.ws, False)
             return self.ids, ranges.view(ntiles, 2), None
         while True:
             ws = self.ws
-            st, m = lgs.lgs_bin_sort(cam, n, _p(depth), _p(tile_rect), _p(touched), _p(ws),
-                                     ws.numel(), self.cap, _p(self.ids), _p(ranges), _stream())
+            st, m = call(ws, True)
             if st == lgs.LGS_OK:
+                out = self.ids[:m]   # the pairs this call wrote (kept alive if the buffer grows)
                 if not self.sync and m * 3 > self.cap * 2:
-                    # room for frames that bring up to half as many pairs again
-                    self._ensure(n, cam.width, cam.height, int(m * 1.5) + 4096)
-                return self.ids[:m], ranges.view(ntiles, 2), m
-            self._ensure(n, cam.width, cam.height, int(m * 1.5) + 4096)
+                    # room for frames that bring up to half as many pairs again; the new
+                    # buffers serve the next calls
+                    self._ensure(rec, c0.width, c0.height, int(m * 1.5) + 4096)
+                return out, ranges.view(ntiles, 2), m
+            self._ensure(rec, c0.width, c0.height, int(m * 1.5) + 4096)
 
     def count(self):
         """(pair count, fitted) of the last call; grows the buffers if it did not fit."""
@@ -212,6 +226,31 @@ def feature_fwd_bwd_l1(ids, w, feat_store, feat_scale, feat_dtype, map_dtype, F_
     return F, dtw
 
 
+def feature_vanilla_fwd(cam, proj, sorted_ids, ranges, fwd, feat_store, feat_scale, feat_dtype):
+    """The vanilla alpha-blended feature map (every blended Gaussian, Eq. 1 on the
+    features): BF16 [H, W, D] from BF16 or FP8 storage."""
+    H, W = cam.height, cam.width
+    d = feat_store.shape[1]
+    F = torch.empty(H, W, d, dtype=torch.bfloat16, device=feat_store.device)
+    _need_cuda(feat_store, feat_scale)
+    lgs.lgs_feature_render_vanilla_fwd(cam, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
+                                       _p(sorted_ids), _p(ranges), _p(fwd["n_contrib"]), d, lgs.DTYPES[feat_dtype],
+                                       _p(feat_store), _p(feat_scale), lgs.LGS_BF16, _p(F), _stream())
+    return F
+
+
+def feature_vanilla_bwd(cam, proj, sorted_ids, ranges, fwd, feat_store, feat_scale, feat_dtype, dF, dfeat, grads):
+    """Adjoint of the vanilla feature render: dL/df rows into dfeat and the feature term
+    of the screen-space gradients into grads (mean2d, conic, opacity), all accumulated."""
+    d = feat_store.shape[1]
+    _need_cuda(feat_store, feat_scale, dF, dfeat)
+    lgs.lgs_feature_render_vanilla_bwd(cam, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
+                                       _p(sorted_ids), _p(ranges), _p(fwd["T"]), _p(fwd["n_contrib"]), d,
+                                       lgs.DTYPES[feat_dtype], _p(feat_store), _p(feat_scale), lgs.LGS_BF16, _p(dF),
+                                       _p(dfeat), _p(grads["mean2d"]), _p(grads["conic"]), _p(grads["opacity"]),
+                                       _stream())
+
+
 def rasterize_bwd(cam, K, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads):
     lgs.lgs_rasterize_topk_bwd(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(fwd["T"]),
@@ -227,6 +266,81 @@ def project_bwd(cam, P, sgrads, pgrads):
                         _p(sgrads["conic"]), _p(sgrads["opacity"]), _p(sgrads["depth"]),
                         _p(pgrads["means"]), _p(pgrads["log_scales"]), _p(pgrads["quats"]),
                         _p(pgrads["opacity_logits"]), _stream())
+
+
+def project_bwd_pose(cam, P, sgrads, dpose, pgrads=None):
+    """Camera-pose gradient dL/d(rho, phi) accumulated into dpose (FP32 [6]), and the
+    parameter gradients into pgrads when given (one pass)."""
+    n = P["means"].shape[0]
+    pg = pgrads or {}
+    lgs.lgs_project_bwd_pose(cam, n, _p(P["means"]), _p(P["log_scales"]), _p(P["quats"]),
+                             _p(P["opacity_logits"]), _p(P["rgb"]), _p(sgrads["mean2d"]), _p(sgrads["conic"]),
+                             _p(sgrads["opacity"]), _p(sgrads["depth"]), _p(pg.get("means")),
+                             _p(pg.get("log_scales")), _p(pg.get("quats")), _p(pg.get("opacity_logits")),
+                             _p(dpose), _stream())
+
+
+# ---------------------------------------------------------------- batched views
+# Several keyframes of one size in one launch per step (Sec. 3.4).  `cams` is the
+# ctypes camera array (lgs.camera_array); projected records and screen-space
+# gradients are [views * n, ...]; per-pixel outputs stack the views as [views * H, W, ...].
+
+def project_views(cams, P):
+    n = P["means"].shape[0]
+    V = len(cams)
+    dev = P["means"].device
+    out = dict(mean2d=torch.empty(V * n, 2, device=dev), conic=torch.empty(V * n, 3, device=dev),
+               depth=torch.empty(V * n, device=dev), opacity=torch.empty(V * n, device=dev),
+               tile_rect=torch.empty(V * n, 4, dtype=torch.int32, device=dev),
+               tiles_touched=torch.empty(V * n, dtype=torch.int32, device=dev))
+    _need_cuda(*(P[k] for k in ("means", "log_scales", "quats", "opacity_logits", "rgb")))
+    lgs.lgs_project_fwd_views(cams, V, n, _p(P["means"]), _p(P["log_scales"]), _p(P["quats"]),
+                              _p(P["opacity_logits"]), _p(P["rgb"]), _p(out["mean2d"]), _p(out["conic"]),
+                              _p(out["depth"]), _p(out["opacity"]), _p(out["tile_rect"]), _p(out["tiles_touched"]),
+                              _stream())
+    return out
+
+
+def rasterize_views(cams, K, n, proj, rgb, sorted_ids, ranges):
+    V = len(cams)
+    H, W = cams[0].height, cams[0].width
+    dev = rgb.device
+    out = dict(C=torch.empty(V * H, W, 3, device=dev), D=torch.empty(V * H, W, device=dev),
+               O=torch.empty(V * H, W, device=dev), T=torch.empty(V * H, W, device=dev),
+               n_contrib=torch.empty(V * H, W, dtype=torch.int32, device=dev),
+               ids=torch.empty(V * H, W, K, dtype=torch.int32, device=dev),
+               w=torch.empty(V * H, W, K, device=dev))
+    lgs.lgs_rasterize_topk_fwd_views(cams, V, K, n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
+                                     _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(out["C"]),
+                                     _p(out["D"]), _p(out["O"]), _p(out["T"]), _p(out["n_contrib"]),
+                                     _p(out["ids"]), _p(out["w"]), _stream())
+    return out
+
+
+def rasterize_bwd_views(cams, K, n, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads):
+    lgs.lgs_rasterize_topk_bwd_views(cams, len(cams), K, n, _p(proj["mean2d"]), _p(proj["conic"]),
+                                     _p(proj["opacity"]), _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges),
+                                     _p(fwd["T"]), _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(fwd["w"]), _p(gC),
+                                     _p(gD), _p(gO), _p(dtw), _p(grads["mean2d"]), _p(grads["conic"]),
+                                     _p(grads["opacity"]), _p(grads["rgb"]), _p(grads["depth"]), _stream())
+
+
+def project_bwd_views(cams, P, sgrads, pgrads=None, dpose=None):
+    n = P["means"].shape[0]
+    pg = pgrads or {}
+    lgs.lgs_project_bwd_views(cams, len(cams), n, _p(P["means"]), _p(P["log_scales"]), _p(P["quats"]),
+                              _p(P["opacity_logits"]), _p(P["rgb"]), _p(sgrads["mean2d"]), _p(sgrads["conic"]),
+                              _p(sgrads["opacity"]), _p(sgrads["depth"]), _p(pg.get("means")),
+                              _p(pg.get("log_scales")), _p(pg.get("quats")), _p(pg.get("opacity_logits")),
+                              _p(dpose), _stream())
+
+
+def screen_grad_buffers_views(n, views, device):
+    """Record-indexed screen-space gradients of `views` views (rgb per Gaussian)."""
+    r = n * views
+    return dict(mean2d=torch.zeros(r, 2, device=device), conic=torch.zeros(r, 3, device=device),
+                opacity=torch.zeros(r, device=device), rgb=torch.zeros(n, 3, device=device),
+                depth=torch.zeros(r, device=device))
 
 
 def screen_grad_buffers(n, device):
@@ -304,14 +418,19 @@ class Renderer:
         self.binner = Binner(device)
         self.store = None
         self.scale = None
+        self._src = None
 
     def set_features(self, feat):
         if self.feat_dtype != "f32":
             self.store, self.scale = quantize(feat.detach(), self.feat_dtype)
+            self._src = (feat.data_ptr(), feat._version, tuple(feat.shape))
+
+    def _stale(self, feat):
+        return self.store is None or self._src != (feat.data_ptr(), feat._version, tuple(feat.shape))
 
     def render(self, params, cam):
         c = cam if isinstance(cam, lgs.lgs_camera) else lgs.make_camera(cam)
-        if self.feat_dtype != "f32" and self.store is None:
+        if self.feat_dtype != "f32" and self._stale(params["feat"]):
             self.set_features(params["feat"])
         return _TopKRender.apply(params["means"], params["log_scales"], params["quats"],
                                  params["opacity_logits"], params["rgb"], params["feat"], self, c)

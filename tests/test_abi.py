@@ -114,3 +114,18 @@ def test_bin_sort_workspace_and_validation():
     with pytest.raises(lgs.LgsError) as e:
         lgs.lgs_bin_sort(_cam(), 1000, FAKE, FAKE, FAKE, FAKE + 16, ws, 5000, FAKE, FAKE)
     assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+
+
+def test_pose_gradient_validation():
+    args = [FAKE] * 9                      # means .. dL_ddepth_g
+    with pytest.raises(lgs.LgsError) as e:   # no pose output
+        lgs.lgs_project_bwd_pose(_cam(), 10, *args, FAKE, FAKE, FAKE, FAKE, None)
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    with pytest.raises(lgs.LgsError) as e:   # a partial set of parameter-gradient outputs
+        lgs.lgs_project_bwd_pose(_cam(), 10, *args, FAKE, None, FAKE, FAKE, FAKE)
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    assert "together" in lgs.lgs_last_error()
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_project_bwd_pose(_cam(f=0.0), 10, *args, None, None, None, None, FAKE)
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    assert lgs.lgs_project_bwd_pose(_cam(), 0, *([None] * 13), FAKE) == lgs.LGS_OK

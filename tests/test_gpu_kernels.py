@@ -166,6 +166,31 @@ def test_bin_sort_without_host_round_trip(torch):
     np.testing.assert_array_equal(r.cpu().numpy(), r0.cpu().numpy())
 
 
+def test_asynchronous_binner_growth_returns_the_written_pairs(torch):
+    """Regression: a first call whose pair count passes two thirds of the buffer grows
+    the buffers for the next calls; the pairs it returns must be the ones it wrote,
+    not a slice of the new buffer."""
+    from paper_2602_06991_amd import lgs, render
+    n, W, H = 60000, 1200, 680
+    ntx, nty, tx0, ty0, tx1, ty1, touched, depth, rect = _synthetic_bins(n, W, H, 12, 0.005)
+    cam = lgs.lgs_camera()
+    cam.width, cam.height, cam.fx, cam.fy = W, H, 1.0, 1.0
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (cam, n, tt(depth), tt(rect), tt(touched))
+    ids0, r0, m = render.Binner()(*args)
+    b = render.Binner(sync=False)
+    b._ensure(n, W, H, m + 16)                             # the first call fills it past 2/3
+    ids1, r1, m1 = b(*args)
+    torch.cuda.synchronize()
+    assert m1 == m and b.cap >= int(m * 1.5)
+    np.testing.assert_array_equal(ids1.cpu().numpy(), ids0.cpu().numpy())
+    np.testing.assert_array_equal(r1.cpu().numpy(), r0.cpu().numpy())
+    ids2, r2, none = b(*args)                              # the next call: asynchronous, grown buffers
+    assert none is None and b.count() == (m, True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ids2[:m].cpu().numpy(), ids0.cpu().numpy())
+
+
 def _oracle_topk(orc, g, cam, K):
     r = orc.render(g, cam, K)
     return r

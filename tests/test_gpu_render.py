@@ -171,3 +171,69 @@ def test_prune_stats_parity(torch, orc, name, K):
     assert bad.sum() <= nfl, (bad.sum(), nfl)
     if nfl == 0:
         np.testing.assert_array_equal(c_gpu // 2, c_orc)
+
+
+@pytest.mark.parametrize("name,K", [("moved0", 4), ("moved1", 8), ("c3s", 4), ("c3s", 1)])
+def test_pose_gradient_parity(torch, orc, name, K):
+    """Camera-pose gradient of the rendering loss (Sec. 4.1's pose refinement): the GPU's
+    dL/d(rho, phi) against the oracle's, on a general camera (every rotation entry
+    nonzero) and on pitched keyframes of the room workload, with the feature term; the
+    parameter gradients of the same pass equal lgs_project_bwd's bit for bit."""
+    from paper_2602_06991_amd import render
+    from test_oracle_pose import _moved
+    if name.startswith("moved"):
+        s = int(name[5:])
+        g0, cam0 = make_tiny(600 + s, n=300, W=97, H=71, scale=(-2.2, 0.8), spread=(-0.4, 1.4))
+        g, cam = _moved(g0, cam0, 20 + s)
+    else:
+        sc = make_scene(3, N=60000, W=200, H=150)
+        g, cam = sc.gaussians, sc.cameras[3]
+    out, state = gpu_forward(g, cam, K)
+    r = orc.render(g, cam, K)
+    fl = orc.flagged(r["margins"], **FLAG_EPS)
+    gC, gD, gO, gF = random_upstream(13, cam.W * cam.H, g.d)
+    m = (~fl).reshape(-1).astype(np.float32)
+    gC *= m[:, None]; gD *= m; gO *= m; gF *= m[:, None]
+    H, W = cam.H, cam.W
+    gpu = _gpu_backward(torch, state, K, gC.reshape(H, W, 3), gD.reshape(H, W), gO.reshape(H, W),
+                        gF.reshape(H, W, g.d))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    sg = {k[2:]: t(v) for k, v in gpu.items() if k.startswith("s_")}
+    n = g.n
+    pg = dict(means=torch.zeros(n, 3, device="cuda"), log_scales=torch.zeros(n, 3, device="cuda"),
+              quats=torch.zeros(n, 4, device="cuda"), opacity_logits=torch.zeros(n, device="cuda"))
+    dpose = torch.zeros(6, device="cuda")
+    render.project_bwd_pose(state["cam"], state["P"], sg, dpose, pg)
+    dpose2 = torch.full((6,), 0.5, device="cuda")
+    render.project_bwd_pose(state["cam"], state["P"], sg, dpose2)            # pose only, accumulated
+    torch.cuda.synchronize()
+    for k in ("means", "log_scales", "quats", "opacity_logits"):
+        np.testing.assert_array_equal(pg[k].cpu().numpy(), gpu["p_" + k], err_msg=k)
+    b = orc.backward(g, cam, K, g.feat.astype(np.float64), gC, gD, gO, gF)
+    want = b["d_pose"]
+    got = dpose.cpu().numpy().astype(np.float64)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"{name} K={K}: dL/d(rho, phi) {np.array2string(got, precision=4)}, max err {err:.2e} "
+          f"(rel to the largest)", flush=True)
+    assert err <= 1e-3, (got, want)
+    np.testing.assert_allclose(dpose2.cpu().numpy() - 0.5, got, rtol=1e-4, atol=1e-4 * np.abs(got).max())
+
+
+def test_autograd_wrapper_requantizes_an_updated_master_table(torch):
+    """The BF16 store follows the FP32 master features: an in-place update (as an
+    optimizer makes) or a new tensor is quantized again before the next render."""
+    from paper_2602_06991_amd.render import Renderer
+    g, cam = _scene("c0")
+    P = dev_params(g)
+    params = {k: v.clone().requires_grad_(True) for k, v in P.items()}
+    r = Renderer(K=4, feat_dtype="bf16")
+    F0 = r.render(params, cam)[3].detach().clone()
+    with torch.no_grad():
+        params["feat"].mul_(-1.0)              # in place: the version counter advances
+    F1 = r.render(params, cam)[3].detach()
+    fresh = Renderer(K=4, feat_dtype="bf16").render(params, cam)[3].detach()
+    assert torch.equal(F1, fresh)
+    assert torch.equal(F1, -F0)                # BF16 rounding is symmetric, so the map negates exactly
+    params["feat"] = (params["feat"].detach() * 0.5).requires_grad_(True)   # a new tensor
+    F2 = r.render(params, cam)[3].detach()
+    assert torch.equal(F2, Renderer(K=4, feat_dtype="bf16").render(params, cam)[3].detach())

@@ -1,0 +1,118 @@
+"""Batched views (Sec. 3.4: one mapping step over several keyframes, the view folded
+into the binning key): every batched call against the single-view calls it batches,
+on the 8 pitched 640x480 keyframes of the 1M-Gaussian room workload and on 4 views of
+a smaller 1200x680 scene.  The forward is bit-identical view by view (same arithmetic,
+same blend order); gradients accumulated with atomics match to summation order.  The
+single-view calls themselves are compared with the oracle in test_gpu_render and
+test_gpu_fullsize."""
+import numpy as np
+import pytest
+
+from gpu_util import dev_params
+from paper_2602_06991_amd.scenegen import make_scene, random_upstream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_06991_amd import lgs
+    lgs.load()
+    return t
+
+
+def _rel(a, b):
+    a = a.double()
+    b = b.double()
+    return float((a - b).norm() / b.norm().clamp_min(1e-30))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("cfg,K,N,W,H", [(3, 4, None, None, None), (4, 8, 400000, 1200, 680)])
+def test_views_match_single_view_calls(torch, cfg, K, N, W, H):
+    from paper_2602_06991_amd import lgs, render
+    sc = make_scene(cfg, N=N, W=W, H=H, D=8) if N else make_scene(cfg, D=8)
+    g = sc.gaussians
+    n, V = g.n, len(sc.cameras)
+    cams_l = [lgs.make_camera(c) for c in sc.cameras]
+    cams = lgs.camera_array(cams_l)
+    P = dev_params(g)
+    Wd, Hd = cams_l[0].width, cams_l[0].height
+    print(f"config {cfg}: {V} views {Wd}x{Hd}, N={n}, K={K}", flush=True)
+
+    # forward, batched
+    proj = render.project_views(cams, P)
+    b = render.Binner()
+    ids, ranges, m = b(cams, n, proj["depth"], proj["tile_rect"], proj["tiles_touched"], views=V)
+    fw = render.rasterize_views(cams, K, n, proj, P["rgb"], ids, ranges)
+    torch.cuda.synchronize()
+    T1 = ((Wd + 15) // 16) * ((Hd + 15) // 16)
+    gC, gD, gO, _ = random_upstream(3, V * Wd * Hd, 8)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    gC, gD, gO = t(gC.reshape(V * Hd, Wd, 3)), t(gD.reshape(V * Hd, Wd)), t(gO.reshape(V * Hd, Wd))
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    dtw = torch.randn(V * Hd, Wd, K, device="cuda", generator=gen)
+    sg = render.screen_grad_buffers_views(n, V, "cuda")
+    render.rasterize_bwd_views(cams, K, n, proj, P["rgb"], ids, ranges, fw, gC, gD, gO, dtw, sg)
+    pg = dict(means=torch.zeros(n, 3, device="cuda"), log_scales=torch.zeros(n, 3, device="cuda"),
+              quats=torch.zeros(n, 4, device="cuda"), opacity_logits=torch.zeros(n, device="cuda"))
+    dpose = torch.zeros(V * 6, device="cuda")
+    render.project_bwd_views(cams, P, sg, pg, dpose)
+    cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    mxw = torch.zeros(n, device="cuda")
+    lgs.lgs_prune_stats_views(cams, V, K, n, proj["mean2d"].data_ptr(), proj["conic"].data_ptr(),
+                              proj["opacity"].data_ptr(), ids.data_ptr(), ranges.data_ptr(),
+                              fw["n_contrib"].data_ptr(), fw["ids"].data_ptr(), cnt.data_ptr(), mxw.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+
+    # the same views one at a time
+    pg1 = {k: torch.zeros_like(v) for k, v in pg.items()}
+    rgb1 = torch.zeros(n, 3, device="cuda")
+    cnt1 = torch.zeros(n, dtype=torch.int32, device="cuda")
+    mxw1 = torch.zeros(n, device="cuda")
+    pairs = 0
+    for v in range(V):
+        c = cams_l[v]
+        p1 = render.project(c, P)
+        for k in p1:
+            assert torch.equal(p1[k], proj[k][v * n:(v + 1) * n]), (v, k)
+        i1, r1, m1 = render.Binner()(c, n, p1["depth"], p1["tile_rect"], p1["tiles_touched"])
+        pairs += m1
+        rv = ranges[v * T1:(v + 1) * T1]
+        nz = (r1[:, 1] > r1[:, 0])
+        assert torch.equal(rv[:, 1] - rv[:, 0], r1[:, 1] - r1[:, 0]), v
+        if m1:
+            lo, hi = int(rv[nz][0, 0]), int(rv[nz][-1, 1])
+            assert hi - lo == m1
+            assert torch.equal(ids[lo:hi] - v * n, i1), v           # records of view v, same order
+        f1 = render.rasterize(c, K, p1, P["rgb"], i1, r1)
+        rows = slice(v * Hd, (v + 1) * Hd)
+        for k in f1:
+            assert torch.equal(f1[k], fw[k][rows]), (v, k)
+        s1 = render.screen_grad_buffers(n, "cuda")
+        render.rasterize_bwd(c, K, p1, P["rgb"], i1, r1, f1, gC[rows].contiguous(), gD[rows].contiguous(),
+                             gO[rows].contiguous(), dtw[rows].contiguous(), s1)
+        for k in ("mean2d", "conic", "opacity", "depth"):
+            assert _rel(sg[k][v * n:(v + 1) * n], s1[k]) <= 1e-5, (v, k)
+        rgb1 += s1["rgb"]
+        render.project_bwd(c, P, s1, pg1)
+        d1 = torch.zeros(6, device="cuda")
+        render.project_bwd_pose(c, P, s1, d1)
+        torch.cuda.synchronize()
+        e = float((dpose[6 * v:6 * v + 6] - d1).abs().max() / d1.abs().max().clamp_min(1e-30))
+        assert e <= 1e-4, (v, e)
+        render.prune_stats(c, K, p1, i1, r1, f1, cnt1, mxw1)
+    torch.cuda.synchronize()
+    assert m == pairs
+    assert _rel(sg["rgb"], rgb1) <= 1e-5
+    for k in pg:
+        e = _rel(pg[k], pg1[k])
+        print(f"   {k}: batched vs per-view sum rel {e:.2e}", flush=True)
+        assert e <= 1e-5, (k, e)
+    assert torch.equal(cnt, cnt1)
+    assert torch.equal(mxw, mxw1)
+    print(f"   {m} pairs over {V} views; forward identical view by view", flush=True)
