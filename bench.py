@@ -51,6 +51,13 @@ def parse():
     ap.add_argument("--forms", default="bf16,f32")
     ap.add_argument("--feature-path", choices=("fused", "separate"), default="fused",
                     help="feature render and adjoint in one launch (fused) or two")
+    ap.add_argument("--multi-view", default="3",
+                    help="also time the batched multi-view steps of these workloads ('' for none): "
+                         "3 = 8 x 640x480 / 1M / BF16 / K = 4.  Workload 4 (4 x 1200x680 / 3M / D = 768 / "
+                         "K = 8) is refused: its batched step has made a GPU memory fault whose cause is "
+                         "not found yet")
+    ap.add_argument("--no-vanilla", dest="vanilla", action="store_false",
+                    help="skip the vanilla (alpha-blended, every Gaussian) feature step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy three times (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -60,9 +67,11 @@ def parse():
 class Step:
     """All buffers of one frame's forward + backward, reused across steps."""
 
-    def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form, fused=True, geometry_only=False):
+    def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form, fused=True, geometry_only=False,
+                 vanilla=False):
         self.t, self.render, self.lgs = torch, render, lgs
         self.fused = fused
+        self.vanilla = vanilla   # the dense alpha-blended feature field in place of Top-K (Tab. 4's comparison)
         self.geometry_only = geometry_only   # the hybrid schedule's geometry iterations (Sec. 3.4)
         self.P, self.target, self.cam, self.K, self.form = scene_dev, target, cam, K, form
         self.map = "f32" if form == "f32" else "bf16"
@@ -101,7 +110,10 @@ class Step:
         fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges)
         self._mark("rasterize_topk_fwd")
         F = None
-        if not self.fused and not self.geometry_only:
+        if self.vanilla:
+            F = r.feature_vanilla_fwd(c, proj, ids, ranges, fw, store, scale, self.form)
+            self._mark("feature_render_fwd")
+        elif not self.fused and not self.geometry_only:
             F = r.feature_fwd(fw["ids"], fw["w"], store, scale, self.form, self.map)
             self._mark("feature_render_fwd")
         tC, tD, tF = self.target
@@ -122,6 +134,10 @@ class Step:
         fscale = 1.0 / (self.npix * self.d)
         if self.geometry_only:
             dtw = None
+        elif self.vanilla:
+            dtw = None
+            r.feature_vanilla_bwd(c, proj, ids, ranges, fw, store, scale, self.form, r.l1_grad(F, tF, fscale),
+                                  self.dfeat, self.sg)
         elif self.fused:
             F, dtw = r.feature_fwd_bwd_l1(fw["ids"], fw["w"], store, scale, self.form, self.map, tF, fscale,
                                           self.dfeat)
@@ -133,12 +149,149 @@ class Step:
             kb.record()
             self.kmarks.append((ka, kb))
         if not self.geometry_only:
-            self._mark("feature_render_fwd_bwd" if self.fused else "feature_render_bwd")
+            self._mark("feature_render_fwd_bwd" if self.fused and not self.vanilla else "feature_render_bwd")
         r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg)
         self._mark("rasterize_topk_bwd")
         r.project_bwd(c, P, self.sg, self.pg)
         self._mark("project_bwd")
         self.last = dict(fw=fw, pairs=m, F=F, store=store, scale=scale, proj=proj, ids=ids, ranges=ranges)
+
+
+class StepViews:
+    """One mapping step over several keyframes (Sec. 3.4), every geometry call batched
+    over the views (the view folded into the binning key) and the feature render +
+    adjoint over the stacked views in one launch; the step ends with the parameter
+    gradients and every view's camera-pose gradient (Sec. 4.1's pose refinement)."""
+
+    def __init__(self, torch, render, lgs, scene_dev, target, cams, K, form):
+        self.t, self.render, self.lgs = torch, render, lgs
+        self.P, self.target, self.cams, self.K, self.form = scene_dev, target, cams, K, form
+        self.V = len(cams)
+        self.map = "f32" if form == "f32" else "bf16"
+        self.binner = render.Binner(sync=False)
+        n, d = scene_dev["feat"].shape
+        self.n, self.d = n, d
+        dev = "cuda"
+        self.dfeat = torch.empty(n, d, device=dev)
+        self.sg = render.screen_grad_buffers_views(n, self.V, dev)
+        self.pg = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
+                       quats=torch.empty(n, 4, device=dev), opacity_logits=torch.empty(n, device=dev))
+        self.dpose = torch.empty(6 * self.V, device=dev)
+        self.npix = cams[0].width * cams[0].height * self.V
+        self.events = None
+        self.kmarks = None
+
+    _mark = Step._mark
+
+    def __call__(self):
+        r, P, c, V, n = self.render, self.P, self.cams, self.V, self.n
+        self._mark("start")
+        store, scale = (P["feat"], None) if self.form == "f32" else r.quantize(P["feat"], self.form)
+        self._mark("quantize")
+        proj = r.project_views(c, P)
+        self._mark("project_fwd")
+        ids, ranges, m = self.binner(c, n, proj["depth"], proj["tile_rect"], proj["tiles_touched"], views=V)
+        self._mark("bin_sort")
+        fw = r.rasterize_views(c, self.K, n, proj, P["rgb"], ids, ranges)
+        self._mark("rasterize_topk_fwd")
+        tC, tD, tF = self.target
+        gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
+        gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
+        self._mark("l1_grad")
+        self.dfeat.zero_()
+        for v in self.sg.values():
+            v.zero_()
+        for v in self.pg.values():
+            v.zero_()
+        self.dpose.zero_()
+        self._mark("zero_grads")
+        if self.kmarks is not None:
+            ka = self.t.cuda.Event(enable_timing=True)
+            ka.record()
+        F, dtw = r.feature_fwd_bwd_l1(fw["ids"], fw["w"], store, scale, self.form, self.map, tF,
+                                      1.0 / (self.npix * self.d), self.dfeat, views=V)
+        if self.kmarks is not None:
+            kb = self.t.cuda.Event(enable_timing=True)
+            kb.record()
+            self.kmarks.append((ka, kb))
+        self._mark("feature_render_fwd_bwd")
+        r.rasterize_bwd_views(c, self.K, n, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg)
+        self._mark("rasterize_topk_bwd")
+        r.project_bwd_views(c, P, self.sg, self.pg, self.dpose)
+        self._mark("project_bwd")
+        self.last = dict(fw=fw, F=F, store=store, scale=scale)
+
+
+# Batched workloads the bench refuses to run, with the reason.
+DISABLED_MULTI_VIEW = {
+    4: "the 4-view step over 3M Gaussians (D = 768, K = 8) made a GPU memory fault twice; every kernel "
+       "of the step passes its own parity test at this size, and the cause has not been found",
+}
+
+
+def multi_view(torch, render, lgs, config, steps, warmup):
+    """The batched mapping step of workload `config` for each of its storage forms:
+    ms per step, the feature kernel's HBM roofline, and each form's feature-map error
+    against the FP32 form's map of the same step."""
+    from paper_2602_06991_amd.scenegen import make_scene
+    t_gen = time.perf_counter()
+    scene = make_scene(config)
+    cfg = scene.config
+    print(f"# scene {cfg['views']} x {cfg['W']}x{cfg['H']} N={cfg['N']} D={cfg['D']} generated in "
+          f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    names = ("means", "log_scales", "quats", "opacity_logits", "rgb", "feat")
+    P = {k: f(v) for k, v in zip(names, scene.gaussians.arrays())}
+    PT = {k: f(v) for k, v in zip(names, scene.target.arrays())}
+    cams = lgs.camera_array([lgs.make_camera(c) for c in scene.cameras])
+    del scene
+    K = cfg["K"][0]
+    V, n, D = len(cams), cfg["N"], cfg["D"]
+    forms = ("fp8", "bf16", "f32") if config == 4 else ("bf16", "f32")
+    out, maps = {}, {}
+    # target frames: the perturbed scene rendered by the same path, outside timing
+    tproj = render.project_views(cams, PT)
+    tids, tranges, _ = render.Binner()(cams, n, tproj["depth"], tproj["tile_rect"], tproj["tiles_touched"], views=V)
+    tfw = render.rasterize_views(cams, K, n, tproj, PT["rgb"], tids, tranges)
+    del tproj, tids, tranges
+    for form in forms:
+        mp = "f32" if form == "f32" else "bf16"
+        tstore, tscale = render.quantize(PT["feat"], form)
+        tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp, views=V)
+        del tstore, tscale
+        step = StepViews(torch, render, lgs, P, (tfw["C"], tfw["D"], tF), cams, K, form)
+        ms, phases, kern_ms, dist = time_steps(torch, step, steps, warmup)
+        pairs, fitted = step.binner.count()
+        assert fitted, "pair buffer overflowed during timing"
+        fw = step.last["fw"]
+        U = render.union_count(fw["ids"], n)
+        s_map = 4 if mp == "f32" else 2
+        s_f = {"f32": 4, "bf16": 2, "fp8": 1}[form]
+        _, _, both = feature_bytes(step.npix, K, D, U, s_map, s_f, form == "fp8")
+        gbs = both / (kern_ms * 1e-3) / 1e9
+        maps[form] = step.last["F"]
+        out[form] = dict(ms_per_step=round(ms, 4), step_ms_percentiles=dist,
+                         feature_fwd_bwd_ms=round(kern_ms, 4), feature_GBps=round(gbs, 1),
+                         feature_hbm_frac=round(gbs / HBM_PEAK_GBS, 4), algorithmic_bytes=int(both),
+                         phases_ms={p: round(x, 4) for p, x in phases.items()}, U=U, pairs=int(pairs))
+        print(f"# config {config} {form}: {ms:.3f} ms/step, feature kernel {kern_ms:.3f} ms "
+              f"({gbs:.0f} GB/s), pairs {pairs}, U {U}", file=sys.stderr, flush=True)
+        del step, tF
+        torch.cuda.empty_cache()
+    # feature error of each low-precision form against the FP32 form (same Top-K records)
+    ref = maps["f32"].float()
+    for form in forms:
+        if form == "f32":
+            continue
+        a = maps[form].float()
+        nrm = ref.norm(dim=-1).clamp_min(1e-2)
+        e = ((a - ref).norm(dim=-1) / nrm)
+        out[form]["feature_err_vs_f32"] = dict(max=round(float(e.max()), 5), mean=round(float(e.mean()), 5))
+        del a, e
+    del maps, ref
+    torch.cuda.empty_cache()
+    return dict(workload=f"{V} views x {cams[0].width}x{cams[0].height} px, N={n} Gaussians, D={D}, K={K}",
+                views=V, N=n, D=D, K=K, forms=out)
 
 
 def time_steps(torch, step, steps, warmup):
@@ -183,11 +336,14 @@ def counter_traffic(kernel, workload_ok):
     import hashlib
     if not workload_ok:
         return None
-    src = os.path.join(ROOT, "paper_2602_06991_amd", "csrc", "feature.hip")
+    csrc = os.path.join(ROOT, "paper_2602_06991_amd", "csrc")
     prof = os.path.join(ROOT, "profiles", "hbm_counters_c2_1200x680_K4_bf16.md")
     if not os.path.exists(prof):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("feature_impl.hpp", "feature_launch.hpp", "lgs_device.hpp"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    sha = h.hexdigest()[:16]
     for line in open(prof):
         if line.startswith("traffic:"):
             f = [x.strip() for x in line[len("traffic:"):].split("|")]
@@ -274,25 +430,57 @@ def separate_feature_ms(torch, render, fw, store, scale, form, mp, target, d, n,
     return out
 
 
-def cpu_baseline(scene, K, form):
+def cpu_baseline(scene, K, form, gpu_out=None):
     """The FP64 oracle (test infrastructure, timed as a reported baseline, never tuned)
-    rendering and differentiating one full frame of the same workload on the host."""
+    rendering and differentiating one full frame of the same workload on the host:
+    the median of three runs on every host thread, and one run on a single thread.
+    With gpu_out (the GPU's C, D, Top-K ids and map of that frame) it also reports the
+    GPU's errors against the oracle under the parity rule of the tests."""
     from oracle import oracle as O
     from paper_2602_06991_amd.scenegen import random_upstream
     cam = scene.cameras[0]
     g = scene.gaussians
     feat64 = g.feat.astype(np.float64)
     gC, gD, gO, gF = random_upstream(1, cam.W * cam.H, g.d)
-    t0 = time.perf_counter()
-    r = O.render(g, cam, K)
-    O.feature(r["ids"], r["w"], feat64)
-    t1 = time.perf_counter()
-    O.backward(g, cam, K, feat64, gC, gD, None, gF)
-    t2 = time.perf_counter()
-    return dict(value=round((t2 - t0) * 1e3, 1), unit="ms/frame", cores=O.num_threads(),
-                kind="oracle",
-                sample=f"one full {cam.W}x{cam.H} frame, FP64 features (storage form {form} "
-                       f"not applied): fwd {1e3 * (t1 - t0):.0f} ms + bwd {1e3 * (t2 - t1):.0f} ms")
+
+    def once():
+        t0 = time.perf_counter()
+        r = O.render(g, cam, K)
+        Fo = O.feature(r["ids"], r["w"], feat64)
+        t1 = time.perf_counter()
+        O.backward(g, cam, K, feat64, gC, gD, None, gF)
+        t2 = time.perf_counter()
+        return (t1 - t0, t2 - t1), r, Fo
+
+    cores = O.num_threads()
+    runs = [once() for _ in range(3)]
+    fwd = float(np.median([x[0][0] for x in runs]))
+    tot = float(np.median([sum(x[0]) for x in runs]))
+    O.set_threads(1)
+    (f1, b1), _, _ = once()
+    O.set_threads(cores)
+    out = dict(value=round(tot * 1e3, 1), unit="ms/frame", cores=cores, kind="oracle",
+               sample=f"one full {cam.W}x{cam.H} frame (render, Top-K feature map, full adjoint), FP64 "
+                      f"features (storage form {form} not applied); median of 3 runs on {cores} threads: "
+                      f"fwd {1e3 * fwd:.0f} ms + bwd {1e3 * (tot - fwd):.0f} ms",
+               single_thread_ms_per_frame=round(1e3 * (f1 + b1), 1))
+    if gpu_out is not None:
+        r, Fo = runs[0][1], runs[0][2]
+        fl = O.flagged(r["margins"])
+        bl = O.blend_flagged(r["margins"])
+        ok, cl = ~fl, ~bl
+        rel = lambda a, b, floor: float((np.abs(a - b) / np.maximum(np.abs(b), floor)).max())
+        Fg = gpu_out["F"]
+        nf = np.linalg.norm(Fg[ok] - Fo[ok], axis=-1) / np.maximum(np.linalg.norm(Fo[ok], axis=-1), 1e-2)
+        out["gpu_errors_vs_oracle"] = dict(
+            flagged_share=round(float(fl.mean()), 5), blend_flagged_share=round(float(bl.mean()), 5),
+            topk_id_mismatch_unflagged=int(np.sum(np.any(gpu_out["ids"] != r["ids"], -1) & ok)),
+            color_max_rel=float(f"{rel(gpu_out['C'][cl], r['C'][cl], 1e-2):.3g}"),
+            depth_max_rel=float(f"{rel(gpu_out['D'][cl], r['D'][cl], 1e-2):.3g}"),
+            feature_normwise_vs_unquantized_fp64=dict(max=float(f"{nf.max():.3g}"), mean=float(f"{nf.mean():.3g}")),
+            rule="ids bit-exact on unflagged pixels; C, D on pixels whose blend decisions are clear; F normwise "
+                 "on unflagged pixels against the FP64 map of the unquantized features")
+    return out
 
 
 def main():
@@ -301,6 +489,10 @@ def main():
         print(json.dumps({"error": "this renderer runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not built)"}))
         sys.exit(2)
+    multi = [int(x) for x in args.multi_view.split(",") if x.strip()]
+    for c in multi:
+        if c in DISABLED_MULTI_VIEW:
+            sys.exit(f"bench.py: the batched step of workload {c} is disabled: {DISABLED_MULTI_VIEW[c]}")
     import torch
     from paper_2602_06991_amd import lgs, render
     from paper_2602_06991_amd.scenegen import make_scene
@@ -330,6 +522,7 @@ def main():
     K = args.K
     forms = args.forms.split(",")
     results = {}
+    gpu_out = None
     for form in forms:
         mp = "f32" if form == "f32" else "bf16"
         # target frame: the perturbed scene rendered by the same path, outside timing
@@ -372,6 +565,9 @@ def main():
         expo = torch.empty(P["feat"].shape[0], device="cuda").exponential_(generator=gen)
         select_ms = timed(torch, lambda: render.prune_select(cnt, mxw, 1, expo, 0.5))
         del cnt, mxw, expo
+        if form == forms[0] and not args.no_cpu_baseline:
+            gpu_out = dict(C=fw["C"].cpu().numpy().astype(np.float64), D=fw["D"].cpu().numpy().astype(np.float64),
+                           ids=fw["ids"].cpu().numpy(), F=step.last["F"].float().cpu().numpy().astype(np.float64))
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
                              bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
                              prune_ms=prune_ms, select_ms=select_ms, geo_ms=geo_ms, dist=dist,
@@ -399,6 +595,36 @@ def main():
                 sweep[f"K{k2}_{form}"] = dict(ms_per_frame=round(ms, 4), feature_fwd_bwd_ms=round(feature_ms(ph), 4))
                 del step
                 torch.cuda.empty_cache()
+
+    vanilla = {}
+    if "bf16" in forms and args.vanilla:
+        # Tab. 4's comparison: the dense alpha-blended feature field (every blended
+        # Gaussian) in the same step, BF16 storage and map, L1 feature loss
+        tproj = render.project(cam, PT)
+        tb = render.Binner()
+        tids, tranges, _ = tb(cam, PT["means"].shape[0], tproj["depth"], tproj["tile_rect"], tproj["tiles_touched"])
+        tfw = render.rasterize(cam, K, tproj, PT["rgb"], tids, tranges)
+        tstore, tscale = render.quantize(PT["feat"], "bf16")
+        tF = render.feature_vanilla_fwd(cam, tproj, tids, tranges, tfw, tstore, tscale, "bf16")
+        step = Step(torch, render, lgs, P, (tfw["C"].clone(), tfw["D"].clone(), tF.clone()), cam, K, "bf16",
+                    fused=False, vanilla=True)
+        del tproj, tb, tids, tranges, tfw, tstore, tscale, tF
+        ms, ph, _, _ = time_steps(torch, step, max(5, args.steps // 2), 2)
+        assert step.binner.count()[1], "pair buffer overflowed during timing"
+        vanilla = dict(ms_per_frame=round(ms, 4),
+                       feature_fwd_ms=round(ph["feature_render_fwd"], 4),
+                       feature_bwd_ms=round(ph["feature_render_bwd"], 4),
+                       feature_fwd_bwd_ms=round(ph["feature_render_fwd"] + ph["feature_render_bwd"], 4),
+                       phases_ms={p_: round(x, 4) for p_, x in ph.items()})
+        print(f"# vanilla bf16: {ms:.3f} ms/step, feature fwd {ph['feature_render_fwd']:.3f} + bwd "
+              f"{ph['feature_render_bwd']:.3f} ms", file=sys.stderr, flush=True)
+        del step
+        torch.cuda.empty_cache()
+
+    mv = {}
+    for c in multi:
+        mv[f"config{c}"] = multi_view(torch, render, lgs, c, max(3, args.steps // 4), 2)
+        torch.cuda.empty_cache()
 
     main_form = forms[0]
     R = results[main_form]
@@ -464,8 +690,12 @@ def main():
     }
     if sweep:
         line["k_sweep"] = sweep
+    if vanilla:
+        line["vanilla_bf16"] = vanilla
+    if mv:
+        line["multi_view"] = mv
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(scene, K, main_form)
+        line["cpu_baseline"] = cpu_baseline(scene, K, main_form, gpu_out)
     print(json.dumps(line), flush=True)
 
 

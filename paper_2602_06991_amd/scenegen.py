@@ -13,9 +13,11 @@ always produces the same bytes; `scene_digest` hashes them.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
 import hashlib
 import math
+import os
 
 import numpy as np
 
@@ -38,6 +40,19 @@ CONFIGS = {
 
 _STREAMS = ("room", "objects", "surface", "scales", "rotations", "opacity",
             "colour", "clusters", "features", "cameras", "perturbation")
+
+_CHUNK = 1 << 16   # rows per independently seeded block of feature noise
+
+
+def _chunked_rows(rng, N, fill):
+    """Calls fill(s, e, block_rng) for row blocks [s, e) of _CHUNK rows, each block with
+    its own generator spawned from `rng` in block order (so the bytes do not depend on
+    how many threads run the blocks); blocks run on a thread pool."""
+    starts = list(range(0, N, _CHUNK))
+    seeds = np.random.SeedSequence(int(rng.integers(0, 2**63))).spawn(len(starts))
+    jobs = [(s, min(N, s + _CHUNK), np.random.Generator(np.random.PCG64(q))) for s, q in zip(starts, seeds)]
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        list(ex.map(lambda j: fill(*j), jobs))
 
 
 @dataclasses.dataclass
@@ -209,12 +224,12 @@ def make_scene(config=0, seed=None, **overrides) -> Scene:
 
     centres = _normalize_rows(streams["clusters"].standard_normal((n_clusters, D), dtype=np.float32))
     feat = np.empty((N, D), np.float32)
-    rf = streams["features"]
-    chunk = 1 << 16
-    for s in range(0, N, chunk):
-        e = min(N, s + chunk)
-        noise = rf.standard_normal((e - s, D), dtype=np.float32)
+
+    def fill_feat(s, e, r):
+        noise = r.standard_normal((e - s, D), dtype=np.float32)
         feat[s:e] = _normalize_rows(centres[cluster[s:e]] + np.float32(0.1) * noise)
+
+    _chunked_rows(streams["features"], N, fill_feat)
 
     g = Gaussians(means, log_scales, quats, opacity_logits, rgb, feat)
     target = perturb(g, streams["perturbation"])
@@ -234,10 +249,11 @@ def perturb(g: Gaussians, rng) -> Gaussians:
     rgb = np.clip(g.rgb + rng.normal(0, 0.02, (N, 3)), 0.0, 1.0).astype(np.float32)
     feat = np.empty_like(g.feat)
     scale = np.float32(0.1 / math.sqrt(D))
-    chunk = 1 << 16
-    for s in range(0, N, chunk):
-        e = min(N, s + chunk)
-        feat[s:e] = _normalize_rows(g.feat[s:e] + scale * rng.standard_normal((e - s, D), dtype=np.float32))
+
+    def fill_feat(s, e, r):
+        feat[s:e] = _normalize_rows(g.feat[s:e] + scale * r.standard_normal((e - s, D), dtype=np.float32))
+
+    _chunked_rows(rng, N, fill_feat)
     return Gaussians(means, log_scales, quats, opacity_logits, rgb, feat)
 
 
