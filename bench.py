@@ -51,11 +51,9 @@ def parse():
     ap.add_argument("--forms", default="bf16,f32")
     ap.add_argument("--feature-path", choices=("fused", "separate"), default="fused",
                     help="feature render and adjoint in one launch (fused) or two")
-    ap.add_argument("--multi-view", default="3",
+    ap.add_argument("--multi-view", default="3,4",
                     help="also time the batched multi-view steps of these workloads ('' for none): "
-                         "3 = 8 x 640x480 / 1M / BF16 / K = 4.  Workload 4 (4 x 1200x680 / 3M / D = 768 / "
-                         "K = 8) is refused: its batched step has made a GPU memory fault whose cause is "
-                         "not found yet")
+                         "3 = 8 x 640x480 / 1M / BF16 / K = 4, 4 = 4 x 1200x680 / 3M / D = 768 / FP8 / K = 8")
     ap.add_argument("--no-vanilla", dest="vanilla", action="store_false",
                     help="skip the vanilla (alpha-blended, every Gaussian) feature step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -220,13 +218,6 @@ class StepViews:
         r.project_bwd_views(c, P, self.sg, self.pg, self.dpose)
         self._mark("project_bwd")
         self.last = dict(fw=fw, F=F, store=store, scale=scale)
-
-
-# Batched workloads the bench refuses to run, with the reason.
-DISABLED_MULTI_VIEW = {
-    4: "the 4-view step over 3M Gaussians (D = 768, K = 8) made a GPU memory fault twice; every kernel "
-       "of the step passes its own parity test at this size, and the cause has not been found",
-}
 
 
 def multi_view(torch, render, lgs, config, steps, warmup):
@@ -490,9 +481,6 @@ def main():
                                    "(multi-GPU sharding is a design note, not built)"}))
         sys.exit(2)
     multi = [int(x) for x in args.multi_view.split(",") if x.strip()]
-    for c in multi:
-        if c in DISABLED_MULTI_VIEW:
-            sys.exit(f"bench.py: the batched step of workload {c} is disabled: {DISABLED_MULTI_VIEW[c]}")
     import torch
     from paper_2602_06991_amd import lgs, render
     from paper_2602_06991_amd.scenegen import make_scene
@@ -568,7 +556,11 @@ def main():
         if form == forms[0] and not args.no_cpu_baseline:
             gpu_out = dict(C=fw["C"].cpu().numpy().astype(np.float64), D=fw["D"].cpu().numpy().astype(np.float64),
                            ids=fw["ids"].cpu().numpy(), F=step.last["F"].float().cpu().numpy().astype(np.float64))
+        # (pixel, Gaussian) pairs the blend walks: per pixel, its list up to the last
+        # Gaussian it blends (n_contrib), the unit of the blend kernels' rates
+        blend_pairs = int(fw["n_contrib"].sum())
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
+                             blend_pairs=blend_pairs,
                              bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
                              prune_ms=prune_ms, select_ms=select_ms, geo_ms=geo_ms, dist=dist,
                              tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
@@ -679,7 +671,10 @@ def main():
                       "prune_stats_ms": round(v["prune_ms"], 4),
                       "prune_select_ms": round(v["select_ms"], 4),
                       "phases_ms": {p: round(x, 4) for p, x in v["phases"].items()},
-                      "U": v["U"], "pairs": v["pairs"], "tile_union": v["tile_union"]}
+                      "U": v["U"], "pairs": v["pairs"], "tile_union": v["tile_union"],
+                      "blend_pairs": v["blend_pairs"],
+                      "blend_fwd_Gpairs_per_s": round(v["blend_pairs"] / v["phases"]["rasterize_topk_fwd"] / 1e6, 2),
+                      "blend_bwd_Gpairs_per_s": round(v["blend_pairs"] / v["phases"]["rasterize_topk_bwd"] / 1e6, 2)}
                   for k, v in results.items()},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

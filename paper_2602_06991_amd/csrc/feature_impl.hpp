@@ -10,10 +10,12 @@
 // the map and the adjoint are dense per-tile products on the matrix cores.  With Ft the
 // union's rows and W the (renormalised) weights, F^T = Ft^T W^T, the dot products
 // S^T = Ft G^T, and the gradient rows dFt = W^T G.  Each FP32 weight enters as a pair
-// of BF16 terms (hi, lo), so every product is exact in the FP32 accumulator.  Wave w
-// owns a quarter of the 32-channel chunks for all 256 pixels; its gradient rows are
-// complete when the tile ends, so each (union row, channel) takes one atomic per tile.
-// Per tile row the weights pass through a three-buffer LDS ring (one barrier per row).
+// of BF16 terms (hi, lo), so every product is exact in the FP32 accumulator.  The
+// channels are taken in slabs of at most 512 (one slab up to D = 512); per slab wave w
+// owns a quarter of the slab's 32-channel chunks for all 256 pixels, so its gradient
+// rows are complete when the slab ends and each (union row, channel) takes one atomic
+// per tile.  Per tile row the weights pass through a three-buffer LDS ring (one
+// barrier per row).
 //
 // Per-pixel path (FP32 storage or map, larger unions, K = 10 or 16): lanes across
 // channels, 64 pixels per wave, rows staged in LDS when they fit; the adjoint sums
@@ -94,7 +96,8 @@ __device__ __forceinline__ void store8(void *F, long row, int D, int c, const fl
 constexpr int kFB = 256;          // threads per feature block
 constexpr int kPixPerWave = 64;
 constexpr int kUP = 32;           // union rows the MFMA path holds (two 16-row blocks)
-constexpr int kCPW = 4;           // 32-channel chunks per wave on the MFMA path (D <= 512)
+constexpr int kCPW = 4;           // 32-channel chunks per wave and channel slab on the MFMA path
+constexpr int kSlabCh = 4 * 32 * kCPW;   // channels of one slab: D above this takes several slabs
 constexpr int kRowBudget = 32 * 1024;   // LDS bytes for staged rows on the per-pixel path
 
 template <int K> struct TileCfg {
@@ -218,15 +221,12 @@ struct Slots {
     float W;
 };
 
-// LDS shared by both kernels (static part; staged rows are dynamic LDS).
+// The tile's union, at the start of the dynamic LDS.  The first fields live for the
+// whole tile; the rest (the hash, the wave lists, the union in hash order) serve the
+// union's construction and the per-pixel path, and on the MFMA path they are dead once
+// the union is ordered, so the MFMA buffers overlay them (union_keep_bytes).
 template <int K, int FT>
 struct UnionLds {
-    int hkey[TileCfg<K>::HS];
-    int hval[TileCfg<K>::HS];
-    int wlist[4][kPixPerWave * K];   // wave-local distinct ids
-    int16_t wmap[4][kPixPerWave * K];   // wave-local index -> tile union index (< 4 * 64 K)
-    int uid[4 * kPixPerWave * K];    // tile union index -> Gaussian id
-    float uscale[FT == FT_FP8 ? 4 * kPixPerWave * K : 1];  // tile union index -> FP8 row scale
     int nw[4];
     int nU;
     // MFMA path (U <= kUP): the union in ascending id order, so both feature
@@ -234,7 +234,23 @@ struct UnionLds {
     int rank[kUP];       // hash-order union index -> ascending-id index
     int uid2[kUP];       // ascending-id index -> Gaussian id
     float uscale2[FT == FT_FP8 ? kUP : 1];  // ascending-id index -> FP8 row scale
+    // construction and per-pixel path
+    int hkey[TileCfg<K>::HS];
+    int hval[TileCfg<K>::HS];
+    int wlist[4][kPixPerWave * K];   // wave-local distinct ids
+    int16_t wmap[4][kPixPerWave * K];   // wave-local index -> tile union index (< 4 * 64 K)
+    int uid[4 * kPixPerWave * K];    // tile union index -> Gaussian id
+    float uscale[FT == FT_FP8 ? 4 * kPixPerWave * K : 1];  // tile union index -> FP8 row scale
 };
+// Bytes of the union that outlive its ordering (where the MFMA buffers start), and of
+// the whole union (where the per-pixel path's buffers start).
+template <int K, int FT>
+constexpr size_t union_keep_bytes() {
+    using UL = UnionLds<K, FT>;
+    return (__builtin_offsetof(UL, hkey) + 15) & ~(size_t)15;
+}
+template <int K, int FT>
+constexpr size_t union_bytes() { return (sizeof(UnionLds<K, FT>) + 15) & ~(size_t)15; }
 
 // Builds the tile union: L.uid[0, U) and, per lane, the slots' union indices.
 // Returns the wave's number of distinct ids.
@@ -439,12 +455,16 @@ __device__ __forceinline__ int blk_ch(int b, int m) { return 8 * (m >> 2) + 4 * 
 // Weights of one tile row in operand-ready layout, shared by the block's four waves:
 // a ring of three such buffers lets one row be read while the next is scattered and
 // the one after is cleared, with a single block barrier per row.
+// Row strides are padded (72 and 48 bytes) so that the 16 lanes of a read group,
+// which take the same offset in consecutive rows, fall on distinct banks.
+constexpr int kWA = kUP + 4;            // BF16 elements per row of wa
+constexpr int kWD = 16 + 8;             // BF16 elements per row of wd
 struct MfRingF {
-    uint16_t wa[2][16][kUP];            // [hi, lo][pixel of the row][union index]
+    uint16_t wa[2][16][kWA];            // [hi, lo][pixel of the row][union index]
 };
 struct MfRingB {
-    uint16_t wa[2][16][kUP];
-    uint16_t wd[2][kUP][16];            // [hi, lo][union index][pixel of the row]
+    uint16_t wa[2][16][kWA];
+    uint16_t wd[2][kUP][kWD];           // [hi, lo][union index][pixel of the row]
 };
 // Per-wave LDS: the forward's map row for the wave's channels (16-byte columns
 // XOR-swizzled by pixel, so neither the writes nor the reads collide on banks), the
@@ -455,41 +475,44 @@ struct MfWaveF {
 struct MfWaveB {
     uint16_t gt[kCPW][2][16][16];       // [chunk][channel block][block row][pixel]
 };
-static_assert(sizeof(MfRingF) == 2048 && sizeof(MfRingB) == 4096, "ring layout");
+static_assert(sizeof(MfRingF) % 16 == 0 && sizeof(MfRingB) % 16 == 0, "ring buffers in 16-byte pieces");
 static_assert(sizeof(MfWaveF) == 4096 && sizeof(MfWaveB) == 4096, "wave buffer layout");
+constexpr int kSP = 20;                 // row stride (floats) of the backward's S^T rows
+static_assert(kUP * kSP * 4 <= (int)sizeof(MfWaveB), "S^T rows fit the wave buffer");
 
-// Dynamic LDS of the MFMA path: [0, R0) half of the union rows staged as BF16
-// ([16][D]) while the operands are loaded; then, in the backward, the waves' partial
-// dot products in the same place, followed by the slot table (per pixel and slot:
-// union index, Wa weight, Wd weight); in the forward the slot table itself takes
-// region 0.  Then the weight ring and the four per-wave buffers.  Up to K = 4 the
-// partial dot products are kept for the whole tile ([4][256][K]) and the slot table
-// holds 32-bit indices and both weights.  Above K = 4, to stay at two blocks per CU,
-// the partials of the last two rows ([2][4][16][K]) are summed row by row into the
-// tile's dot products ([256][K]), and the slot table holds 16-bit indices and, without
-// FP8 row scales (Wa = Wd), one weight.
+// Dynamic LDS of the MFMA path.  Backward: the waves' partial dot products first,
+// then the slot table (per pixel and slot: union index, Wa weight, Wd weight), the
+// weight ring and the four per-wave buffers.  Forward: the slot table, the ring and
+// the wave buffers.  While a channel slab's operands are loaded, half of the union
+// rows are staged as BF16 ([16][slab channels], at most 16 KB) over the ring and the
+// wave buffers, which are idle then.  Up to K = 4 the partial dot products are kept
+// for the whole tile ([4][256][K]) and the slot table holds 32-bit indices and both
+// weights.  Above K = 4, to stay at two blocks per CU, the partials of the last two
+// rows ([2][4][16][K]) are summed row by row into the tile's dot products ([256][K]),
+// and the slot table holds 16-bit indices and, without FP8 row scales (Wa = Wd), one
+// weight.
 __host__ __device__ inline size_t mf_align(size_t a) { return (a + 15) & ~(size_t)15; }
 __host__ __device__ constexpr bool mf_compact(int K) { return K > 4; }
-__host__ __device__ inline size_t mf_region0(int D, int K) {
-    size_t a = (size_t)16 * D * 2;
-    size_t b = mf_compact(K) ? (size_t)(2 * 4 * 16 + kTilePix) * K * 4 : (size_t)4 * kTilePix * K * 4;
-    return mf_align(a > b ? a : b);
+__host__ __device__ inline size_t mf_partials_bytes(int K) {
+    return mf_align(mf_compact(K) ? (size_t)(2 * 4 * 16 + kTilePix) * K * 4 : (size_t)4 * kTilePix * K * 4);
 }
 __host__ __device__ inline size_t mf_slots_bytes(int K, bool fp8) {
     if (!mf_compact(K)) return (size_t)3 * kTilePix * K * 4;
     return mf_align((size_t)kTilePix * K * (2 + 4 * (fp8 ? 2 : 1)));
 }
-__host__ __device__ inline size_t mf_slots_at(int D, int K, bool bwd) { return bwd ? mf_region0(D, K) : 0; }
-__host__ __device__ inline size_t mf_ring_at(int D, int K, bool bwd, bool fp8) {
-    const size_t a = mf_region0(D, K), b = mf_slots_bytes(K, fp8);
-    return bwd ? a + b : mf_align(a > b ? a : b);
+__host__ __device__ inline size_t mf_slots_at(int K, bool bwd) { return bwd ? mf_partials_bytes(K) : 0; }
+__host__ __device__ inline size_t mf_ring_at(int K, bool bwd, bool fp8) {
+    return mf_slots_at(K, bwd) + mf_slots_bytes(K, fp8);
 }
-__host__ __device__ inline size_t mf_waves_at(int D, int K, bool bwd, bool fp8) {
-    return mf_ring_at(D, K, bwd, fp8) + 3 * (bwd ? sizeof(MfRingB) : sizeof(MfRingF));
+__host__ __device__ inline size_t mf_waves_at(int K, bool bwd, bool fp8) {
+    return mf_ring_at(K, bwd, fp8) + 3 * (bwd ? sizeof(MfRingB) : sizeof(MfRingF));
 }
-__host__ __device__ inline size_t mf_lds_bytes(int D, int K, bool bwd, bool fp8) {
-    return mf_waves_at(D, K, bwd, fp8) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
+__host__ __device__ inline size_t mf_lds_bytes(int K, bool bwd, bool fp8) {
+    return mf_waves_at(K, bwd, fp8) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
 }
+// the staged rows of a slab fit over the ring and the wave buffers
+static_assert(3 * sizeof(MfRingF) + 4 * sizeof(MfWaveF) >= 16 * kSlabCh * 2, "staging area (forward)");
+static_assert(3 * sizeof(MfRingB) + 4 * sizeof(MfWaveB) >= 16 * kSlabCh * 2, "staging area (backward)");
 
 template <int K>
 struct SlotTable {
@@ -497,9 +520,9 @@ struct SlotTable {
     float *wa, *wd;
 };
 template <int K, bool FP8>
-__device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, int D, bool bwd) {
+__device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, bool bwd) {
     SlotTable<K> st;
-    float *w = (float *)(dyn + mf_slots_at(D, K, bwd));
+    float *w = (float *)(dyn + mf_slots_at(K, bwd));
     if constexpr (mf_compact(K)) {
         st.wa = w;
         st.wd = FP8 ? w + kTilePix * K : w;
@@ -534,104 +557,196 @@ __device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int
     for (int k = 0; k < K; ++k) s.u[k] = s.u[k] >= 0 ? L.rank[s.u[k]] : -1;
 }
 
-// Stages union rows 16 h .. 16 h + 15 (those below U) as BF16 into ft = [16][D].
-template <int K, int FT>
-__device__ __forceinline__ void mf_stage_half(const UnionLds<K, FT> &L, int U, int D, int h,
-                                              const void *__restrict__ feat, uint16_t *ft) {
-    const int c8 = D >> 3;
-    const int nr = min(16, U - 16 * h);
-    for (int q = threadIdx.x; q < nr * c8; q += kFB) {
-        const int r = q / c8, c = (q - r * c8) * 8;
-        const long src = (long)L.uid2[16 * h + r] * D + c;
-        u32x4 o;
-        if constexpr (FT == FT_BF16) {
-            o = *(const u32x4 *)((const uint16_t *)feat + src);
-        } else {
-            const u32x2 a = *(const u32x2 *)((const uint8_t *)feat + src);
-            float v[8];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                v[i] = e4m3_to_f32((a.x >> (8 * i)) & 0xFFu);
-                v[4 + i] = e4m3_to_f32((a.y >> (8 * i)) & 0xFFu);
-            }
-            o.x = pk_bf16(v[0], v[1]); o.y = pk_bf16(v[2], v[3]);
-            o.z = pk_bf16(v[4], v[5]); o.w = pk_bf16(v[6], v[7]);
-        }
-        *(u32x4 *)(ft + (long)r * D + c) = o;
-    }
-}
-
-// The wave's chunks: [beg, beg + n) of the ceil(D / 32) chunks.
-struct MfChunks {
-    int beg, n;
+// Storage and map formats on the MFMA path.  BF16 rows (and FP8 codes, widened
+// exactly) are one BF16 operand; an FP32 row value f is the exact sum of three BF16
+// terms t0 = RNE(f), t1 = RNE(f - t0), t2 = f - t0 - t1 (exact for |f| above about
+// 2^-100; below, the absolute error is under 2^-133), each multiplied in turn.  With
+// three terms or an FP32 map a wave holds two 32-channel chunks per slab instead of
+// four, so the operands and the FP32 target rows fit the register budget.
+template <int FT, int MT>
+struct MfForm {
+    static constexpr int NT = FT == FT_F32 ? 3 : 1;        // BF16 terms per stored value
+    static constexpr bool M32 = MT == MT_F32;              // FP32 map (and target)
+    static constexpr int CPW = (NT == 3 || M32) ? 2 : 4;   // chunks per wave and slab
+    static_assert(CPW <= kCPW, "wave buffers sized for kCPW chunks");
 };
-__device__ __forceinline__ MfChunks mf_chunks(int D, int wave) {
-    const int nch = (D + 31) >> 5, cpw = (nch + 3) >> 2;
-    MfChunks m;
-    m.beg = wave * cpw;
-    m.n = max(0, min(cpw, nch - m.beg));
+
+// Channel slabs: the ceil(D / 32) chunks are split into ceil(chunks / (4 CPW)) slabs
+// of near-equal size (at most 4 CPW chunks); a tile runs its row loop once per slab
+// with that slab's operands in registers.
+struct MfSlab {
+    int c0, n;   // first chunk, chunk count
+};
+__device__ __forceinline__ int mf_nslabs(int D, int per_slab) {
+    return (((D + 31) >> 5) + per_slab - 1) / per_slab;
+}
+__device__ __forceinline__ MfSlab mf_slab(int D, int ns, int sl) {
+    const int nch = (D + 31) >> 5, per = (nch + ns - 1) / ns;
+    MfSlab m;
+    m.c0 = sl * per;
+    m.n = min(per, nch - m.c0);
     return m;
 }
 
+// Stages union rows 16 h .. 16 h + 15 (those below U), channels of the slab, into
+// ft = [16][32 slab.n]: BF16 (FP8 codes widened exactly), or FP32 as stored.
+template <int K, int FT>
+__device__ __forceinline__ void mf_stage_half(const UnionLds<K, FT> &L, int U, int D, int h, const MfSlab &sb,
+                                              const void *__restrict__ feat, void *ft) {
+    const int cb = sb.c0 * 32, ds = sb.n * 32;
+    const int c8 = (min(D, cb + ds) - cb) >> 3;
+    const int nr = min(16, U - 16 * h);
+    for (int q = threadIdx.x; q < nr * c8; q += kFB) {
+        const int r = q / c8, c = (q - r * c8) * 8;
+        const long src = (long)L.uid2[16 * h + r] * D + cb + c;
+        if constexpr (FT == FT_F32) {
+            const u32x4 *a = (const u32x4 *)((const float *)feat + src);
+            u32x4 *d = (u32x4 *)((float *)ft + r * ds + c);
+            d[0] = a[0];
+            d[1] = a[1];
+        } else {
+            u32x4 o;
+            if constexpr (FT == FT_BF16) {
+                o = *(const u32x4 *)((const uint16_t *)feat + src);
+            } else {
+                const u32x2 a = *(const u32x2 *)((const uint8_t *)feat + src);
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = e4m3_to_f32((a.x >> (8 * i)) & 0xFFu);
+                    v[4 + i] = e4m3_to_f32((a.y >> (8 * i)) & 0xFFu);
+                }
+                o.x = pk_bf16(v[0], v[1]); o.y = pk_bf16(v[2], v[3]);
+                o.z = pk_bf16(v[4], v[5]); o.w = pk_bf16(v[6], v[7]);
+            }
+            *(u32x4 *)((uint16_t *)ft + r * ds + c) = o;
+        }
+    }
+}
+
+// The wave's chunks of the slab: [beg, beg + n) of the ceil(D / 32) chunks.
+struct MfChunks {
+    int beg, n;
+};
+__device__ __forceinline__ MfChunks mf_chunks(const MfSlab &sb, int wave) {
+    const int cpw = (sb.n + 3) >> 2;
+    MfChunks m;
+    m.beg = sb.c0 + wave * cpw;
+    m.n = max(0, min(cpw, sb.n - wave * cpw));
+    return m;
+}
+
+// The three BF16 terms of an FP32 value (see MfForm).
+__device__ __forceinline__ void split3(float v, short &t0, short &t1, short &t2) {
+    const uint16_t a = bits_bf16(v);
+    const float r = v - bf16_to_f32(a);
+    const uint16_t b = bits_bf16(r);
+    t0 = (short)a;
+    t1 = (short)b;
+    t2 = (short)bits_bf16(r - bf16_to_f32(b));
+}
+
 // Register operands of union block h (rows 16 h .. 16 h + 15, staged in ft), zero
-// outside the union and past D:
-//   opA[i][b][h]: lane (i16, g) = Ft[16 h + 4 g + j][chunk + blk_ch(b, i16)], j < 4
-//   opC[i][h]:    lane (i16, g) = Ft[16 h + i16][chunk + 8 g + j], j < 8
-__device__ __forceinline__ void mf_load_ops(const uint16_t *ft, int U, int D, int h, const MfChunks &mc,
-                                            int lane, i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
+// outside the union and past D; term t of NT:
+//   opA[t][i][b][h]: lane (i16, g) = Ft[16 h + 4 g + j][chunk + blk_ch(b, i16)], j < 4
+//   opC[t][i][h]:    lane (i16, g) = Ft[16 h + i16][chunk + 8 g + j], j < 8
+template <int FT, int NT, int CPW>
+__device__ __forceinline__ void mf_load_ops(const void *ft, int U, int D, int h, const MfSlab &sb,
+                                            const MfChunks &mc, int lane, i16x4 (&opA)[NT][CPW][2][2],
+                                            i16x8 (&opC)[NT][CPW][2]) {
     const int i16 = lane & 15, g = lane >> 4;
     const int nr = U - 16 * h;   // staged rows of this block
+    const int cb = sb.c0 * 32, ds = sb.n * 32;
+    const uint16_t *fb = (const uint16_t *)ft;
+    const float *ff = (const float *)ft;
 #pragma unroll
-    for (int i = 0; i < kCPW; ++i) {
+    for (int i = 0; i < CPW; ++i) {
         const int c0 = (mc.beg + i) * 32;
         const bool on = i < mc.n;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            i16x4 a;
+            i16x4 a[NT];
             const int ch = c0 + blk_ch(b, i16);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int r = 4 * g + j;
-                a[j] = (on && r < nr && ch < D) ? (short)ft[r * D + ch] : (short)0;
+                const bool in = on && r < nr && ch < D;
+                if constexpr (NT == 1) {
+                    a[0][j] = in ? (short)fb[r * ds + ch - cb] : (short)0;
+                } else {
+                    short t0, t1, t2;
+                    split3(in ? ff[r * ds + ch - cb] : 0.f, t0, t1, t2);
+                    a[0][j] = t0;
+                    a[1][j] = t1;
+                    a[2][j] = t2;
+                }
             }
-            opA[i][b][h] = a;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) opA[t][i][b][h] = a[t];
         }
         const int ch = c0 + 8 * g;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (on && i16 < nr && ch < D) v = *(const u32x4 *)(ft + i16 * D + ch);
-        opC[i][h] = as_op8(v);
+        const bool in = on && i16 < nr && ch < D;
+        if constexpr (NT == 1) {
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (in) v = *(const u32x4 *)(fb + i16 * ds + ch - cb);
+            opC[0][i][h] = as_op8(v);
+        } else {
+            f32x4 v0 = {0.f, 0.f, 0.f, 0.f}, v1 = {0.f, 0.f, 0.f, 0.f};
+            if (in) {
+                v0 = *(const f32x4 *)(ff + i16 * ds + ch - cb);
+                v1 = *(const f32x4 *)(ff + i16 * ds + ch - cb + 4);
+            }
+            i16x8 c[3];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                short t0, t1, t2;
+                split3(j < 4 ? v0[j] : v1[j - 4], t0, t1, t2);
+                c[0][j] = t0;
+                c[1][j] = t1;
+                c[2][j] = t2;
+            }
+#pragma unroll
+            for (int t = 0; t < 3; ++t) opC[t][i][h] = c[t];
+        }
     }
 }
 
-// Prologue and operands of the MFMA path; on return region 0 is free.
+// Prologue of the MFMA path: the union ordered by id and the slot table.
 template <int K, int FT>
-__device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U, int D, const void *__restrict__ feat,
-                                         unsigned char *dyn, const SlotTable<K> &st, const MfChunks &mc, int lane,
-                                         i16x4 (&opA)[kCPW][2][2], i16x8 (&opC)[kCPW][2]) {
-    uint16_t *ft = (uint16_t *)dyn;
+__device__ __forceinline__ void mf_begin(UnionLds<K, FT> &L, Slots<K> &s, int U, const SlotTable<K> &st) {
     mf_prologue<K, FT>(L, s, U);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h == 1 && U <= 16) {
-#pragma unroll
-            for (int i = 0; i < kCPW; ++i) {
-                opA[i][0][1] = (i16x4){0, 0, 0, 0};
-                opA[i][1][1] = (i16x4){0, 0, 0, 0};
-                opC[i][1] = (i16x8){0, 0, 0, 0, 0, 0, 0, 0};
-            }
-            break;
-        }
-        mf_stage_half<K, FT>(L, U, D, h, feat, ft);
-        __syncthreads();
-        mf_load_ops(ft, U, D, h, mc, lane, opA, opC);
-        __syncthreads();
-    }
     const int t = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         st.u[t * K + k] = s.u[k];
         st.wa[t * K + k] = s.u[k] >= 0 ? s.wf[k] : 0.f;
         if constexpr (FT == FT_FP8 || !mf_compact(K)) st.wd[t * K + k] = s.u[k] >= 0 ? s.wp[k] : 0.f;
+    }
+}
+
+// The slab's operands, through the staging area `ft` (over the ring and the wave
+// buffers: every wave must be done with them, hence the barrier first).
+template <int K, int FT, int NT, int CPW>
+__device__ __forceinline__ void mf_load_slab(const UnionLds<K, FT> &L, int U, int D, const void *__restrict__ feat,
+                                             void *ft, const MfSlab &sb, const MfChunks &mc, int lane,
+                                             i16x4 (&opA)[NT][CPW][2][2], i16x8 (&opC)[NT][CPW][2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h == 1 && U <= 16) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int i = 0; i < CPW; ++i) {
+                    opA[t][i][0][1] = (i16x4){0, 0, 0, 0};
+                    opA[t][i][1][1] = (i16x4){0, 0, 0, 0};
+                    opC[t][i][1] = (i16x8){0, 0, 0, 0, 0, 0, 0, 0};
+                }
+            break;
+        }
+        __syncthreads();
+        mf_stage_half<K, FT>(L, U, D, h, sb, feat, ft);
+        __syncthreads();
+        mf_load_ops<FT, NT, CPW>(ft, U, D, h, sb, mc, lane, opA, opC);
     }
     __syncthreads();
 }
@@ -640,8 +755,10 @@ __device__ __forceinline__ void mf_setup(UnionLds<K, FT> &L, Slots<K> &s, int U,
 template <typename RB>
 __device__ __forceinline__ void ring_clear(RB &rb) {
     constexpr int n16 = (int)sizeof(RB) / 16;
-    static_assert(n16 <= kFB, "one 16-byte store per thread");
+    static_assert(n16 <= 2 * kFB, "at most two 16-byte stores per thread");
     if ((int)threadIdx.x < n16) ((u32x4 *)&rb)[threadIdx.x] = (u32x4){0u, 0u, 0u, 0u};
+    if constexpr (n16 > kFB)
+        if ((int)threadIdx.x < n16 - kFB) ((u32x4 *)&rb)[kFB + threadIdx.x] = (u32x4){0u, 0u, 0u, 0u};
 }
 
 // Scatters tile row `row`'s slots (16 pixels x K) into a cleared ring buffer, each
@@ -706,13 +823,18 @@ __device__ __forceinline__ void ring_row(RB *ring, const SlotTable<K> &st, int r
 // Map block (chunk i, channel block b) of the current row: lane (i16, g) gets
 // F[pixel i16][chunk + 8 g + 4 b + r], r < 4.  Forward and backward run this same
 // sequence, so the recomputed map is bit-identical to the stored one.
-__device__ __forceinline__ f32x4 mf_map(const i16x4 (&a)[2], const i16x4 (&wa)[2][2], int nub) {
+template <int NT, int CPW>
+__device__ __forceinline__ f32x4 mf_map(const i16x4 (&opA)[NT][CPW][2][2], int i, int b, const i16x4 (&wa)[2][2],
+                                        int nub) {
     f32x4 F = {0.f, 0.f, 0.f, 0.f};
-    F = mfma16(a[0], wa[0][0], F);
-    F = mfma16(a[0], wa[0][1], F);
-    if (nub > 1) {
-        F = mfma16(a[1], wa[1][0], F);
-        F = mfma16(a[1], wa[1][1], F);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h == 1 && nub < 2) break;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            F = mfma16(opA[t][i][b][h], wa[h][0], F);
+            F = mfma16(opA[t][i][b][h], wa[h][1], F);
+        }
     }
     return F;
 }
@@ -728,75 +850,120 @@ __device__ __forceinline__ uint32_t l1_sign2(uint32_t f, uint32_t t) {
     const float s1 = __builtin_amdgcn_fmed3f(__builtin_ldexpf(d1, 140), -1.f, 1.f);
     return pk_bf16(s0, s1);
 }
+// The same for FP32 map values (the rounded difference keeps the sign of the exact one).
+__device__ __forceinline__ float l1_sign(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
+__device__ __forceinline__ u32x4 l1_sign8(f32x4 F0, f32x4 F1, u32x4 T0, u32x4 T1) {
+    const f32x4 t0 = __builtin_bit_cast(f32x4, T0), t1 = __builtin_bit_cast(f32x4, T1);
+    u32x4 G;
+    G.x = pk_bf16(l1_sign(F0[0] - t0[0]), l1_sign(F0[1] - t0[1]));
+    G.y = pk_bf16(l1_sign(F0[2] - t0[2]), l1_sign(F0[3] - t0[3]));
+    G.z = pk_bf16(l1_sign(F1[0] - t1[0]), l1_sign(F1[1] - t1[1]));
+    G.w = pk_bf16(l1_sign(F1[2] - t1[2]), l1_sign(F1[3] - t1[3]));
+    return G;
+}
 
-template <int K, int FT>
+template <int K, int FT, int MT>
 __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int D, int U,
-                                           const void *__restrict__ feat, uint16_t *__restrict__ F,
+                                           const void *__restrict__ feat, void *__restrict__ F,
                                            UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
+    typedef MfForm<FT, MT> Fm;
+    constexpr int NT = Fm::NT, CPW = Fm::CPW;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, D, false);
-    MfRingF *ring = (MfRingF *)(dyn + mf_ring_at(D, K, false, FT == FT_FP8));
-    MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(D, K, false, FT == FT_FP8)))[wave];
-    const MfChunks mc = mf_chunks(D, wave);
-    i16x4 opA[kCPW][2][2];
-    i16x8 opC[kCPW][2];
-    mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
-    ring_start<K>(ring, st);
+    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, false);
+    MfRingF *ring = (MfRingF *)(dyn + mf_ring_at(K, false, FT == FT_FP8));
+    MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(K, false, FT == FT_FP8)))[wave];
+    mf_begin<K, FT>(L, s, U, st);
     const int nub = U > 16 ? 2 : 1;
     const int i16 = lane & 15, g = lane >> 4;
     const int rows = min(16, H - tg.ty0);
-    for (int row = 0; row < rows; ++row) {
-        i16x4 wa[2][2];
-        i16x8 wd[2];
-        ring_row<K>(ring, st, row, lane, wa, wd);
-        // the row's map values go through LDS so that every store instruction writes
-        // whole pixel rows: 16 lanes x 16 bytes per pixel, four pixels per instruction
+    const int ns = mf_nslabs(D, 4 * CPW);
+    for (int sl = 0; sl < ns; ++sl) {
+        const MfSlab sb = mf_slab(D, ns, sl);
+        const MfChunks mc = mf_chunks(sb, wave);
+        i16x4 opA[NT][CPW][2][2];
+        i16x8 opC[NT][CPW][2];
+        mf_load_slab<K, FT, NT, CPW>(L, U, D, feat, ring, sb, mc, lane, opA, opC);
+        ring_start<K>(ring, st);
+        for (int row = 0; row < rows; ++row) {
+            i16x4 wa[2][2];
+            i16x8 wd[2];
+            ring_row<K>(ring, st, row, lane, wa, wd);
+            // the row's map values go through LDS (16-byte pieces XOR-swizzled by pixel)
+            // so that every store instruction writes whole pixel rows: 16 lanes x 16
+            // bytes per pixel, four pixels per instruction
+            const long rowpix = (long)tg.view * W * H + (long)(tg.ty0 + row) * W + tg.tx0;
+            const int piece = lane & 15;
+            if constexpr (!Fm::M32) {
 #pragma unroll
-        for (int i = 0; i < kCPW; ++i) {
-            if (i >= mc.n) break;
-            const f32x4 F0 = mf_map(opA[i][0], wa, nub);
-            const f32x4 F1 = mf_map(opA[i][1], wa, nub);
-            u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
-                       pk_bf16(F1[2], F1[3])};
-            *(u32x4 *)&mw.out[i16][8 * ((4 * i + g) ^ i16)] = o;
-        }
-        wave_lds_sync();
-        const long rowpix = (long)tg.view * W * H + (long)(tg.ty0 + row) * W + tg.tx0;
-        const int piece = lane & 15;                      // 8 channels each
-        const int ch = mc.beg * 32 + 8 * piece;
+                for (int i = 0; i < CPW; ++i) {
+                    if (i >= mc.n) break;
+                    const f32x4 F0 = mf_map<NT, CPW>(opA, i, 0, wa, nub);
+                    const f32x4 F1 = mf_map<NT, CPW>(opA, i, 1, wa, nub);
+                    u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
+                               pk_bf16(F1[2], F1[3])};
+                    *(u32x4 *)&mw.out[i16][8 * ((4 * i + g) ^ i16)] = o;
+                }
+                wave_lds_sync();
+                const int ch = mc.beg * 32 + 8 * piece;   // 8 channels per piece
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int px = 4 * q + (lane >> 4);
-            if (tg.tx0 + px < W && piece < 4 * mc.n && ch < D)
-                *(u32x4 *)(F + (rowpix + px) * D + ch) = *(const u32x4 *)&mw.out[px][8 * (piece ^ px)];
+                for (int q = 0; q < 4; ++q) {
+                    const int px = 4 * q + (lane >> 4);
+                    if (tg.tx0 + px < W && piece < 4 * mc.n && ch < D)
+                        *(u32x4 *)((uint16_t *)F + (rowpix + px) * D + ch) =
+                            *(const u32x4 *)&mw.out[px][8 * (piece ^ px)];
+                }
+            } else {
+                float(*out)[64] = (float(*)[64])mw.out;   // [pixel][64 channels]
+#pragma unroll
+                for (int i = 0; i < CPW; ++i) {
+                    if (i >= mc.n) break;
+                    const f32x4 F0 = mf_map<NT, CPW>(opA, i, 0, wa, nub);
+                    const f32x4 F1 = mf_map<NT, CPW>(opA, i, 1, wa, nub);
+                    const int pc = 8 * i + 2 * g;
+                    *(f32x4 *)&out[i16][4 * (pc ^ i16)] = F0;
+                    *(f32x4 *)&out[i16][4 * ((pc + 1) ^ i16)] = F1;
+                }
+                wave_lds_sync();
+                const int ch = mc.beg * 32 + 4 * piece;   // 4 channels per piece
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int px = 4 * q + (lane >> 4);
+                    if (tg.tx0 + px < W && piece < 8 * mc.n && ch < D)
+                        *(f32x4 *)((float *)F + (rowpix + px) * D + ch) = *(const f32x4 *)&out[px][4 * (piece ^ px)];
+                }
+            }
+            wave_lds_sync();
         }
-        wave_lds_sync();
     }
 }
 
 // Backward of the MFMA path.  L1: dF holds the target map and G = l1_scale
 // sign(F - F^) is formed from the recomputed map (the products take the sign, the
-// sums the scale); otherwise dF holds dL/dF.  SF (with L1): the map is also stored
-// to Fo, so one pass renders and differentiates.
-template <int K, int FT, bool L1, bool SF, int R>
+// sums the scale); otherwise dF holds dL/dF (BF16 map only).  SF (with L1): the map
+// is also stored to Fo, so one pass renders and differentiates.
+template <int K, int FT, int MT, bool L1, bool SF, int R, bool MULTI>
 __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, int D, int U,
-                                            const void *__restrict__ feat, const uint16_t *__restrict__ dF,
+                                            const void *__restrict__ feat, const void *__restrict__ dF,
                                             float gs, float *__restrict__ dfeat, float *__restrict__ dtw,
-                                            uint16_t *__restrict__ Fo, UnionLds<K, FT> &L, Slots<K> &s,
+                                            void *__restrict__ Fo, UnionLds<K, FT> &L, Slots<K> &s,
                                             unsigned char *dyn) {
+    typedef MfForm<FT, MT> Fm;
+    constexpr int NT = Fm::NT, CPW = Fm::CPW, TW = Fm::M32 ? 2 : 1;   // target pieces per chunk
     static_assert(L1 || !SF, "the map is stored only on the L1 path");
+    static_assert(L1 || !Fm::M32, "dL/dF enters the products as BF16");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // once the operands are in registers: the waves' partial dot products, [4][256][K]
-    // (K <= 4), or those of the last two rows [2][4][16][K] and the tile's sums [256][K]
+    // the waves' partial dot products, [4][256][K] (K <= 4), or those of the last two
+    // rows [2][4][16][K] and the tile's sums [256][K]; slabs after the first add theirs
     constexpr bool RS = mf_compact(K);
     float *sred = (float *)dyn;
     float *sring = (float *)dyn;
     float *gsum = sring + 2 * 4 * 16 * K;
-    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, D, true);
-    MfRingB *ring = (MfRingB *)(dyn + mf_ring_at(D, K, true, FT == FT_FP8));
-    MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(D, K, true, FT == FT_FP8)))[wave];
-    // row r's four partials meet after the barrier of row r + 1, in a fixed order
-    auto sum_row = [&](int r) {
+    const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, true);
+    MfRingB *ring = (MfRingB *)(dyn + mf_ring_at(K, true, FT == FT_FP8));
+    MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(K, true, FT == FT_FP8)))[wave];
+    // row r's four partials meet after the barrier of row r + 1, in a fixed order (the
+    // first slab stores the sums, later slabs add theirs)
+    auto sum_row = [&](int r, bool first) {
         const int t = threadIdx.x;
         if (t < 16 * K) {
             const int i = t & 15, k = t >> 4;
@@ -804,156 +971,196 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             float v = b[(0 * 16 + i) * K + k] + b[(1 * 16 + i) * K + k];
             v += b[(2 * 16 + i) * K + k];
             v += b[(3 * 16 + i) * K + k];
-            gsum[(r * 16 + i) * K + k] = v;
+            float &d = gsum[(r * 16 + i) * K + k];
+            d = first ? v : d + v;
         }
     };
-    const MfChunks mc = mf_chunks(D, wave);
-    i16x4 opA[kCPW][2][2];
-    i16x8 opC[kCPW][2];
-    mf_setup<K, FT>(L, s, U, D, feat, dyn, st, mc, lane, opA, opC);
-    ring_start<K>(ring, st);
+    mf_begin<K, FT>(L, s, U, st);
     const int nub = U > 16 ? 2 : 1;
     const int i16 = lane & 15, g = lane >> 4;
     const int x = tg.tx0 + i16;
     const int rows = min(16, H - tg.ty0);
     const float gscale = L1 ? gs : 1.f;   // the L1 path accumulates sign(F - F^)
-
-    f32x4 acc[kCPW][2][2];   // [chunk][channel block][union block]
-#pragma unroll
-    for (int i = 0; i < kCPW; ++i)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int v = 0; v < 2; ++v) acc[i][b][v] = (f32x4){0.f, 0.f, 0.f, 0.f};
-
-    // dL/dF (or the target) of R - 1 rows ahead, in an R-deep register ring; lane
-    // (i16, g) reads channels 8g..8g+7 of each chunk for pixel i16.  The loads carry
-    // no branches: each is a uniform row base plus a per-lane offset fixed for the
-    // tile, where a lane whose pixel or channels lie outside reads the row's first
-    // element (rows past the image read the last row).  Such values meet only zero
-    // weights and zero operands; the L1 gradient is always finite, dL/dF is masked.
-    u32x4 tb[R][kCPW];
-    uint32_t loff[kCPW];
-    bool lon[kCPW];
-#pragma unroll
-    for (int i = 0; i < kCPW; ++i) {
-        const int ch = (mc.beg + i) * 32 + 8 * g;
-        lon[i] = x < W && i < mc.n && ch < D;
-        loff[i] = lon[i] ? (uint32_t)(i16 * D + ch) : 0u;
-    }
     auto row_at = [&](int row) { return ((long)tg.view * W * H + (long)(tg.ty0 + row) * W + tg.tx0) * D; };
-    auto fetch = [&](int row, u32x4 (&dst)[kCPW]) {
-        const uint16_t *base = dF + row_at(min(row, rows - 1));
-#pragma unroll
-        for (int i = 0; i < kCPW; ++i) dst[i] = *(const u32x4 *)(base + loff[i]);
-    };
-#pragma unroll
-    for (int r = 0; r < R - 1; ++r) fetch(r, tb[r]);
+    const int ns = mf_nslabs(D, 4 * CPW);
+    // one slab's row loop; the first slab is peeled out of the loop over the others.
+    // MULTI: the launch's D takes several slabs; the one-slab kernel has no loop at all,
+    // which keeps its register allocation free of the loop's live ranges
+    auto slab = [&](int sl, auto first_tag) __attribute__((always_inline)) {
+        constexpr bool FIRST = decltype(first_tag)::value;
+        const MfSlab sb = mf_slab(D, ns, sl);
+        const MfChunks mc = mf_chunks(sb, wave);
+        i16x4 opA[NT][CPW][2][2];
+        i16x8 opC[NT][CPW][2];
+        mf_load_slab<K, FT, NT, CPW>(L, U, D, feat, ring, sb, mc, lane, opA, opC);
+        ring_start<K>(ring, st);
 
-    // every wave walks all 16 rows and all kCPW chunks: rows past the image and
-    // chunks past D carry zero weights and zero operands
-#pragma unroll 1
-    for (int row0 = 0; row0 < 16; row0 += R) {
+        f32x4 acc[CPW][2][2];   // [chunk][channel block][union block]
 #pragma unroll
-        for (int h = 0; h < R; ++h) {
-            const int row = row0 + h;
-            fetch(row + R - 1, tb[(h + R - 1) % R]);
-            i16x4 wa[2][2];
-            i16x8 wd[2];
-            ring_row<K>(ring, st, row, lane, wa, wd);
-            if constexpr (RS)
-                if (row > 0) sum_row(row - 1);
-            f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        for (int i = 0; i < CPW; ++i)
 #pragma unroll
-            for (int i = 0; i < kCPW; ++i) {
-                const u32x4 T = (L1 || (row < rows && lon[i])) ? tb[h][i] : (u32x4){0u, 0u, 0u, 0u};
-                u32x4 G;
-                if constexpr (L1) {
-                    const f32x4 F0 = mf_map(opA[i][0], wa, nub);
-                    const f32x4 F1 = mf_map(opA[i][1], wa, nub);
-                    u32x4 Fp = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
-                                pk_bf16(F1[2], F1[3])};
-                    __asm__ volatile("" : "+v"(Fp.x), "+v"(Fp.y), "+v"(Fp.z), "+v"(Fp.w));
-                    // the stored map: the target's layout, so the same per-lane offsets
-                    if constexpr (SF)
-                        if (row < rows && lon[i]) *(u32x4 *)(Fo + row_at(row) + loff[i]) = Fp;
-                    G.x = l1_sign2(Fp.x, T.x);
-                    G.y = l1_sign2(Fp.y, T.y);
-                    G.z = l1_sign2(Fp.z, T.z);
-                    G.w = l1_sign2(Fp.w, T.w);
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) acc[i][b][v] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+        // dL/dF (or the target) of R - 1 rows ahead, in an R-deep register ring; lane
+        // (i16, g) reads channels 8g..8g+7 of each chunk for pixel i16 (one 16-byte
+        // piece in BF16, two in FP32).  The loads carry no branches: each is a uniform
+        // row base plus a per-lane offset fixed for the tile, where a lane whose pixel or
+        // channels lie outside reads the row's first element (rows past the image read
+        // the last row).  Such values meet only zero weights and zero operands; the L1
+        // gradient is always finite, dL/dF is masked.
+        u32x4 tb[R][CPW][TW];
+        uint32_t loff[CPW];
+        bool lon[CPW];
+#pragma unroll
+        for (int i = 0; i < CPW; ++i) {
+            const int ch = (mc.beg + i) * 32 + 8 * g;
+            lon[i] = x < W && i < mc.n && ch < D;
+            loff[i] = lon[i] ? (uint32_t)(i16 * D + ch) : 0u;
+        }
+        auto fetch = [&](int row, u32x4 (&dst)[CPW][TW]) {
+            const long base = row_at(min(row, rows - 1));
+#pragma unroll
+            for (int i = 0; i < CPW; ++i) {
+                if constexpr (Fm::M32) {
+                    const float *p = (const float *)dF + base + loff[i];
+                    dst[i][0] = *(const u32x4 *)p;
+                    dst[i][TW - 1] = *(const u32x4 *)(p + 4);
                 } else {
-                    G = T;
+                    dst[i][0] = *(const u32x4 *)((const uint16_t *)dF + base + loff[i]);
                 }
-                // keep G packed: its halves are stored as they are, not re-derived
-                __asm__ volatile("" : "+v"(G.x), "+v"(G.y), "+v"(G.z), "+v"(G.w));
-                // dot products over the chunk's 32 channels
-                sacc[0] = mfma32(opC[i][0], as_op8(G), sacc[0]);
-                if (nub > 1) sacc[1] = mfma32(opC[i][1], as_op8(G), sacc[1]);
-                // G transposed: block b row 4g + r <- this lane's channel 8g + 4b + r
-                mw.gt[i][0][4 * g + 0][i16] = (uint16_t)(G.x & 0xFFFFu);
-                mw.gt[i][0][4 * g + 1][i16] = (uint16_t)(G.x >> 16);
-                mw.gt[i][0][4 * g + 2][i16] = (uint16_t)(G.y & 0xFFFFu);
-                mw.gt[i][0][4 * g + 3][i16] = (uint16_t)(G.y >> 16);
-                mw.gt[i][1][4 * g + 0][i16] = (uint16_t)(G.z & 0xFFFFu);
-                mw.gt[i][1][4 * g + 1][i16] = (uint16_t)(G.z >> 16);
-                mw.gt[i][1][4 * g + 2][i16] = (uint16_t)(G.w & 0xFFFFu);
-                mw.gt[i][1][4 * g + 3][i16] = (uint16_t)(G.w >> 16);
             }
-            wave_lds_sync();
-            // gradient rows: B operand [hi pixels; lo pixels] x 16 block rows, i.e. G of
-            // pixels 8 (g % 2) + j
+        };
 #pragma unroll
-            for (int i = 0; i < kCPW; ++i)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const i16x8 g2 = *(const i16x8 *)&mw.gt[i][b][i16][8 * (g & 1)];
-                    acc[i][b][0] = mfma32(wd[0], g2, acc[i][b][0]);
-                    if (nub > 1) acc[i][b][1] = mfma32(wd[1], g2, acc[i][b][1]);
-                }
-            wave_lds_sync();
-            // this wave's share of S^T for the row -> its K slots, through LDS
-            float *spb = (float *)&mw;   // [kUP][16], over the G buffer
-#pragma unroll
-            for (int v = 0; v < 2; ++v)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) spb[(16 * v + 4 * g + r) * 16 + i16] = sacc[v][r];
-            wave_lds_sync();
-            const int p = row * 16 + i16;
-            for (int k = g; k < K; k += 4) {
-                const int u = st.u[p * K + k];
-                const float val = u >= 0 ? gscale * spb[u * 16 + i16] : 0.f;
-                if constexpr (RS) sring[(((row & 1) * 4 + wave) * 16 + i16) * K + k] = val;
-                else sred[(wave * kTilePix + p) * K + k] = val;
-            }
-            wave_lds_sync();
-        }
-    }
-    if constexpr (RS) {
-        __syncthreads();
-        sum_row(15);
-    }
+        for (int r = 0; r < R - 1; ++r) fetch(r, tb[r]);
 
-    // gradient rows: lane (i16, g) holds dFt[16 v + 4 g + r][chunk + blk_ch(b, i16)]
+        // every wave walks all 16 rows and all CPW chunks: rows past the image and
+        // chunks past D carry zero weights and zero operands
+#pragma unroll 1
+        for (int row0 = 0; row0 < 16; row0 += R) {
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        if (v >= nub) break;
+            for (int h = 0; h < R; ++h) {
+                const int row = row0 + h;
+                fetch(row + R - 1, tb[(h + R - 1) % R]);
+                i16x4 wa[2][2];
+                i16x8 wd[2];
+                ring_row<K>(ring, st, row, lane, wa, wd);
+                if constexpr (RS)
+                    if (row > 0) sum_row(row - 1, FIRST);
+                f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int u = 16 * v + 4 * g + r;
-            if (u >= U) continue;
-            float *dst = dfeat + (long)L.uid2[u] * D;
+                for (int i = 0; i < CPW; ++i) {
+                    u32x4 G;
+                    if constexpr (L1) {
+                        const f32x4 F0 = mf_map<NT, CPW>(opA, i, 0, wa, nub);
+                        const f32x4 F1 = mf_map<NT, CPW>(opA, i, 1, wa, nub);
+                        if constexpr (!Fm::M32) {
+                            u32x4 Fp = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
+                                        pk_bf16(F1[2], F1[3])};
+                            __asm__ volatile("" : "+v"(Fp.x), "+v"(Fp.y), "+v"(Fp.z), "+v"(Fp.w));
+                            // the stored map: the target's layout, so the same per-lane offsets
+                            if constexpr (SF)
+                                if (row < rows && lon[i]) *(u32x4 *)((uint16_t *)Fo + row_at(row) + loff[i]) = Fp;
+                            const u32x4 T = tb[h][i][0];
+                            G.x = l1_sign2(Fp.x, T.x);
+                            G.y = l1_sign2(Fp.y, T.y);
+                            G.z = l1_sign2(Fp.z, T.z);
+                            G.w = l1_sign2(Fp.w, T.w);
+                        } else {
+                            if constexpr (SF)
+                                if (row < rows && lon[i]) {
+                                    float *p = (float *)Fo + row_at(row) + loff[i];
+                                    *(f32x4 *)p = F0;
+                                    *(f32x4 *)(p + 4) = F1;
+                                }
+                            G = l1_sign8(F0, F1, tb[h][i][0], tb[h][i][TW - 1]);
+                        }
+                    } else {
+                        G = (row < rows && lon[i]) ? tb[h][i][0] : (u32x4){0u, 0u, 0u, 0u};
+                    }
+                    // keep G packed: its halves are stored as they are, not re-derived
+                    __asm__ volatile("" : "+v"(G.x), "+v"(G.y), "+v"(G.z), "+v"(G.w));
+                    // dot products over the chunk's 32 channels
 #pragma unroll
-            for (int i = 0; i < kCPW; ++i) {
-                if (i >= mc.n) break;
+                    for (int t = 0; t < NT; ++t) {
+                        sacc[0] = mfma32(opC[t][i][0], as_op8(G), sacc[0]);
+                        if (nub > 1) sacc[1] = mfma32(opC[t][i][1], as_op8(G), sacc[1]);
+                    }
+                    // G transposed: block b row 4g + r <- this lane's channel 8g + 4b + r
+                    mw.gt[i][0][4 * g + 0][i16] = (uint16_t)(G.x & 0xFFFFu);
+                    mw.gt[i][0][4 * g + 1][i16] = (uint16_t)(G.x >> 16);
+                    mw.gt[i][0][4 * g + 2][i16] = (uint16_t)(G.y & 0xFFFFu);
+                    mw.gt[i][0][4 * g + 3][i16] = (uint16_t)(G.y >> 16);
+                    mw.gt[i][1][4 * g + 0][i16] = (uint16_t)(G.z & 0xFFFFu);
+                    mw.gt[i][1][4 * g + 1][i16] = (uint16_t)(G.z >> 16);
+                    mw.gt[i][1][4 * g + 2][i16] = (uint16_t)(G.w & 0xFFFFu);
+                    mw.gt[i][1][4 * g + 3][i16] = (uint16_t)(G.w >> 16);
+                }
+                wave_lds_sync();
+                // gradient rows: B operand [hi pixels; lo pixels] x 16 block rows, i.e. G of
+                // pixels 8 (g % 2) + j
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int ch = (mc.beg + i) * 32 + blk_ch(b, i16);
-                    const float val = gscale * acc[i][b][v][r];
-                    if (ch < D && val != 0.f) unsafeAtomicAdd(dst + ch, val);
+                for (int i = 0; i < CPW; ++i)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const i16x8 g2 = *(const i16x8 *)&mw.gt[i][b][i16][8 * (g & 1)];
+                        acc[i][b][0] = mfma32(wd[0], g2, acc[i][b][0]);
+                        if (nub > 1) acc[i][b][1] = mfma32(wd[1], g2, acc[i][b][1]);
+                    }
+                wave_lds_sync();
+                // this wave's share of S^T for the row -> its K slots, through LDS; rows of
+                // 20 floats, so the four lane groups g of a store fall on distinct banks
+                float *spb = (float *)&mw;   // [kUP][kSP], over the G buffer
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) spb[(16 * v + 4 * g + r) * kSP + i16] = sacc[v][r];
+                wave_lds_sync();
+                const int p = row * 16 + i16;
+                for (int k = g; k < K; k += 4) {
+                    const int u = st.u[p * K + k];
+                    const float val = u >= 0 ? gscale * spb[u * kSP + i16] : 0.f;
+                    if constexpr (RS) {
+                        sring[(((row & 1) * 4 + wave) * 16 + i16) * K + k] = val;
+                    } else {
+                        float &d = sred[(wave * kTilePix + p) * K + k];
+                        d = FIRST ? val : d + val;
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+        if constexpr (RS) {
+            __syncthreads();
+            sum_row(15, FIRST);
+        }
+
+        // gradient rows: lane (i16, g) holds dFt[16 v + 4 g + r][chunk + blk_ch(b, i16)]
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            if (v >= nub) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int u = 16 * v + 4 * g + r;
+                if (u >= U) continue;
+                float *dst = dfeat + (long)L.uid2[u] * D;
+#pragma unroll
+                for (int i = 0; i < CPW; ++i) {
+                    if (i >= mc.n) break;
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const int ch = (mc.beg + i) * 32 + blk_ch(b, i16);
+                        const float val = gscale * acc[i][b][v][r];
+                        if (ch < D && val != 0.f) unsafeAtomicAdd(dst + ch, val);
+                    }
                 }
             }
         }
-    }
+    };
+    slab(0, std::true_type{});
+    if constexpr (MULTI)
+        for (int sl = 1; sl < ns; ++sl) slab(sl, std::false_type{});
     __syncthreads();
     // gamma_k = (g_k - sum_j w'_j g_j) / W for the thread's own pixel
     const int t = threadIdx.x;
@@ -1033,10 +1240,12 @@ __device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int
     }
 }
 
-// Tiles take the MFMA path when the storage / map formats allow it and the union fits.
-template <int K, int FT, int MT>
+// Tiles take the MFMA path when the union fits (at most kUP Gaussians), K <= 8, and,
+// in the adjoint, dL/dF is exact in BF16: a BF16 map, or the L1 loss, whose gradient
+// enters as sign(F - F^) with the scale applied to the sums.  MODE -1: the forward.
+template <int K, int FT, int MT, int MODE>
 struct MfOk {
-    static constexpr bool v = (FT == FT_BF16 || FT == FT_FP8) && MT == MT_BF16 && K <= 8;
+    static constexpr bool v = K <= 8 && (MODE < 0 || MT == MT_BF16 || MODE >= 1);
 };
 
 template <int K, int FT, int MT>
@@ -1046,8 +1255,9 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
                                                           const int *__restrict__ ids,
                                                           const float *__restrict__ tw,
                                                           void *__restrict__ F) {
-    extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ UnionLds<K, FT> L;
+    extern __shared__ __align__(16) unsigned char lds[];
+    UnionLds<K, FT> &L = *reinterpret_cast<UnionLds<K, FT> *>(lds);
+    unsigned char *dyn = lds + union_bytes<K, FT>();   // the per-pixel path's staged rows
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
@@ -1056,9 +1266,9 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
     Slots<K> sl;
     int U;
     tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
-    if constexpr (MfOk<K, FT, MT>::v) {
-        if (U <= kUP && D <= 128 * kCPW) {
-            mf_forward<K, FT>(tg, W, H, D, U, feat, (uint16_t *)F, L, sl, dyn);
+    if constexpr (MfOk<K, FT, MT, -1>::v) {
+        if (U <= kUP) {
+            mf_forward<K, FT, MT>(tg, W, H, D, U, feat, F, L, sl, lds + union_keep_bytes<K, FT>());
             return;
         }
     }
@@ -1212,7 +1422,7 @@ template <int K, int CPL>
 constexpr size_t fallback_extra() { return (size_t)4 * kPixPerWave * K * 4 + (size_t)4 * 64 * CPL * 4; }
 
 // Two blocks per CU: registers are capped at 256 per lane.
-template <int K, int FT, int MT, int MODE>
+template <int K, int FT, int MT, int MODE, bool MULTI>
 __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int views, int D, int ucap,
                                                           const void *__restrict__ feat,
                                                           const float *__restrict__ scale,
@@ -1223,8 +1433,9 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
                                                           float *__restrict__ dtw, void *__restrict__ Fo) {
     constexpr int CPL = TileCfg<K>::CPL;
     constexpr bool L1 = MODE >= 1, SF = MODE == 2;
-    extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ UnionLds<K, FT> L;
+    extern __shared__ __align__(16) unsigned char lds[];
+    UnionLds<K, FT> &L = *reinterpret_cast<UnionLds<K, FT> *>(lds);
+    unsigned char *dyn = lds + union_bytes<K, FT>();   // the per-pixel path's buffers
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
@@ -1233,11 +1444,12 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
     Slots<K> sl;
     int U;
     const int nw = tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
-    if constexpr (MfOk<K, FT, MT>::v) {
-        if (U <= kUP && D <= 128 * kCPW) {
-            const float gs = bf16_to_f32(f32_to_bf16(l1_scale));
-            mf_backward<K, FT, L1, SF, kRing + 1>(tg, W, H, D, U, feat, (const uint16_t *)dF, gs, dfeat, dtw,
-                                                  (uint16_t *)Fo, L, sl, dyn);
+    if constexpr (MfOk<K, FT, MT, MODE>::v) {
+        if (U <= kUP) {
+            // the loss scale as the unfused path's L1 gradient holds it (in the map's format)
+            const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
+            mf_backward<K, FT, MT, L1, SF, kRing + 1, MULTI>(tg, W, H, D, U, feat, dF, gs, dfeat, dtw, Fo, L, sl,
+                                                             lds + union_keep_bytes<K, FT>());
             return;
         }
     }
@@ -1283,16 +1495,19 @@ lgs_status feature_fwd_launch(int W, int H, int views, int D, const void *feat, 
                               const int *ids, const float *tw, void *F, hipStream_t st) {
     const unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
     const int rb = D * Bytes<FT>::v;
+    const size_t ub = union_bytes<K, FT>();
     // MFMA-capable kernels give the per-pixel path (unions beyond kUP) whatever rows
-    // fit the MFMA path's LDS, so that both paths keep their blocks per CU
+    // fit beside the union in the MFMA path's LDS, so that both paths keep their
+    // blocks per CU
     size_t lds;
     int ucap;
-    if (MfOk<K, FT, MT>::v) {
-        lds = mf_lds_bytes(D, K, false, FT == FT_FP8);
-        ucap = (int)(lds / rb);
+    if (MfOk<K, FT, MT, -1>::v) {
+        lds = union_keep_bytes<K, FT>() + mf_lds_bytes(K, false, FT == FT_FP8);
+        ucap = lds > ub ? (int)((lds - ub) / rb) : 0;
+        lds = std::max(lds, ub);
     } else {
         ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
-        lds = (size_t)ucap * rb;
+        lds = ub + (size_t)ucap * rb;
     }
     hipLaunchKernelGGL((feature_fwd_kernel<K, FT, MT>), dim3(grid), dim3(kFB), lds, st, W, H, views, D, ucap,
                        feat, scale, ids, tw, F);
@@ -1305,9 +1520,18 @@ lgs_status feature_bwd_launch(int W, int H, int views, int D, const void *feat, 
                               float *dtw, void *Fo, hipStream_t st) {
     const unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
     const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
-    size_t lds = kRowBudget + fallback_extra<K, TileCfg<K>::CPL>();
-    if (MfOk<K, FT, MT>::v) lds = std::max(lds, mf_lds_bytes(D, K, true, FT == FT_FP8));
-    hipLaunchKernelGGL((feature_bwd_kernel<K, FT, MT, MODE>), dim3(grid), dim3(kFB), lds, st, W, H, views, D,
+    size_t lds = union_bytes<K, FT>() + kRowBudget + fallback_extra<K, TileCfg<K>::CPL>();
+    if (MfOk<K, FT, MT, MODE>::v)
+        lds = std::max(lds, union_keep_bytes<K, FT>() + mf_lds_bytes(K, true, FT == FT_FP8));
+    // D beyond one channel slab takes the kernel with the loop over slabs
+    if constexpr (MfOk<K, FT, MT, MODE>::v) {
+        if (D > 4 * 32 * MfForm<FT, MT>::CPW) {
+            hipLaunchKernelGGL((feature_bwd_kernel<K, FT, MT, MODE, true>), dim3(grid), dim3(kFB), lds, st, W, H,
+                               views, D, ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw, Fo);
+            return check_launch("feature_render_bwd");
+        }
+    }
+    hipLaunchKernelGGL((feature_bwd_kernel<K, FT, MT, MODE, false>), dim3(grid), dim3(kFB), lds, st, W, H, views, D,
                        ucap, feat, scale, ids, tw, dF, l1_scale, dfeat, dtw, Fo);
     return check_launch("feature_render_bwd");
 }

@@ -310,7 +310,11 @@ def _synthetic_topk(rng, views, H, W, K, n, spread):
     (8, "fp8", "bf16", 1, 40, 40, 512, 30),
     (4, "fp8", "bf16", 1, 33, 35, 96, 12),
     (2, "bf16", "bf16", 1, 30, 30, 8, 10),
-    (5, "bf16", "bf16", 1, 64, 64, 512, 60)])
+    (5, "bf16", "bf16", 1, 64, 64, 512, 60),
+    # FP32 rows on the matrix cores (the forward), channel slabs of 256
+    (4, "f32", "f32", 1, 40, 53, 512, 24),
+    (8, "f32", "f32", 2, 33, 40, 768, 30),
+    (3, "fp8", "f32", 1, 36, 36, 520, 20)])
 def test_feature_kernels_on_synthetic_topk(torch, orc, K, fdt, mdt, views, H, W, D, spread):
     from paper_2602_06991_amd import render
     rng = np.random.default_rng(K * 100 + D)
@@ -426,12 +430,16 @@ def test_fused_l1_matches_unfused(torch, K, fdt, D, spread):
 
 @pytest.mark.parametrize("K,fdt,mdt,views,H,W,D,spread", [
     (4, "bf16", "bf16", 1, 40, 53, 512, 24),       # MFMA path, ragged tiles
-    (8, "fp8", "bf16", 2, 33, 40, 768, 30),        # FP8 rows, D = 768 (per-pixel path), two views
+    (8, "fp8", "bf16", 2, 33, 40, 768, 30),        # FP8 rows, D = 768 (two 384-channel slabs), two views
     (8, "bf16", "bf16", 1, 40, 53, 512, 24),       # K = 8 MFMA path (compact slot table), unions <= 32
     (8, "fp8", "bf16", 1, 40, 40, 512, 30),        # K = 8 MFMA path with FP8 row scales
     (4, "bf16", "bf16", 1, 48, 48, 256, 20000),    # unions beyond 32: per-pixel path in the same launch
     (3, "bf16", "f32", 1, 20, 36, 200, 14),        # FP32 map, channel tail
     (4, "f32", "f32", 1, 37, 53, 64, 40),          # FP32 form
+    (4, "f32", "f32", 1, 40, 53, 512, 24),         # FP32 rows as three BF16 terms: two 256-channel slabs
+    (8, "f32", "f32", 2, 33, 40, 768, 30),         # FP32 form at K = 8, D = 768: three slabs, two views
+    (8, "fp8", "f32", 1, 40, 40, 520, 30),         # FP8 rows, FP32 map, channel tail (slabs of 6, 6, 5 chunks)
+    (4, "f32", "f32", 1, 48, 48, 256, 20000),      # FP32 form, unions beyond 32 beside MFMA tiles
     (16, "bf16", "bf16", 1, 32, 32, 128, 300)])    # K beyond the MFMA path
 def test_one_pass_render_and_l1_adjoint(torch, orc, K, fdt, mdt, views, H, W, D, spread):
     """lgs_feature_render_fwd_bwd_l1 against the two separate launches (the map bit for

@@ -233,7 +233,10 @@ def test_autograd_wrapper_requantizes_an_updated_master_table(torch):
     F1 = r.render(params, cam)[3].detach()
     fresh = Renderer(K=4, feat_dtype="bf16").render(params, cam)[3].detach()
     assert torch.equal(F1, fresh)
-    assert torch.equal(F1, -F0)                # BF16 rounding is symmetric, so the map negates exactly
+    # the map follows the sign flip (the matrix-core sums need not round symmetrically,
+    # so this is to one BF16 rounding, not bit for bit)
+    assert not torch.equal(F1, F0)
+    assert torch.allclose(F1.float(), -F0.float(), rtol=1e-2, atol=1e-4)
     params["feat"] = (params["feat"].detach() * 0.5).requires_grad_(True)   # a new tensor
     F2 = r.render(params, cam)[3].detach()
     assert torch.equal(F2, Renderer(K=4, feat_dtype="bf16").render(params, cam)[3].detach())

@@ -109,10 +109,14 @@ def test_views_match_single_view_calls(torch, cfg, K, N, W, H):
     torch.cuda.synchronize()
     assert m == pairs
     assert _rel(sg["rgb"], rgb1) <= 1e-5
+    # the blend adjoint's atomics add in a different order in the batched and the per-view
+    # launches (screen-space sums agree to a few ulps, checked above at 1e-5); the
+    # projection adjoint then sums each Gaussian's views, with cancellation, so the
+    # parameter gradients are compared at 1e-4 (a missing or doubled view is O(1))
     for k in pg:
         e = _rel(pg[k], pg1[k])
         print(f"   {k}: batched vs per-view sum rel {e:.2e}", flush=True)
-        assert e <= 1e-5, (k, e)
+        assert e <= 1e-4, (k, e)
     assert torch.equal(cnt, cnt1)
     assert torch.equal(mxw, mxw1)
     print(f"   {m} pairs over {V} views; forward identical view by view", flush=True)
