@@ -629,7 +629,10 @@ def main():
     kbytes = R["bytes_both"] if R["fused"] else R["bytes_bwd"]
     achieved = kbytes / (R["kern_ms"] * 1e-3) / 1e9
     ft = {"bf16": "1, 1", "f32": "0, 0", "fp8": "2, 1"}[main_form]
-    kname = f"feature_bwd_kernel<{K}, {ft}, {mode}>"
+    # the adjoint kernel's multi-slab variant serves D above one channel slab (512
+    # channels with a BF16 map and one-term rows, 256 in the FP32 form)
+    multi = cfg["D"] > (256 if main_form == "f32" else 512)
+    kname = f"feature_bwd_kernel<{K}, {ft}, {mode}, {'true' if multi else 'false'}>"
     t = counter_traffic(kname, args.config == 2 and K == 4 and main_form == "bf16")
     traffic = None if t is None else t["total"]
     feat_ms = feature_ms(ph)
