@@ -350,29 +350,37 @@ __device__ __forceinline__ int tile_union(const TileGeom &tg, int W, int H,
     return nw;
 }
 
-// Stages the first min(U, ucap) union rows in their storage format into `rows`:
-// 16-byte pieces (8-byte for FP8 rows).
+// The per-pixel path walks the channels in passes of 64 CPL (one value per lane and
+// channel group); per pass it stages the first min(U, ucap) union rows' channels of that
+// pass, in their storage format, into `rows` = [ucap][64 CPL]: 16-byte pieces (8-byte
+// for FP8 rows).  Staging a pass rather than whole rows lets the same LDS hold 2-4x the
+// rows, so large unions rarely fall back to global reads.  All threads take part; the
+// barriers around it keep the previous pass's readers and the next pass's writers apart.
+template <int K> constexpr int pass_ch() { return 64 * TileCfg<K>::CPL; }
+
 template <int K, int FT>
-__device__ __forceinline__ void stage_rows(const UnionLds<K, FT> &L, int U, int D, int ucap,
+__device__ __forceinline__ void stage_pass(const UnionLds<K, FT> &L, int U, int D, int ucap, int pass,
                                            const void *__restrict__ feat, unsigned char *rows) {
     typedef typename std::conditional<FT == FT_FP8, u32x2, u32x4>::type piece;
-    const int t = threadIdx.x;
+    constexpr int PW = pass_ch<K>();
+    constexpr int per = (int)sizeof(piece) / Bytes<FT>::v;   // channels per piece (8, or 4 in FP32)
+    const int cb = pass * PW;
+    const int pieces = (min(D, cb + PW) - cb) / per;
     const int nr = min(U, ucap);
-    const int rb = D * Bytes<FT>::v;
-    const int chunks = rb / (int)sizeof(piece);
-    for (int q = t; q < nr * chunks; q += kFB) {
-        const int r = q / chunks, c = q - r * chunks;
-        const piece *src = (const piece *)((const unsigned char *)feat + (long)L.uid[r] * rb) + c;
-        ((piece *)(rows + (long)r * rb))[c] = *src;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nr * pieces; q += kFB) {
+        const int r = q / pieces, c = q - r * pieces;
+        const piece *src = (const piece *)((const unsigned char *)feat + ((long)L.uid[r] * D + cb) * Bytes<FT>::v) + c;
+        ((piece *)(rows + (long)r * PW * Bytes<FT>::v))[c] = *src;
     }
     __syncthreads();
 }
 
-// CPL values of union row u from LDS (staged) or global memory.
-template <int FT, int CPL>
-__device__ __forceinline__ void urow(const unsigned char *rows, int ucap, const int *uid, int u,
+// CPL values of union row u at channel c0 of pass `pass`: from LDS (staged) or global memory.
+template <int K, int FT, int CPL>
+__device__ __forceinline__ void urow(const unsigned char *rows, int ucap, const int *uid, int u, int pass,
                                      const void *__restrict__ feat, int D, int c0, float (&v)[CPL]) {
-    if (u < ucap) loadc<FT, CPL>(rows, (long)u * D + c0, v);
+    if (u < ucap) loadc<FT, CPL>(rows, (long)u * pass_ch<K>() + c0 - pass * pass_ch<K>(), v);
     else loadc<FT, CPL>(feat, (long)uid[u] * D + c0, v);
 }
 
@@ -1191,14 +1199,15 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
 // The wave's pixels.  STAGED: every union row of the tile is in LDS, so the loop
 // issues no global loads at all and its stores never have to be waited for.
 template <int K, int FT, int MT, bool STAGED>
-__device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
+__device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int D, int U, int ucap,
                                            const void *__restrict__ feat, void *__restrict__ F,
                                            const Slots<K> &sl, const UnionLds<K, FT> &L,
-                                           const unsigned char *rows, int wave, int lane) {
-    constexpr int CPL = TileCfg<K>::CPL;
-    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
+                                           unsigned char *rows, int wave, int lane) {
+    constexpr int CPL = TileCfg<K>::CPL, PW = pass_ch<K>();
+    const int passes = (D + PW - 1) / PW;
     for (int pass = 0; pass < passes; ++pass) {
-        const int c0 = pass * 64 * CPL + lane * CPL;
+        stage_pass<K, FT>(L, U, D, ucap, pass, feat, rows);
+        const int c0 = pass * PW + lane * CPL;
         const bool lane_on = c0 < D;
         for (int i = 0; i < kPixPerWave; ++i) {
             const int x = tg.tx0 + (i & 15), y = tg.ty0 + wave * 4 + (i >> 4);
@@ -1209,13 +1218,13 @@ __device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int
             for (int j = 0; j < CPL; ++j) out[j] = 0.f;
             if constexpr (STAGED) {
                 // branch-free: an empty slot reads row 0 with weight 0, a lane past D
-                // reads channel 0 and stores nothing; all K reads issue together
-                const int cc = lane_on ? c0 : 0;
+                // reads the pass's first channel and stores nothing; all K reads issue together
+                const int cc = lane_on ? lane * CPL : 0;
                 float v[K][CPL];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int u = rdlane(sl.u[k], i);
-                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * D + cc, v[k]);
+                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * PW + cc, v[k]);
                 }
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -1230,7 +1239,7 @@ __device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int
                     if (u < 0 || !lane_on) continue;
                     const float wf = rdlane(sl.wf[k], i);
                     float v[CPL];
-                    urow<FT, CPL>(rows, ucap, L.uid, u, feat, D, c0, v);
+                    urow<K, FT, CPL>(rows, ucap, L.uid, u, pass, feat, D, c0, v);
 #pragma unroll
                     for (int j = 0; j < CPL; ++j) out[j] = fmaf(wf, v[j], out[j]);
                 }
@@ -1272,9 +1281,8 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
             return;
         }
     }
-    stage_rows<K, FT>(L, U, D, ucap, feat, dyn);
-    if (U >= 1 && U <= ucap) fwd_pixels<K, FT, MT, true>(tg, W, H, D, ucap, feat, F, sl, L, dyn, wave, lane);
-    else fwd_pixels<K, FT, MT, false>(tg, W, H, D, ucap, feat, F, sl, L, dyn, wave, lane);
+    if (U >= 1 && U <= ucap) fwd_pixels<K, FT, MT, true>(tg, W, H, D, U, ucap, feat, F, sl, L, dyn, wave, lane);
+    else fwd_pixels<K, FT, MT, false>(tg, W, H, D, U, ucap, feat, F, sl, L, dyn, wave, lane);
 }
 
 // ---------------------------------------------------------------- backward
@@ -1282,18 +1290,19 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
 // The wave's pixels for one channel pass after another.  STAGED: every union row of
 // the tile is in LDS, so the only global traffic in the loop is dL/dF (or the target).
 template <int K, int FT, int MT, bool L1, bool SF, bool STAGED>
-__device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int D, int ucap,
+__device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int D, int U, int ucap,
                                            const void *__restrict__ feat, const void *__restrict__ dF,
                                            float l1_scale, float *__restrict__ dfeat, void *__restrict__ Fo,
                                            const Slots<K> &sl, const UnionLds<K, FT> &L,
-                                           const unsigned char *rows, int nw,
+                                           unsigned char *rows, int nw,
                                            float (*sdot)[K], float *xbuf, int wave, int lane) {
-    constexpr int CPL = TileCfg<K>::CPL, RA = TileCfg<K>::RA;
+    constexpr int CPL = TileCfg<K>::CPL, RA = TileCfg<K>::RA, PW = pass_ch<K>();
     const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
     constexpr int MS = MT == MT_F32 ? FT_F32 : FT_BF16;
-    const int passes = (D + 64 * CPL - 1) / (64 * CPL);
+    const int passes = (D + PW - 1) / PW;
     for (int pass = 0; pass < passes; ++pass) {
-        const int c0 = pass * 64 * CPL + lane * CPL;
+        stage_pass<K, FT>(L, U, D, ucap, pass, feat, rows);
+        const int c0 = pass * PW + lane * CPL;
         const bool lane_on = c0 < D;
         float acc[RA][CPL];
 #pragma unroll
@@ -1342,13 +1351,13 @@ __device__ __forceinline__ void bwd_pixels(const TileGeom &tg, int W, int H, int
                 if constexpr (STAGED) {
                     // branch-free (see the forward); empty slots carry weight 0 and
                     // their dot product is never used
-                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * D + (lane_on ? c0 : 0), v[k]);
+                    loadc<FT, CPL>(rows, (long)(u < 0 ? 0 : u) * PW + (lane_on ? lane * CPL : 0), v[k]);
                     if (!lane_on) {
 #pragma unroll
                         for (int j = 0; j < CPL; ++j) v[k][j] = 0.f;
                     }
                 } else if (u >= 0 && lane_on) {
-                    urow<FT, CPL>(rows, ucap, L.uid, u, feat, D, c0, v[k]);
+                    urow<K, FT, CPL>(rows, ucap, L.uid, u, pass, feat, D, c0, v[k]);
                 }
             }
             float G[CPL];
@@ -1457,14 +1466,13 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
     float(*s_dot)[kPixPerWave][K] = (float(*)[kPixPerWave][K])(dyn + kRowBudget);
     float(*s_x)[64 * CPL] = (float(*)[64 * CPL])(dyn + kRowBudget + (size_t)4 * kPixPerWave * K * 4);
     float *xbuf = s_x[wave];
-    stage_rows<K, FT>(L, U, D, ucap, feat, dyn);
 #pragma unroll
     for (int k = 0; k < K; ++k) s_dot[wave][lane][k] = 0.f;
     if (U >= 1 && U <= ucap)
-        bwd_pixels<K, FT, MT, L1, SF, true>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
+        bwd_pixels<K, FT, MT, L1, SF, true>(tg, W, H, D, U, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
                                            s_dot[wave], xbuf, wave, lane);
     else
-        bwd_pixels<K, FT, MT, L1, SF, false>(tg, W, H, D, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
+        bwd_pixels<K, FT, MT, L1, SF, false>(tg, W, H, D, U, ucap, feat, dF, l1_scale, dfeat, Fo, sl, L, dyn, nw,
                                             s_dot[wave], xbuf, wave, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1486,7 +1494,9 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
 // ---------------------------------------------------------------- launches
 
 // Staged union rows per block: as many as fit in `budget` bytes (at least 0).
-inline int pick_ucap(int D, int sf, int budget) { return budget / (D * sf); }
+// Staged union rows per block on the per-pixel path: one pass's channels of as many rows
+// as fit in `budget` bytes.
+inline int pick_ucap(int pass_channels, int sf, int budget) { return budget / (pass_channels * sf); }
 
 }  // namespace
 
@@ -1494,7 +1504,7 @@ template <int K, int FT, int MT>
 lgs_status feature_fwd_launch(int W, int H, int views, int D, const void *feat, const float *scale,
                               const int *ids, const float *tw, void *F, hipStream_t st) {
     const unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
-    const int rb = D * Bytes<FT>::v;
+    const int rb = pass_ch<K>() * Bytes<FT>::v;   // staged bytes per row and pass
     const size_t ub = union_bytes<K, FT>();
     // MFMA-capable kernels give the per-pixel path (unions beyond kUP) whatever rows
     // fit beside the union in the MFMA path's LDS, so that both paths keep their
@@ -1506,7 +1516,7 @@ lgs_status feature_fwd_launch(int W, int H, int views, int D, const void *feat, 
         ucap = lds > ub ? (int)((lds - ub) / rb) : 0;
         lds = std::max(lds, ub);
     } else {
-        ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
+        ucap = pick_ucap(pass_ch<K>(), Bytes<FT>::v, kRowBudget);
         lds = ub + (size_t)ucap * rb;
     }
     hipLaunchKernelGGL((feature_fwd_kernel<K, FT, MT>), dim3(grid), dim3(kFB), lds, st, W, H, views, D, ucap,
@@ -1519,7 +1529,7 @@ lgs_status feature_bwd_launch(int W, int H, int views, int D, const void *feat, 
                               const int *ids, const float *tw, const void *dF, float l1_scale, float *dfeat,
                               float *dtw, void *Fo, hipStream_t st) {
     const unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
-    const int ucap = pick_ucap(D, Bytes<FT>::v, kRowBudget);
+    const int ucap = pick_ucap(pass_ch<K>(), Bytes<FT>::v, kRowBudget);
     size_t lds = union_bytes<K, FT>() + kRowBudget + fallback_extra<K, TileCfg<K>::CPL>();
     if (MfOk<K, FT, MT, MODE>::v)
         lds = std::max(lds, union_keep_bytes<K, FT>() + mf_lds_bytes(K, true, FT == FT_FP8));
