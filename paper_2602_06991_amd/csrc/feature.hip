@@ -39,6 +39,19 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // One wave per row: power-of-two scale from the row's largest magnitude, then codes.
+// Eight channels per lane and step (two 16-byte loads, one 8-byte store of codes); up
+// to kQSteps steps (2048 channels) the row stays in registers between the two passes,
+// longer rows are read again.
+constexpr int kQSteps = 4;
+
+__device__ __forceinline__ uint32_t e4m3x4(f32x4 v, float inv) {
+    return f32_to_e4m3(v.x * inv) | (f32_to_e4m3(v.y * inv) << 8) | (f32_to_e4m3(v.z * inv) << 16) |
+           (f32_to_e4m3(v.w * inv) << 24);
+}
+__device__ __forceinline__ float amax4(f32x4 v, float m) {
+    return fmaxf(fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
+}
+
 __global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const float *__restrict__ src,
                                                         uint8_t *__restrict__ dst,
                                                         float *__restrict__ scale) {
@@ -46,8 +59,24 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const floa
     const int lane = threadIdx.x & 63;
     if (row >= n) return;   // whole wave leaves together
     const float *x = src + (long)row * D;
+    uint8_t *y = dst + (long)row * D;
+    const int steps = (D + 511) >> 9;
+    f32x4 v[kQSteps][2];
     float amax = 0.f;
-    for (int c = lane; c < D; c += 64) amax = fmaxf(amax, fabsf(x[c]));
+#pragma unroll
+    for (int s = 0; s < kQSteps; ++s) {
+        const int c = s * 512 + lane * 8;
+        v[s][0] = v[s][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        if (c < D) {
+            v[s][0] = *(const f32x4 *)(x + c);
+            v[s][1] = *(const f32x4 *)(x + c + 4);
+        }
+        amax = amax4(v[s][1], amax4(v[s][0], amax));
+    }
+    for (int s = kQSteps; s < steps; ++s) {
+        const int c = s * 512 + lane * 8;
+        if (c < D) amax = amax4(*(const f32x4 *)(x + c + 4), amax4(*(const f32x4 *)(x + c), amax));
+    }
     amax = wave_max(amax);
     // s = 2^floor(log2(amax / 224)): with amax = m 2^E (m in [1, 2)) the exponent is
     // E - 7, less one when m < 1.75
@@ -60,10 +89,19 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const floa
         if ((u >> 23) == 0) e = -126;      // subnormal amax
         e = max(e, -126);
     }
-    const float s = __uint_as_float((uint32_t)(127 + e) << 23);
+    const float sc = __uint_as_float((uint32_t)(127 + e) << 23);
     const float inv = __uint_as_float((uint32_t)(127 - e) << 23);
-    for (int c = lane; c < D; c += 64) dst[(long)row * D + c] = (uint8_t)f32_to_e4m3(x[c] * inv);
-    if (lane == 0) scale[row] = s;
+#pragma unroll
+    for (int s = 0; s < kQSteps; ++s) {
+        const int c = s * 512 + lane * 8;
+        if (c < D) *(u32x2 *)(y + c) = (u32x2){e4m3x4(v[s][0], inv), e4m3x4(v[s][1], inv)};
+    }
+    for (int s = kQSteps; s < steps; ++s) {
+        const int c = s * 512 + lane * 8;
+        if (c < D)
+            *(u32x2 *)(y + c) = (u32x2){e4m3x4(*(const f32x4 *)(x + c), inv), e4m3x4(*(const f32x4 *)(x + c + 4), inv)};
+    }
+    if (lane == 0) scale[row] = sc;
 }
 
 __device__ __forceinline__ float l1_sign(float d, float g) { return d > 0.f ? g : (d < 0.f ? -g : 0.f); }

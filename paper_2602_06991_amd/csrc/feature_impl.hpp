@@ -95,7 +95,8 @@ __device__ __forceinline__ void store8(void *F, long row, int D, int c, const fl
 // each accumulator to dL/df once, with coalesced atomics.
 constexpr int kFB = 256;          // threads per feature block
 constexpr int kPixPerWave = 64;
-constexpr int kUP = 32;           // union rows the MFMA path holds (two 16-row blocks)
+constexpr int kUP = 32;           // union rows of the MFMA path (two 16-row blocks)
+constexpr int kUP2 = 64;          // ... and of its large-union form (four blocks; K > 4 only)
 constexpr int kCPW = 4;           // 32-channel chunks per wave and channel slab on the MFMA path
 constexpr int kSlabCh = 4 * 32 * kCPW;   // channels of one slab: D above this takes several slabs
 constexpr int kRowBudget = 32 * 1024;   // LDS bytes for staged rows on the per-pixel path
@@ -231,9 +232,9 @@ struct UnionLds {
     int nU;
     // MFMA path (U <= kUP): the union in ascending id order, so both feature
     // kernels order the K dimension of their products identically
-    int rank[kUP];       // hash-order union index -> ascending-id index
-    int uid2[kUP];       // ascending-id index -> Gaussian id
-    float uscale2[FT == FT_FP8 ? kUP : 1];  // ascending-id index -> FP8 row scale
+    int rank[kUP2];      // hash-order union index -> ascending-id index
+    int uid2[kUP2];      // ascending-id index -> Gaussian id
+    float uscale2[FT == FT_FP8 ? kUP2 : 1];  // ascending-id index -> FP8 row scale
     // construction and per-pixel path
     int hkey[TileCfg<K>::HS];
     int hval[TileCfg<K>::HS];
@@ -462,17 +463,21 @@ __device__ __forceinline__ int blk_ch(int b, int m) { return 8 * (m >> 2) + 4 * 
 
 // Weights of one tile row in operand-ready layout, shared by the block's four waves:
 // a ring of three such buffers lets one row be read while the next is scattered and
-// the one after is cleared, with a single block barrier per row.
-// Row strides are padded (72 and 48 bytes) so that the 16 lanes of a read group,
-// which take the same offset in consecutive rows, fall on distinct banks.
-constexpr int kWA = kUP + 4;            // BF16 elements per row of wa
-constexpr int kWD = 16 + 8;             // BF16 elements per row of wd
+// the one after is cleared, with a single block barrier per row.  NUB union blocks of
+// 16 (2, or 4 for the large-union form).  Row strides are padded so that the 16 lanes
+// of a read group, which take the same offset in consecutive rows, fall on distinct
+// banks (wa: 72 or 136 bytes; wd: 48 bytes with two blocks, unpadded with four, where
+// the LDS it would take is needed more).
+template <int NUB>
 struct MfRingF {
-    uint16_t wa[2][16][kWA];            // [hi, lo][pixel of the row][union index]
+    static constexpr bool WD = false;
+    uint16_t wa[2][16][16 * NUB + 4];   // [hi, lo][pixel of the row][union index]
 };
+template <int NUB>
 struct MfRingB {
-    uint16_t wa[2][16][kWA];
-    uint16_t wd[2][kUP][kWD];           // [hi, lo][union index][pixel of the row]
+    static constexpr bool WD = true;
+    uint16_t wa[2][16][16 * NUB + 4];
+    uint16_t wd[2][16 * NUB][NUB == 2 ? 24 : 16];   // [hi, lo][union index][pixel of the row]
 };
 // Per-wave LDS: the forward's map row for the wave's channels (16-byte columns
 // XOR-swizzled by pixel, so neither the writes nor the reads collide on banks), the
@@ -483,10 +488,17 @@ struct MfWaveF {
 struct MfWaveB {
     uint16_t gt[kCPW][2][16][16];       // [chunk][channel block][block row][pixel]
 };
-static_assert(sizeof(MfRingF) % 16 == 0 && sizeof(MfRingB) % 16 == 0, "ring buffers in 16-byte pieces");
+static_assert(sizeof(MfRingF<2>) % 16 == 0 && sizeof(MfRingB<2>) % 16 == 0 && sizeof(MfRingF<4>) % 16 == 0 &&
+                  sizeof(MfRingB<4>) % 16 == 0,
+              "ring buffers in 16-byte pieces");
 static_assert(sizeof(MfWaveF) == 4096 && sizeof(MfWaveB) == 4096, "wave buffer layout");
-constexpr int kSP = 20;                 // row stride (floats) of the backward's S^T rows
-static_assert(kUP * kSP * 4 <= (int)sizeof(MfWaveB), "S^T rows fit the wave buffer");
+// row stride (floats) of the backward's S^T rows: 20 with two union blocks, so the four
+// lane groups of a store fall on distinct banks; 16 with four, to fit the wave buffer
+template <int NUB> constexpr int sp_stride() { return NUB == 2 ? 20 : 16; }
+static_assert(kUP * sp_stride<2>() * 4 <= (int)sizeof(MfWaveB) && kUP2 * sp_stride<4>() * 4 <= (int)sizeof(MfWaveB),
+              "S^T rows fit the wave buffer");
+// union blocks of the largest MFMA form a kernel of this K runs
+__host__ __device__ constexpr int mf_nub_max(int K) { return K > 4 ? 4 : 2; }
 
 // Dynamic LDS of the MFMA path.  Backward: the waves' partial dot products first,
 // then the slot table (per pixel and slot: union index, Wa weight, Wd weight), the
@@ -512,15 +524,19 @@ __host__ __device__ inline size_t mf_slots_at(int K, bool bwd) { return bwd ? mf
 __host__ __device__ inline size_t mf_ring_at(int K, bool bwd, bool fp8) {
     return mf_slots_at(K, bwd) + mf_slots_bytes(K, fp8);
 }
+__host__ __device__ inline size_t mf_ring_bytes(int K, bool bwd) {
+    return mf_nub_max(K) == 4 ? (bwd ? sizeof(MfRingB<4>) : sizeof(MfRingF<4>))
+                              : (bwd ? sizeof(MfRingB<2>) : sizeof(MfRingF<2>));
+}
 __host__ __device__ inline size_t mf_waves_at(int K, bool bwd, bool fp8) {
-    return mf_ring_at(K, bwd, fp8) + 3 * (bwd ? sizeof(MfRingB) : sizeof(MfRingF));
+    return mf_ring_at(K, bwd, fp8) + 3 * mf_ring_bytes(K, bwd);
 }
 __host__ __device__ inline size_t mf_lds_bytes(int K, bool bwd, bool fp8) {
     return mf_waves_at(K, bwd, fp8) + 4 * (bwd ? sizeof(MfWaveB) : sizeof(MfWaveF));
 }
 // the staged rows of a slab fit over the ring and the wave buffers
-static_assert(3 * sizeof(MfRingF) + 4 * sizeof(MfWaveF) >= 16 * kSlabCh * 2, "staging area (forward)");
-static_assert(3 * sizeof(MfRingB) + 4 * sizeof(MfWaveB) >= 16 * kSlabCh * 2, "staging area (backward)");
+static_assert(3 * sizeof(MfRingF<2>) + 4 * sizeof(MfWaveF) >= 16 * kSlabCh * 2, "staging area (forward)");
+static_assert(3 * sizeof(MfRingB<2>) + 4 * sizeof(MfWaveB) >= 16 * kSlabCh * 2, "staging area (backward)");
 
 template <int K>
 struct SlotTable {
@@ -543,11 +559,12 @@ __device__ __forceinline__ SlotTable<K> slot_table(unsigned char *dyn, bool bwd)
     return st;
 }
 
-// Prologue of the MFMA path (all 256 threads; U <= kUP): orders the union by id.
+// Prologue of the MFMA path (all 256 threads; U <= kUP2): orders the union by id.
 template <int K, int FT>
 __device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int U) {
     const int t = threadIdx.x;
-    if (t < 128) {   // four threads per member (waves 0 and 1 whole, so the shuffles see every lane)
+    static_assert(4 * kUP2 <= kFB, "four threads per member");
+    {   // four threads per member (whole waves, so the shuffles see every lane)
         const int u = t >> 2, q = t & 3;
         const int g = u < U ? L.uid[u] : 0;
         int r = 0;
@@ -571,12 +588,14 @@ __device__ __forceinline__ void mf_prologue(UnionLds<K, FT> &L, Slots<K> &s, int
 // 2^-100; below, the absolute error is under 2^-133), each multiplied in turn.  With
 // three terms or an FP32 map a wave holds two 32-channel chunks per slab instead of
 // four, so the operands and the FP32 target rows fit the register budget.
-template <int FT, int MT>
+template <int FT, int MT, int NUB = 2>
 struct MfForm {
     static constexpr int NT = FT == FT_F32 ? 3 : 1;        // BF16 terms per stored value
     static constexpr bool M32 = MT == MT_F32;              // FP32 map (and target)
-    static constexpr int CPW = (NT == 3 || M32) ? 2 : 4;   // chunks per wave and slab
-    static_assert(CPW <= kCPW, "wave buffers sized for kCPW chunks");
+    // chunks per wave and slab; the large-union form (four union blocks, rare tiles)
+    // holds one, so that its registers stay well below the common form's
+    static constexpr int CPW = NUB == 4 ? 1 : ((NT == 3 || M32) ? 2 : 4);
+    static_assert(CPW >= 1 && CPW <= kCPW, "wave buffers sized for kCPW chunks");
 };
 
 // Channel slabs: the ceil(D / 32) chunks are split into ceil(chunks / (4 CPW)) slabs
@@ -658,10 +677,10 @@ __device__ __forceinline__ void split3(float v, short &t0, short &t1, short &t2)
 // outside the union and past D; term t of NT:
 //   opA[t][i][b][h]: lane (i16, g) = Ft[16 h + 4 g + j][chunk + blk_ch(b, i16)], j < 4
 //   opC[t][i][h]:    lane (i16, g) = Ft[16 h + i16][chunk + 8 g + j], j < 8
-template <int FT, int NT, int CPW>
+template <int FT, int NT, int CPW, int NUB>
 __device__ __forceinline__ void mf_load_ops(const void *ft, int U, int D, int h, const MfSlab &sb,
-                                            const MfChunks &mc, int lane, i16x4 (&opA)[NT][CPW][2][2],
-                                            i16x8 (&opC)[NT][CPW][2]) {
+                                            const MfChunks &mc, int lane, i16x4 (&opA)[NT][CPW][2][NUB],
+                                            i16x8 (&opC)[NT][CPW][NUB]) {
     const int i16 = lane & 15, g = lane >> 4;
     const int nr = U - 16 * h;   // staged rows of this block
     const int cb = sb.c0 * 32, ds = sb.n * 32;
@@ -733,28 +752,29 @@ __device__ __forceinline__ void mf_begin(UnionLds<K, FT> &L, Slots<K> &s, int U,
 }
 
 // The slab's operands, through the staging area `ft` (over the ring and the wave
-// buffers: every wave must be done with them, hence the barrier first).
-template <int K, int FT, int NT, int CPW>
+// buffers: every wave must be done with them, hence the barrier first).  Union blocks
+// past U get zero operands.
+template <int K, int FT, int NT, int CPW, int NUB>
 __device__ __forceinline__ void mf_load_slab(const UnionLds<K, FT> &L, int U, int D, const void *__restrict__ feat,
                                              void *ft, const MfSlab &sb, const MfChunks &mc, int lane,
-                                             i16x4 (&opA)[NT][CPW][2][2], i16x8 (&opC)[NT][CPW][2]) {
+                                             i16x4 (&opA)[NT][CPW][2][NUB], i16x8 (&opC)[NT][CPW][NUB]) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h == 1 && U <= 16) {
+    for (int h = 0; h < NUB; ++h) {
+        if (h > 0 && 16 * h >= U) {   // uniform over the block
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
                 for (int i = 0; i < CPW; ++i) {
-                    opA[t][i][0][1] = (i16x4){0, 0, 0, 0};
-                    opA[t][i][1][1] = (i16x4){0, 0, 0, 0};
-                    opC[t][i][1] = (i16x8){0, 0, 0, 0, 0, 0, 0, 0};
+                    opA[t][i][0][h] = (i16x4){0, 0, 0, 0};
+                    opA[t][i][1][h] = (i16x4){0, 0, 0, 0};
+                    opC[t][i][h] = (i16x8){0, 0, 0, 0, 0, 0, 0, 0};
                 }
-            break;
+            continue;
         }
         __syncthreads();
         mf_stage_half<K, FT>(L, U, D, h, sb, feat, ft);
         __syncthreads();
-        mf_load_ops<FT, NT, CPW>(ft, U, D, h, sb, mc, lane, opA, opC);
+        mf_load_ops<FT, NT, CPW, NUB>(ft, U, D, h, sb, mc, lane, opA, opC);
     }
     __syncthreads();
 }
@@ -763,17 +783,17 @@ __device__ __forceinline__ void mf_load_slab(const UnionLds<K, FT> &L, int U, in
 template <typename RB>
 __device__ __forceinline__ void ring_clear(RB &rb) {
     constexpr int n16 = (int)sizeof(RB) / 16;
-    static_assert(n16 <= 2 * kFB, "at most two 16-byte stores per thread");
-    if ((int)threadIdx.x < n16) ((u32x4 *)&rb)[threadIdx.x] = (u32x4){0u, 0u, 0u, 0u};
-    if constexpr (n16 > kFB)
-        if ((int)threadIdx.x < n16 - kFB) ((u32x4 *)&rb)[kFB + threadIdx.x] = (u32x4){0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < (n16 + kFB - 1) / kFB; ++q) {
+        const int i = q * kFB + (int)threadIdx.x;
+        if (i < n16) ((u32x4 *)&rb)[i] = (u32x4){0u, 0u, 0u, 0u};
+    }
 }
 
 // Scatters tile row `row`'s slots (16 pixels x K) into a cleared ring buffer, each
 // FP32 weight as hi = RNE(w) and lo = RNE(w - hi).
 template <int K, typename RB>
 __device__ __forceinline__ void ring_scatter(int row, const SlotTable<K> &st, RB &rb) {
-    constexpr bool WD = sizeof(RB) == sizeof(MfRingB);
     const int t = threadIdx.x;
     if (t < 16 * K) {
         const int x = t & 15, k = t >> 4, p = row * 16 + x;
@@ -782,28 +802,26 @@ __device__ __forceinline__ void ring_scatter(int row, const SlotTable<K> &st, RB
             const float a = st.wa[p * K + k];
             rb.wa[0][x][u] = bits_bf16(a);
             rb.wa[1][x][u] = bits_bf16(a - bf16_to_f32(bits_bf16(a)));
-            if constexpr (WD) {
+            if constexpr (RB::WD) {
                 const float d = st.wd[p * K + k];
-                MfRingB &rbb = reinterpret_cast<MfRingB &>(rb);
-                rbb.wd[0][u][x] = bits_bf16(d);
-                rbb.wd[1][u][x] = bits_bf16(d - bf16_to_f32(bits_bf16(d)));
+                rb.wd[0][u][x] = bits_bf16(d);
+                rb.wd[1][u][x] = bits_bf16(d - bf16_to_f32(bits_bf16(d)));
             }
         }
     }
 }
 
-// Operands of one row from its ring buffer:
+// Operands of one row from its ring buffer, for union blocks s < NUB:
 //   wa[s][h]: lane (i16, g) = Wa_h[pixel i16][16 s + 4 g + j], j < 4     (16x16x16 B)
 //   wd[s]:    lane (i16, g) = Wd_{g/2}[pixel 8 (g % 2) + j][16 s + i16]    (16x16x32 A)
-template <typename RB>
-__device__ __forceinline__ void ring_read(const RB &rb, int lane, i16x4 (&wa)[2][2], i16x8 (&wd)[2]) {
+template <int NUB, typename RB>
+__device__ __forceinline__ void ring_read(const RB &rb, int lane, i16x4 (&wa)[NUB][2], i16x8 (&wd)[NUB]) {
     const int i16 = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NUB; ++s) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) wa[s][h] = *(const i16x4 *)&rb.wa[h][i16][16 * s + 4 * g];
-        if constexpr (sizeof(RB) == sizeof(MfRingB))
-            wd[s] = *(const i16x8 *)&reinterpret_cast<const MfRingB &>(rb).wd[g >> 1][16 * s + i16][8 * (g & 1)];
+        if constexpr (RB::WD) wd[s] = *(const i16x8 *)&rb.wd[g >> 1][16 * s + i16][8 * (g & 1)];
     }
 }
 
@@ -818,12 +836,12 @@ __device__ __forceinline__ void ring_start(RB *ring, const SlotTable<K> &st) {
     __syncthreads();
     ring_scatter<K>(0, st, ring[0]);
 }
-template <int K, typename RB>
-__device__ __forceinline__ void ring_row(RB *ring, const SlotTable<K> &st, int row, int lane, i16x4 (&wa)[2][2],
-                                         i16x8 (&wd)[2]) {
+template <int K, int NUB, typename RB>
+__device__ __forceinline__ void ring_row(RB *ring, const SlotTable<K> &st, int row, int lane, i16x4 (&wa)[NUB][2],
+                                         i16x8 (&wd)[NUB]) {
     __syncthreads();
     const int b = row % 3;
-    ring_read(ring[b], lane, wa, wd);
+    ring_read<NUB>(ring[b], lane, wa, wd);
     if (row + 1 < 16) ring_scatter<K>(row + 1, st, ring[b == 2 ? 0 : b + 1]);
     ring_clear(ring[b == 0 ? 2 : b - 1]);
 }
@@ -831,13 +849,13 @@ __device__ __forceinline__ void ring_row(RB *ring, const SlotTable<K> &st, int r
 // Map block (chunk i, channel block b) of the current row: lane (i16, g) gets
 // F[pixel i16][chunk + 8 g + 4 b + r], r < 4.  Forward and backward run this same
 // sequence, so the recomputed map is bit-identical to the stored one.
-template <int NT, int CPW>
-__device__ __forceinline__ f32x4 mf_map(const i16x4 (&opA)[NT][CPW][2][2], int i, int b, const i16x4 (&wa)[2][2],
-                                        int nub) {
+template <int NT, int CPW, int NUB>
+__device__ __forceinline__ f32x4 mf_map(const i16x4 (&opA)[NT][CPW][2][NUB], int i, int b,
+                                        const i16x4 (&wa)[NUB][2], int nub) {
     f32x4 F = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h == 1 && nub < 2) break;
+    for (int h = 0; h < NUB; ++h) {
+        if (h > 0 && h >= nub) break;   // block 0 unconditionally (straight-line MFMAs)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             F = mfma16(opA[t][i][b][h], wa[h][0], F);
@@ -870,32 +888,33 @@ __device__ __forceinline__ u32x4 l1_sign8(f32x4 F0, f32x4 F1, u32x4 T0, u32x4 T1
     return G;
 }
 
-template <int K, int FT, int MT>
+template <int K, int FT, int MT, int NUB>
 __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int D, int U,
                                            const void *__restrict__ feat, void *__restrict__ F,
                                            UnionLds<K, FT> &L, Slots<K> &s, unsigned char *dyn) {
-    typedef MfForm<FT, MT> Fm;
+    typedef MfForm<FT, MT, NUB> Fm;
     constexpr int NT = Fm::NT, CPW = Fm::CPW;
+    static_assert(NUB <= mf_nub_max(K), "the LDS layout holds this form's ring");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, false);
-    MfRingF *ring = (MfRingF *)(dyn + mf_ring_at(K, false, FT == FT_FP8));
+    MfRingF<NUB> *ring = (MfRingF<NUB> *)(dyn + mf_ring_at(K, false, FT == FT_FP8));
     MfWaveF &mw = ((MfWaveF *)(dyn + mf_waves_at(K, false, FT == FT_FP8)))[wave];
     mf_begin<K, FT>(L, s, U, st);
-    const int nub = U > 16 ? 2 : 1;
+    const int nub = (U + 15) >> 4;   // union blocks in use
     const int i16 = lane & 15, g = lane >> 4;
     const int rows = min(16, H - tg.ty0);
     const int ns = mf_nslabs(D, 4 * CPW);
     for (int sl = 0; sl < ns; ++sl) {
         const MfSlab sb = mf_slab(D, ns, sl);
         const MfChunks mc = mf_chunks(sb, wave);
-        i16x4 opA[NT][CPW][2][2];
-        i16x8 opC[NT][CPW][2];
-        mf_load_slab<K, FT, NT, CPW>(L, U, D, feat, ring, sb, mc, lane, opA, opC);
+        i16x4 opA[NT][CPW][2][NUB];
+        i16x8 opC[NT][CPW][NUB];
+        mf_load_slab<K, FT, NT, CPW, NUB>(L, U, D, feat, ring, sb, mc, lane, opA, opC);
         ring_start<K>(ring, st);
         for (int row = 0; row < rows; ++row) {
-            i16x4 wa[2][2];
-            i16x8 wd[2];
-            ring_row<K>(ring, st, row, lane, wa, wd);
+            i16x4 wa[NUB][2];
+            i16x8 wd[NUB];
+            ring_row<K, NUB>(ring, st, row, lane, wa, wd);
             // the row's map values go through LDS (16-byte pieces XOR-swizzled by pixel)
             // so that every store instruction writes whole pixel rows: 16 lanes x 16
             // bytes per pixel, four pixels per instruction
@@ -905,8 +924,8 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
 #pragma unroll
                 for (int i = 0; i < CPW; ++i) {
                     if (i >= mc.n) break;
-                    const f32x4 F0 = mf_map<NT, CPW>(opA, i, 0, wa, nub);
-                    const f32x4 F1 = mf_map<NT, CPW>(opA, i, 1, wa, nub);
+                    const f32x4 F0 = mf_map<NT, CPW, NUB>(opA, i, 0, wa, nub);
+                    const f32x4 F1 = mf_map<NT, CPW, NUB>(opA, i, 1, wa, nub);
                     u32x4 o = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
                                pk_bf16(F1[2], F1[3])};
                     *(u32x4 *)&mw.out[i16][8 * ((4 * i + g) ^ i16)] = o;
@@ -925,8 +944,8 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
 #pragma unroll
                 for (int i = 0; i < CPW; ++i) {
                     if (i >= mc.n) break;
-                    const f32x4 F0 = mf_map<NT, CPW>(opA, i, 0, wa, nub);
-                    const f32x4 F1 = mf_map<NT, CPW>(opA, i, 1, wa, nub);
+                    const f32x4 F0 = mf_map<NT, CPW, NUB>(opA, i, 0, wa, nub);
+                    const f32x4 F1 = mf_map<NT, CPW, NUB>(opA, i, 1, wa, nub);
                     const int pc = 8 * i + 2 * g;
                     *(f32x4 *)&out[i16][4 * (pc ^ i16)] = F0;
                     *(f32x4 *)&out[i16][4 * ((pc + 1) ^ i16)] = F1;
@@ -949,14 +968,16 @@ __device__ __forceinline__ void mf_forward(const TileGeom &tg, int W, int H, int
 // sign(F - F^) is formed from the recomputed map (the products take the sign, the
 // sums the scale); otherwise dF holds dL/dF (BF16 map only).  SF (with L1): the map
 // is also stored to Fo, so one pass renders and differentiates.
-template <int K, int FT, int MT, bool L1, bool SF, int R, bool MULTI>
+template <int K, int FT, int MT, int NUB, bool L1, bool SF, int R, bool MULTI>
 __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, int D, int U,
                                             const void *__restrict__ feat, const void *__restrict__ dF,
                                             float gs, float *__restrict__ dfeat, float *__restrict__ dtw,
                                             void *__restrict__ Fo, UnionLds<K, FT> &L, Slots<K> &s,
                                             unsigned char *dyn) {
-    typedef MfForm<FT, MT> Fm;
+    typedef MfForm<FT, MT, NUB> Fm;
     constexpr int NT = Fm::NT, CPW = Fm::CPW, TW = Fm::M32 ? 2 : 1;   // target pieces per chunk
+    constexpr int SP = sp_stride<NUB>();
+    static_assert(NUB <= mf_nub_max(K), "the LDS layout holds this form's ring");
     static_assert(L1 || !SF, "the map is stored only on the L1 path");
     static_assert(L1 || !Fm::M32, "dL/dF enters the products as BF16");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -967,7 +988,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
     float *sring = (float *)dyn;
     float *gsum = sring + 2 * 4 * 16 * K;
     const SlotTable<K> st = slot_table<K, FT == FT_FP8>(dyn, true);
-    MfRingB *ring = (MfRingB *)(dyn + mf_ring_at(K, true, FT == FT_FP8));
+    MfRingB<NUB> *ring = (MfRingB<NUB> *)(dyn + mf_ring_at(K, true, FT == FT_FP8));
     MfWaveB &mw = ((MfWaveB *)(dyn + mf_waves_at(K, true, FT == FT_FP8)))[wave];
     // row r's four partials meet after the barrier of row r + 1, in a fixed order (the
     // first slab stores the sums, later slabs add theirs)
@@ -984,7 +1005,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
         }
     };
     mf_begin<K, FT>(L, s, U, st);
-    const int nub = U > 16 ? 2 : 1;
+    const int nub = (U + 15) >> 4;   // union blocks in use
     const int i16 = lane & 15, g = lane >> 4;
     const int x = tg.tx0 + i16;
     const int rows = min(16, H - tg.ty0);
@@ -998,18 +1019,18 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
         constexpr bool FIRST = decltype(first_tag)::value;
         const MfSlab sb = mf_slab(D, ns, sl);
         const MfChunks mc = mf_chunks(sb, wave);
-        i16x4 opA[NT][CPW][2][2];
-        i16x8 opC[NT][CPW][2];
-        mf_load_slab<K, FT, NT, CPW>(L, U, D, feat, ring, sb, mc, lane, opA, opC);
+        i16x4 opA[NT][CPW][2][NUB];
+        i16x8 opC[NT][CPW][NUB];
+        mf_load_slab<K, FT, NT, CPW, NUB>(L, U, D, feat, ring, sb, mc, lane, opA, opC);
         ring_start<K>(ring, st);
 
-        f32x4 acc[CPW][2][2];   // [chunk][channel block][union block]
+        f32x4 acc[CPW][2][NUB];   // [chunk][channel block][union block]
 #pragma unroll
         for (int i = 0; i < CPW; ++i)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int v = 0; v < 2; ++v) acc[i][b][v] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                for (int v = 0; v < NUB; ++v) acc[i][b][v] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
         // dL/dF (or the target) of R - 1 rows ahead, in an R-deep register ring; lane
         // (i16, g) reads channels 8g..8g+7 of each chunk for pixel i16 (one 16-byte
@@ -1051,18 +1072,20 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             for (int h = 0; h < R; ++h) {
                 const int row = row0 + h;
                 fetch(row + R - 1, tb[(h + R - 1) % R]);
-                i16x4 wa[2][2];
-                i16x8 wd[2];
-                ring_row<K>(ring, st, row, lane, wa, wd);
+                i16x4 wa[NUB][2];
+                i16x8 wd[NUB];
+                ring_row<K, NUB>(ring, st, row, lane, wa, wd);
                 if constexpr (RS)
                     if (row > 0) sum_row(row - 1, FIRST);
-                f32x4 sacc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                f32x4 sacc[NUB];
+#pragma unroll
+                for (int v = 0; v < NUB; ++v) sacc[v] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int i = 0; i < CPW; ++i) {
                     u32x4 G;
                     if constexpr (L1) {
-                        const f32x4 F0 = mf_map<NT, CPW>(opA, i, 0, wa, nub);
-                        const f32x4 F1 = mf_map<NT, CPW>(opA, i, 1, wa, nub);
+                        const f32x4 F0 = mf_map<NT, CPW, NUB>(opA, i, 0, wa, nub);
+                        const f32x4 F1 = mf_map<NT, CPW, NUB>(opA, i, 1, wa, nub);
                         if constexpr (!Fm::M32) {
                             u32x4 Fp = {pk_bf16(F0[0], F0[1]), pk_bf16(F0[2], F0[3]), pk_bf16(F1[0], F1[1]),
                                         pk_bf16(F1[2], F1[3])};
@@ -1091,9 +1114,10 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
                     __asm__ volatile("" : "+v"(G.x), "+v"(G.y), "+v"(G.z), "+v"(G.w));
                     // dot products over the chunk's 32 channels
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        sacc[0] = mfma32(opC[t][i][0], as_op8(G), sacc[0]);
-                        if (nub > 1) sacc[1] = mfma32(opC[t][i][1], as_op8(G), sacc[1]);
+                    for (int v = 0; v < NUB; ++v) {
+                        if (v > 0 && v >= nub) break;
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) sacc[v] = mfma32(opC[t][i][v], as_op8(G), sacc[v]);
                     }
                     // G transposed: block b row 4g + r <- this lane's channel 8g + 4b + r
                     mw.gt[i][0][4 * g + 0][i16] = (uint16_t)(G.x & 0xFFFFu);
@@ -1113,22 +1137,25 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
 #pragma unroll
                     for (int b = 0; b < 2; ++b) {
                         const i16x8 g2 = *(const i16x8 *)&mw.gt[i][b][i16][8 * (g & 1)];
-                        acc[i][b][0] = mfma32(wd[0], g2, acc[i][b][0]);
-                        if (nub > 1) acc[i][b][1] = mfma32(wd[1], g2, acc[i][b][1]);
+#pragma unroll
+                        for (int v = 0; v < NUB; ++v) {
+                            if (v > 0 && v >= nub) break;
+                            acc[i][b][v] = mfma32(wd[v], g2, acc[i][b][v]);
+                        }
                     }
                 wave_lds_sync();
-                // this wave's share of S^T for the row -> its K slots, through LDS; rows of
-                // 20 floats, so the four lane groups g of a store fall on distinct banks
-                float *spb = (float *)&mw;   // [kUP][kSP], over the G buffer
+                // this wave's share of S^T for the row -> its K slots, through LDS (rows of
+                // SP floats)
+                float *spb = (float *)&mw;   // [16 NUB][SP], over the G buffer
 #pragma unroll
-                for (int v = 0; v < 2; ++v)
+                for (int v = 0; v < NUB; ++v)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) spb[(16 * v + 4 * g + r) * kSP + i16] = sacc[v][r];
+                    for (int r = 0; r < 4; ++r) spb[(16 * v + 4 * g + r) * SP + i16] = sacc[v][r];
                 wave_lds_sync();
                 const int p = row * 16 + i16;
                 for (int k = g; k < K; k += 4) {
                     const int u = st.u[p * K + k];
-                    const float val = u >= 0 ? gscale * spb[u * kSP + i16] : 0.f;
+                    const float val = u >= 0 ? gscale * spb[u * SP + i16] : 0.f;
                     if constexpr (RS) {
                         sring[(((row & 1) * 4 + wave) * 16 + i16) * K + k] = val;
                     } else {
@@ -1146,7 +1173,7 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
 
         // gradient rows: lane (i16, g) holds dFt[16 v + 4 g + r][chunk + blk_ch(b, i16)]
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < NUB; ++v) {
             if (v >= nub) break;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -1249,7 +1276,7 @@ __device__ __forceinline__ void fwd_pixels(const TileGeom &tg, int W, int H, int
     }
 }
 
-// Tiles take the MFMA path when the union fits (at most kUP Gaussians), K <= 8, and,
+// Tiles take the MFMA path when the union fits (at most kUP Gaussians, or kUP2 for K > 4), K <= 8, and,
 // in the adjoint, dL/dF is exact in BF16: a BF16 map, or the L1 loss, whose gradient
 // enters as sign(F - F^) with the scale applied to the sums.  MODE -1: the forward.
 template <int K, int FT, int MT, int MODE>
@@ -1277,8 +1304,14 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
     tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
     if constexpr (MfOk<K, FT, MT, -1>::v) {
         if (U <= kUP) {
-            mf_forward<K, FT, MT>(tg, W, H, D, U, feat, F, L, sl, lds + union_keep_bytes<K, FT>());
+            mf_forward<K, FT, MT, 2>(tg, W, H, D, U, feat, F, L, sl, lds + union_keep_bytes<K, FT>());
             return;
+        }
+        if constexpr (mf_nub_max(K) == 4) {
+            if (U <= kUP2) {
+                mf_forward<K, FT, MT, 4>(tg, W, H, D, U, feat, F, L, sl, lds + union_keep_bytes<K, FT>());
+                return;
+            }
         }
     }
     if (U >= 1 && U <= ucap) fwd_pixels<K, FT, MT, true>(tg, W, H, D, U, ucap, feat, F, sl, L, dyn, wave, lane);
@@ -1454,12 +1487,24 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
     int U;
     const int nw = tile_union<K, FT>(tg, W, H, ids, tw, scale, L, sl, U);
     if constexpr (MfOk<K, FT, MT, MODE>::v) {
+        // gs: the loss scale as the unfused path's L1 gradient holds it (in the map's
+        // format); formed inside each branch, where it costs no register across the union
+        // build (formed before the branches, the one-pass kernel spilled)
         if (U <= kUP) {
-            // the loss scale as the unfused path's L1 gradient holds it (in the map's format)
             const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
-            mf_backward<K, FT, MT, L1, SF, kRing + 1, MULTI>(tg, W, H, D, U, feat, dF, gs, dfeat, dtw, Fo, L, sl,
-                                                             lds + union_keep_bytes<K, FT>());
+            mf_backward<K, FT, MT, 2, L1, SF, kRing + 1, MULTI>(tg, W, H, D, U, feat, dF, gs, dfeat, dtw, Fo, L,
+                                                                sl, lds + union_keep_bytes<K, FT>());
             return;
+        }
+        // unions of 33..64 (K > 4): four union blocks, one chunk per wave and slab, so
+        // D takes several slabs and the loop over them
+        if constexpr (mf_nub_max(K) == 4) {
+            if (U <= kUP2) {
+                const float gs = MT == MT_F32 ? l1_scale : bf16_to_f32(f32_to_bf16(l1_scale));
+                mf_backward<K, FT, MT, 4, L1, SF, kRing + 1, true>(tg, W, H, D, U, feat, dF, gs, dfeat, dtw, Fo,
+                                                                   L, sl, lds + union_keep_bytes<K, FT>());
+                return;
+            }
         }
     }
     // per-pixel path: staged rows, then the dot products and the transpose buffers

@@ -31,7 +31,8 @@ namespace {
 typedef short v_i16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 v_bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kVB = 32;        // Gaussians per batch (the MFMA K of the map product)
+constexpr int kVB = 32;        // Gaussians per batch of the forward (the MFMA K of the map product)
+constexpr int kVBB = 16;       // Gaussians per batch of the adjoint (one MFMA row block; its LDS fits two blocks per CU)
 constexpr int kVC = 128;       // channels per block
 constexpr int kVT = 256;       // threads per block
 constexpr int kWS = kVB + 8;   // LDS row stride (BF16) of the weight rows, padded against bank conflicts
@@ -68,11 +69,12 @@ struct VanArgs {
 // B operand), else into ft[row][kFS].
 constexpr int kTS = kVB + 8;   // LDS row stride (BF16) of the channel-major rows
 
-template <int FT, bool TRANS>
+template <int FT, bool TRANS, int NR = kVB>
 __device__ __forceinline__ void stage_rows32(const VanArgs &a, const void *__restrict__ feat, const int *s_id, int cnt,
                                              int c0, uint16_t *ft) {
     const int t = threadIdx.x;
     const int j = t >> 3, cc = (t & 7) * 16;
+    if (j >= NR) return;   // NR rows of 8 threads each
     uint16_t v[16];
     const int c = c0 + cc;
     if (j < cnt && c < a.D) {
@@ -234,24 +236,24 @@ __device__ __forceinline__ void vrow_sum(float (&v)[N]) {
 }
 
 template <int FT>
-__global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const void *__restrict__ feat,
+__global__ __launch_bounds__(kVT, 2) void vanilla_bwd_kernel(VanArgs a, const void *__restrict__ feat,
                                                             const float *__restrict__ scale,
                                                             const float *__restrict__ T_final,
                                                             const uint16_t *__restrict__ G,
                                                             float *__restrict__ dfeat, float *__restrict__ g_mean2d,
                                                             float *__restrict__ g_conic, float *__restrict__ g_opac) {
     extern __shared__ __align__(16) unsigned char dyn[];
-    // batch area (the first 64 KB also stage the tile's dL/dF chunk at the start)
-    uint16_t *ft = (uint16_t *)dyn;                                  // [kVB][kFS] BF16
-    float *s_S = (float *)(dyn + kVB * kFS * 2);                     // [256][kVB + 1] FP32
-    uint16_t *wt_hi = (uint16_t *)(s_S + kVT * (kVB + 1));           // [kVB][kVT + 8] BF16
-    uint16_t *wt_lo = wt_hi + kVB * (kVT + 8);                       // [kVB][kVT + 8]
-    float *s_dF = (float *)(wt_lo + kVB * (kVT + 8));                // [kVB][kVC] FP32
-    float *s_part = s_dF + kVB * kVC;                                // [16 rows][kVB][kNV]
-    __shared__ int s_id[kVB];
-    __shared__ float2 s_xy[kVB];
-    __shared__ float4 s_co[kVB];
-    __shared__ float s_sc[kVB];
+    // batch area (its start also stages half of the tile's dL/dF chunk at a time)
+    uint16_t *ft = (uint16_t *)dyn;                                  // [kVBB][kFS] BF16
+    float *s_S = (float *)(dyn + kVBB * kFS * 2);                    // [256][kVBB + 1] FP32
+    uint16_t *wt_hi = (uint16_t *)(s_S + kVT * (kVBB + 1));          // [kVBB][kVT + 8] BF16
+    uint16_t *wt_lo = wt_hi + kVBB * (kVT + 8);                      // [kVBB][kVT + 8]
+    float *s_dF = (float *)(wt_lo + kVBB * (kVT + 8));               // [kVBB][kVC] FP32
+    float *s_part = s_dF + kVBB * kVC;                               // [16 rows][kVBB][kNV]
+    __shared__ int s_id[kVBB];
+    __shared__ float2 s_xy[kVBB];
+    __shared__ float4 s_co[kVBB];
+    __shared__ float s_sc[kVBB];
     __shared__ int s_max;
     const int nchunks = (a.D + kVC - 1) / kVC;
     const int ntiles = a.ntx * a.nty;
@@ -270,40 +272,44 @@ __global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const vo
     if (t == 0) s_max = 0;
     __syncthreads();
     atomicMax(&s_max, last);
-    // the tile's dL/dF chunk [256 px][128 ch] into LDS (BF16, padded rows; zero past
-    // the image or D), then into registers in the two operand layouts
-    uint16_t *gs = (uint16_t *)dyn;   // [256][kFS]
-    for (int q = t; q < kVT * 16; q += kVT) {
-        const int pix = q >> 4, seg = q & 15;
-        const int xx = x0 + (pix & 15), yy = y0 + (pix >> 4);
-        const int c = c0 + 8 * seg;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (xx < a.W && yy < a.H && c < a.D) v = *(const u32x4 *)&G[((long)yy * a.W + xx) * a.D + c];
-        *(u32x4 *)&gs[pix * kFS + 8 * seg] = v;
-    }
-    __syncthreads();
-    const int maxl = s_max;
-    // S = G Ft^T: A[i][8g..] = G[px 64 w + 16 mb + i][ch 32 ks + 8 g ..], 4 x 4 operands
-    u32x4 ga[4][4];
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) ga[mb][ks] = *(const u32x4 *)&gs[(64 * wave + 16 * mb + li) * kFS + 32 * ks + 8 * lg];
-    // dFt = W^T G: B[8g..][i] = G[px 64 w + 32 kp + 8 g + q][ch 16 nb + i], 2 x 8 operands
-    u32x4 gb[2][8];
-#pragma unroll
-    for (int kp = 0; kp < 2; ++kp)
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-            uint16_t col[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) col[q] = gs[(64 * wave + 32 * kp + 8 * lg + q) * kFS + 16 * nb + li];
-            gb[kp][nb] = *(u32x4 *)col;
+    // the tile's dL/dF chunk [256 px][128 ch] through LDS, half the pixels at a time (BF16,
+    // padded rows; zero past the image or D), into registers in the two operand layouts;
+    // the waves whose pixels the half holds (two each) take their operands from it
+    uint16_t *gs = (uint16_t *)dyn;   // [128][kFS]
+    u32x4 ga[4][4];   // S = G Ft^T: A[i][8g..] = G[px 64 w + 16 mb + i][ch 32 ks + 8 g ..]
+    u32x4 gb[2][8];   // dFt = W^T G: B[8g..][i] = G[px 64 w + 32 kp + 8 g + q][ch 16 nb + i]
+    for (int half = 0; half < 2; ++half) {
+        if (half) __syncthreads();   // the first half's operands are loaded
+        for (int q = t; q < (kVT / 2) * 16; q += kVT) {
+            const int pix = (kVT / 2) * half + (q >> 4), seg = q & 15;
+            const int xx = x0 + (pix & 15), yy = y0 + (pix >> 4);
+            const int c = c0 + 8 * seg;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (xx < a.W && yy < a.H && c < a.D) v = *(const u32x4 *)&G[((long)yy * a.W + xx) * a.D + c];
+            *(u32x4 *)&gs[(q >> 4) * kFS + 8 * seg] = v;
         }
+        __syncthreads();
+        if ((wave >> 1) != half) continue;
+        const int wrow = 64 * (wave & 1);   // the wave's first pixel within the half
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) ga[mb][ks] = *(const u32x4 *)&gs[(wrow + 16 * mb + li) * kFS + 32 * ks + 8 * lg];
+#pragma unroll
+        for (int kp = 0; kp < 2; ++kp)
+#pragma unroll
+            for (int nb = 0; nb < 8; ++nb) {
+                uint16_t col[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) col[q] = gs[(wrow + 32 * kp + 8 * lg + q) * kFS + 16 * nb + li];
+                gb[kp][nb] = *(u32x4 *)col;
+            }
+    }
+    const int maxl = s_max;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     float A = 0.f;
-    for (int hi = maxl; hi > 0; hi -= kVB) {
-        const int lo = hi > kVB ? hi - kVB : 0;
+    for (int hi = maxl; hi > 0; hi -= kVBB) {
+        const int lo = hi > kVBB ? hi - kVBB : 0;
         const int cnt = hi - lo;
         __syncthreads();   // the previous batch (and the G staging) are consumed
         if (t < cnt) {
@@ -313,13 +319,13 @@ __global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const vo
             s_co[t] = make_float4(a.conic[3 * r], a.conic[3 * r + 1], a.conic[3 * r + 2], a.opacity[r]);
             s_sc[t] = FT == VF_FP8 ? scale[r] : 1.0f;
         }
-        for (int q = t; q < kVB * kVC; q += kVT) s_dF[q] = 0.f;
+        for (int q = t; q < kVBB * kVC; q += kVT) s_dF[q] = 0.f;
         __syncthreads();
-        stage_rows32<FT, false>(a, feat, s_id, cnt, c0, ft);
+        stage_rows32<FT, false, kVBB>(a, feat, s_id, cnt, c0, ft);
         __syncthreads();
-        // S chunk of the batch: the wave's 64 px x 32 Gaussians
+        // S chunk of the batch: the wave's 64 px x kVBB Gaussians
 #pragma unroll
-        for (int nbg = 0; nbg < 2; ++nbg) {
+        for (int nbg = 0; nbg < kVBB / 16; ++nbg) {
             u32x4 bs[4];   // B[8g..][i] = Ft[Gaussian 16 nbg + i][ch 32 ks + 8 g ..]
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) bs[ks] = *(const u32x4 *)&ft[(16 * nbg + li) * kFS + 32 * ks + 8 * lg];
@@ -329,12 +335,12 @@ __global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const vo
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) s = vmfma(ga[mb][ks], bs[ks], s);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) s_S[(64 * wave + 16 * mb + 4 * lg + r) * (kVB + 1) + 16 * nbg + li] = s[r];
+                for (int r = 0; r < 4; ++r) s_S[(64 * wave + 16 * mb + 4 * lg + r) * (kVBB + 1) + 16 * nbg + li] = s[r];
             }
         }
         __syncthreads();
         // back-to-front replay of the pixel over the batch
-        for (int j = kVB - 1; j >= 0; --j) {
+        for (int j = kVBB - 1; j >= 0; --j) {
             float v[kNV] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             float w = 0.f;
             bool hit = false;
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const vo
                     const float r = __builtin_amdgcn_rcpf(1.0f - alpha);
                     T *= r;                               // transmittance in front of this Gaussian
                     w = alpha * T;
-                    const float e = s_S[t * (kVB + 1) + j] * s_sc[j];
+                    const float e = s_S[t * (kVBB + 1) + j] * s_sc[j];
                     const float dal = T * e - A * r;
                     A = fmaf(e, w, A);
                     if (raw <= kAlphaMax) {               // unclamped: alpha = o e^-sigma
@@ -367,7 +373,7 @@ __global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const vo
             wt_lo[j * (kVT + 8) + t] = to_bf16(w - from_bf16(whi));
             if (__ballot(hit) != 0ull) vrow_sum<kNV>(v);
             if ((t & 15) == 0) {
-                float *dst = &s_part[((t >> 4) * kVB + j) * kNV];
+                float *dst = &s_part[((t >> 4) * kVBB + j) * kNV];
 #pragma unroll
                 for (int q = 0; q < kNV; ++q) dst[q] = v[q];
             }
@@ -379,15 +385,15 @@ __global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const vo
             const int j = o / kNV, q = o - j * kNV;
             float sum = 0.f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) sum += s_part[(r * kVB + j) * kNV + q];
+            for (int r = 0; r < 16; ++r) sum += s_part[(r * kVBB + j) * kNV + q];
             if (sum == 0.f) continue;
             const int rec = s_id[j];
             float *dst = q < 2 ? &g_mean2d[2 * rec + q] : q < 5 ? &g_conic[3 * rec + (q - 2)] : &g_opac[rec];
             unsafeAtomicAdd(dst, sum);
         }
-        // dFt[32 Gaussians][128 ch] = W^T G over the wave's 64 pixels, partial sums meet in LDS
+        // dFt[kVBB Gaussians][128 ch] = W^T G over the wave's 64 pixels, partial sums meet in LDS
 #pragma unroll
-        for (int mbg = 0; mbg < 2; ++mbg) {
+        for (int mbg = 0; mbg < kVBB / 16; ++mbg) {
             u32x4 ah[2], al[2];   // A[i][8g..] = W^T[Gaussian 16 mbg + i][px 64 w + 32 kp + 8 g ..]
 #pragma unroll
             for (int kp = 0; kp < 2; ++kp) {
@@ -417,9 +423,9 @@ __global__ __launch_bounds__(kVT, 1) void vanilla_bwd_kernel(VanArgs a, const vo
 
 constexpr size_t kFwdLds = (size_t)2 * kVT * kWS * 2 + (size_t)kVC * kTS * 2;
 constexpr size_t kFwdLdsStore = (size_t)4 * 64 * kFS * 2;
-constexpr size_t kBwdLds = (size_t)kVB * kFS * 2 + (size_t)kVT * (kVB + 1) * 4 + (size_t)2 * kVB * (kVT + 8) * 2 +
-                           (size_t)kVB * kVC * 4 + (size_t)16 * kVB * kNV * 4;
-constexpr size_t kBwdLdsStage = (size_t)kVT * kFS * 2;
+constexpr size_t kBwdLds = (size_t)kVBB * kFS * 2 + (size_t)kVT * (kVBB + 1) * 4 + (size_t)2 * kVBB * (kVT + 8) * 2 +
+                           (size_t)kVBB * kVC * 4 + (size_t)16 * kVBB * kNV * 4;
+constexpr size_t kBwdLdsStage = (size_t)(kVT / 2) * kFS * 2;
 
 lgs_status van_args(const lgs_camera *cam, int d, lgs_dtype feat_dt, const void *feat, const float *feat_scale,
                     lgs_dtype map_dt, const float *mean2d, const float *conic, const float *opacity,

@@ -20,14 +20,18 @@ def torch():
     return t
 
 
-def test_quantize_bit_exact(torch, orc):
+@pytest.mark.parametrize("d", [8, 200, 512, 768, 2056, 2568])
+def test_quantize_bit_exact(torch, orc, d):
+    """Storage quantizers bit for bit, at row lengths below one 512-channel step, ragged,
+    and beyond the 2048 channels the FP8 quantizer holds in registers (rows read twice)."""
     from paper_2602_06991_amd import render
-    rng = np.random.default_rng(0)
-    n, d = 3000, 512
+    rng = np.random.default_rng(d)
+    n = 3000 if d <= 768 else 600
     x = (rng.standard_normal((n, d)) * np.exp(rng.uniform(-20, 20, (n, 1)))).astype(np.float32)
     x[0] = 0
     x[1, :] = 1e-40          # subnormal row
-    x[2, 5] = 448.0 * 3      # row whose amax sets a larger scale
+    x[2, min(5, d - 1)] = 448.0 * 3      # row whose amax sets a larger scale
+    x[3, d - 1] = -448.0 * 5             # ... in the last channel
     t = torch.from_numpy(x).cuda()
     b, _ = render.quantize(t, "bf16")
     q, s = render.quantize(t, "fp8")
@@ -314,7 +318,10 @@ def _synthetic_topk(rng, views, H, W, K, n, spread):
     # FP32 rows on the matrix cores (the forward), channel slabs of 256
     (4, "f32", "f32", 1, 40, 53, 512, 24),
     (8, "f32", "f32", 2, 33, 40, 768, 30),
-    (3, "fp8", "f32", 1, 36, 36, 520, 20)])
+    (3, "fp8", "f32", 1, 36, 36, 520, 20),
+    # unions of 33..64 at K > 4 (four union blocks)
+    (8, "bf16", "bf16", 1, 40, 53, 512, 48),
+    (8, "f32", "f32", 2, 33, 35, 520, 60)])
 def test_feature_kernels_on_synthetic_topk(torch, orc, K, fdt, mdt, views, H, W, D, spread):
     from paper_2602_06991_amd import render
     rng = np.random.default_rng(K * 100 + D)
@@ -440,6 +447,11 @@ def test_fused_l1_matches_unfused(torch, K, fdt, D, spread):
     (8, "f32", "f32", 2, 33, 40, 768, 30),         # FP32 form at K = 8, D = 768: three slabs, two views
     (8, "fp8", "f32", 1, 40, 40, 520, 30),         # FP8 rows, FP32 map, channel tail (slabs of 6, 6, 5 chunks)
     (4, "f32", "f32", 1, 48, 48, 256, 20000),      # FP32 form, unions beyond 32 beside MFMA tiles
+    # unions of 33..64 at K > 4: four union blocks, one chunk per wave, several slabs
+    (8, "bf16", "bf16", 1, 40, 53, 512, 48),
+    (8, "fp8", "bf16", 1, 33, 40, 768, 60),
+    (8, "f32", "f32", 1, 32, 40, 264, 40),
+    (5, "bf16", "f32", 1, 30, 30, 200, 36),
     (16, "bf16", "bf16", 1, 32, 32, 128, 300)])    # K beyond the MFMA path
 def test_one_pass_render_and_l1_adjoint(torch, orc, K, fdt, mdt, views, H, W, D, spread):
     """lgs_feature_render_fwd_bwd_l1 against the two separate launches (the map bit for
