@@ -77,7 +77,11 @@ class Step:
         n, d = scene_dev["feat"].shape
         self.n, self.d = n, d
         dev = "cuda"
-        self.dfeat = torch.empty(n, d, device=dev)
+        self.dfeat = torch.zeros(n, d, device=dev)
+        # the Top-K adjoint writes only the rows of the step's Top-K lists: the table is
+        # cleared by zeroing the rows the previous step named (the vanilla adjoint writes
+        # every blended Gaussian's row and clears the whole table)
+        self.rows = None if vanilla else render.SparseGradRows(self.dfeat)
         self.sg = render.screen_grad_buffers(n, dev)
         self.pg = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
                        quats=torch.empty(n, 4, device=dev), opacity_logits=torch.empty(n, device=dev))
@@ -118,8 +122,11 @@ class Step:
         gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
         gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
         self._mark("l1_grad")
-        if not self.geometry_only:
+        if self.vanilla:
             self.dfeat.zero_()
+        elif not self.geometry_only:
+            self.rows.clear()
+            self.rows.mark(fw["ids"])
         for v in self.sg.values():
             v.zero_()
         for v in self.pg.values():
@@ -170,7 +177,8 @@ class StepViews:
         n, d = scene_dev["feat"].shape
         self.n, self.d = n, d
         dev = "cuda"
-        self.dfeat = torch.empty(n, d, device=dev)
+        self.dfeat = torch.zeros(n, d, device=dev)
+        self.rows = render.SparseGradRows(self.dfeat)   # cleared row by row, as in Step
         self.sg = render.screen_grad_buffers_views(n, self.V, dev)
         self.pg = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
                        quats=torch.empty(n, 4, device=dev), opacity_logits=torch.empty(n, device=dev))
@@ -196,7 +204,8 @@ class StepViews:
         gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
         gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
         self._mark("l1_grad")
-        self.dfeat.zero_()
+        self.rows.clear()
+        self.rows.mark(fw["ids"])
         for v in self.sg.values():
             v.zero_()
         for v in self.pg.values():

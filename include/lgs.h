@@ -468,6 +468,27 @@ lgs_status lgs_l1_grad(int64_t n, lgs_dtype dt, const void *x, const void *targe
                        void *grad, hipStream_t stream);
 
 /*
+ * Sparse clearing of the dense feature-gradient table dL/df [n][d] between steps (caller
+ * work of a training step).  The feature adjoint writes only rows of Gaussians in a
+ * pixel's Top-K list (a pixel's feature depends on its K rows alone, Eq. 3-4), so a table
+ * that is zero except for the rows named in the last step's Top-K lists can be cleared
+ * by zeroing those rows:
+ *   step s:  lgs_zero_marked_rows(gen = s - 1)  ->  feature adjoint  ->
+ *            lgs_mark_topk_rows(step s's topk_ids, gen = s)
+ * row_gen[n] (int32, caller memory) holds each row's last generation; start with the
+ * table all zero and row_gen below every generation used (e.g. INT32_MIN).
+ *
+ * lgs_mark_topk_rows: row_gen[g] = gen for every id g in [0, n) among the n_slots entries
+ *   of topk_ids (slots holding -1 are skipped).
+ * lgs_zero_marked_rows: zeroes row g of table (FP32, d a multiple of 4, 16-byte aligned)
+ *   wherever row_gen[g] == gen; other rows are not touched.
+ */
+lgs_status lgs_mark_topk_rows(int64_t n_slots, const int32_t *topk_ids, int32_t n, int32_t gen, int32_t *row_gen,
+                              hipStream_t stream);
+lgs_status lgs_zero_marked_rows(int32_t n, int32_t d, int32_t gen, const int32_t *row_gen, float *table,
+                                hipStream_t stream);
+
+/*
  * Number of distinct Gaussians over all pixels' Top-K slots (ids in [0, n) in
  * topk_ids[n_pix*k]); the U of the feature adjoint's memory traffic.  flags[n + 1]
  * is caller scratch (overwritten); *count (host) receives the result.

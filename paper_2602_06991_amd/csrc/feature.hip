@@ -176,6 +176,33 @@ __global__ __launch_bounds__(256) void union_sum_kernel(int n, int *__restrict__
     if (threadIdx.x == 0 && s[0]) atomicAdd(&flags[n], s[0]);
 }
 
+// Rows of the feature-gradient table the adjoint can write: row_gen[g] = gen for each
+// Gaussian g named in a Top-K slot.
+__global__ __launch_bounds__(256) void mark_rows_kernel(long m, const int *__restrict__ ids, int n, int gen,
+                                                        int *__restrict__ row_gen) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int g = ids[i];
+    if (g >= 0 && g < n) row_gen[g] = gen;
+}
+
+// Zeroes the rows whose row_gen equals gen: each wave takes 64 rows, finds the marked
+// ones with a ballot and clears each with the whole wave (16-byte stores).
+__global__ __launch_bounds__(256) void zero_marked_rows_kernel(int n, int d, int gen, const int *__restrict__ row_gen,
+                                                               float *__restrict__ table) {
+    const int lane = threadIdx.x & 63;
+    const long r0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    if (r0 >= n) return;   // whole wave
+    const long r = r0 + lane;
+    unsigned long long m = __ballot(r < n && row_gen[r] == gen);
+    while (m) {
+        const int j = __builtin_ctzll(m);
+        m &= m - 1;
+        f32x4 *row = (f32x4 *)(table + (r0 + j) * (long)d);
+        for (int c = lane; c < d / 4; c += 64) row[c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 
 template <int FT, int MT>
@@ -359,4 +386,27 @@ extern "C" lgs_status lgs_union_count(int64_t n_pix, int32_t k, int32_t n, const
     if (st) return st;
     *count = c;
     return LGS_OK;
+}
+
+extern "C" lgs_status lgs_mark_topk_rows(int64_t n_slots, const int32_t *topk_ids, int32_t n, int32_t gen,
+                                         int32_t *row_gen, hipStream_t stream) {
+    LGS_REQUIRE(n_slots >= 0 && n >= 0, LGS_ERR_INVALID_ARG, "lgs_mark_topk_rows: bad sizes");
+    if (n_slots == 0 || n == 0) return LGS_OK;
+    LGS_REQUIRE(topk_ids && row_gen, LGS_ERR_INVALID_ARG, "lgs_mark_topk_rows: NULL pointer");
+    hipLaunchKernelGGL(mark_rows_kernel, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, stream, (long)n_slots,
+                       topk_ids, n, gen, row_gen);
+    return check_launch("mark_topk_rows");
+}
+
+extern "C" lgs_status lgs_zero_marked_rows(int32_t n, int32_t d, int32_t gen, const int32_t *row_gen, float *table,
+                                           hipStream_t stream) {
+    LGS_REQUIRE(n >= 0 && d > 0 && d % 4 == 0, LGS_ERR_INVALID_ARG, "lgs_zero_marked_rows: bad sizes n=%d d=%d", n,
+                d);
+    if (n == 0) return LGS_OK;
+    LGS_REQUIRE(row_gen && table, LGS_ERR_INVALID_ARG, "lgs_zero_marked_rows: NULL pointer");
+    LGS_REQUIRE(aligned16(table), LGS_ERR_INVALID_ARG, "table must be 16-byte aligned");
+    const long waves = ((long)n + 63) / 64;
+    hipLaunchKernelGGL(zero_marked_rows_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, n, d, gen,
+                       row_gen, table);
+    return check_launch("zero_marked_rows");
 }

@@ -94,6 +94,8 @@ _SIG = {
     "lgs_quantize_features": [_I32, _I32, _P, ctypes.c_int, _P, _P, _P],
     "lgs_l1_grad": [_I64, ctypes.c_int, _P, _P, _F, _P, _P],
     "lgs_union_count": [_I64, _I32, _I32, _P, _P, ctypes.POINTER(ctypes.c_int64), _P],
+    "lgs_mark_topk_rows": [_I64, _P, _I32, _I32, _P, _P],
+    "lgs_zero_marked_rows": [_I32, _I32, _I32, _P, _P, _P],
 }
 EXPORTS = ["lgs_abi_version", "lgs_last_error", "lgs_supported_k", *_SIG]
 
@@ -352,6 +354,14 @@ def lgs_quantize_features(n, d, src, dst_dt, dst, dst_scale, stream=None):
 
 def lgs_l1_grad(n, dt, x, target, scale, grad, stream=None):
     return _check(load().lgs_l1_grad(n, dt, x, target, scale, grad, stream))
+
+
+def lgs_mark_topk_rows(n_slots, topk_ids, n, gen, row_gen, stream=None):
+    return _check(load().lgs_mark_topk_rows(n_slots, topk_ids, n, gen, row_gen, stream))
+
+
+def lgs_zero_marked_rows(n, d, gen, row_gen, table, stream=None):
+    return _check(load().lgs_zero_marked_rows(n, d, gen, row_gen, table, stream))
 
 
 def lgs_union_count(n_pix, k, n, topk_ids, flags, stream=None):

@@ -358,6 +358,27 @@ def l1_grad(x, target, scale):
     return g
 
 
+class SparseGradRows:
+    """Clears a dense feature-gradient table [n, d] between steps by zeroing only the
+    rows the previous step's Top-K lists named (the only rows the feature adjoint
+    writes).  Per step: clear(), then the adjoint, then mark(topk_ids)."""
+
+    def __init__(self, table):
+        self.table = table
+        n = table.shape[0]
+        self.row_gen = torch.full((n,), -2**31, dtype=torch.int32, device=table.device)
+        self.gen = 0
+
+    def clear(self):
+        n, d = self.table.shape
+        lgs.lgs_zero_marked_rows(n, d, self.gen - 1, _p(self.row_gen), _p(self.table), _stream())
+
+    def mark(self, topk_ids):
+        n = self.table.shape[0]
+        lgs.lgs_mark_topk_rows(topk_ids.numel(), _p(topk_ids), n, self.gen, _p(self.row_gen), _stream())
+        self.gen += 1
+
+
 def union_count(ids, n):
     flags = torch.empty(n + 1, dtype=torch.int32, device=ids.device)
     K = ids.shape[-1]

@@ -129,3 +129,21 @@ def test_pose_gradient_validation():
         lgs.lgs_project_bwd_pose(_cam(f=0.0), 10, *args, None, None, None, None, FAKE)
     assert e.value.status == lgs.LGS_ERR_INVALID_ARG
     assert lgs.lgs_project_bwd_pose(_cam(), 0, *([None] * 13), FAKE) == lgs.LGS_OK
+
+
+def test_sparse_row_clearing_validation():
+    # empty inputs are no-ops; bad sizes and NULL buffers are rejected before any launch
+    assert lgs.lgs_mark_topk_rows(0, None, 10, 1, None) == lgs.LGS_OK
+    assert lgs.lgs_zero_marked_rows(0, 8, 1, None, None) == lgs.LGS_OK
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_mark_topk_rows(-1, FAKE, 10, 1, FAKE)
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_mark_topk_rows(100, None, 10, 1, FAKE)
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_zero_marked_rows(10, 6, 1, FAKE, FAKE)      # d not a multiple of 4
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_zero_marked_rows(10, 8, 1, FAKE, FAKE + 4)  # table not 16-byte aligned
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG

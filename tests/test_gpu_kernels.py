@@ -4,7 +4,7 @@ seeded generator produced, never another HIP kernel's output."""
 import numpy as np
 import pytest
 
-from gpu_util import FLAG_EPS, dev_params, normwise, rel_close
+from gpu_util import FLAG_EPS, dev_params, gpu_forward, normwise, rel_close
 from paper_2602_06991_amd.scenegen import make_scene, make_tiny
 
 pytestmark = pytest.mark.gpu
@@ -533,3 +533,38 @@ def test_prune_select_matches_oracle(torch, orc, n, below, ratio, seed):
     cand = count < below
     print(f"n={n}: candidates {cand.sum()}, survivors among them {want[cand].sum()}", flush=True)
     np.testing.assert_array_equal(got, want)
+
+
+def test_sparse_gradient_clearing_matches_dense(torch):
+    """Clearing the feature-gradient table by zeroing the rows the previous step's Top-K
+    lists named gives the table dense zeroing gives, step after step, with the Top-K sets
+    changing between steps (three views of a room scene, then the first again)."""
+    from paper_2602_06991_amd import render
+    sc = make_scene(3, N=60000, W=200, H=150, D=64)
+    g = sc.gaussians
+    P = dev_params(g)
+    n, d = g.n, g.d
+    store, scale = render.quantize(P["feat"], "bf16")
+    dense = torch.zeros(n, d, device="cuda")
+    table = torch.zeros(n, d, device="cuda")
+    rows = render.SparseGradRows(table)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    for step, v in enumerate([0, 1, 2, 0]):
+        out, st = gpu_forward(g, sc.cameras[v], 4)
+        fw = st["fw"]
+        target = torch.randn(fw["ids"].shape[0], fw["ids"].shape[1], d, device="cuda", generator=gen).to(torch.bfloat16)
+        dense.zero_()
+        render.feature_bwd_l1(fw["ids"], fw["w"], store, scale, "bf16", "bf16", target, 1e-3, dense)
+        rows.clear()
+        rows.mark(fw["ids"])
+        render.feature_bwd_l1(fw["ids"], fw["w"], store, scale, "bf16", "bf16", target, 1e-3, table)
+        torch.cuda.synchronize()
+        nz = dense.abs().sum(1) > 0
+        assert torch.equal(nz, table.abs().sum(1) > 0), step
+        rel = float((dense - table).norm() / dense.norm().clamp_min(1e-30))
+        assert rel <= 1e-6, (step, rel)
+        ids = fw["ids"].reshape(-1)
+        marked = torch.zeros(n, dtype=torch.bool, device="cuda")
+        marked[ids[ids >= 0].long()] = True
+        assert torch.equal(rows.row_gen == step, marked), step
+        assert not bool(nz[~marked].any())        # every written row was marked
