@@ -4,9 +4,9 @@
 // replaces, Sec. 3.2 and Tab. 4), and its adjoint.  It serves as the comparison path.
 //
 // Both kernels take one 256-thread block per (16x16 tile, 128-channel chunk) and walk
-// the tile's depth-sorted list in batches of 32 Gaussians, replaying the blend of each
-// pixel with the forward's arithmetic up to its n_contrib, so every weight is the
-// forward's bit for bit.
+// the tile's depth-sorted list in batches (32 Gaussians in the forward, 16 in the
+// adjoint), replaying the blend of each pixel with the forward's arithmetic up to its
+// n_contrib, so every weight is the forward's bit for bit.
 //
 // Forward: per batch the weights W[256 px][32] (split into two BF16 terms, hi and lo)
 // and the rows Ft[32][128 ch] go to LDS and the chunk of the map accumulates on the
