@@ -62,6 +62,49 @@ def parse():
     return ap.parse_args()
 
 
+# The storage quantization of the FP32 master table and the clearing of the previous
+# step's gradient rows depend on nothing the projection, binning and blend compute, so
+# the timed steps run them on a second stream (default priority) beside those phases;
+# the main stream waits for them before marking the new Top-K rows and before the
+# feature kernel reads the store.  The per-phase pass (events after every phase) runs
+# everything in order on one stream.
+def _side_init(st, torch, form, n, d, dev, sparse):
+    st.sparse = sparse
+    st.side = torch.cuda.Stream()
+    st.out = None
+    if form in ("bf16", "fp8"):
+        st.out = (torch.empty(n, d, dtype=torch.bfloat16 if form == "bf16" else torch.uint8, device=dev),
+                  torch.empty(n, device=dev) if form == "fp8" else None)
+
+
+def _side_begin(st):
+    """Issues the quantization (and the row clearing); returns (store, scale, event or None)."""
+    t, r, P = st.t, st.render, st.P
+    def work():
+        store, scale = (P["feat"], None) if st.form == "f32" else r.quantize(P["feat"], st.form, out=st.out)
+        if st.sparse:
+            st.rows.clear()
+        return store, scale
+    if st.events is not None:            # the per-phase pass: in order on the main stream
+        store, scale = work()
+        return store, scale, None
+    ready = t.cuda.Event()
+    ready.record()                       # the previous step's reads of the store are queued before this
+    st.side.wait_event(ready)
+    with t.cuda.stream(st.side):
+        store, scale = work()
+        done = t.cuda.Event()
+        done.record()
+    return store, scale, done
+
+
+def _side_join(st, done):
+    """The main stream waits for the side stream's work (before anything reads the store
+    or marks rows)."""
+    if done is not None:
+        st.t.cuda.current_stream().wait_event(done)
+
+
 class Step:
     """All buffers of one frame's forward + backward, reused across steps."""
 
@@ -88,6 +131,7 @@ class Step:
         self.npix = cam.width * cam.height
         self.events = None
         self.kmarks = None
+        _side_init(self, torch, None if geometry_only else form, n, d, dev, not geometry_only and not vanilla)
 
     def _mark(self, name):
         if self.events is not None:
@@ -100,10 +144,8 @@ class Step:
         self._mark("start")
         if self.geometry_only:
             store, scale = None, None
-        elif self.form == "f32":
-            store, scale = P["feat"], None
         else:
-            store, scale = r.quantize(P["feat"], self.form)
+            store, scale, joined = _side_begin(self)
         self._mark("quantize")
         proj = r.project(c, P)
         self._mark("project_fwd")
@@ -111,6 +153,8 @@ class Step:
         self._mark("bin_sort")
         fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges)
         self._mark("rasterize_topk_fwd")
+        if not self.geometry_only:
+            _side_join(self, joined)
         F = None
         if self.vanilla:
             F = r.feature_vanilla_fwd(c, proj, ids, ranges, fw, store, scale, self.form)
@@ -125,7 +169,6 @@ class Step:
         if self.vanilla:
             self.dfeat.zero_()
         elif not self.geometry_only:
-            self.rows.clear()
             self.rows.mark(fw["ids"])
         for v in self.sg.values():
             v.zero_()
@@ -186,13 +229,14 @@ class StepViews:
         self.npix = cams[0].width * cams[0].height * self.V
         self.events = None
         self.kmarks = None
+        _side_init(self, torch, form, n, d, dev, True)
 
     _mark = Step._mark
 
     def __call__(self):
         r, P, c, V, n = self.render, self.P, self.cams, self.V, self.n
         self._mark("start")
-        store, scale = (P["feat"], None) if self.form == "f32" else r.quantize(P["feat"], self.form)
+        store, scale, joined = _side_begin(self)
         self._mark("quantize")
         proj = r.project_views(c, P)
         self._mark("project_fwd")
@@ -200,11 +244,11 @@ class StepViews:
         self._mark("bin_sort")
         fw = r.rasterize_views(c, self.K, n, proj, P["rgb"], ids, ranges)
         self._mark("rasterize_topk_fwd")
+        _side_join(self, joined)
         tC, tD, tF = self.target
         gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
         gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
         self._mark("l1_grad")
-        self.rows.clear()
         self.rows.mark(fw["ids"])
         for v in self.sg.values():
             v.zero_()
@@ -297,9 +341,11 @@ def multi_view(torch, render, lgs, config, steps, warmup):
 def time_steps(torch, step, steps, warmup):
     """Times `steps` steps after `warmup` untimed ones.  Inside the timed steps only
     the feature adjoint (the dominant HBM-bound kernel) is bracketed by HIP events, on
-    torch's stream, where every launch goes; a second, separate pass puts an event
-    after every phase for the per-phase breakdown (each event costs a few us of GPU
-    time, which is why the timed pass carries only two per step)."""
+    torch's stream, where it and the main stream's work run (the side stream's work is
+    joined into it before the feature kernel and before the end event); a second,
+    separate pass runs every phase in order on one stream with an event after each, for
+    the per-phase breakdown (each event costs a few us of GPU time, which is why the
+    timed pass carries only two per step)."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()

@@ -7,8 +7,10 @@
 // keep id order because every pass is stable and the first starts in id order.
 //
 // Every sort pass is an LSD radix pass with 8-bit digits in three launches:
-// per-block digit histograms, a per-digit scan over blocks, and a stable scatter in
-// which each wave ranks equal digits with ballots.
+// per-block digit histograms, a per-digit scan over blocks, and a stable scatter.
+// The scatter ranks equal digits within a wave with ballots, orders the block's items
+// by digit in LDS, and then writes each digit's run of the block with consecutive
+// lanes, so the stores of a wave cover a few runs instead of up to 64 buckets.
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
 
@@ -18,8 +20,13 @@ namespace lgs {
 namespace {
 
 constexpr int kSortThreads = 256;
+// Items per thread of a sort pass: 4 (1024 items per block, so the 0.5-2 M items of
+// one frame still spread over hundreds of blocks), or 16 (4096 per block) from
+// kBigPass items on, where fewer, fuller blocks write longer runs per digit.
 constexpr int kSortIpt = 4;
-constexpr int kSortItems = kSortThreads * kSortIpt;   // 1024 items per block: several blocks per CU
+constexpr int kSortIptBig = 16;
+constexpr int kSortItems = kSortThreads * kSortIpt;   // the smallest block: sizes the histogram
+constexpr long kBigPass = 1L << 22;
 constexpr int kScanItems = 4096;
 
 // Exclusive scan of one value per thread over a 256-thread block.
@@ -56,18 +63,44 @@ __device__ __forceinline__ int items_of(int n, const long long *n_dev) {
     return n_dev ? (int)min((long long)n, *n_dev) : n;
 }
 
+// Lanes of the wave (among those with `valid`) whose 8-bit digit equals this lane's.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(on);
+        m &= on ? bb : ~bb;
+    }
+    return m;
+}
+
+// Digit counts of one block of IPT * 256 items, written digit-major (hist[d * nb + b]).
+// Each wave counts a digit group once, by its lowest lane, so keys that share a digit
+// (the top byte of nearby depths) do not serialise on one LDS counter.
+template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
                                                                   int n, const long long *__restrict__ n_dev,
                                                                   int shift, int nb, int *__restrict__ hist) {
     __shared__ int h[256];
-    int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     n = items_of(n, n_dev);
     h[t] = 0;
     __syncthreads();
-    long base = (long)blockIdx.x * kSortItems;
-    for (int r = 0; r < kSortIpt; ++r) {
-        long i = base + r * kSortThreads + t;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    const long base = (long)blockIdx.x * (kSortThreads * IPT);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t k[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const long i = base + r * kSortThreads + t;
+        k[r] = i < n ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const bool valid = base + r * kSortThreads + t < n;
+        const uint32_t d = (k[r] >> shift) & 255u;
+        const uint64_t m = digit_peers(d, valid);
+        if (valid && (m & lt) == 0) atomicAdd(&h[d], __popcll(m));
     }
     __syncthreads();
     hist[t * nb + blockIdx.x] = h[t];
@@ -91,58 +124,84 @@ __global__ __launch_bounds__(256) void radix_scan_digits_kernel(int *__restrict_
     if (threadIdx.x == 0) totals[d] = carry;
 }
 
+// Stable scatter of one block of IPT * 256 items.  Wave w takes the block's items
+// [64 IPT w, 64 IPT (w + 1)) in order, 64 per round, so (wave, round, lane) order is
+// input order.  Per round the lanes of a digit group take consecutive offsets after
+// the wave's running count of that digit (the group's lowest lane advances it).
+// The block's items are then placed in LDS in (digit, input) order and written out
+// with thread t on items t, t + 256, ...: consecutive lanes write consecutive slots of
+// a digit's run.
+template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ kin, const int *__restrict__ vin, int n, const long long *__restrict__ n_dev,
     int shift, int nb, const int *__restrict__ hist, const int *__restrict__ totals, uint32_t *__restrict__ kout,
     int *__restrict__ vout) {
+    constexpr int kItems = kSortThreads * IPT;
     n = items_of(n, n_dev);
-    __shared__ int base[256];
-    __shared__ int run[256];
-    __shared__ int wcnt[4][256];
-    __shared__ int pre[4][256];
-    __shared__ int scan_lds[256];
-    int t = threadIdx.x;
-    int wave = t >> 6;
-    int lane = t & 63;
-    int tot;
-    int ex = block_exscan256(totals[t], scan_lds, tot);
-    base[t] = ex + hist[t * nb + blockIdx.x];
-    run[t] = 0;
-    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0;
+    const long b0 = (long)blockIdx.x * kItems;
+    if (b0 >= n) return;   // the whole block: past the items
+    __shared__ uint32_t s_key[kItems];
+    __shared__ int s_val[kItems];
+    __shared__ int s_cnt[4][256];   // per wave and digit: running count, then the wave's first slot
+    __shared__ int s_dst[256];      // per digit: global slot of block slot 0 of the digit's run
+    __shared__ int s_scan[256];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int cnt = (int)min((long)kItems, n - b0);
+    for (int w = 0; w < 4; ++w) s_cnt[w][t] = 0;
     __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    long b0 = (long)blockIdx.x * kSortItems;
-    for (int r = 0; r < kSortIpt; ++r) {
-        long i = b0 + r * kSortThreads + t;
-        bool valid = i < n;
-        uint32_t key = valid ? kin[i] : 0u;
-        int val = valid ? vin[i] : 0;
-        uint32_t d = (key >> shift) & 255u;
-        uint64_t mask = __ballot(valid);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[IPT];
+    int val[IPT], off[IPT];
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            bool on = (d >> bit) & 1u;
-            uint64_t bb = __ballot(on);
-            mask &= on ? bb : ~bb;
+    for (int r = 0; r < IPT; ++r) {
+        const int j = wave * 64 * IPT + r * 64 + lane;
+        const bool valid = j < cnt;
+        key[r] = valid ? kin[b0 + j] : 0u;
+        val[r] = valid ? vin[b0 + j] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const bool valid = wave * 64 * IPT + r * 64 + lane < cnt;
+        const uint32_t d = (key[r] >> shift) & 255u;
+        const uint64_t m = digit_peers(d, valid);
+        const int lead = m ? __builtin_ctzll(m) : 0;
+        int before = 0;
+        if (valid && lane == lead) before = atomicAdd(&s_cnt[wave][d], __popcll(m));
+        before = __shfl(before, lead);
+        off[r] = before + __popcll(m & lt);
+    }
+    __syncthreads();
+    {
+        // digit t: the block's first slot of the digit, each wave's first slot within it,
+        // and the global slot the block's run of the digit starts at
+        const int c0 = s_cnt[0][t], c1 = s_cnt[1][t], c2 = s_cnt[2][t], c3 = s_cnt[3][t];
+        int tot;
+        const int start = block_exscan256(c0 + c1 + c2 + c3, s_scan, tot);
+        s_cnt[0][t] = start;
+        s_cnt[1][t] = start + c0;
+        s_cnt[2][t] = start + c0 + c1;
+        s_cnt[3][t] = start + c0 + c1 + c2;
+        const int gstart = block_exscan256(totals[t], s_scan, tot);
+        s_dst[t] = gstart + hist[t * nb + blockIdx.x] - start;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        if (wave * 64 * IPT + r * 64 + lane < cnt) {
+            const int p = s_cnt[wave][(key[r] >> shift) & 255u] + off[r];
+            s_key[p] = key[r];
+            s_val[p] = val[r];
         }
-        int rank = __popcll(mask & lt);
-        if (valid && rank == 0) wcnt[wave][d] = __popcll(mask);
-        __syncthreads();
-        {
-            int c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-            int p = run[t];
-            pre[0][t] = p;
-            pre[1][t] = p + c0;
-            pre[2][t] = p + c0 + c1;
-            pre[3][t] = p + c0 + c1 + c2;
-            run[t] = p + c0 + c1 + c2 + c3;
-            wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
-        }
-        __syncthreads();
-        if (valid) {
-            int dst = base[d] + pre[wave][d] + rank;
-            kout[dst] = key;
-            vout[dst] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const int i = r * kSortThreads + t;
+        if (i < cnt) {
+            const uint32_t k = s_key[i];
+            const int dst = s_dst[(k >> shift) & 255u] + i;
+            kout[dst] = k;
+            vout[dst] = s_val[i];
         }
     }
 }
@@ -337,13 +396,23 @@ Layout layout_of(long n, long max_pairs) {
 
 // One stable LSD pass over bits [shift, shift + 8) of n items (min(n, *n_dev) if
 // n_dev is given: the grid is sized for n).
+template <int IPT>
+void radix_launch(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int n, const long long *n_dev,
+                  int shift, int *hist, int *totals, hipStream_t st) {
+    const int nb = (int)(((long)n + kSortThreads * IPT - 1) / (kSortThreads * IPT));
+    hipLaunchKernelGGL(radix_hist_kernel<IPT>, dim3(nb), dim3(kSortThreads), 0, st, kin, n, n_dev, shift, nb,
+                       hist);
+    hipLaunchKernelGGL(radix_scan_digits_kernel, dim3(256), dim3(256), 0, st, hist, nb, totals);
+    hipLaunchKernelGGL(radix_scatter_kernel<IPT>, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, n, n_dev, shift,
+                       nb, hist, totals, kout, vout);
+}
+
 lgs_status radix_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int n,
                       const long long *n_dev, int shift, int *hist, int *totals, hipStream_t st) {
-    int nb = (n + kSortItems - 1) / kSortItems;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, n, n_dev, shift, nb, hist);
-    hipLaunchKernelGGL(radix_scan_digits_kernel, dim3(256), dim3(256), 0, st, hist, nb, totals);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, n, n_dev, shift,
-                       nb, hist, totals, kout, vout);
+    if (n >= kBigPass)
+        radix_launch<kSortIptBig>(kin, vin, kout, vout, n, n_dev, shift, hist, totals, st);
+    else
+        radix_launch<kSortIpt>(kin, vin, kout, vout, n, n_dev, shift, hist, totals, st);
     return check_launch("radix pass");
 }
 

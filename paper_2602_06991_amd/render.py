@@ -154,22 +154,30 @@ def prune_select(topk_count, max_w, count_below, expo, keep_ratio=0.5):
     return survive
 
 
-def quantize(feat, dtype):
-    """FP32 [N,D] -> storage (bf16 tensor, or (uint8 codes, f32 scale) for fp8)."""
+def quantize(feat, dtype, out=None):
+    """FP32 [N,D] -> storage (bf16 tensor, or (uint8 codes, f32 scale) for fp8).  `out`:
+    an existing (store, scale) pair of the right shapes and dtypes to write into."""
     n, d = feat.shape
     _need_cuda(feat)
     if dtype == "f32":
         return feat, None
+    if dtype not in ("bf16", "fp8"):
+        raise ValueError(dtype)
+    sdt = torch.bfloat16 if dtype == "bf16" else torch.uint8
+    if out is None:
+        store = torch.empty(n, d, dtype=sdt, device=feat.device)
+        scale = torch.empty(n, dtype=torch.float32, device=feat.device) if dtype == "fp8" else None
+    else:
+        store, scale = out
+        if store.shape != (n, d) or store.dtype != sdt or not store.is_contiguous():
+            raise ValueError("quantize: store must be a contiguous [n, d] tensor of the storage dtype")
+        if dtype == "fp8" and (scale is None or scale.shape != (n,) or scale.dtype != torch.float32):
+            raise ValueError("quantize: FP8 needs a float32 scale of n rows")
     if dtype == "bf16":
-        out = torch.empty(n, d, dtype=torch.bfloat16, device=feat.device)
-        lgs.lgs_quantize_features(n, d, _p(feat), lgs.LGS_BF16, _p(out), None, _stream())
-        return out, None
-    if dtype == "fp8":
-        out = torch.empty(n, d, dtype=torch.uint8, device=feat.device)
-        scale = torch.empty(n, dtype=torch.float32, device=feat.device)
-        lgs.lgs_quantize_features(n, d, _p(feat), lgs.LGS_FP8_E4M3, _p(out), _p(scale), _stream())
-        return out, scale
-    raise ValueError(dtype)
+        lgs.lgs_quantize_features(n, d, _p(feat), lgs.LGS_BF16, _p(store), None, _stream())
+        return store, None
+    lgs.lgs_quantize_features(n, d, _p(feat), lgs.LGS_FP8_E4M3, _p(store), _p(scale), _stream())
+    return store, scale
 
 
 def feature_fwd(ids, w, feat_store, feat_scale, feat_dtype, map_dtype, views=1):

@@ -103,12 +103,25 @@ def _synthetic_bins(n, W, H, seed, big):
     return ntx, nty, tx0, ty0, tx1, ty1, touched, depth, rect
 
 
+def _expected_pairs(n, ntx, tx0, ty0, tx1, touched):
+    """Every (tile, Gaussian) pair of the synthetic rects, tiles of a rect row by row."""
+    c = np.where(touched > 0, touched, 0).astype(np.int64)
+    g = np.repeat(np.arange(n, dtype=np.int64), c)
+    k = np.arange(len(g), dtype=np.int64) - np.repeat(np.cumsum(c) - c, c)
+    w = (tx1 - tx0).astype(np.int64)[g]
+    return (ty0.astype(np.int64)[g] + k // w) * ntx + tx0.astype(np.int64)[g] + k % w, g
+
+
 @pytest.mark.parametrize("n,W,H,seed,big", [(1, 16, 16, 0, 0.0), (1000, 64, 48, 1, 0.0),
                                             (20000, 640, 480, 2, 0.0), (100000, 1200, 680, 3, 0.0),
-                                            (50000, 1200, 680, 4, 0.01)])
+                                            (50000, 1200, 680, 4, 0.01),
+                                            # passes of 4 M items and more take blocks of 4096:
+                                            # the tile sort only, then the depth sort too
+                                            (1500000, 1200, 680, 5, 0.0), (4500000, 1200, 680, 6, 0.0)])
 def test_bin_sort_matches_lexsort(torch, n, W, H, seed, big):
     """Synthetic rects and depth keys (with deliberate ties): the pairs must come out
-    ordered by (tile, depth key, id), exactly as numpy's lexsort orders them."""
+    ordered by (tile, depth key, id), exactly as numpy's lexsort orders them; from 1.5 M
+    Gaussians on, the asynchronous mode (grids sized for the buffer) must bin the same."""
     from paper_2602_06991_amd import lgs, render
     ntx, nty, tx0, ty0, tx1, ty1, touched, depth, rect = _synthetic_bins(n, W, H, seed, big)
     cam = lgs.lgs_camera()
@@ -116,18 +129,10 @@ def test_bin_sort_matches_lexsort(torch, n, W, H, seed, big):
     tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     b = render.Binner()
     b._ensure(n, W, H, 64)                                  # force the capacity retry path
-    ids, ranges, m = b(cam, n, tt(depth), tt(rect), tt(touched))
+    args = (cam, n, tt(depth), tt(rect), tt(touched))
+    ids, ranges, m = b(*args)
     torch.cuda.synchronize()
-    exp_t, exp_g = [], []
-    for g in range(n):
-        if touched[g] == 0:
-            continue
-        for ty in range(ty0[g], ty1[g]):
-            for tx in range(tx0[g], tx1[g]):
-                exp_t.append(ty * ntx + tx)
-                exp_g.append(g)
-    exp_t = np.array(exp_t, np.int64)
-    exp_g = np.array(exp_g, np.int64)
+    exp_t, exp_g = _expected_pairs(n, ntx, tx0, ty0, tx1, touched)
     order = np.lexsort((exp_g, depth[exp_g], exp_t))
     assert m == len(exp_t)
     np.testing.assert_array_equal(ids.cpu().numpy(), exp_g[order])
@@ -136,6 +141,14 @@ def test_bin_sort_matches_lexsort(torch, n, W, H, seed, big):
     np.testing.assert_array_equal(r[:, 1] - r[:, 0], cnt)
     starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])
     np.testing.assert_array_equal(r[cnt > 0, 0], starts[cnt > 0])
+    if n >= 1500000:
+        a = render.Binner(sync=False)
+        a(*args)                                             # sizes the buffers
+        ids_a, r_a, _ = a(*args)
+        assert a.count() == (m, True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ids_a[:m].cpu().numpy(), exp_g[order])
+        np.testing.assert_array_equal(r_a.cpu().numpy(), r)
 
 
 def test_bin_sort_without_host_round_trip(torch):
