@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--multi-view", default="3,4",
                     help="also time the batched multi-view steps of these workloads ('' for none): "
                          "3 = 8 x 640x480 / 1M / BF16 / K = 4, 4 = 4 x 1200x680 / 3M / D = 768 / FP8 / K = 8")
+    ap.add_argument("--quantize", choices=("rows", "dense"), default="rows",
+                    help="refresh the BF16/FP8 store in the rows the step's Top-K lists name (rows), "
+                         "or convert the whole FP32 table every step (dense)")
     ap.add_argument("--no-vanilla", dest="vanilla", action="store_false",
                     help="skip the vanilla (alpha-blended, every Gaussian) feature step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -62,14 +65,20 @@ def parse():
     return ap.parse_args()
 
 
-# The storage quantization of the FP32 master table and the clearing of the previous
-# step's gradient rows depend on nothing the projection, binning and blend compute, so
-# the timed steps run them on a second stream (default priority) beside those phases;
-# the main stream waits for them before marking the new Top-K rows and before the
-# feature kernel reads the store.  The per-phase pass (events after every phase) runs
-# everything in order on one stream.
-def _side_init(st, torch, form, n, d, dev, sparse):
+# The storage form (BF16 or FP8) is read only by the feature kernels, and the Top-K
+# feature kernels read only the rows named in the step's Top-K lists, which the step
+# stamps for the sparse gradient clearing anyway: so a Top-K step refreshes just those
+# rows of the store from the FP32 master table, after the blend (for every row the step
+# reads, the same bits as converting the whole table).  The vanilla render reads every
+# blended Gaussian's row and converts the whole table, as does `--quantize dense`.
+# The clearing of the previous step's gradient rows, and a whole-table conversion,
+# depend on nothing the projection, binning and blend compute, so the timed steps run
+# them on a second stream (default priority) beside those phases; the main stream
+# waits for them after the blend, before it marks rows or anything reads the store.
+# The per-phase pass (events after every phase) runs everything in order on one stream.
+def _side_init(st, torch, form, n, d, dev, sparse, dense_quantize):
     st.sparse = sparse
+    st.dense_q = dense_quantize or not sparse
     st.side = torch.cuda.Stream()
     st.out = None
     if form in ("bf16", "fp8"):
@@ -78,38 +87,51 @@ def _side_init(st, torch, form, n, d, dev, sparse):
 
 
 def _side_begin(st):
-    """Issues the quantization (and the row clearing); returns (store, scale, event or None)."""
+    """Issues the side work (the previous step's row clearing, a whole-table
+    conversion); returns the event the main stream waits for (None in the per-phase
+    pass, which runs the work in order)."""
     t, r, P = st.t, st.render, st.P
     def work():
-        store, scale = (P["feat"], None) if st.form == "f32" else r.quantize(P["feat"], st.form, out=st.out)
         if st.sparse:
             st.rows.clear()
-        return store, scale
-    if st.events is not None:            # the per-phase pass: in order on the main stream
-        store, scale = work()
-        return store, scale, None
+            st._mark("clear_rows")
+        if st.dense_q and st.out is not None:
+            r.quantize(P["feat"], st.form, out=st.out)
+            st._mark("quantize")
+    if st.events is not None:
+        work()
+        return None
     ready = t.cuda.Event()
     ready.record()                       # the previous step's reads of the store are queued before this
     st.side.wait_event(ready)
     with t.cuda.stream(st.side):
-        store, scale = work()
+        work()
         done = t.cuda.Event()
         done.record()
-    return store, scale, done
+    return done
 
 
-def _side_join(st, done):
-    """The main stream waits for the side stream's work (before anything reads the store
-    or marks rows)."""
+def _side_join(st, done, topk_ids):
+    """After the blend: the main stream waits for the side work, stamps the step's Top-K
+    rows and refreshes them in the store; returns (store, scale)."""
     if done is not None:
         st.t.cuda.current_stream().wait_event(done)
+    if st.sparse:
+        st.rows.mark(topk_ids)
+        st._mark("mark_rows")
+    if st.out is None:
+        return st.P["feat"], None
+    if not st.dense_q:
+        st.rows.quantize(st.P["feat"], st.form, st.out)
+        st._mark("quantize")
+    return st.out
 
 
 class Step:
     """All buffers of one frame's forward + backward, reused across steps."""
 
     def __init__(self, torch, render, lgs, scene_dev, target, cam, K, form, fused=True, geometry_only=False,
-                 vanilla=False):
+                 vanilla=False, dense_quantize=False):
         self.t, self.render, self.lgs = torch, render, lgs
         self.fused = fused
         self.vanilla = vanilla   # the dense alpha-blended feature field in place of Top-K (Tab. 4's comparison)
@@ -131,7 +153,8 @@ class Step:
         self.npix = cam.width * cam.height
         self.events = None
         self.kmarks = None
-        _side_init(self, torch, None if geometry_only else form, n, d, dev, not geometry_only and not vanilla)
+        _side_init(self, torch, None if geometry_only else form, n, d, dev, not geometry_only and not vanilla,
+                   dense_quantize)
 
     def _mark(self, name):
         if self.events is not None:
@@ -142,19 +165,14 @@ class Step:
     def __call__(self):
         r, P, c = self.render, self.P, self.cam
         self._mark("start")
-        if self.geometry_only:
-            store, scale = None, None
-        else:
-            store, scale, joined = _side_begin(self)
-        self._mark("quantize")
+        joined = None if self.geometry_only else _side_begin(self)
         proj = r.project(c, P)
         self._mark("project_fwd")
         ids, ranges, m = self.binner(c, self.n, proj["depth"], proj["tile_rect"], proj["tiles_touched"])
         self._mark("bin_sort")
         fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges)
         self._mark("rasterize_topk_fwd")
-        if not self.geometry_only:
-            _side_join(self, joined)
+        store, scale = (None, None) if self.geometry_only else _side_join(self, joined, fw["ids"])
         F = None
         if self.vanilla:
             F = r.feature_vanilla_fwd(c, proj, ids, ranges, fw, store, scale, self.form)
@@ -168,8 +186,6 @@ class Step:
         self._mark("l1_grad")
         if self.vanilla:
             self.dfeat.zero_()
-        elif not self.geometry_only:
-            self.rows.mark(fw["ids"])
         for v in self.sg.values():
             v.zero_()
         for v in self.pg.values():
@@ -211,7 +227,7 @@ class StepViews:
     adjoint over the stacked views in one launch; the step ends with the parameter
     gradients and every view's camera-pose gradient (Sec. 4.1's pose refinement)."""
 
-    def __init__(self, torch, render, lgs, scene_dev, target, cams, K, form):
+    def __init__(self, torch, render, lgs, scene_dev, target, cams, K, form, dense_quantize=False):
         self.t, self.render, self.lgs = torch, render, lgs
         self.P, self.target, self.cams, self.K, self.form = scene_dev, target, cams, K, form
         self.V = len(cams)
@@ -229,27 +245,25 @@ class StepViews:
         self.npix = cams[0].width * cams[0].height * self.V
         self.events = None
         self.kmarks = None
-        _side_init(self, torch, form, n, d, dev, True)
+        _side_init(self, torch, form, n, d, dev, True, dense_quantize)
 
     _mark = Step._mark
 
     def __call__(self):
         r, P, c, V, n = self.render, self.P, self.cams, self.V, self.n
         self._mark("start")
-        store, scale, joined = _side_begin(self)
-        self._mark("quantize")
+        joined = _side_begin(self)
         proj = r.project_views(c, P)
         self._mark("project_fwd")
         ids, ranges, m = self.binner(c, n, proj["depth"], proj["tile_rect"], proj["tiles_touched"], views=V)
         self._mark("bin_sort")
         fw = r.rasterize_views(c, self.K, n, proj, P["rgb"], ids, ranges)
         self._mark("rasterize_topk_fwd")
-        _side_join(self, joined)
+        store, scale = _side_join(self, joined, fw["ids"])
         tC, tD, tF = self.target
         gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
         gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
         self._mark("l1_grad")
-        self.rows.mark(fw["ids"])
         for v in self.sg.values():
             v.zero_()
         for v in self.pg.values():
@@ -273,7 +287,7 @@ class StepViews:
         self.last = dict(fw=fw, F=F, store=store, scale=scale)
 
 
-def multi_view(torch, render, lgs, config, steps, warmup):
+def multi_view(torch, render, lgs, config, steps, warmup, dense_quantize=False):
     """The batched mapping step of workload `config` for each of its storage forms:
     ms per step, the feature kernel's HBM roofline, and each form's feature-map error
     against the FP32 form's map of the same step."""
@@ -303,7 +317,7 @@ def multi_view(torch, render, lgs, config, steps, warmup):
         tstore, tscale = render.quantize(PT["feat"], form)
         tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp, views=V)
         del tstore, tscale
-        step = StepViews(torch, render, lgs, P, (tfw["C"], tfw["D"], tF), cams, K, form)
+        step = StepViews(torch, render, lgs, P, (tfw["C"], tfw["D"], tF), cams, K, form, dense_quantize)
         ms, phases, kern_ms, dist = time_steps(torch, step, steps, warmup)
         pairs, fitted = step.binner.count()
         assert fitted, "pair buffer overflowed during timing"
@@ -579,7 +593,7 @@ def main():
         target = (tfw["C"].clone(), tfw["D"].clone(), tF.clone())
         del tproj, tb, tids, tranges, tfw, tstore, tscale, tF
         fused = args.feature_path == "fused"
-        step = Step(torch, render, lgs, P, target, cam, K, form, fused)
+        step = Step(torch, render, lgs, P, target, cam, K, form, fused, dense_quantize=args.quantize == "dense")
         ms, phases, kern_ms, dist = time_steps(torch, step, args.steps, args.warmup)
         pairs, fitted = step.binner.count()
         assert fitted, "pair buffer overflowed during timing"
@@ -603,6 +617,12 @@ def main():
         geo_ms, _, _, _ = time_steps(torch, geo, args.steps, args.warmup)
         assert geo.binner.count()[1], "pair buffer overflowed during timing"
         del geo
+        # the same step converting the whole FP32 table every step (the other schedule)
+        dense_ms = None
+        if form != "f32" and args.quantize == "rows":
+            dq = Step(torch, render, lgs, P, target, cam, K, form, fused, dense_quantize=True)
+            dense_ms, _, _, _ = time_steps(torch, dq, args.steps, args.warmup)
+            del dq
         # and the Eq. 6 survival draw over the Gaussians never in a Top-K list, keeping half
         gen = torch.Generator(device="cuda").manual_seed(5)
         expo = torch.empty(P["feat"].shape[0], device="cuda").exponential_(generator=gen)
@@ -617,9 +637,10 @@ def main():
         results[form] = dict(ms=ms, phases=phases, kern_ms=kern_ms, U=U, pairs=int(step.last["pairs"]),
                              blend_pairs=blend_pairs,
                              bytes_fwd=bf, bytes_bwd=bb, bytes_both=b2, fused=fused, separate=sep,
-                             prune_ms=prune_ms, select_ms=select_ms, geo_ms=geo_ms, dist=dist,
+                             prune_ms=prune_ms, select_ms=select_ms, geo_ms=geo_ms, dense_ms=dense_ms, dist=dist,
                              tile_union=tile_union_stats(fw["ids"], cam.width, cam.height))
-        print(f"# {form}: {ms:.3f} ms/step, U={U}, pairs={step.last['pairs']}, phases "
+        print(f"# {form}: {ms:.3f} ms/step" + (f" (whole-table quantize {dense_ms:.3f})" if dense_ms else "")
+              + f", U={U}, pairs={step.last['pairs']}, phases "
               + ", ".join(f"{k} {v:.3f}" for k, v in phases.items()), file=sys.stderr, flush=True)
         del step, target
         torch.cuda.empty_cache()
@@ -636,7 +657,7 @@ def main():
                 tstore, tscale = render.quantize(PT["feat"], form)
                 tF = render.feature_fwd(tfw["ids"], tfw["w"], tstore, tscale, form, mp)
                 step = Step(torch, render, lgs, P, (tfw["C"].clone(), tfw["D"].clone(), tF.clone()), cam,
-                            k2, form, args.feature_path == "fused")
+                            k2, form, args.feature_path == "fused", dense_quantize=args.quantize == "dense")
                 ms, ph, _, _ = time_steps(torch, step, max(5, args.steps // 2), 2)
                 assert step.binner.count()[1], "pair buffer overflowed during timing"
                 sweep[f"K{k2}_{form}"] = dict(ms_per_frame=round(ms, 4), feature_fwd_bwd_ms=round(feature_ms(ph), 4))
@@ -670,7 +691,7 @@ def main():
 
     mv = {}
     for c in multi:
-        mv[f"config{c}"] = multi_view(torch, render, lgs, c, max(3, args.steps // 4), 2)
+        mv[f"config{c}"] = multi_view(torch, render, lgs, c, max(3, args.steps // 4), 2, args.quantize == "dense")
         torch.cuda.empty_cache()
 
     main_form = forms[0]
@@ -724,7 +745,10 @@ def main():
                       # the render's own fwd+bwd: without the storage quantization of the
                       # master features and the caller's gradient zeroing
                       "ms_per_frame_excl_quantize_zeroing": round(sum(x for p, x in v["phases"].items()
-                                                                      if p not in ("quantize", "zero_grads")), 4),
+                                                                      if p not in ("quantize", "zero_grads",
+                                                                                   "clear_rows", "mark_rows")), 4),
+                      "quantize": args.quantize if k != "f32" else None,
+                      "dense_quantize_ms_per_frame": v["dense_ms"] and round(v["dense_ms"], 4),
                       "geometry_only_ms_per_frame": round(v["geo_ms"], 4),
                       "prune_stats_ms": round(v["prune_ms"], 4),
                       "prune_select_ms": round(v["select_ms"], 4),

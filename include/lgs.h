@@ -281,6 +281,8 @@ lgs_status lgs_feature_render_vanilla_bwd(const lgs_camera *cam, const float *me
 /*
  * Adjoint of the blend (Eq. 1) including the Top-K weight path, replayed back to
  * front per pixel from T_final and n_contrib.  dL_dalpha and dL_dtopkw may be NULL.
+ * T_final, n_contrib, topk_ids and topk_w are lgs_rasterize_topk_fwd's outputs for the
+ * same inputs (the recorded weights tell which Gaussians can be Top-K members).
  * Accumulates per-Gaussian screen-space gradients:
  *   dL_dmean2d[n*2], dL_dconic[n*3] (w.r.t. a, b, c), dL_dopacity[n], dL_drgb[n*3],
  *   dL_ddepth_g[n] (w.r.t. the depth z of each Gaussian).
@@ -473,8 +475,9 @@ lgs_status lgs_l1_grad(int64_t n, lgs_dtype dt, const void *x, const void *targe
  * pixel's Top-K list (a pixel's feature depends on its K rows alone, Eq. 3-4), so a table
  * that is zero except for the rows named in the last step's Top-K lists can be cleared
  * by zeroing those rows:
- *   step s:  lgs_zero_marked_rows(gen = s - 1)  ->  feature adjoint  ->
- *            lgs_mark_topk_rows(step s's topk_ids, gen = s)
+ *   step s:  lgs_zero_marked_rows(gen = s - 1), then lgs_mark_topk_rows(step s's
+ *            topk_ids, gen = s) (never before the zeroing: a row named in both steps would
+ *            keep its old values), then the feature adjoint
  * row_gen[n] (int32, caller memory) holds each row's last generation; start with the
  * table all zero and row_gen below every generation used (e.g. INT32_MIN).
  *
@@ -487,6 +490,22 @@ lgs_status lgs_mark_topk_rows(int64_t n_slots, const int32_t *topk_ids, int32_t 
                               hipStream_t stream);
 lgs_status lgs_zero_marked_rows(int32_t n, int32_t d, int32_t gen, const int32_t *row_gen, float *table,
                                 hipStream_t stream);
+
+/*
+ * Refresh of the storage form (the quantizers of lgs_quantize_features) for the rows the
+ * feature kernels will read.  A pixel's feature reads only the K rows of its Top-K list
+ * (Eq. 3-4), so after lgs_mark_topk_rows has stamped the step's Top-K rows with gen, the
+ * store is complete for that step's feature render and adjoint once these rows are
+ * converted from the FP32 master table; the other rows of dst are not touched and may
+ * hold older values.
+ *
+ * Quantizes row g of src [n][d] (FP32, d a multiple of 8, 16-byte aligned) into dst
+ * (dst_dt BF16 [n][d] or FP8 E4M3 codes [n][d] plus dst_scale[n]; 16-byte aligned) for
+ * every g with row_gen[g] == gen, with the same arithmetic as lgs_quantize_features (the
+ * same bits).
+ */
+lgs_status lgs_quantize_marked_rows(int32_t n, int32_t d, int32_t gen, const int32_t *row_gen, const float *src,
+                                   lgs_dtype dst_dt, void *dst, float *dst_scale, hipStream_t stream);
 
 /*
  * Number of distinct Gaussians over all pixels' Top-K slots (ids in [0, n) in

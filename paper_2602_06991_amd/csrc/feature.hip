@@ -52,14 +52,9 @@ __device__ __forceinline__ float amax4(f32x4 v, float m) {
     return fmaxf(fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
 }
 
-__global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const float *__restrict__ src,
-                                                        uint8_t *__restrict__ dst,
-                                                        float *__restrict__ scale) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= n) return;   // whole wave leaves together
-    const float *x = src + (long)row * D;
-    uint8_t *y = dst + (long)row * D;
+// Codes and scale of one row of D values, by one wave (lane = its lane index).
+__device__ __forceinline__ void fp8_row(const float *__restrict__ x, uint8_t *__restrict__ y,
+                                        float *__restrict__ scale_row, int D, int lane) {
     const int steps = (D + 511) >> 9;
     f32x4 v[kQSteps][2];
     float amax = 0.f;
@@ -101,7 +96,50 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const floa
         if (c < D)
             *(u32x2 *)(y + c) = (u32x2){e4m3x4(*(const f32x4 *)(x + c), inv), e4m3x4(*(const f32x4 *)(x + c + 4), inv)};
     }
-    if (lane == 0) scale[row] = sc;
+    if (lane == 0) *scale_row = sc;
+}
+
+__global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const float *__restrict__ src,
+                                                        uint8_t *__restrict__ dst,
+                                                        float *__restrict__ scale) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;   // whole wave leaves together
+    fp8_row(src + (long)row * D, dst + (long)row * D, scale + row, D, threadIdx.x & 63);
+}
+
+// BF16 codes of one row of D values by one wave: 8 channels per lane and step.
+__device__ __forceinline__ void bf16_row(const float *__restrict__ x, uint16_t *__restrict__ y, int D, int lane) {
+    for (int c = lane * 8; c < D; c += 512) {
+        const f32x4 a = *(const f32x4 *)(x + c), b = *(const f32x4 *)(x + c + 4);
+        u32x4 o;
+        o.x = (uint32_t)f32_to_bf16(a.x) | ((uint32_t)f32_to_bf16(a.y) << 16);
+        o.y = (uint32_t)f32_to_bf16(a.z) | ((uint32_t)f32_to_bf16(a.w) << 16);
+        o.z = (uint32_t)f32_to_bf16(b.x) | ((uint32_t)f32_to_bf16(b.y) << 16);
+        o.w = (uint32_t)f32_to_bf16(b.z) | ((uint32_t)f32_to_bf16(b.w) << 16);
+        *(u32x4 *)(y + c) = o;
+    }
+}
+
+// Quantizes the rows whose row_gen equals gen: each wave takes 64 rows, finds the marked
+// ones with a ballot and converts each with the whole wave.
+template <int DT>
+__global__ __launch_bounds__(256) void quant_marked_rows_kernel(int n, int D, int gen,
+                                                                const int *__restrict__ row_gen,
+                                                                const float *__restrict__ src, void *__restrict__ dst,
+                                                                float *__restrict__ scale) {
+    const int lane = threadIdx.x & 63;
+    const long r0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    if (r0 >= n) return;   // whole wave
+    const long r = r0 + lane;
+    unsigned long long m = __ballot(r < n && row_gen[r] == gen);
+    while (m) {
+        const long row = r0 + __builtin_ctzll(m);
+        m &= m - 1;
+        if constexpr (DT == LGS_BF16)
+            bf16_row(src + row * D, (uint16_t *)dst + row * D, D, lane);
+        else
+            fp8_row(src + row * D, (uint8_t *)dst + row * D, scale + row, D, lane);
+    }
 }
 
 __device__ __forceinline__ float l1_sign(float d, float g) { return d > 0.f ? g : (d < 0.f ? -g : 0.f); }
@@ -409,4 +447,25 @@ extern "C" lgs_status lgs_zero_marked_rows(int32_t n, int32_t d, int32_t gen, co
     hipLaunchKernelGGL(zero_marked_rows_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, n, d, gen,
                        row_gen, table);
     return check_launch("zero_marked_rows");
+}
+
+extern "C" lgs_status lgs_quantize_marked_rows(int32_t n, int32_t d, int32_t gen, const int32_t *row_gen,
+                                               const float *src, lgs_dtype dst_dt, void *dst, float *dst_scale,
+                                               hipStream_t stream) {
+    LGS_REQUIRE(n >= 0 && d > 0 && d % 8 == 0, LGS_ERR_INVALID_ARG, "lgs_quantize_marked_rows: bad sizes n=%d d=%d",
+                n, d);
+    if (n == 0) return LGS_OK;
+    LGS_REQUIRE(row_gen && src && dst, LGS_ERR_INVALID_ARG, "lgs_quantize_marked_rows: NULL pointer");
+    LGS_REQUIRE(aligned16(src) && aligned16(dst), LGS_ERR_INVALID_ARG, "src and dst must be 16-byte aligned");
+    const unsigned grid = (unsigned)((((long)n + 63) / 64 + 3) / 4);
+    if (dst_dt == LGS_BF16) {
+        hipLaunchKernelGGL(quant_marked_rows_kernel<LGS_BF16>, dim3(grid), dim3(256), 0, stream, n, d, gen, row_gen,
+                           src, dst, (float *)nullptr);
+        return check_launch("quantize marked rows bf16");
+    }
+    LGS_REQUIRE(dst_dt == LGS_FP8_E4M3, LGS_ERR_UNSUPPORTED, "quantize target must be BF16 or FP8");
+    LGS_REQUIRE(dst_scale, LGS_ERR_INVALID_ARG, "FP8 quantization needs dst_scale");
+    hipLaunchKernelGGL(quant_marked_rows_kernel<LGS_FP8_E4M3>, dim3(grid), dim3(256), 0, stream, n, d, gen, row_gen,
+                       src, dst, dst_scale);
+    return check_launch("quantize marked rows fp8");
 }

@@ -96,6 +96,7 @@ _SIG = {
     "lgs_union_count": [_I64, _I32, _I32, _P, _P, ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_mark_topk_rows": [_I64, _P, _I32, _I32, _P, _P],
     "lgs_zero_marked_rows": [_I32, _I32, _I32, _P, _P, _P],
+    "lgs_quantize_marked_rows": [_I32, _I32, _I32, _P, _P, ctypes.c_int, _P, _P, _P],
 }
 EXPORTS = ["lgs_abi_version", "lgs_last_error", "lgs_supported_k", *_SIG]
 
@@ -362,6 +363,10 @@ def lgs_mark_topk_rows(n_slots, topk_ids, n, gen, row_gen, stream=None):
 
 def lgs_zero_marked_rows(n, d, gen, row_gen, table, stream=None):
     return _check(load().lgs_zero_marked_rows(n, d, gen, row_gen, table, stream))
+
+
+def lgs_quantize_marked_rows(n, d, gen, row_gen, src, dst_dt, dst, dst_scale, stream=None):
+    return _check(load().lgs_quantize_marked_rows(n, d, gen, row_gen, src, dst_dt, dst, dst_scale, stream))
 
 
 def lgs_union_count(n_pix, k, n, topk_ids, flags, stream=None):

@@ -369,7 +369,9 @@ def l1_grad(x, target, scale):
 class SparseGradRows:
     """Clears a dense feature-gradient table [n, d] between steps by zeroing only the
     rows the previous step's Top-K lists named (the only rows the feature adjoint
-    writes).  Per step: clear(), then the adjoint, then mark(topk_ids)."""
+    writes).  Per step: clear(), mark(topk_ids), then the adjoint.  The same marks
+    name the rows of the quantized store the step's feature kernels read, which
+    quantize() refreshes from the FP32 table."""
 
     def __init__(self, table):
         self.table = table
@@ -385,6 +387,23 @@ class SparseGradRows:
         n = self.table.shape[0]
         lgs.lgs_mark_topk_rows(topk_ids.numel(), _p(topk_ids), n, self.gen, _p(self.row_gen), _stream())
         self.gen += 1
+
+    def quantize(self, feat, dtype, out):
+        """Refreshes the storage form `out` = (store, scale) from the FP32 table `feat`
+        in the rows the last mark() named (the rows the step's feature kernels read)."""
+        n, d = feat.shape
+        _need_cuda(feat)
+        store, scale = out
+        sdt = torch.bfloat16 if dtype == "bf16" else torch.uint8
+        if dtype not in ("bf16", "fp8") or store.shape != (n, d) or store.dtype != sdt or \
+                not (store.is_contiguous() and feat.is_contiguous()) or n != self.table.shape[0]:
+            raise ValueError("quantize: a contiguous [n, d] store of the storage dtype over the marked table")
+        if dtype == "fp8" and (scale is None or scale.shape != (n,) or scale.dtype != torch.float32):
+            raise ValueError("quantize: FP8 needs a float32 scale of n rows")
+        lgs.lgs_quantize_marked_rows(n, d, self.gen - 1, _p(self.row_gen), _p(feat),
+                                     lgs.LGS_BF16 if dtype == "bf16" else lgs.LGS_FP8_E4M3, _p(store),
+                                     _p(scale) if scale is not None else None, _stream())
+        return store, scale
 
 
 def union_count(ids, n):

@@ -147,3 +147,16 @@ def test_sparse_row_clearing_validation():
     with pytest.raises(lgs.LgsError) as e:
         lgs.lgs_zero_marked_rows(10, 8, 1, FAKE, FAKE + 4)  # table not 16-byte aligned
     assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+
+
+def test_marked_row_quantize_validation():
+    assert lgs.lgs_quantize_marked_rows(0, 8, 1, None, None, lgs.LGS_BF16, None, None) == lgs.LGS_OK
+    for args, status in [((10, 12, 1, FAKE, FAKE, lgs.LGS_BF16, FAKE, None), lgs.LGS_ERR_INVALID_ARG),   # d % 8
+                         ((-1, 8, 1, FAKE, FAKE, lgs.LGS_BF16, FAKE, None), lgs.LGS_ERR_INVALID_ARG),
+                         ((10, 8, 1, None, FAKE, lgs.LGS_BF16, FAKE, None), lgs.LGS_ERR_INVALID_ARG),
+                         ((10, 8, 1, FAKE, FAKE + 4, lgs.LGS_BF16, FAKE, None), lgs.LGS_ERR_INVALID_ARG),
+                         ((10, 8, 1, FAKE, FAKE, lgs.LGS_FP8_E4M3, FAKE, None), lgs.LGS_ERR_INVALID_ARG),
+                         ((10, 8, 1, FAKE, FAKE, lgs.LGS_F32, FAKE, None), lgs.LGS_ERR_UNSUPPORTED)]:
+        with pytest.raises(lgs.LgsError) as e:
+            lgs.lgs_quantize_marked_rows(*args)
+        assert e.value.status == status, args

@@ -40,6 +40,28 @@ def test_quantize_bit_exact(torch, orc, d):
     codes, scale = orc.fp8_quantize(x)
     np.testing.assert_array_equal(s.cpu().numpy(), scale)
     np.testing.assert_array_equal(q.cpu().numpy(), codes)
+    # the refresh of marked rows: the same bits in the rows stamped with gen, the other
+    # rows of the store untouched
+    from paper_2602_06991_amd import lgs
+    gen = 7
+    stamp = np.where(rng.random(n) < 0.3, gen, rng.choice([gen - 1, gen + 1, -2**31], n)).astype(np.int32)
+    stamp[:4] = gen
+    marked = stamp == gen
+    row_gen = torch.from_numpy(stamp).cuda()
+    b2 = torch.full((n, d), 0x7F7F, dtype=torch.int16, device="cuda").view(torch.bfloat16)
+    q2 = torch.full((n, d), 0x55, dtype=torch.uint8, device="cuda")
+    s2 = torch.full((n,), -1.0, device="cuda")
+    p = lambda a: a.data_ptr()
+    lgs.lgs_quantize_marked_rows(n, d, gen, p(row_gen), p(t), lgs.LGS_BF16, p(b2), None)
+    lgs.lgs_quantize_marked_rows(n, d, gen, p(row_gen), p(t), lgs.LGS_FP8_E4M3, p(q2), p(s2))
+    torch.cuda.synchronize()
+    b2 = b2.view(torch.int16).cpu().numpy().view(np.uint16)
+    np.testing.assert_array_equal(b2[marked], orc.bf16_bits(x)[marked])
+    assert (b2[~marked] == 0x7F7F).all()
+    q2, s2 = q2.cpu().numpy(), s2.cpu().numpy()
+    np.testing.assert_array_equal(q2[marked], codes[marked])
+    np.testing.assert_array_equal(s2[marked], scale[marked])
+    assert (q2[~marked] == 0x55).all() and (s2[~marked] == -1.0).all()
 
 
 @pytest.mark.parametrize("cfg", ["tiny", "c0", "c1"])
@@ -546,6 +568,50 @@ def test_prune_select_matches_oracle(torch, orc, n, below, ratio, seed):
     cand = count < below
     print(f"n={n}: candidates {cand.sum()}, survivors among them {want[cand].sum()}", flush=True)
     np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("form", ["bf16", "fp8"])
+def test_marked_row_refresh_feeds_the_feature_kernels_the_whole_table_bits(torch, form):
+    """A store refreshed only in the rows the step's Top-K lists stamp gives the one-pass
+    feature render + L1 adjoint exactly what the whole-table conversion gives, step after
+    step, while the FP32 master table changes between steps and the Top-K sets change
+    (three views of a room, then the first again): the map and dL/dw bit for bit, the
+    gradient rows to summation order."""
+    from paper_2602_06991_amd import render
+    sc = make_scene(3, N=60000, W=200, H=150, D=64)
+    g = sc.gaussians
+    n, d = g.n, g.d
+    feat = torch.from_numpy(np.ascontiguousarray(g.feat, np.float32)).cuda()
+    store = render.quantize(feat, form)                # rows refreshed below; the rest stale
+    rows = render.SparseGradRows(torch.zeros(n, d, device="cuda"))
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    for step, v in enumerate([0, 1, 2, 0]):
+        feat.add_(torch.randn(n, d, device="cuda", generator=gen), alpha=0.05)   # an optimiser's update
+        out, st = gpu_forward(g, sc.cameras[v], 4)
+        fw = st["fw"]
+        rows.clear()
+        rows.mark(fw["ids"])
+        rows.quantize(feat, form, store)
+        whole = render.quantize(feat, form)
+        target = torch.randn(fw["ids"].shape[0], fw["ids"].shape[1], d, device="cuda", generator=gen)
+        target = target.to(torch.bfloat16)
+        res = []
+        for s_, sc_ in (store, whole):
+            gf = torch.zeros(n, d, device="cuda")
+            F, dtw = render.feature_fwd_bwd_l1(fw["ids"], fw["w"], s_, sc_, form, "bf16", target, 1e-3, gf)
+            res.append((F, dtw, gf))
+        torch.cuda.synchronize()
+        (F0, w0, g0), (F1, w1, g1) = res
+        assert torch.equal(F0.view(torch.int16), F1.view(torch.int16)), step
+        assert torch.equal(w0, w1), step
+        rel = float((g0 - g1).norm() / g1.norm().clamp_min(1e-30))
+        assert rel <= 1e-6, (step, rel)
+        # the refreshed rows are the whole table's bits
+        ids = fw["ids"].reshape(-1)
+        used = torch.unique(ids[ids >= 0]).long()
+        assert torch.equal(store[0][used].view(torch.uint8), whole[0][used].view(torch.uint8)), step
+        if form == "fp8":
+            assert torch.equal(store[1][used], whole[1][used]), step
 
 
 def test_sparse_gradient_clearing_matches_dense(torch):
