@@ -374,12 +374,15 @@ def time_steps(torch, step, steps, warmup):
     total_ms = t0.elapsed_time(t1)
     kern = [a.elapsed_time(b) for a, b in step.kmarks]
     step.kmarks = None
-    phases, per_step = {}, []
+    # the per-phase steps run back to back as the timed ones do (a synchronization after
+    # each would let the GPU idle and its first kernels start cold), then one wait
+    phases, per_step, runs = {}, [], []
     for _ in range(steps):
         step.events = []
         step()
-        torch.cuda.synchronize()
-        ev = step.events
+        runs.append(step.events)
+    torch.cuda.synchronize()
+    for ev in runs:
         for (_, a), (name, b) in zip(ev[:-1], ev[1:]):
             phases.setdefault(name, []).append(a.elapsed_time(b))
         per_step.append(ev[0][1].elapsed_time(ev[-1][1]))

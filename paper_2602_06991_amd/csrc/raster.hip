@@ -187,7 +187,7 @@ constexpr int kBwdRows = kBwdThreads / 16;   // lane rows of 16 per block
 template <int K>
 __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
     RasterArgs a, const float *__restrict__ T_final, const int *__restrict__ n_contrib,
-    const int *__restrict__ topk_ids, const float *__restrict__ dL_dtopkw,
+    const int *__restrict__ topk_ids, const float *__restrict__ topk_w, const float *__restrict__ dL_dtopkw,
     const float *__restrict__ dL_dcolor, const float *__restrict__ dL_ddepth,
     const float *__restrict__ dL_dalpha, float *__restrict__ g_mean2d, float *__restrict__ g_conic,
     float *__restrict__ g_opac, float *__restrict__ g_rgb, float *__restrict__ g_depth) {
@@ -211,6 +211,12 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
     int last[kPPT];
     int ti[kPPT][K];
     float gam[kPPT][K];
+    // A pixel's Top-K members are the Gaussians whose weight reached its smallest recorded
+    // Top-K weight; the weights recomputed here differ from the recorded ones only by the
+    // rounding of T (relative 3 n 2^-24 over a list of n), so only a Gaussian whose weight
+    // passes wth (that smallest weight, over the slots with a nonzero dL/dw, less 1/64)
+    // can be a member that adds a gamma term, and only then are its K ids compared.
+    float wth[kPPT];
     const float fx = (float)px + 0.5f;
     int lmax = 0;
 #pragma unroll
@@ -219,6 +225,7 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
         fy[h] = (float)py + 0.5f;
         T[h] = 1.0f; gC0[h] = gC1[h] = gC2[h] = gD[h] = gO[h] = A[h] = 0.f;
         last[h] = 0;
+        wth[h] = __builtin_inff();
 #pragma unroll
         for (int k = 0; k < K; ++k) { ti[h][k] = -1; gam[h][k] = 0.f; }
         if (px < a.W && py < a.H) {
@@ -234,7 +241,9 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
             for (int k = 0; k < K; ++k) {
                 ti[h][k] = topk_ids[p * K + k];
                 gam[h][k] = dL_dtopkw ? dL_dtopkw[p * K + k] : 0.f;
+                if (ti[h][k] >= 0 && gam[h][k] != 0.f) wth[h] = fminf(wth[h], topk_w[p * K + k]);
             }
+            wth[h] *= 1.0f - 1.0f / 64.0f;
         }
     }
     if (t == 0) s_max = 0;
@@ -275,10 +284,12 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
                 T[h] *= r;                          // transmittance in front of this Gaussian
                 const float w = alpha * T[h];
                 const float4 cz = s_cz[j];
-                const int g = s_id[j];
                 float e = gC0[h] * cz.x + gC1[h] * cz.y + gC2[h] * cz.z + gD[h] * cz.w + gO[h];
+                if (w >= wth[h]) {
+                    const int g = s_id[j];
 #pragma unroll
-                for (int k = 0; k < K; ++k) e += (ti[h][k] == g) ? gam[h][k] : 0.f;
+                    for (int k = 0; k < K; ++k) e += (ti[h][k] == g) ? gam[h][k] : 0.f;
+                }
                 const float dal = T[h] * e - A[h] * r;
                 A[h] = fmaf(e, w, A[h]);
                 v[5] += w * gC0[h];
@@ -428,11 +439,11 @@ void launch_fwd(RasterArgs a, float *color, float *depth_map, float *alpha_map, 
 
 template <int K>
 void launch_bwd(RasterArgs a, const float *T_final, const int *n_contrib, const int *topk_ids,
-                const float *dL_dtopkw, const float *dL_dcolor, const float *dL_ddepth,
+                const float *topk_w, const float *dL_dtopkw, const float *dL_dcolor, const float *dL_ddepth,
                 const float *dL_dalpha, float *gm, float *gc, float *go, float *grgb, float *gz,
                 hipStream_t st) {
     hipLaunchKernelGGL(raster_bwd_kernel<K>, dim3(padded_grid((long long)a.ntx * a.nty * a.views)), dim3(kBwdThreads), 0,
-                       st, a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha,
+                       st, a, T_final, n_contrib, topk_ids, topk_w, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha,
                        gm, gc, go, grgb, gz);
 }
 
@@ -545,7 +556,7 @@ extern "C" lgs_status lgs_rasterize_topk_bwd_views(
     a.sorted_ids = sorted_ids;
     a.ranges = (const int2 *)tile_ranges;
 #define CALL_BWD(KK)                                                                             \
-    launch_bwd<KK>(a, T_final, n_contrib, topk_ids, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha, \
+    launch_bwd<KK>(a, T_final, n_contrib, topk_ids, topk_w, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha, \
                    dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream)
     LGS_K_SWITCH(k, CALL_BWD)
 #undef CALL_BWD
