@@ -127,6 +127,28 @@ def _side_join(st, done, topk_ids):
     return st.out
 
 
+def _grad_slab(torch, shapes, dev):
+    """One allocation holding a step's gradient buffers (each a view at a 256-byte
+    offset), so that one fill clears them all."""
+    sizes = [int(np.prod(s)) for s in shapes.values()]
+    offs, at = [], 0
+    for z in sizes:
+        offs.append(at)
+        at += (z + 63) // 64 * 64
+    flat = torch.zeros(at, device=dev)
+    return flat, {k: flat[o:o + z].view(*s) for (k, s), o, z in zip(shapes.items(), offs, sizes)}
+
+
+def _geometry_grads(torch, n, rec, dev):
+    """Screen-space gradients of `rec` records (rgb per Gaussian) and parameter
+    gradients of n Gaussians, in one slab."""
+    flat, b = _grad_slab(torch, dict(mean2d=(rec, 2), conic=(rec, 3), opacity=(rec,), rgb=(n, 3), depth=(rec,),
+                                     means=(n, 3), log_scales=(n, 3), quats=(n, 4), opacity_logits=(n,)), dev)
+    sg = {k: b[k] for k in ("mean2d", "conic", "opacity", "rgb", "depth")}
+    pg = {k: b[k] for k in ("means", "log_scales", "quats", "opacity_logits")}
+    return flat, sg, pg
+
+
 class Step:
     """All buffers of one frame's forward + backward, reused across steps."""
 
@@ -147,9 +169,7 @@ class Step:
         # cleared by zeroing the rows the previous step named (the vanilla adjoint writes
         # every blended Gaussian's row and clears the whole table)
         self.rows = None if vanilla else render.SparseGradRows(self.dfeat)
-        self.sg = render.screen_grad_buffers(n, dev)
-        self.pg = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
-                       quats=torch.empty(n, 4, device=dev), opacity_logits=torch.empty(n, device=dev))
+        self.gflat, self.sg, self.pg = _geometry_grads(torch, n, n, dev)
         self.npix = cam.width * cam.height
         self.events = None
         self.kmarks = None
@@ -186,10 +206,7 @@ class Step:
         self._mark("l1_grad")
         if self.vanilla:
             self.dfeat.zero_()
-        for v in self.sg.values():
-            v.zero_()
-        for v in self.pg.values():
-            v.zero_()
+        self.gflat.zero_()
         self._mark("zero_grads")
         # Eq. 9's L1 feature loss: its gradient is formed inside the feature adjoint
         if self.kmarks is not None:
@@ -238,9 +255,7 @@ class StepViews:
         dev = "cuda"
         self.dfeat = torch.zeros(n, d, device=dev)
         self.rows = render.SparseGradRows(self.dfeat)   # cleared row by row, as in Step
-        self.sg = render.screen_grad_buffers_views(n, self.V, dev)
-        self.pg = dict(means=torch.empty(n, 3, device=dev), log_scales=torch.empty(n, 3, device=dev),
-                       quats=torch.empty(n, 4, device=dev), opacity_logits=torch.empty(n, device=dev))
+        self.gflat, self.sg, self.pg = _geometry_grads(torch, n, n * self.V, dev)
         self.dpose = torch.empty(6 * self.V, device=dev)
         self.npix = cams[0].width * cams[0].height * self.V
         self.events = None
@@ -264,10 +279,7 @@ class StepViews:
         gC = r.l1_grad(fw["C"], tC, 1.0 / (3 * self.npix))
         gD = r.l1_grad(fw["D"], tD, 1.0 / self.npix)
         self._mark("l1_grad")
-        for v in self.sg.values():
-            v.zero_()
-        for v in self.pg.values():
-            v.zero_()
+        self.gflat.zero_()
         self.dpose.zero_()
         self._mark("zero_grads")
         if self.kmarks is not None:

@@ -52,93 +52,135 @@ __device__ __forceinline__ float amax4(f32x4 v, float m) {
     return fmaxf(fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
 }
 
-// Codes and scale of one row of D values, by one wave (lane = its lane index).
-__device__ __forceinline__ void fp8_row(const float *__restrict__ x, uint8_t *__restrict__ y,
-                                        float *__restrict__ scale_row, int D, int lane) {
+// Codes and scales of NR rows of D values, by one wave (lane = its lane index): the
+// loads of all NR rows are issued before the first row's maximum is taken.  rows[u] < 0
+// skips row u (the same for every lane).
+template <int NR>
+__device__ __forceinline__ void fp8_rows(const float *__restrict__ src, uint8_t *__restrict__ dst,
+                                         float *__restrict__ scale, const long (&rows)[NR], int D, int lane) {
     const int steps = (D + 511) >> 9;
-    f32x4 v[kQSteps][2];
-    float amax = 0.f;
+    f32x4 v[NR][kQSteps][2];
+    float amax[NR];
 #pragma unroll
-    for (int s = 0; s < kQSteps; ++s) {
-        const int c = s * 512 + lane * 8;
-        v[s][0] = v[s][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
-        if (c < D) {
-            v[s][0] = *(const f32x4 *)(x + c);
-            v[s][1] = *(const f32x4 *)(x + c + 4);
+    for (int u = 0; u < NR; ++u) {
+        amax[u] = 0.f;
+        const float *x = src + (rows[u] < 0 ? 0 : rows[u]) * D;
+#pragma unroll
+        for (int s = 0; s < kQSteps; ++s) {
+            const int c = s * 512 + lane * 8;
+            v[u][s][0] = v[u][s][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            if (rows[u] >= 0 && c < D) {
+                v[u][s][0] = *(const f32x4 *)(x + c);
+                v[u][s][1] = *(const f32x4 *)(x + c + 4);
+            }
         }
-        amax = amax4(v[s][1], amax4(v[s][0], amax));
     }
-    for (int s = kQSteps; s < steps; ++s) {
-        const int c = s * 512 + lane * 8;
-        if (c < D) amax = amax4(*(const f32x4 *)(x + c + 4), amax4(*(const f32x4 *)(x + c), amax));
-    }
-    amax = wave_max(amax);
-    // s = 2^floor(log2(amax / 224)): with amax = m 2^E (m in [1, 2)) the exponent is
-    // E - 7, less one when m < 1.75
-    int e = 0;
-    if (amax > 0.f) {
-        uint32_t u = __float_as_uint(amax);
-        int E = (int)(u >> 23) - 127;
-        uint32_t mant = u & 0x7FFFFFu;
-        e = E - 7 - (mant < 0x600000u ? 1 : 0);
-        if ((u >> 23) == 0) e = -126;      // subnormal amax
-        e = max(e, -126);
-    }
-    const float sc = __uint_as_float((uint32_t)(127 + e) << 23);
-    const float inv = __uint_as_float((uint32_t)(127 - e) << 23);
 #pragma unroll
-    for (int s = 0; s < kQSteps; ++s) {
-        const int c = s * 512 + lane * 8;
-        if (c < D) *(u32x2 *)(y + c) = (u32x2){e4m3x4(v[s][0], inv), e4m3x4(v[s][1], inv)};
+    for (int u = 0; u < NR; ++u) {
+        if (rows[u] < 0) continue;
+        const float *x = src + rows[u] * D;
+        uint8_t *y = dst + rows[u] * D;
+        float am = 0.f;
+#pragma unroll
+        for (int s = 0; s < kQSteps; ++s) am = amax4(v[u][s][1], amax4(v[u][s][0], am));
+        for (int s = kQSteps; s < steps; ++s) {
+            const int c = s * 512 + lane * 8;
+            if (c < D) am = amax4(*(const f32x4 *)(x + c + 4), amax4(*(const f32x4 *)(x + c), am));
+        }
+        am = wave_max(am);
+        // s = 2^floor(log2(amax / 224)): with amax = m 2^E (m in [1, 2)) the exponent is
+        // E - 7, less one when m < 1.75
+        int e = 0;
+        if (am > 0.f) {
+            uint32_t uu = __float_as_uint(am);
+            int E = (int)(uu >> 23) - 127;
+            uint32_t mant = uu & 0x7FFFFFu;
+            e = E - 7 - (mant < 0x600000u ? 1 : 0);
+            if ((uu >> 23) == 0) e = -126;      // subnormal amax
+            e = max(e, -126);
+        }
+        const float sc = __uint_as_float((uint32_t)(127 + e) << 23);
+        const float inv = __uint_as_float((uint32_t)(127 - e) << 23);
+#pragma unroll
+        for (int s = 0; s < kQSteps; ++s) {
+            const int c = s * 512 + lane * 8;
+            if (c < D) *(u32x2 *)(y + c) = (u32x2){e4m3x4(v[u][s][0], inv), e4m3x4(v[u][s][1], inv)};
+        }
+        for (int s = kQSteps; s < steps; ++s) {
+            const int c = s * 512 + lane * 8;
+            if (c < D)
+                *(u32x2 *)(y + c) =
+                    (u32x2){e4m3x4(*(const f32x4 *)(x + c), inv), e4m3x4(*(const f32x4 *)(x + c + 4), inv)};
+        }
+        if (lane == 0) scale[rows[u]] = sc;
     }
-    for (int s = kQSteps; s < steps; ++s) {
-        const int c = s * 512 + lane * 8;
-        if (c < D)
-            *(u32x2 *)(y + c) = (u32x2){e4m3x4(*(const f32x4 *)(x + c), inv), e4m3x4(*(const f32x4 *)(x + c + 4), inv)};
-    }
-    if (lane == 0) *scale_row = sc;
 }
 
 __global__ __launch_bounds__(256) void quant_fp8_kernel(int n, int D, const float *__restrict__ src,
                                                         uint8_t *__restrict__ dst,
                                                         float *__restrict__ scale) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= n) return;   // whole wave leaves together
-    fp8_row(src + (long)row * D, dst + (long)row * D, scale + row, D, threadIdx.x & 63);
+    const long rows[1] = {row};
+    fp8_rows<1>(src, dst, scale, rows, D, threadIdx.x & 63);
 }
 
-// BF16 codes of one row of D values by one wave: 8 channels per lane and step.
-__device__ __forceinline__ void bf16_row(const float *__restrict__ x, uint16_t *__restrict__ y, int D, int lane) {
+__device__ __forceinline__ uint32_t bf16x2(float a, float b) {
+    return (uint32_t)f32_to_bf16(a) | ((uint32_t)f32_to_bf16(b) << 16);
+}
+
+// BF16 codes of NR rows of D values by one wave, 8 channels per lane and step; the
+// loads of all NR rows of a step are issued before the first conversion.  rows[u] < 0
+// skips row u (the same for every lane).
+template <int NR>
+__device__ __forceinline__ void bf16_rows(const float *__restrict__ src, uint16_t *__restrict__ dst,
+                                          const long (&rows)[NR], int D, int lane) {
     for (int c = lane * 8; c < D; c += 512) {
-        const f32x4 a = *(const f32x4 *)(x + c), b = *(const f32x4 *)(x + c + 4);
-        u32x4 o;
-        o.x = (uint32_t)f32_to_bf16(a.x) | ((uint32_t)f32_to_bf16(a.y) << 16);
-        o.y = (uint32_t)f32_to_bf16(a.z) | ((uint32_t)f32_to_bf16(a.w) << 16);
-        o.z = (uint32_t)f32_to_bf16(b.x) | ((uint32_t)f32_to_bf16(b.y) << 16);
-        o.w = (uint32_t)f32_to_bf16(b.z) | ((uint32_t)f32_to_bf16(b.w) << 16);
-        *(u32x4 *)(y + c) = o;
+        f32x4 a[NR], b[NR];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            if (rows[u] < 0) continue;
+            a[u] = *(const f32x4 *)(src + rows[u] * D + c);
+            b[u] = *(const f32x4 *)(src + rows[u] * D + c + 4);
+        }
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            if (rows[u] < 0) continue;
+            *(u32x4 *)(dst + rows[u] * D + c) =
+                (u32x4){bf16x2(a[u].x, a[u].y), bf16x2(a[u].z, a[u].w), bf16x2(b[u].x, b[u].y), bf16x2(b[u].z, b[u].w)};
+        }
     }
 }
 
 // Quantizes the rows whose row_gen equals gen: each wave takes 64 rows, finds the marked
-// ones with a ballot and converts each with the whole wave.
+// ones with a ballot and converts them with the whole wave, NR rows at a time (Top-K ids
+// cluster, so one wave may hold dozens of marked rows, and one row at a time would wait
+// a full load latency per row).
 template <int DT>
 __global__ __launch_bounds__(256) void quant_marked_rows_kernel(int n, int D, int gen,
                                                                 const int *__restrict__ row_gen,
                                                                 const float *__restrict__ src, void *__restrict__ dst,
                                                                 float *__restrict__ scale) {
+    constexpr int NR = DT == LGS_BF16 ? 8 : 2;
     const int lane = threadIdx.x & 63;
     const long r0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
     if (r0 >= n) return;   // whole wave
     const long r = r0 + lane;
     unsigned long long m = __ballot(r < n && row_gen[r] == gen);
     while (m) {
-        const long row = r0 + __builtin_ctzll(m);
-        m &= m - 1;
+        long rows[NR];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            rows[u] = -1;
+            if (m) {
+                rows[u] = r0 + __builtin_ctzll(m);
+                m &= m - 1;
+            }
+        }
         if constexpr (DT == LGS_BF16)
-            bf16_row(src + row * D, (uint16_t *)dst + row * D, D, lane);
+            bf16_rows<NR>(src, (uint16_t *)dst, rows, D, lane);
         else
-            fp8_row(src + row * D, (uint8_t *)dst + row * D, scale + row, D, lane);
+            fp8_rows<NR>(src, (uint8_t *)dst, scale, rows, D, lane);
     }
 }
 
