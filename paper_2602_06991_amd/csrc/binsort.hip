@@ -28,6 +28,9 @@ constexpr int kSortIptBig = 16;
 constexpr int kSortItems = kSortThreads * kSortIpt;   // the smallest block: sizes the histogram
 constexpr long kBigPass = 1L << 22;
 constexpr int kScanItems = 4096;
+// Depth key of a record that touches no tile: sorts last, and the depth sort's first
+// pass drops it (a positive depth's bit pattern never has the sign bit).
+constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 
 // Exclusive scan of one value per thread over a 256-thread block.
 template <typename T>
@@ -54,7 +57,7 @@ __global__ __launch_bounds__(256) void depth_keys_kernel(int n, const float *__r
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     // positive depths order like their bit patterns; culled Gaussians go last
-    keys[i] = touched[i] > 0 ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
+    keys[i] = touched[i] > 0 ? __float_as_uint(depth[i]) : kDropKey;
     vals[i] = i;
 }
 
@@ -81,7 +84,8 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
                                                                   int n, const long long *__restrict__ n_dev,
-                                                                  int shift, int nb, int *__restrict__ hist) {
+                                                                  int shift, bool drop, int nb,
+                                                                  int *__restrict__ hist) {
     __shared__ int h[256];
     const int t = threadIdx.x, lane = t & 63;
     n = items_of(n, n_dev);
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
     }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const bool valid = base + r * kSortThreads + t < n;
+        const bool valid = base + r * kSortThreads + t < n && !(drop && k[r] == kDropKey);
         const uint32_t d = (k[r] >> shift) & 255u;
         const uint64_t m = digit_peers(d, valid);
         if (valid && (m & lt) == 0) atomicAdd(&h[d], __popcll(m));
@@ -134,8 +138,8 @@ __global__ __launch_bounds__(256) void radix_scan_digits_kernel(int *__restrict_
 template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ kin, const int *__restrict__ vin, int n, const long long *__restrict__ n_dev,
-    int shift, int nb, const int *__restrict__ hist, const int *__restrict__ totals, uint32_t *__restrict__ kout,
-    int *__restrict__ vout) {
+    int shift, bool drop, long long *__restrict__ n_out, int nb, const int *__restrict__ hist,
+    const int *__restrict__ totals, uint32_t *__restrict__ kout, int *__restrict__ vout) {
     constexpr int kItems = kSortThreads * IPT;
     n = items_of(n, n_dev);
     const long b0 = (long)blockIdx.x * kItems;
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     }
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        const bool valid = wave * 64 * IPT + r * 64 + lane < cnt;
+        const bool valid = wave * 64 * IPT + r * 64 + lane < cnt && !(drop && key[r] == kDropKey);
         const uint32_t d = (key[r] >> shift) & 255u;
         const uint64_t m = digit_peers(d, valid);
         const int lead = m ? __builtin_ctzll(m) : 0;
@@ -171,23 +175,25 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         off[r] = before + __popcll(m & lt);
     }
     __syncthreads();
+    int kept;   // the block's items that take part (all but dropped ones)
     {
         // digit t: the block's first slot of the digit, each wave's first slot within it,
         // and the global slot the block's run of the digit starts at
         const int c0 = s_cnt[0][t], c1 = s_cnt[1][t], c2 = s_cnt[2][t], c3 = s_cnt[3][t];
-        int tot;
-        const int start = block_exscan256(c0 + c1 + c2 + c3, s_scan, tot);
+        const int start = block_exscan256(c0 + c1 + c2 + c3, s_scan, kept);
         s_cnt[0][t] = start;
         s_cnt[1][t] = start + c0;
         s_cnt[2][t] = start + c0 + c1;
         s_cnt[3][t] = start + c0 + c1 + c2;
-        const int gstart = block_exscan256(totals[t], s_scan, tot);
+        int all;
+        const int gstart = block_exscan256(totals[t], s_scan, all);
         s_dst[t] = gstart + hist[t * nb + blockIdx.x] - start;
+        if (n_out && blockIdx.x == 0 && t == 0) *n_out = all;   // the items the pass kept
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
-        if (wave * 64 * IPT + r * 64 + lane < cnt) {
+        if (wave * 64 * IPT + r * 64 + lane < cnt && !(drop && key[r] == kDropKey)) {
             const int p = s_cnt[wave][(key[r] >> shift) & 255u] + off[r];
             s_key[p] = key[r];
             s_val[p] = val[r];
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
         const int i = r * kSortThreads + t;
-        if (i < cnt) {
+        if (i < kept) {
             const uint32_t k = s_key[i];
             const int dst = s_dst[(k >> shift) & 255u] + i;
             kout[dst] = k;
@@ -208,11 +214,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 
 // ---------------------------------------------------------------- int64 scan
 
-__global__ __launch_bounds__(256) void gather_counts_kernel(int n, const int *__restrict__ order,
+// Pair counts in depth order; the entries past the kept records (n_kept) count zero.
+__global__ __launch_bounds__(256) void gather_counts_kernel(int n, const long long *__restrict__ n_kept,
+                                                            const int *__restrict__ order,
                                                             const int *__restrict__ touched,
                                                             long long *__restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) cnt[i] = touched[order[i]];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cnt[i] = i < items_of(n, n_kept) ? touched[order[i]] : 0;
 }
 
 __global__ __launch_bounds__(256) void scan_partial_kernel(const long long *__restrict__ in, long n,
@@ -275,7 +283,8 @@ __global__ __launch_bounds__(256) void scan_final_kernel(const long long *__rest
 // Gaussian covering hundreds of tiles does not hold up its wave.
 // Records of several views are binned together: record r belongs to view r / n_view,
 // whose tiles take keys view * T + tile, so one stable sort orders (view, tile).
-__global__ __launch_bounds__(256) void duplicate_kernel(int n, const int *__restrict__ order,
+__global__ __launch_bounds__(256) void duplicate_kernel(int n, const long long *__restrict__ n_kept,
+                                                        const int *__restrict__ order,
                                                         const long long *__restrict__ offs,
                                                         const int4 *__restrict__ rect,
                                                         const int *__restrict__ touched, int ntx,
@@ -287,6 +296,7 @@ __global__ __launch_bounds__(256) void duplicate_kernel(int n, const int *__rest
     __shared__ int4 s_rect[256];
     __shared__ long long s_base;
     __shared__ int s_total;
+    n = items_of(n, n_kept);   // the records the depth sort kept
     const int t = threadIdx.x;
     const int s = blockIdx.x * 256 + t;
     int g = -1, c = 0;
@@ -346,22 +356,38 @@ __global__ __launch_bounds__(256) void zero_ranges_kernel(int n2, int *__restric
 
 // Run boundaries of the sorted tile keys; keys outside [0, T) (a caller's box past the
 // tile grid) mark nothing.
+// Each thread takes four consecutive keys (one 16-byte load; keys 16-byte aligned) and
+// their two neighbours.
 __global__ __launch_bounds__(256) void mark_ranges_kernel(int m, const long long *__restrict__ m_dev,
                                                           const uint32_t *__restrict__ keys, uint32_t T,
                                                           int *__restrict__ ranges) {
     m = items_of(m, m_dev);
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    uint32_t k = keys[i];
-    if (k >= T) return;
-    if (i == 0 || keys[i - 1] != k) ranges[2 * k] = i;
-    if (i == m - 1 || keys[i + 1] != k) ranges[2 * k + 1] = i + 1;
+    const long i0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= m) return;
+    uint32_t k[6];   // keys i0 - 1 .. i0 + 4 (the ends are only read inside [0, m))
+    k[0] = i0 > 0 ? keys[i0 - 1] : 0u;
+    if (i0 + 4 <= m) {
+        const uint4 v = *(const uint4 *)(keys + i0);
+        k[1] = v.x; k[2] = v.y; k[3] = v.z; k[4] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < m ? keys[i0 + j] : 0u;
+    }
+    k[5] = i0 + 4 < m ? keys[i0 + 4] : 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const long i = i0 + j;
+        const uint32_t kk = k[1 + j];
+        if (i >= m || kk >= T) continue;
+        if (i == 0 || k[j] != kk) ranges[2 * kk] = (int)i;
+        if (i == m - 1 || k[2 + j] != kk) ranges[2 * kk + 1] = (int)(i + 1);
+    }
 }
 
 // ---------------------------------------------------------------- host side
 
 struct Layout {
-    size_t dk0, dv0, dk1, dv1, cnt, offs, sums, total, hist, totals, pk0, pk1, pv1, bytes;
+    size_t dk0, dv0, dk1, dv1, cnt, offs, sums, total, kept, hist, totals, pk0, pk1, pv1, bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -385,6 +411,7 @@ Layout layout_of(long n, long max_pairs) {
     L.offs = take(8 * (size_t)n);
     L.sums = take(8 * (size_t)(nb_scan + 1));
     L.total = take(8);
+    L.kept = take(8);
     L.hist = take(4 * 256 * (size_t)(nb_sort + 1));
     L.totals = take(4 * 256);
     L.pk0 = take(4 * (size_t)max_pairs);
@@ -398,21 +425,23 @@ Layout layout_of(long n, long max_pairs) {
 // n_dev is given: the grid is sized for n).
 template <int IPT>
 void radix_launch(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int n, const long long *n_dev,
-                  int shift, int *hist, int *totals, hipStream_t st) {
+                  int shift, bool drop, long long *n_out, int *hist, int *totals, hipStream_t st) {
     const int nb = (int)(((long)n + kSortThreads * IPT - 1) / (kSortThreads * IPT));
-    hipLaunchKernelGGL(radix_hist_kernel<IPT>, dim3(nb), dim3(kSortThreads), 0, st, kin, n, n_dev, shift, nb,
+    hipLaunchKernelGGL(radix_hist_kernel<IPT>, dim3(nb), dim3(kSortThreads), 0, st, kin, n, n_dev, shift, drop, nb,
                        hist);
     hipLaunchKernelGGL(radix_scan_digits_kernel, dim3(256), dim3(256), 0, st, hist, nb, totals);
     hipLaunchKernelGGL(radix_scatter_kernel<IPT>, dim3(nb), dim3(kSortThreads), 0, st, kin, vin, n, n_dev, shift,
-                       nb, hist, totals, kout, vout);
+                       drop, n_out, nb, hist, totals, kout, vout);
 }
 
+// drop: items keyed kDropKey leave the sort (n_out, if given, receives the kept count).
 lgs_status radix_pass(const uint32_t *kin, const int *vin, uint32_t *kout, int *vout, int n,
-                      const long long *n_dev, int shift, int *hist, int *totals, hipStream_t st) {
+                      const long long *n_dev, int shift, int *hist, int *totals, hipStream_t st,
+                      bool drop = false, long long *n_out = nullptr) {
     if (n >= kBigPass)
-        radix_launch<kSortIptBig>(kin, vin, kout, vout, n, n_dev, shift, hist, totals, st);
+        radix_launch<kSortIptBig>(kin, vin, kout, vout, n, n_dev, shift, drop, n_out, hist, totals, st);
     else
-        radix_launch<kSortIpt>(kin, vin, kout, vout, n, n_dev, shift, hist, totals, st);
+        radix_launch<kSortIpt>(kin, vin, kout, vout, n, n_dev, shift, drop, n_out, hist, totals, st);
     return check_launch("radix pass");
 }
 
@@ -469,20 +498,23 @@ lgs_status bin_sort_on(const lgs_camera *cam, int32_t views, int32_t n_view, con
     int *dv0 = (int *)(ws + L.dv0), *dv1 = (int *)(ws + L.dv1);
     long long *cnt = (long long *)(ws + L.cnt), *offs = (long long *)(ws + L.offs);
     long long *sums = (long long *)(ws + L.sums), *total = (long long *)(ws + L.total);
+    long long *kept = (long long *)(ws + L.kept);
     int *hist = (int *)(ws + L.hist), *totals = (int *)(ws + L.totals);
 
-    // 1. sort Gaussians by depth key (4 passes of 8 bits), ending in dk0/dv0
+    // 1. sort Gaussians by depth key (4 passes of 8 bits), ending in dk0/dv0; the first
+    // pass drops the records that touch no tile, the later ones sort the kept count
     unsigned g1 = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(depth_keys_kernel, dim3(g1), dim3(256), 0, stream, n, depth, tiles_touched,
                        dk0, dv0);
     for (int pass = 0; pass < 4; ++pass) {
         bool even = (pass & 1) == 0;
         st = radix_pass(even ? dk0 : dk1, even ? dv0 : dv1, even ? dk1 : dk0, even ? dv1 : dv0, n,
-                        nullptr, 8 * pass, hist, totals, stream);
+                        pass == 0 ? nullptr : kept, 8 * pass, hist, totals, stream, pass == 0,
+                        pass == 0 ? kept : nullptr);
         if (st) return st;
     }
     // 2. pair offsets in depth order
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(g1), dim3(256), 0, stream, n, dv0, tiles_touched,
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(g1), dim3(256), 0, stream, n, kept, dv0, tiles_touched,
                        cnt);
     int nbs = (n + kScanItems - 1) / kScanItems;
     hipLaunchKernelGGL(scan_partial_kernel, dim3(nbs), dim3(256), 0, stream, cnt, (long)n, sums);
@@ -520,7 +552,7 @@ lgs_status bin_sort_on(const lgs_camera *cam, int32_t views, int32_t n_view, con
     int *pv0 = sorted_ids;
     uint32_t *kcur = pk0, *knext = pk1;
     int *vcur = (passes % 2 == 0) ? pv0 : pv1, *vnext = (passes % 2 == 0) ? pv1 : pv0;
-    hipLaunchKernelGGL(duplicate_kernel, dim3(g1), dim3(256), 0, stream, n, dv0, offs,
+    hipLaunchKernelGGL(duplicate_kernel, dim3(g1), dim3(256), 0, stream, n, kept, dv0, offs,
                        (const int4 *)tile_rect, tiles_touched, ntx, n_view > 0 ? n_view : 1, T1,
                        (long long)max_pairs, kcur, vcur);
     st = check_launch("bin_sort duplicate");
@@ -531,7 +563,7 @@ lgs_status bin_sort_on(const lgs_camera *cam, int32_t views, int32_t n_view, con
         uint32_t *tk = kcur; kcur = knext; knext = tk;
         int *tv = vcur; vcur = vnext; vnext = tv;
     }
-    hipLaunchKernelGGL(mark_ranges_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(mark_ranges_kernel, dim3((unsigned)((M + 1023) / 1024)), dim3(256), 0, stream,
                        (int)M, M_dev, kcur, (uint32_t)T, tile_ranges);
     return check_launch("bin_sort ranges");
 }

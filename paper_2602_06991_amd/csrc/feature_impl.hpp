@@ -1202,9 +1202,13 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
     const int px = tg.tx0 + (t & 15), py = tg.ty0 + (t >> 4);
     if (px >= W || py >= H) return;
     const long p = (long)tg.view * W * H + (long)py * W + px;
+    // the pixel's slots come back from the slot table (its union indices, and w'_k in wd,
+    // 0 for an empty slot), so they need no registers through the slab loop
     float gk[K], mean = 0.f;
+    int uk[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+        uk[k] = st.u[t * K + k];
         float v;
         if constexpr (RS) {
             v = gsum[t * K + k];
@@ -1213,12 +1217,12 @@ __device__ __forceinline__ void mf_backward(const TileGeom &tg, int W, int H, in
             v += sred[(2 * kTilePix + t) * K + k];
             v += sred[(3 * kTilePix + t) * K + k];
         }
-        if constexpr (FT == FT_FP8) v *= s.u[k] >= 0 ? L.uscale2[s.u[k]] : 0.f;
-        gk[k] = s.u[k] >= 0 ? v : 0.f;
-        mean = fmaf(s.wp[k], gk[k], mean);
+        if constexpr (FT == FT_FP8) v *= uk[k] >= 0 ? L.uscale2[uk[k]] : 0.f;
+        gk[k] = uk[k] >= 0 ? v : 0.f;
+        mean = fmaf(st.wd[t * K + k], gk[k], mean);
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) dtw[p * K + k] = s.u[k] >= 0 ? (gk[k] - mean) / s.W : 0.f;
+    for (int k = 0; k < K; ++k) dtw[p * K + k] = uk[k] >= 0 ? (gk[k] - mean) / s.W : 0.f;
 }
 
 // ---------------------------------------------------------------- forward
