@@ -357,38 +357,99 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
     d_opl[g] += acc.opl;
 }
 
-constexpr int kPoseBlocks = 512;   // blocks per view of the pose reduction: at most this many atomics per component
+constexpr int kPoseGrid = 2048;   // blocks of the pose reduction: at most this many atomics per component
 
-// Camera-pose gradient of every view (blockIdx.y): a block sum per component, one
-// atomic per block; the grid strides over the Gaussians.
-__global__ __launch_bounds__(256) void project_pose_kernel(
-    CamSet cs, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
+// The projection adjoint with the camera-pose gradient of every view (Sec. 4.1), in one
+// pass: the grid strides over the Gaussians; per Gaussian the views are walked in order,
+// its parameter gradients (PARAMS) summed and written once as in project_bwd_kernel
+// (the same bits), and its share of each view's pose gradient added to the thread's
+// registers (MAXV >= views).  Each block then sums every view's six components (wave
+// sums, the four wave partials in a fixed order) and adds them with one atomic each.
+template <bool PARAMS, int MAXV>
+__global__ __launch_bounds__(256) void project_bwd_pose_kernel(
+    CamSet cs, int views, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
     const float *__restrict__ quats, const float *__restrict__ opacity_logits,
     const float *__restrict__ rgb, const float *__restrict__ d_mean2d,
     const float *__restrict__ d_conic, const float *__restrict__ d_opac,
-    const float *__restrict__ d_depth, float *__restrict__ d_pose) {
-    const int v = blockIdx.y;
-    const CamDev &c = cs.c[v];
-    float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float *__restrict__ d_depth, float *__restrict__ d_means, float *__restrict__ d_ls,
+    float *__restrict__ d_quats, float *__restrict__ d_opl, float *__restrict__ d_pose) {
+    float pose[MAXV][6];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) pose[v][q] = 0.f;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
-        Splat s;
-        if (!splat_of(c, g, means, log_scales, quats, opacity_logits, rgb, s)) continue;
-        ParamGrad unused;
-        float sh[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        project_bwd_one<false, true>(c, (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, unused, sh);
-        for (int q = 0; q < 6; ++q) pose[q] += sh[q];
+        ParamGrad acc = {};
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < MAXV; ++v) {
+            if (v >= views) break;
+            Splat s;
+            if (!splat_of(cs.c[v], g, means, log_scales, quats, opacity_logits, rgb, s)) continue;
+            ParamGrad pg;
+            float sh[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            project_bwd_one<PARAMS, true>(cs.c[v], (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, pg, sh);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) pose[v][q] += sh[q];
+            if constexpr (PARAMS) {
+                if (!any) {
+                    acc = pg;
+                    any = true;
+                    continue;
+                }
+                for (int j = 0; j < 3; ++j) acc.mu[j] += pg.mu[j];
+                for (int j = 0; j < 3; ++j) acc.ls[j] += pg.ls[j];
+                for (int j = 0; j < 4; ++j) acc.q[j] += pg.q[j];
+                acc.opl += pg.opl;
+            }
+        }
+        if constexpr (PARAMS) {
+            if (any) {
+                for (int j = 0; j < 3; ++j) d_means[3 * g + j] += acc.mu[j];
+                for (int j = 0; j < 3; ++j) d_ls[3 * g + j] += acc.ls[j];
+                for (int j = 0; j < 4; ++j) d_quats[4 * g + j] += acc.q[j];
+                d_opl[g] += acc.opl;
+            }
+        }
     }
-    __shared__ float part[4][6];
-    float sum[6];
-    wave_sum_many<6>(pose, sum);
+    // every lane of the block takes part in the sums
+    __shared__ float part[4][MAXV][6];
     const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        for (int q = 0; q < 6; ++q) part[wave][q] = sum[q];
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const float val = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
-        if (val != 0.f) unsafeAtomicAdd(&d_pose[6 * v + threadIdx.x], val);
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        if (v >= views) break;
+        float sum[6];
+        wave_sum_many<6>(pose[v], sum);
+        if ((threadIdx.x & 63) == 0)
+            for (int q = 0; q < 6; ++q) part[wave][v][q] = sum[q];
     }
+    __syncthreads();
+    if ((int)threadIdx.x < 6 * views) {
+        const int v = threadIdx.x / 6, q = threadIdx.x - 6 * v;
+        const float val = (part[0][v][q] + part[1][v][q]) + (part[2][v][q] + part[3][v][q]);
+        if (val != 0.f) unsafeAtomicAdd(&d_pose[6 * v + q], val);
+    }
+}
+
+template <bool PARAMS>
+void launch_bwd_pose(const CamSet &cs, int views, int n, const float *means, const float *log_scales,
+                     const float *quats, const float *opacity_logits, const float *rgb, const float *d_mean2d,
+                     const float *d_conic, const float *d_opac, const float *d_depth, float *d_means, float *d_ls,
+                     float *d_quats, float *d_opl, float *d_pose, hipStream_t st) {
+    const unsigned grid = (unsigned)std::min<long>(((long)n + 255) / 256, kPoseGrid);
+#define POSE_CALL(MV)                                                                                            \
+    hipLaunchKernelGGL((project_bwd_pose_kernel<PARAMS, MV>), dim3(grid), dim3(256), 0, st, cs, views, n, means, \
+                       log_scales, quats, opacity_logits, rgb, d_mean2d, d_conic, d_opac, d_depth, d_means, d_ls,  \
+                       d_quats, d_opl, d_pose)
+    if (views <= 2)
+        POSE_CALL(2);
+    else if (views <= 4)
+        POSE_CALL(4);
+    else if (views <= 8)
+        POSE_CALL(8);
+    else
+        POSE_CALL(16);
+#undef POSE_CALL
 }
 
 // Host-side set of cameras; all views must share the image size.
@@ -463,15 +524,17 @@ extern "C" lgs_status lgs_project_bwd_views(const lgs_camera *cams, int32_t view
     LGS_REQUIRE(means && log_scales && quats && opacity_logits && rgb && dL_dmean2d && dL_dconic && dL_dopacity &&
                     dL_ddepth_g,
                 LGS_ERR_INVALID_ARG, "lgs_project_bwd: NULL input");
-    if (nparams)
+    if (!dL_dpose)
         hipLaunchKernelGGL(project_bwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, cs, views, n, means,
                            log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic, dL_dopacity, dL_ddepth_g,
                            dL_dmeans, dL_dlog_scales, dL_dquats, dL_dopacity_logits);
-    if (dL_dpose) {
-        const unsigned gx = (unsigned)std::min<long>((n + 255) / 256, kPoseBlocks);
-        hipLaunchKernelGGL(project_pose_kernel, dim3(gx, views), dim3(256), 0, stream, cs, n, means, log_scales,
-                           quats, opacity_logits, rgb, dL_dmean2d, dL_dconic, dL_dopacity, dL_ddepth_g, dL_dpose);
-    }
+    else if (nparams)
+        launch_bwd_pose<true>(cs, views, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,
+                              dL_dopacity, dL_ddepth_g, dL_dmeans, dL_dlog_scales, dL_dquats, dL_dopacity_logits,
+                              dL_dpose, stream);
+    else
+        launch_bwd_pose<false>(cs, views, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,
+                               dL_dopacity, dL_ddepth_g, nullptr, nullptr, nullptr, nullptr, dL_dpose, stream);
     return check_launch("project_bwd");
 }
 
