@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kVT, 2) void vanilla_fwd_kernel(VanArgs a, const vo
     __shared__ int s_max;
     const int nchunks = (a.D + kVC - 1) / kVC;
     const int ntiles = a.ntx * a.nty;
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = xcd_strips(blockIdx.x);   // strips of items over the XCDs, as the blend kernels
     if (item >= ntiles * nchunks) return;
     const int tile = item / nchunks, chunk = item - tile * nchunks;
     const int c0 = chunk * kVC;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kVT, 2) void vanilla_bwd_kernel(VanArgs a, const vo
     __shared__ int s_max;
     const int nchunks = (a.D + kVC - 1) / kVC;
     const int ntiles = a.ntx * a.nty;
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = xcd_strips(blockIdx.x);   // strips of items over the XCDs, as the blend kernels
     if (item >= ntiles * nchunks) return;
     const int tile = item / nchunks, chunk = item - tile * nchunks;
     const int c0 = chunk * kVC;
@@ -473,10 +473,10 @@ extern "C" lgs_status lgs_feature_render_vanilla_fwd(const lgs_camera *cam, cons
     const long items = (long)a.ntx * a.nty * ((d + kVC - 1) / kVC);
     const size_t lds = std::max(kFwdLds, kFwdLdsStore);
     if (feat_dt == LGS_BF16)
-        hipLaunchKernelGGL(vanilla_fwd_kernel<VF_BF16>, dim3(padded_grid(items)), dim3(kVT), lds, stream, a, feat,
+        hipLaunchKernelGGL(vanilla_fwd_kernel<VF_BF16>, dim3(strip_grid(items)), dim3(kVT), lds, stream, a, feat,
                            feat_scale, (uint16_t *)F);
     else
-        hipLaunchKernelGGL(vanilla_fwd_kernel<VF_FP8>, dim3(padded_grid(items)), dim3(kVT), lds, stream, a, feat,
+        hipLaunchKernelGGL(vanilla_fwd_kernel<VF_FP8>, dim3(strip_grid(items)), dim3(kVT), lds, stream, a, feat,
                            feat_scale, (uint16_t *)F);
     return check_launch("feature_render_vanilla_fwd");
 }
@@ -498,10 +498,10 @@ extern "C" lgs_status lgs_feature_render_vanilla_bwd(const lgs_camera *cam, cons
     const long items = (long)a.ntx * a.nty * ((d + kVC - 1) / kVC);
     const size_t lds = std::max(kBwdLds, kBwdLdsStage);
     if (feat_dt == LGS_BF16)
-        hipLaunchKernelGGL(vanilla_bwd_kernel<VF_BF16>, dim3(padded_grid(items)), dim3(kVT), lds, stream, a, feat,
+        hipLaunchKernelGGL(vanilla_bwd_kernel<VF_BF16>, dim3(strip_grid(items)), dim3(kVT), lds, stream, a, feat,
                            feat_scale, T_final, (const uint16_t *)dL_dF, dL_dfeat, dL_dmean2d, dL_dconic, dL_dopacity);
     else
-        hipLaunchKernelGGL(vanilla_bwd_kernel<VF_FP8>, dim3(padded_grid(items)), dim3(kVT), lds, stream, a, feat,
+        hipLaunchKernelGGL(vanilla_bwd_kernel<VF_FP8>, dim3(strip_grid(items)), dim3(kVT), lds, stream, a, feat,
                            feat_scale, T_final, (const uint16_t *)dL_dF, dL_dfeat, dL_dmean2d, dL_dconic, dL_dopacity);
     return check_launch("feature_render_vanilla_bwd");
 }
