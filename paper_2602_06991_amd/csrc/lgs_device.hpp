@@ -137,19 +137,4 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
     return (b & 7) * per + (b >> 3);
 }
 
-// For kernels bound by instruction issue, whose tiles differ in work (the blend and its
-// adjoint): strips of kStrip consecutive tiles, the strips dealt to the XCDs in turn
-// (XCD x takes strips x, x + 8, ...).  Neighbours along a strip still meet in one L2,
-// while every XCD gets an even share of the image; one contiguous range per XCD left the
-// XCDs with up to 1.2x the mean work.  Bijective on grids of strip_grid() blocks.
-constexpr int kStrip = 16;
-__device__ __forceinline__ int xcd_strips(int b) {
-    const int x = b & 7, l = b >> 3;
-    return ((l / kStrip) * 8 + x) * kStrip + (l % kStrip);
-}
-__host__ __device__ inline unsigned strip_grid(long long blocks) {
-    const long long s = 8LL * kStrip;
-    return (unsigned)(((blocks + s - 1) / s) * s);
-}
-
 }  // namespace lgs

@@ -14,6 +14,7 @@
 // 8 x 640x480 blend and adjoint against 0.72 + 1.42 in strips; strips take 0.50 + 0.97 ms
 // at 4 x 1200x680 against 0.61 + 1.23 in bands; one 1200x680 view is even.
 #include "lgs_device.hpp"
+#include "tile_map.hpp"
 #include "lgs_host.hpp"
 
 namespace lgs {

@@ -23,6 +23,7 @@
 // feature rows take dFt = W^T G (MFMA, the four waves' partial sums meet in LDS), one
 // atomic per element and (tile, batch).
 #include "lgs_device.hpp"
+#include "tile_map.hpp"
 #include "lgs_host.hpp"
 
 namespace lgs {
