@@ -152,10 +152,12 @@ __device__ __forceinline__ void bf16_rows(const float *__restrict__ src, uint16_
     }
 }
 
-// Quantizes the rows whose row_gen equals gen: each wave takes 64 rows, finds the marked
-// ones with a ballot and converts them with the whole wave, NR rows at a time (Top-K ids
-// cluster, so one wave may hold dozens of marked rows, and one row at a time would wait
-// a full load latency per row).
+// Quantizes the rows whose row_gen equals gen: each wave takes kMarkRows rows, finds the
+// marked ones with a ballot and converts them with the whole wave, NR rows at a time.
+// Top-K ids cluster, so a range of rows may be marked throughout: short ranges per wave
+// and NR rows per pass (their loads issued together) keep such a wave from waiting one
+// load latency per row.
+constexpr int kMarkRows = 16;
 template <int DT>
 __global__ __launch_bounds__(256) void quant_marked_rows_kernel(int n, int D, int gen,
                                                                 const int *__restrict__ row_gen,
@@ -163,10 +165,10 @@ __global__ __launch_bounds__(256) void quant_marked_rows_kernel(int n, int D, in
                                                                 float *__restrict__ scale) {
     constexpr int NR = DT == LGS_BF16 ? 8 : 2;
     const int lane = threadIdx.x & 63;
-    const long r0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    const long r0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * kMarkRows;
     if (r0 >= n) return;   // whole wave
     const long r = r0 + lane;
-    unsigned long long m = __ballot(r < n && row_gen[r] == gen);
+    unsigned long long m = __ballot(lane < kMarkRows && r < n && row_gen[r] == gen);
     while (m) {
         long rows[NR];
 #pragma unroll
@@ -499,7 +501,7 @@ extern "C" lgs_status lgs_quantize_marked_rows(int32_t n, int32_t d, int32_t gen
     if (n == 0) return LGS_OK;
     LGS_REQUIRE(row_gen && src && dst, LGS_ERR_INVALID_ARG, "lgs_quantize_marked_rows: NULL pointer");
     LGS_REQUIRE(aligned16(src) && aligned16(dst), LGS_ERR_INVALID_ARG, "src and dst must be 16-byte aligned");
-    const unsigned grid = (unsigned)((((long)n + 63) / 64 + 3) / 4);
+    const unsigned grid = (unsigned)((((long)n + kMarkRows - 1) / kMarkRows + 3) / 4);
     if (dst_dt == LGS_BF16) {
         hipLaunchKernelGGL(quant_marked_rows_kernel<LGS_BF16>, dim3(grid), dim3(256), 0, stream, n, d, gen, row_gen,
                            src, dst, (float *)nullptr);
