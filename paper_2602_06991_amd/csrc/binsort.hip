@@ -79,8 +79,10 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 }
 
 // Digit counts of one block of IPT * 256 items, written digit-major (hist[d * nb + b]).
-// Each wave counts a digit group once, by its lowest lane, so keys that share a digit
-// (the top byte of nearby depths) do not serialise on one LDS counter.
+// When every valid lane of a wave holds the same digit (the top byte of nearby depths),
+// the first of them adds the wave's count at once, so such keys do not serialise on one
+// LDS counter; otherwise each lane adds its own (spread digits rarely collide, and the
+// test costs two ballots where grouping equal digits costs eight).
 template <int IPT>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
                                                                   int n, const long long *__restrict__ n_dev,
@@ -92,7 +94,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
     h[t] = 0;
     __syncthreads();
     const long base = (long)blockIdx.x * (kSortThreads * IPT);
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t k[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
@@ -103,8 +104,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint32_t
     for (int r = 0; r < IPT; ++r) {
         const bool valid = base + r * kSortThreads + t < n && !(drop && k[r] == kDropKey);
         const uint32_t d = (k[r] >> shift) & 255u;
-        const uint64_t m = digit_peers(d, valid);
-        if (valid && (m & lt) == 0) atomicAdd(&h[d], __popcll(m));
+        const uint64_t vm = __ballot(valid);
+        if (vm == 0ull) continue;   // the same for the whole wave
+        const int first = (int)__builtin_ctzll(vm);
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, first);
+        if (__ballot(valid && d == d0) == vm) {
+            if (lane == first) atomicAdd(&h[d0], (int)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[d], 1);
+        }
     }
     __syncthreads();
     hist[t * nb + blockIdx.x] = h[t];
@@ -293,7 +301,9 @@ __global__ __launch_bounds__(256) void duplicate_kernel(int n, const long long *
                                                         int *__restrict__ ids) {
     __shared__ int s_start[256];
     __shared__ int s_g[256];
-    __shared__ int4 s_rect[256];
+    __shared__ int s_key0[256];   // the key of the record's first tile: view * T + y0 * ntx + x0
+    __shared__ int s_rw[256];     // its box width in tiles, and the width's reciprocal
+    __shared__ float s_inv[256];
     __shared__ long long s_base;
     __shared__ int s_total;
     n = items_of(n, n_kept);   // the records the depth sort kept
@@ -316,7 +326,9 @@ __global__ __launch_bounds__(256) void duplicate_kernel(int n, const long long *
     const int start = s < n ? (int)(o - s_base) : 0x7FFFFFFF;
     s_start[t] = start;
     s_g[t] = g;
-    s_rect[t] = r;
+    s_key0[t] = g >= 0 ? (g / n_view) * T + r.y * ntx + r.x : 0;
+    s_rw[t] = r.z - r.x;
+    s_inv[t] = 1.0f / (float)(r.z - r.x);
     if (s < n) atomicMax(&s_total, start + c);
     __syncthreads();
     const int total = s_total;
@@ -338,13 +350,16 @@ __global__ __launch_bounds__(256) void duplicate_kernel(int n, const long long *
         for (int u = 0; u < kU; ++u) {
             const int q = q0 + u * 256;
             if (q >= lim) break;
-            const int4 rr = s_rect[lo[u]];
-            const int k = q - s_start[lo[u]];
-            const int rw = rr.z - rr.x;
-            const int ty = rr.y + k / rw, tx = rr.x + k - (k / rw) * rw;
-            const int r = s_g[lo[u]];
-            tile_keys[base + q] = (uint32_t)((r / n_view) * T + ty * ntx + tx);
-            ids[base + q] = r;
+            const int j = lo[u];
+            const int k = q - s_start[j];   // the pair's tile within the record's box, row by row
+            const int rw = s_rw[j];
+            // dy = k / rw: the float product is within 0.5 of it for k < 2^22 (a box of at
+            // most a view's tiles), the integer steps make it exact for any k
+            int dy = (int)((float)k * s_inv[j]);
+            while (dy * rw > k) --dy;
+            while ((dy + 1) * rw <= k) ++dy;
+            tile_keys[base + q] = (uint32_t)(s_key0[j] + dy * ntx + (k - dy * rw));
+            ids[base + q] = s_g[j];
         }
     }
 }
