@@ -87,9 +87,11 @@ class Binner:
             st, m = call(ws, True)
             if st == lgs.LGS_OK:
                 out = self.ids[:m]   # the pairs this call wrote (kept alive if the buffer grows)
-                if not self.sync and m * 3 > self.cap * 2:
-                    # room for frames that bring up to half as many pairs again; the new
-                    # buffers serve the next calls
+                if not self.sync and (m * 3 > self.cap * 2 or self.cap > 2 * m + 65536):
+                    # room for frames that bring up to half as many pairs again (the
+                    # asynchronous calls size their grids for the capacity, so a first
+                    # guess far above the count is cut down too); the new sizes serve
+                    # the next calls
                     self._ensure(rec, c0.width, c0.height, int(m * 1.5) + 4096)
                 return out, ranges.view(ntiles, 2), m
             self._ensure(rec, c0.width, c0.height, int(m * 1.5) + 4096)
