@@ -278,9 +278,12 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
         }
         __syncthreads();
         for (int j = cnt - 1; j >= 0; --j) {
+            // -0 is the exact additive identity (x + -0 == x for every x, unlike +0), so the
+            // first term of each sum costs no add; the sums (gradients, not replayed
+            // decisions) are formed with fused multiply-adds
             float v[kNG];
 #pragma unroll
-            for (int q = 0; q < kNG; ++q) v[q] = 0.f;
+            for (int q = 0; q < kNG; ++q) v[q] = -0.0f;
             bool hit = false;
             const float2 m = s_xy[j];
             const float4 co = s_co[j];
@@ -295,26 +298,27 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
                 T[h] *= r;                          // transmittance in front of this Gaussian
                 const float w = alpha * T[h];
                 const float4 cz = s_cz[j];
-                float e = gC0[h] * cz.x + gC1[h] * cz.y + gC2[h] * cz.z + gD[h] * cz.w + gO[h];
+                float e = fmaf(gC0[h], cz.x, fmaf(gC1[h], cz.y, fmaf(gC2[h], cz.z, fmaf(gD[h], cz.w, gO[h]))));
                 if (w >= wth[h]) {
                     const int g = s_id[j];
 #pragma unroll
                     for (int k = 0; k < K; ++k) e += (ti[h][k] == g) ? gam[h][k] : 0.f;
                 }
-                const float dal = T[h] * e - A[h] * r;
+                const float dal = fmaf(T[h], e, -A[h] * r);
                 A[h] = fmaf(e, w, A[h]);
-                v[5] += w * gC0[h];
-                v[6] += w * gC1[h];
-                v[7] += w * gC2[h];
-                v[8] += w * gD[h];
+                v[5] = fmaf(w, gC0[h], v[5]);
+                v[6] = fmaf(w, gC1[h], v[6]);
+                v[7] = fmaf(w, gC2[h], v[7]);
+                v[8] = fmaf(w, gD[h], v[8]);
                 if (raw <= kAlphaMax) {             // unclamped: alpha = o e^-sigma
                     const float ds = -alpha * dal;
-                    v[0] += -ds * (co.x * dx + co.y * dy);
-                    v[1] += -ds * (co.y * dx + co.z * dy);
-                    v[2] += ds * 0.5f * dx * dx;
-                    v[3] += ds * dx * dy;
-                    v[4] += ds * 0.5f * dy * dy;
-                    v[9] += dal * ex;
+                    const float hds = 0.5f * ds;
+                    v[0] = fmaf(-ds, fmaf(co.x, dx, co.y * dy), v[0]);
+                    v[1] = fmaf(-ds, fmaf(co.y, dx, co.z * dy), v[1]);
+                    v[2] = fmaf(hds * dx, dx, v[2]);
+                    v[3] = fmaf(ds * dx, dy, v[3]);
+                    v[4] = fmaf(hds * dy, dy, v[4]);
+                    v[9] = fmaf(dal, ex, v[9]);
                 }
             }
             // sums over each lane row (16 lanes, 16 kPPT pixels; every lane takes part); the
