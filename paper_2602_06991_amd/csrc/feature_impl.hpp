@@ -32,6 +32,7 @@
 #include "feature_launch.hpp"
 #include "lgs_device.hpp"
 #include "lgs_host.hpp"
+#include "tile_map.hpp"
 
 namespace lgs {
 namespace {
@@ -1299,7 +1300,7 @@ __global__ __launch_bounds__(kFB) void feature_fwd_kernel(int W, int H, int view
     UnionLds<K, FT> &L = *reinterpret_cast<UnionLds<K, FT> *>(lds);
     unsigned char *dyn = lds + union_bytes<K, FT>();   // the per-pixel path's staged rows
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = xcd_strips(blockIdx.x);
     if (tile >= ntiles) return;
     const TileGeom tg = tile_geom(tile, W, H);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1483,7 +1484,7 @@ __global__ __launch_bounds__(kFB, 2) void feature_bwd_kernel(int W, int H, int v
     UnionLds<K, FT> &L = *reinterpret_cast<UnionLds<K, FT> *>(lds);
     unsigned char *dyn = lds + union_bytes<K, FT>();   // the per-pixel path's buffers
     const int ntiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) * views;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = xcd_strips(blockIdx.x);
     if (tile >= ntiles) return;
     const TileGeom tg = tile_geom(tile, W, H);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1552,7 +1553,7 @@ inline int pick_ucap(int pass_channels, int sf, int budget) { return budget / (p
 template <int K, int FT, int MT>
 lgs_status feature_fwd_launch(int W, int H, int views, int D, const void *feat, const float *scale,
                               const int *ids, const float *tw, void *F, hipStream_t st) {
-    const unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
+    const unsigned grid = strip_grid((long)tiles_x(W) * tiles_y(H) * views);
     const int rb = pass_ch<K>() * Bytes<FT>::v;   // staged bytes per row and pass
     const size_t ub = union_bytes<K, FT>();
     // MFMA-capable kernels give the per-pixel path (unions beyond kUP) whatever rows
@@ -1577,7 +1578,7 @@ template <int K, int FT, int MT, int MODE>
 lgs_status feature_bwd_launch(int W, int H, int views, int D, const void *feat, const float *scale,
                               const int *ids, const float *tw, const void *dF, float l1_scale, float *dfeat,
                               float *dtw, void *Fo, hipStream_t st) {
-    const unsigned grid = padded_grid((long)tiles_x(W) * tiles_y(H) * views);
+    const unsigned grid = strip_grid((long)tiles_x(W) * tiles_y(H) * views);
     const int ucap = pick_ucap(pass_ch<K>(), Bytes<FT>::v, kRowBudget);
     size_t lds = union_bytes<K, FT>() + kRowBudget + fallback_extra<K, TileCfg<K>::CPL>();
     if (MfOk<K, FT, MT, MODE>::v)

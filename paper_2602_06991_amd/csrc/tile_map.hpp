@@ -1,15 +1,17 @@
-// Tile -> block maps of the kernels bound by instruction issue (the blend, its adjoint,
-// the pruning statistics, the vanilla feature render), beside xcd_remap of lgs_device.hpp.
+// Tile -> block map in strips over the XCDs, used by the blend kernels (unless the views
+// come in eights), the pruning statistics, the vanilla feature render and the Top-K
+// feature kernels; xcd_remap of lgs_device.hpp gives contiguous bands instead.
 #pragma once
 #include "lgs_device.hpp"
 
 namespace lgs {
 
-// For kernels bound by instruction issue, whose tiles differ in work (the blend and its
-// adjoint): strips of kStrip consecutive tiles, the strips dealt to the XCDs in turn
-// (XCD x takes strips x, x + 8, ...).  Neighbours along a strip still meet in one L2,
-// while every XCD gets an even share of the image; one contiguous range per XCD left the
-// XCDs with up to 1.2x the mean work.  Bijective on grids of strip_grid() blocks.
+// For kernels whose tiles differ in work: strips of kStrip consecutive tiles, the strips
+// dealt to the XCDs in turn (XCD x takes strips x, x + 8, ...).  Neighbours along a strip
+// still meet in one L2, while every XCD gets an even share of the image; one contiguous
+// range per XCD left the XCDs with up to 1.2x the mean work in the blend, and the
+// feature kernels' tiles differ too (union sizes, the two MFMA forms).  Bijective on
+// grids of strip_grid() blocks.
 constexpr int kStrip = 16;
 __device__ __forceinline__ int xcd_strips(int b) {
     const int x = b & 7, l = b >> 3;
