@@ -55,11 +55,13 @@ __device__ __forceinline__ bool finite3(const float *p) {
     return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
 }
 
-// Returns false for a culled Gaussian.
-__device__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means,
-                         const float *__restrict__ log_scales, const float *__restrict__ quats,
-                         const float *__restrict__ opacity_logits, const float *__restrict__ rgb,
-                         Splat &s) {
+// The view-independent half of splat_of: the validity tests on the parameters, the
+// scales, the unit quaternion and its rotation, the 3D covariance and the opacity;
+// m receives the mean.  Returns false for a Gaussian culled in every view.
+__device__ __forceinline__ bool splat_gauss(int g, const float *__restrict__ means,
+                                            const float *__restrict__ log_scales, const float *__restrict__ quats,
+                                            const float *__restrict__ opacity_logits,
+                                            const float *__restrict__ rgb, Splat &s, float (&mv)[3]) {
     const float *m = means + 3 * g;
     const float *ls = log_scales + 3 * g;
     const float *q = quats + 4 * g;
@@ -70,12 +72,7 @@ __device__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means
     if (q[0] == 0.0f && q[1] == 0.0f && q[2] == 0.0f && q[3] == 0.0f) return false;
     if (ls[0] > 10.0f || ls[1] > 10.0f || ls[2] > 10.0f) return false;
     if (opl < -5.53733427f) return false;                 // opacity < 1/255
-    float mx = m[0], my = m[1], mz = m[2];
-    float z = fmaf(c.R[8], mz, fmaf(c.R[7], my, fmaf(c.R[6], mx, c.t[2])));
-    if (!(z > 0.2f)) return false;
-    s.t[0] = fmaf(c.R[0], mx, fmaf(c.R[1], my, fmaf(c.R[2], mz, c.t[0])));
-    s.t[1] = fmaf(c.R[3], mx, fmaf(c.R[4], my, fmaf(c.R[5], mz, c.t[1])));
-    s.t[2] = z;
+    mv[0] = m[0]; mv[1] = m[1]; mv[2] = m[2];
     for (int i = 0; i < 3; ++i) s.s[i] = expf(ls[i]);
     // normalise the quaternion; pre-scale by its largest entry so tiny ones survive
     float qm = fmaxf(fmaxf(fabsf(q[0]), fabsf(q[1])), fmaxf(fabsf(q[2]), fabsf(q[3])));
@@ -96,6 +93,19 @@ __device__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means
     for (int i = 0; i < 3; ++i)
         for (int j = i; j < 3; ++j)
             s.Sg[k6++] = M[3 * i] * M[3 * j] + M[3 * i + 1] * M[3 * j + 1] + M[3 * i + 2] * M[3 * j + 2];
+    s.o = 1.0f / (1.0f + expf(-opl));
+    return true;
+}
+
+// The view-dependent half: view-space mean, the depth test, the perspective Jacobian,
+// the 2D covariance, its conic and the screen-space mean.  Returns false when culled.
+__device__ __forceinline__ bool splat_view(const CamDev &c, const float (&m)[3], Splat &s) {
+    float mx = m[0], my = m[1], mz = m[2];
+    float z = fmaf(c.R[8], mz, fmaf(c.R[7], my, fmaf(c.R[6], mx, c.t[2])));
+    if (!(z > 0.2f)) return false;
+    s.t[0] = fmaf(c.R[0], mx, fmaf(c.R[1], my, fmaf(c.R[2], mz, c.t[0])));
+    s.t[1] = fmaf(c.R[3], mx, fmaf(c.R[4], my, fmaf(c.R[5], mz, c.t[1])));
+    s.t[2] = z;
     // perspective Jacobian with the guard-band clamp
     float tx = s.t[0], ty = s.t[1];
     float rx = tx / z, ry = ty / z;
@@ -128,56 +138,71 @@ __device__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means
     s.cc = s.A / det;
     s.mx = c.fx * tx / z + c.cx;
     s.my = c.fy * ty / z + c.cy;
-    s.o = 1.0f / (1.0f + expf(-opl));
     return true;
 }
 
+// The splat of Gaussian g in camera c; returns false for a culled Gaussian.
+__device__ __forceinline__ bool splat_of(const CamDev &c, int g, const float *__restrict__ means,
+                                         const float *__restrict__ log_scales, const float *__restrict__ quats,
+                                         const float *__restrict__ opacity_logits,
+                                         const float *__restrict__ rgb, Splat &s) {
+    float m[3];
+    return splat_gauss(g, means, log_scales, quats, opacity_logits, rgb, s, m) && splat_view(c, m, s);
+}
 
+
+// One thread per Gaussian: its view-independent state once, then its splat in each view
+// (record v * n + g), written in view order.
 __global__ __launch_bounds__(256) void project_fwd_kernel(
-    CamSet cs, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
+    CamSet cs, int views, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
     const float *__restrict__ quats, const float *__restrict__ opacity_logits,
     const float *__restrict__ rgb, float2 *__restrict__ mean2d, float *__restrict__ conic,
     float *__restrict__ depth, float *__restrict__ opacity, int4 *__restrict__ tile_rect,
     int *__restrict__ tiles_touched) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    const CamDev &c = cs.c[blockIdx.y];
-    const long r = (long)blockIdx.y * n + g;   // the record of (view, Gaussian)
-    Splat s;
-    if (!splat_of(c, g, means, log_scales, quats, opacity_logits, rgb, s)) {
-        mean2d[r] = make_float2(0.f, 0.f);
-        conic[3 * r] = conic[3 * r + 1] = conic[3 * r + 2] = 0.f;
-        depth[r] = 0.f;
-        opacity[r] = 0.f;
-        tile_rect[r] = make_int4(0, 0, 0, 0);
-        tiles_touched[r] = 0;
-        return;
+    Splat base;
+    float m[3];
+    const bool live = splat_gauss(g, means, log_scales, quats, opacity_logits, rgb, base, m);
+    for (int v = 0; v < views; ++v) {
+        const CamDev &c = cs.c[v];
+        const long r = (long)v * n + g;   // the record of (view, Gaussian)
+        Splat s = base;
+        if (!live || !splat_view(c, m, s)) {
+            mean2d[r] = make_float2(0.f, 0.f);
+            conic[3 * r] = conic[3 * r + 1] = conic[3 * r + 2] = 0.f;
+            depth[r] = 0.f;
+            opacity[r] = 0.f;
+            tile_rect[r] = make_int4(0, 0, 0, 0);
+            tiles_touched[r] = 0;
+            continue;
+        }
+        mean2d[r] = make_float2(s.mx, s.my);
+        conic[3 * r] = s.ca;
+        conic[3 * r + 1] = s.cb;
+        conic[3 * r + 2] = s.cc;
+        depth[r] = s.t[2];
+        opacity[r] = s.o;
+        // support {alpha >= 1/255} is the ellipse d^T Sigma2D^-1 d <= 2 ln(255 o); its box
+        // has half extents sqrt(2 ln(255 o) A), sqrt(2 ln(255 o) C); pad by a pixel
+        float lvl = fmaxf(2.0f * logf(255.0f * s.o), 0.0f);
+        float hx = sqrtf(lvl * s.A), hy = sqrtf(lvl * s.C);
+        float fx0 = ceilf(s.mx - hx - 0.5f) - 1.0f, fx1 = floorf(s.mx + hx - 0.5f) + 1.0f;
+        float fy0 = ceilf(s.my - hy - 0.5f) - 1.0f, fy1 = floorf(s.my + hy - 0.5f) + 1.0f;
+        fx0 = fmaxf(fx0, 0.0f);
+        fy0 = fmaxf(fy0, 0.0f);
+        fx1 = fminf(fx1, (float)(c.W - 1));
+        fy1 = fminf(fy1, (float)(c.H - 1));
+        if (!(fx1 >= fx0) || !(fy1 >= fy0)) {
+            tile_rect[r] = make_int4(0, 0, 0, 0);
+            tiles_touched[r] = 0;
+            continue;
+        }
+        int tx0 = (int)fx0 / kTile, tx1 = (int)fx1 / kTile + 1;
+        int ty0 = (int)fy0 / kTile, ty1 = (int)fy1 / kTile + 1;
+        tile_rect[r] = make_int4(tx0, ty0, tx1, ty1);
+        tiles_touched[r] = (tx1 - tx0) * (ty1 - ty0);
     }
-    mean2d[r] = make_float2(s.mx, s.my);
-    conic[3 * r] = s.ca;
-    conic[3 * r + 1] = s.cb;
-    conic[3 * r + 2] = s.cc;
-    depth[r] = s.t[2];
-    opacity[r] = s.o;
-    // support {alpha >= 1/255} is the ellipse d^T Sigma2D^-1 d <= 2 ln(255 o); its box
-    // has half extents sqrt(2 ln(255 o) A), sqrt(2 ln(255 o) C); pad by a pixel
-    float lvl = fmaxf(2.0f * logf(255.0f * s.o), 0.0f);
-    float hx = sqrtf(lvl * s.A), hy = sqrtf(lvl * s.C);
-    float fx0 = ceilf(s.mx - hx - 0.5f) - 1.0f, fx1 = floorf(s.mx + hx - 0.5f) + 1.0f;
-    float fy0 = ceilf(s.my - hy - 0.5f) - 1.0f, fy1 = floorf(s.my + hy - 0.5f) + 1.0f;
-    fx0 = fmaxf(fx0, 0.0f);
-    fy0 = fmaxf(fy0, 0.0f);
-    fx1 = fminf(fx1, (float)(c.W - 1));
-    fy1 = fminf(fy1, (float)(c.H - 1));
-    if (!(fx1 >= fx0) || !(fy1 >= fy0)) {
-        tile_rect[r] = make_int4(0, 0, 0, 0);
-        tiles_touched[r] = 0;
-        return;
-    }
-    int tx0 = (int)fx0 / kTile, tx1 = (int)fx1 / kTile + 1;
-    int ty0 = (int)fy0 / kTile, ty1 = (int)fy1 / kTile + 1;
-    tile_rect[r] = make_int4(tx0, ty0, tx1, ty1);
-    tiles_touched[r] = (tx1 - tx0) * (ty1 - ty0);
 }
 
 // Per-Gaussian share of the camera-pose gradient for a left increment exp(xi^) [R|t],
@@ -209,22 +234,32 @@ __device__ __forceinline__ void pose_share(const CamDev &c, const Splat &s, cons
     out[5] += M[1] - M[3];
 }
 
-// Parameter gradients of one Gaussian in one view (rec: its record in the screen-space
-// gradient arrays).
+// Parameter gradients of one Gaussian.
 struct ParamGrad {
     float mu[3], ls[3], q[4], opl;
 };
 
-// The adjoint of splat_of for one record.  PARAMS: the parameter gradients into pg;
-// POSE: this record's share of the camera-pose gradient into pose.
-template <bool PARAMS, bool POSE>
-__device__ __forceinline__ void project_bwd_one(const CamDev &c, long rec, const Splat &s,
-                                                const float *__restrict__ d_mean2d, const float *__restrict__ d_conic,
-                                                const float *__restrict__ d_opac, const float *__restrict__ d_depth,
-                                                ParamGrad &pg, float (&pose)[6]) {
+// What the views of one Gaussian contribute to its parameter gradients, summed over
+// the views.  Each piece is linear in the view's screen-space gradients given the
+// view-independent state (rotation, scales, opacity), so the sum over views is taken
+// before the one transform to the parameters: the mean's gradient (R^T dt), the
+// symmetrised covariance gradient E = dS + dS^T (xx xy xz yy yz zz) and the opacity's.
+struct ViewSum {
+    float mu[3], E[6], go;
+};
+
+// The adjoint of splat_view for one record (rec: its index in the screen-space gradient
+// arrays): its contribution vs to the parameter gradients and, for POSE, its share of
+// the camera-pose gradient.
+template <bool POSE>
+__device__ __forceinline__ void project_bwd_view(const CamDev &c, long rec, const Splat &s,
+                                                 const float *__restrict__ d_mean2d, const float *__restrict__ d_conic,
+                                                 const float *__restrict__ d_opac, const float *__restrict__ d_depth,
+                                                 ViewSum &vs, float (&pose)[6]) {
     float gmx = d_mean2d[2 * rec], gmy = d_mean2d[2 * rec + 1];
     float ga = d_conic[3 * rec], gb = d_conic[3 * rec + 1], gc = d_conic[3 * rec + 2];
-    float go = d_opac[rec], gz = d_depth[rec];
+    vs.go = d_opac[rec];
+    float gz = d_depth[rec];
 
     // conic -> Sigma2D: dSigma2D = -Q G Q with G = [[ga, gb/2], [gb/2, gc]]
     float a = s.ca, b = s.cb, cq = s.cc;
@@ -244,6 +279,9 @@ __device__ __forceinline__ void project_bwd_one(const CamDev &c, long rec, const
     float dS[9];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) dS[3 * i + j] = T[i] * GT0[j] + T[3 + i] * GT1[j];
+    int k6 = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int k = i; k < 3; ++k) vs.E[k6++] = dS[3 * i + k] + dS[3 * k + i];
     const float *S = s.Sg;
     float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
     float dT[6];
@@ -279,24 +317,37 @@ __device__ __forceinline__ void project_bwd_one(const CamDev &c, long rec, const
     dty += gmy * c.fy * iz;
     dtz -= (gmx * c.fx * tx + gmy * c.fy * ty) * iz2;
     dtz += gz;
-    if constexpr (POSE) {
-        float sh[6];
-        pose_share(c, s, dT, dtx, dty, dtz, sh);
-        for (int q = 0; q < 6; ++q) pose[q] += sh[q];
-    }
-    if constexpr (!PARAMS) return;
+    if constexpr (POSE) pose_share(c, s, dT, dtx, dty, dtz, pose);
     // t = R mu + t_cam
-    for (int j = 0; j < 3; ++j) pg.mu[j] = c.R[j] * dtx + c.R[3 + j] * dty + c.R[6 + j] * dtz;
-    // Sigma = M M^T, M = Rq diag(s): dM = (dS + dS^T) M
+    for (int j = 0; j < 3; ++j) vs.mu[j] = c.R[j] * dtx + c.R[3 + j] * dty + c.R[6 + j] * dtz;
+}
+
+// Adds view v's contribution to the running sum (the first view's is taken as is).
+__device__ __forceinline__ void view_sum_add(ViewSum &acc, const ViewSum &vs, bool first) {
+    if (first) {
+        acc = vs;
+        return;
+    }
+    for (int j = 0; j < 3; ++j) acc.mu[j] += vs.mu[j];
+    for (int j = 0; j < 6; ++j) acc.E[j] += vs.E[j];
+    acc.go += vs.go;
+}
+
+// The parameter gradients from the views' summed contributions (s: the Gaussian's
+// view-independent state from splat_gauss).
+__device__ __forceinline__ void param_grads(const Splat &s, const ViewSum &a, ParamGrad &pg) {
+    for (int j = 0; j < 3; ++j) pg.mu[j] = a.mu[j];
+    // Sigma = M M^T, M = Rq diag(s): dM = E M
     float M[9];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) M[3 * i + j] = s.Rq[3 * i + j] * s.s[j];
+    const float Ef[9] = {a.E[0], a.E[1], a.E[2], a.E[1], a.E[3], a.E[4], a.E[2], a.E[4], a.E[5]};
     float dR[9];
     for (int j = 0; j < 3; ++j) {
         float ds = 0.f;
         for (int i = 0; i < 3; ++i) {
             float dM = 0.f;
-            for (int k = 0; k < 3; ++k) dM += (dS[3 * i + k] + dS[3 * k + i]) * M[3 * k + j];
+            for (int k = 0; k < 3; ++k) dM += Ef[3 * i + k] * M[3 * k + j];
             ds += dM * s.Rq[3 * i + j];
             dR[3 * i + j] = dM * s.s[j];
         }
@@ -317,12 +368,22 @@ __device__ __forceinline__ void project_bwd_one(const CamDev &c, long rec, const
     pg.q[1] = (dx - x * dot) * il;
     pg.q[2] = (dy - y * dot) * il;
     pg.q[3] = (dz - zq * dot) * il;
-    pg.opl = go * s.o * (1.0f - s.o);
+    pg.opl = a.go * s.o * (1.0f - s.o);
+}
+
+__device__ __forceinline__ void add_param_grads(int g, const ParamGrad &pg, float *__restrict__ d_means,
+                                                float *__restrict__ d_ls, float *__restrict__ d_quats,
+                                                float *__restrict__ d_opl) {
+    for (int j = 0; j < 3; ++j) d_means[3 * g + j] += pg.mu[j];
+    for (int j = 0; j < 3; ++j) d_ls[3 * g + j] += pg.ls[j];
+    for (int j = 0; j < 4; ++j) d_quats[4 * g + j] += pg.q[j];
+    d_opl[g] += pg.opl;
 }
 
 
-// Parameter gradients summed over the views, one thread per Gaussian: the views'
-// shares are added in view order and the sum goes to memory once (deterministic).
+// Parameter gradients summed over the views, one thread per Gaussian: the Gaussian's
+// view-independent state once, each view's contribution added in view order, one
+// transform to the parameters, and the result added to memory once (deterministic).
 __global__ __launch_bounds__(256) void project_bwd_kernel(
     CamSet cs, int views, int n, const float *__restrict__ means, const float *__restrict__ log_scales,
     const float *__restrict__ quats, const float *__restrict__ opacity_logits,
@@ -332,36 +393,31 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
     float *__restrict__ d_quats, float *__restrict__ d_opl) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    ParamGrad acc = {};
+    Splat base;
+    float m[3];
+    if (!splat_gauss(g, means, log_scales, quats, opacity_logits, rgb, base, m)) return;
+    ViewSum acc = {};
     bool any = false;
     float unused[6];
     for (int v = 0; v < views; ++v) {
-        Splat s;
-        if (!splat_of(cs.c[v], g, means, log_scales, quats, opacity_logits, rgb, s)) continue;
-        ParamGrad pg;
-        project_bwd_one<true, false>(cs.c[v], (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, pg, unused);
-        if (!any) {
-            acc = pg;
-            any = true;
-            continue;
-        }
-        for (int j = 0; j < 3; ++j) acc.mu[j] += pg.mu[j];
-        for (int j = 0; j < 3; ++j) acc.ls[j] += pg.ls[j];
-        for (int j = 0; j < 4; ++j) acc.q[j] += pg.q[j];
-        acc.opl += pg.opl;
+        Splat s = base;
+        if (!splat_view(cs.c[v], m, s)) continue;
+        ViewSum vs;
+        project_bwd_view<false>(cs.c[v], (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, vs, unused);
+        view_sum_add(acc, vs, !any);
+        any = true;
     }
     if (!any) return;
-    for (int j = 0; j < 3; ++j) d_means[3 * g + j] += acc.mu[j];
-    for (int j = 0; j < 3; ++j) d_ls[3 * g + j] += acc.ls[j];
-    for (int j = 0; j < 4; ++j) d_quats[4 * g + j] += acc.q[j];
-    d_opl[g] += acc.opl;
+    ParamGrad pg;
+    param_grads(base, acc, pg);
+    add_param_grads(g, pg, d_means, d_ls, d_quats, d_opl);
 }
 
 constexpr int kPoseGrid = 2048;   // blocks of the pose reduction: at most this many atomics per component
 
 // The projection adjoint with the camera-pose gradient of every view (Sec. 4.1), in one
 // pass: the grid strides over the Gaussians; per Gaussian the views are walked in order,
-// its parameter gradients (PARAMS) summed and written once as in project_bwd_kernel
+// its parameter gradients (PARAMS) formed and written once as in project_bwd_kernel
 // (the same bits), and its share of each view's pose gradient added to the thread's
 // registers (MAXV >= views).  Each block then sums every view's six components (wave
 // sums, the four wave partials in a fixed order) and adds them with one atomic each.
@@ -379,36 +435,29 @@ __global__ __launch_bounds__(256) void project_bwd_pose_kernel(
 #pragma unroll
         for (int q = 0; q < 6; ++q) pose[v][q] = 0.f;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
-        ParamGrad acc = {};
+        Splat base;
+        float m[3];
+        if (!splat_gauss(g, means, log_scales, quats, opacity_logits, rgb, base, m)) continue;
+        ViewSum acc = {};
         bool any = false;
 #pragma unroll
         for (int v = 0; v < MAXV; ++v) {
             if (v >= views) break;
-            Splat s;
-            if (!splat_of(cs.c[v], g, means, log_scales, quats, opacity_logits, rgb, s)) continue;
-            ParamGrad pg;
-            float sh[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            project_bwd_one<PARAMS, true>(cs.c[v], (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, pg, sh);
+            Splat s = base;
+            if (!splat_view(cs.c[v], m, s)) continue;
+            ViewSum vs;
+            float sh[6];
+            project_bwd_view<true>(cs.c[v], (long)v * n + g, s, d_mean2d, d_conic, d_opac, d_depth, vs, sh);
 #pragma unroll
             for (int q = 0; q < 6; ++q) pose[v][q] += sh[q];
-            if constexpr (PARAMS) {
-                if (!any) {
-                    acc = pg;
-                    any = true;
-                    continue;
-                }
-                for (int j = 0; j < 3; ++j) acc.mu[j] += pg.mu[j];
-                for (int j = 0; j < 3; ++j) acc.ls[j] += pg.ls[j];
-                for (int j = 0; j < 4; ++j) acc.q[j] += pg.q[j];
-                acc.opl += pg.opl;
-            }
+            if constexpr (PARAMS) view_sum_add(acc, vs, !any);
+            any = true;
         }
         if constexpr (PARAMS) {
             if (any) {
-                for (int j = 0; j < 3; ++j) d_means[3 * g + j] += acc.mu[j];
-                for (int j = 0; j < 3; ++j) d_ls[3 * g + j] += acc.ls[j];
-                for (int j = 0; j < 4; ++j) d_quats[4 * g + j] += acc.q[j];
-                d_opl[g] += acc.opl;
+                ParamGrad pg;
+                param_grads(base, acc, pg);
+                add_param_grads(g, pg, d_means, d_ls, d_quats, d_opl);
             }
         }
     }
@@ -488,7 +537,7 @@ extern "C" lgs_status lgs_project_fwd_views(const lgs_camera *cams, int32_t view
                 LGS_ERR_INVALID_ARG, "lgs_project_fwd: NULL pointer");
     LGS_REQUIRE(((uintptr_t)mean2d & 7u) == 0 && aligned16(tile_rect), LGS_ERR_INVALID_ARG,
                 "lgs_project_fwd: mean2d must be 8-byte and tile_rect 16-byte aligned");
-    hipLaunchKernelGGL(project_fwd_kernel, dim3((n + 255) / 256, views), dim3(256), 0, stream, cs, n, means,
+    hipLaunchKernelGGL(project_fwd_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, cs, views, n, means,
                        log_scales, quats, opacity_logits, rgb, (float2 *)mean2d, conic, depth, opacity,
                        (int4 *)tile_rect, tiles_touched);
     return check_launch("project_fwd");
