@@ -260,28 +260,44 @@ __global__ __launch_bounds__(256) void scan_sums_kernel(long long *__restrict__ 
     if (threadIdx.x == 0) *total = carry;
 }
 
+// Thread t scans 16 consecutive items of the block's 4096.  The items pass through LDS
+// so that every global load and store is coalesced (item k at k + k / 16: one pad
+// word per 16 keeps a thread's run off its neighbours' banks).
+constexpr int kScanPer = kScanItems / 256;
+__device__ __forceinline__ int scan_slot(int k) { return k + k / kScanPer; }
+
 __global__ __launch_bounds__(256) void scan_final_kernel(const long long *__restrict__ in, long n,
                                                          const long long *__restrict__ sums,
                                                          long long *__restrict__ out) {
     __shared__ long long lds[256];
-    // thread t owns 16 consecutive items of the block's 4096
-    constexpr int per = kScanItems / 256;
-    long base = (long)blockIdx.x * kScanItems + (long)threadIdx.x * per;
-    long long v[per];
+    __shared__ long long stage[kScanItems + kScanItems / kScanPer];
+    const int t = threadIdx.x;
+    const long base = (long)blockIdx.x * kScanItems;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int k = j * 256 + t;
+        stage[scan_slot(k)] = base + k < n ? in[base + k] : 0;
+    }
+    __syncthreads();
+    long long v[kScanPer];
     long long s = 0;
 #pragma unroll
-    for (int j = 0; j < per; ++j) {
-        long i = base + j;
-        v[j] = i < n ? in[i] : 0;
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = stage[scan_slot(t * kScanPer + j)];
         s += v[j];
     }
     long long tot;
     long long run = block_exscan256(s, lds, tot) + sums[blockIdx.x];
 #pragma unroll
-    for (int j = 0; j < per; ++j) {
-        long i = base + j;
-        if (i < n) out[i] = run;
+    for (int j = 0; j < kScanPer; ++j) {
+        stage[scan_slot(t * kScanPer + j)] = run;   // only this thread reads these slots back
         run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int k = j * 256 + t;
+        if (base + k < n) out[base + k] = stage[scan_slot(k)];
     }
 }
 
