@@ -172,6 +172,7 @@ class Step:
         self.gflat, self.sg, self.pg = _geometry_grads(torch, n, n, dev)
         self.npix = cam.width * cam.height
         self.events = None
+        self.order = None   # the blend's dispatch order, rewritten each step
         self.kmarks = None
         _side_init(self, torch, None if geometry_only else form, n, d, dev, not geometry_only and not vanilla,
                    dense_quantize)
@@ -190,7 +191,9 @@ class Step:
         self._mark("project_fwd")
         ids, ranges, m = self.binner(c, self.n, proj["depth"], proj["tile_rect"], proj["tiles_touched"])
         self._mark("bin_sort")
-        fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges)
+        self.order = order = r.tile_order(c, ranges, out=self.order)
+        self._mark("tile_order")
+        fw = r.rasterize(c, self.K, proj, P["rgb"], ids, ranges, order)
         self._mark("rasterize_topk_fwd")
         store, scale = (None, None) if self.geometry_only else _side_join(self, joined, fw["ids"])
         F = None
@@ -231,7 +234,7 @@ class Step:
             self.kmarks.append((ka, kb))
         if not self.geometry_only:
             self._mark("feature_render_fwd_bwd" if self.fused and not self.vanilla else "feature_render_bwd")
-        r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg)
+        r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg, order)
         self._mark("rasterize_topk_bwd")
         r.project_bwd(c, P, self.sg, self.pg)
         self._mark("project_bwd")
@@ -259,6 +262,7 @@ class StepViews:
         self.dpose = torch.empty(6 * self.V, device=dev)
         self.npix = cams[0].width * cams[0].height * self.V
         self.events = None
+        self.order = None
         self.kmarks = None
         _side_init(self, torch, form, n, d, dev, True, dense_quantize)
 
@@ -272,7 +276,9 @@ class StepViews:
         self._mark("project_fwd")
         ids, ranges, m = self.binner(c, n, proj["depth"], proj["tile_rect"], proj["tiles_touched"], views=V)
         self._mark("bin_sort")
-        fw = r.rasterize_views(c, self.K, n, proj, P["rgb"], ids, ranges)
+        self.order = order = r.tile_order(c, ranges, views=V, out=self.order)
+        self._mark("tile_order")
+        fw = r.rasterize_views(c, self.K, n, proj, P["rgb"], ids, ranges, order)
         self._mark("rasterize_topk_fwd")
         store, scale = _side_join(self, joined, fw["ids"])
         tC, tD, tF = self.target
@@ -292,7 +298,7 @@ class StepViews:
             kb.record()
             self.kmarks.append((ka, kb))
         self._mark("feature_render_fwd_bwd")
-        r.rasterize_bwd_views(c, self.K, n, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg)
+        r.rasterize_bwd_views(c, self.K, n, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg, order)
         self._mark("rasterize_topk_bwd")
         r.project_bwd_views(c, P, self.sg, self.pg, self.dpose)
         self._mark("project_bwd")
@@ -754,7 +760,7 @@ def main():
                       "feature_fwd_bwd_ms": round(feature_ms(v["phases"]), 4),
                       "separate_launches_ms": v["separate"],
                       "fwd_ms_per_frame": round(v["phases"]["project_fwd"] + v["phases"]["bin_sort"] +
-                                                v["phases"]["rasterize_topk_fwd"] +
+                                                v["phases"]["tile_order"] + v["phases"]["rasterize_topk_fwd"] +
                                                 v["separate"]["feature_render_fwd"], 4),
                       "step_ms_percentiles": v["dist"],
                       # the render's own fwd+bwd: without the storage quantization of the

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LGS_ABI_VERSION 1
+#define LGS_ABI_VERSION 2
 #define LGS_TILE 16
 
 typedef enum {
@@ -172,6 +172,8 @@ lgs_status lgs_bin_sort_noalloc(const lgs_camera *cam, int32_t n, const float *d
  *      n_contrib[P] (entries of the tile's sorted run up to and including the last
  *      blended Gaussian; the backward replays from there), topk_ids[P*k],
  *      topk_w[P*k] (raw weights w), with P = width * height.
+ * tile_order: NULL (fixed tile mapping) or lgs_tile_order's output for these
+ *      tile_ranges (dispatch order only: the outputs are the same bits).
  * Errors: UNSUPPORTED if k is not one of lgs_supported_k().
  */
 lgs_status lgs_rasterize_topk_fwd(const lgs_camera *cam, int32_t k,
@@ -180,7 +182,8 @@ lgs_status lgs_rasterize_topk_fwd(const lgs_camera *cam, int32_t k,
                                   const int32_t *sorted_ids, const int32_t *tile_ranges,
                                   float *color, float *depth_map, float *alpha_map,
                                   float *T_final, int32_t *n_contrib,
-                                  int32_t *topk_ids, float *topk_w, hipStream_t stream);
+                                  int32_t *topk_ids, float *topk_w, const int32_t *tile_order,
+                                  hipStream_t stream);
 
 /*
  * Top-K feature render (Eq. 3-4): W = sum_k w_k, F[p] = sum_k (w_k / W) f[id_k],
@@ -286,6 +289,7 @@ lgs_status lgs_feature_render_vanilla_bwd(const lgs_camera *cam, const float *me
  * Accumulates per-Gaussian screen-space gradients:
  *   dL_dmean2d[n*2], dL_dconic[n*3] (w.r.t. a, b, c), dL_dopacity[n], dL_drgb[n*3],
  *   dL_ddepth_g[n] (w.r.t. the depth z of each Gaussian).
+ * tile_order: as for lgs_rasterize_topk_fwd.
  */
 lgs_status lgs_rasterize_topk_bwd(const lgs_camera *cam, int32_t k,
                                   const float *mean2d, const float *conic, const float *opacity,
@@ -296,7 +300,8 @@ lgs_status lgs_rasterize_topk_bwd(const lgs_camera *cam, int32_t k,
                                   const float *dL_dcolor, const float *dL_ddepth,
                                   const float *dL_dalpha, const float *dL_dtopkw,
                                   float *dL_dmean2d, float *dL_dconic, float *dL_dopacity,
-                                  float *dL_drgb, float *dL_ddepth_g, hipStream_t stream);
+                                  float *dL_drgb, float *dL_ddepth_g, const int32_t *tile_order,
+                                  hipStream_t stream);
 
 /*
  * Adjoint of the projection: chain rule from the screen-space gradients to the
@@ -373,7 +378,8 @@ lgs_status lgs_rasterize_topk_fwd_views(const lgs_camera *cams, int32_t views, i
                                         const int32_t *sorted_ids, const int32_t *tile_ranges,
                                         float *color, float *depth_map, float *alpha_map,
                                         float *T_final, int32_t *n_contrib,
-                                        int32_t *topk_ids, float *topk_w, hipStream_t stream);
+                                        int32_t *topk_ids, float *topk_w, const int32_t *tile_order,
+                                        hipStream_t stream);
 
 /* Blend adjoint of every view: record-indexed screen-space gradients, per-Gaussian
  * dL_drgb summed over the views (all accumulated). */
@@ -386,7 +392,30 @@ lgs_status lgs_rasterize_topk_bwd_views(const lgs_camera *cams, int32_t views, i
                                         const float *dL_dcolor, const float *dL_ddepth,
                                         const float *dL_dalpha, const float *dL_dtopkw,
                                         float *dL_dmean2d, float *dL_dconic, float *dL_dopacity,
-                                        float *dL_drgb, float *dL_ddepth_g, hipStream_t stream);
+                                        float *dL_drgb, float *dL_ddepth_g, const int32_t *tile_order,
+                                        hipStream_t stream);
+
+/*
+ * Dispatch order of the blend and its adjoint (the per-tile work of Eq. 1-2 and its
+ * adjoint; a scheduling aid that changes no result).  A tile's cost grows with its
+ * sorted run, and runs differ by an order of magnitude across a frame, so with tiles
+ * in raster order a few long ones finish last on an otherwise idle GPU.  This writes,
+ * on the device, an order in which each XCD's tiles start longest run first (pair
+ * counts in log-spaced buckets, eight per octave), from the tile_ranges of
+ * lgs_bin_sort / lgs_bin_sort_views for the same cameras and views.
+ * order[lgs_tile_order_size(width, height, views)] int32, caller-owned: entry b is the
+ * tile workgroup b renders (values >= the tile count are padding).  Pass it as
+ * tile_order to lgs_rasterize_topk_fwd(_views) and lgs_rasterize_topk_bwd(_views); a
+ * NULL tile_order keeps the fixed mapping.  The blend's outputs are the same bits
+ * either way; the adjoint's atomic sums may round in another order, as they may between
+ * any two runs.  The order is valid as long as tile_ranges is; a tile_order not
+ * written by this call for the same tiles is undefined (entries outside the tile
+ * range are skipped, so such an order can drop tiles but not fault).
+ * Errors: INVALID_ARG for NULL pointers, a misaligned tile_ranges or bad cameras.
+ */
+int64_t lgs_tile_order_size(int32_t width, int32_t height, int32_t views);
+lgs_status lgs_tile_order(const lgs_camera *cams, int32_t views, const int32_t *tile_ranges,
+                          int32_t *order, hipStream_t stream);
 
 /* Projection adjoint of every view: the parameter gradients summed over the views (one
  * thread per Gaussian adds its views in order and writes once: deterministic), and,

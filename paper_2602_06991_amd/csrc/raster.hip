@@ -34,6 +34,7 @@ struct RasterArgs {
     const float *depth;
     const int *sorted_ids;
     const int2 *ranges;
+    const int *order;   // block -> tile from lgs_tile_order, or null for the fixed mapping
 };
 
 struct TilePos {
@@ -53,6 +54,16 @@ __device__ __forceinline__ TilePos tile_pos(const RasterArgs &a, int tile) {
     t.pix0 = (long)t.view * a.W * a.H;
     t.rec0 = t.view * a.n;
     return t;
+}
+
+// The tile block blockIdx.x renders: from the dispatch order when one is given (an entry
+// outside [0, ntiles) runs nothing), else bands or strips over the XCDs.
+__device__ __forceinline__ int block_tile(const RasterArgs &a, int ntiles) {
+    if (a.order) {
+        const int t = a.order[blockIdx.x];
+        return (unsigned)t < (unsigned)ntiles ? t : ntiles;
+    }
+    return a.bands ? xcd_remap(blockIdx.x, gridDim.x) : xcd_strips(blockIdx.x);
 }
 
 template <int K>
@@ -88,7 +99,7 @@ __global__ __launch_bounds__(kFwdThreads) void raster_fwd_kernel(RasterArgs a, f
     __shared__ float4 s_co[256];   // conic a, b, c, opacity
     __shared__ float4 s_cz[256];   // r, g, b, depth
     const int ntiles = a.ntx * a.nty * a.views;
-    const int tile = a.bands ? xcd_remap(blockIdx.x, gridDim.x) : xcd_strips(blockIdx.x);
+    const int tile = block_tile(a, ntiles);
     if (tile >= ntiles) return;
     const TilePos tp = tile_pos(a, tile);
     const int t = threadIdx.x;
@@ -209,7 +220,7 @@ __global__ __launch_bounds__(kBwdThreads) void raster_bwd_kernel(
     __shared__ __align__(16) float s_part[kBwdRows][kRB][kNGP];   // [lane row][Gaussian][slot]
     __shared__ int s_max;
     const int ntiles = a.ntx * a.nty * a.views;
-    const int tile = a.bands ? xcd_remap(blockIdx.x, gridDim.x) : xcd_strips(blockIdx.x);
+    const int tile = block_tile(a, ntiles);
     if (tile >= ntiles) return;
     const TilePos tp = tile_pos(a, tile);
     const int t = threadIdx.x;
@@ -368,7 +379,7 @@ __global__ __launch_bounds__(kFwdThreads) void prune_stats_kernel(RasterArgs a, 
     __shared__ float4 s_co[256];
     __shared__ int s_max;
     const int ntiles = a.ntx * a.nty * a.views;
-    const int tile = a.bands ? xcd_remap(blockIdx.x, gridDim.x) : xcd_strips(blockIdx.x);
+    const int tile = block_tile(a, ntiles);
     if (tile >= ntiles) return;
     const TilePos tp = tile_pos(a, tile);
     const int t = threadIdx.x, lane = t & 63;
@@ -480,6 +491,46 @@ void launch_prune(RasterArgs a, const int *n_contrib, const int *topk_ids, int *
     case 16: CALL(16); break;            \
     }
 
+// The dispatch order of the tile kernels (lgs_tile_order).  Workgroups go to the XCDs
+// in turn, so block b runs on XCD b % 8; the blocks of XCD x keep the tiles the fixed
+// mapping gives that XCD (its L2 still holds their neighbours' records), reordered
+// so that tiles with more pairs start first and the short ones fill the tail.  The
+// weight is the tile's pair count in log-spaced buckets, eight per octave (a counting
+// sort in LDS; the order inside a bucket is whatever the atomics give: the tile
+// kernels' outputs do not depend on it).  One block per XCD.
+constexpr int kOrderBins = 257;   // 256 weight buckets, heaviest first, then the padding slots
+__global__ __launch_bounds__(1024) void tile_order_kernel(RasterArgs a, int grid, int *__restrict__ order) {
+    __shared__ int cnt[kOrderBins];
+    __shared__ int off[kOrderBins];
+    const int x = blockIdx.x, per = grid / 8, ntiles = a.ntx * a.nty * a.views;
+    auto tile_of = [&](int i) {
+        const int b = x + 8 * i;
+        return a.bands ? xcd_remap(b, grid) : xcd_strips(b);
+    };
+    auto bin_of = [&](int tile) {
+        if (tile >= ntiles) return kOrderBins - 1;
+        const int2 r = a.ranges[tile];
+        const int w = max(r.y - r.x, 0);
+        return 255 - min(255, (int)(8.0f * __log2f((float)w + 1.0f)));
+    };
+    for (int i = threadIdx.x; i < kOrderBins; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < per; i += blockDim.x) atomicAdd(&cnt[bin_of(tile_of(i))], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sum = 0;
+        for (int k = 0; k < kOrderBins; ++k) {
+            off[k] = sum;
+            sum += cnt[k];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < per; i += blockDim.x) {
+        const int t = tile_of(i);
+        order[x + 8 * atomicAdd(&off[bin_of(t)], 1)] = t;
+    }
+}
+
 // Checks the batched cameras (one image size) and fills the geometry part of RasterArgs.
 lgs_status raster_args(const lgs_camera *cams, int views, int n, RasterArgs &a) {
     LGS_REQUIRE(cams, LGS_ERR_INVALID_ARG, "camera array is NULL");
@@ -498,6 +549,7 @@ lgs_status raster_args(const lgs_camera *cams, int views, int n, RasterArgs &a) 
     a.views = views;
     a.n = n;
     a.bands = views % 8 == 0;
+    a.order = nullptr;
     return LGS_OK;
 }
 
@@ -511,7 +563,8 @@ extern "C" lgs_status lgs_rasterize_topk_fwd_views(const lgs_camera *cams, int32
                                                    const float *rgb, const float *depth, const int32_t *sorted_ids,
                                                    const int32_t *tile_ranges, float *color, float *depth_map,
                                                    float *alpha_map, float *T_final, int32_t *n_contrib,
-                                                   int32_t *topk_ids, float *topk_w, hipStream_t stream) {
+                                                   int32_t *topk_ids, float *topk_w, const int32_t *tile_order,
+                                                   hipStream_t stream) {
     RasterArgs a;
     lgs_status st = raster_args(cams, views, n, a);
     if (st) return st;
@@ -528,6 +581,7 @@ extern "C" lgs_status lgs_rasterize_topk_fwd_views(const lgs_camera *cams, int32
     a.depth = depth;
     a.sorted_ids = sorted_ids;
     a.ranges = (const int2 *)tile_ranges;
+    a.order = tile_order;
 #define CALL_FWD(KK) launch_fwd<KK>(a, color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w, stream)
     LGS_K_SWITCH(k, CALL_FWD)
 #undef CALL_FWD
@@ -540,11 +594,11 @@ extern "C" lgs_status lgs_rasterize_topk_fwd(const lgs_camera *cam, int32_t k, c
                                              const int32_t *sorted_ids, const int32_t *tile_ranges,
                                              float *color, float *depth_map, float *alpha_map,
                                              float *T_final, int32_t *n_contrib, int32_t *topk_ids,
-                                             float *topk_w, hipStream_t stream) {
+                                             float *topk_w, const int32_t *tile_order, hipStream_t stream) {
     // one view: the record of Gaussian g is g (n only splits views)
     return lgs_rasterize_topk_fwd_views(cam, 1, k, 0x7FFFFFFF, mean2d, conic, opacity, rgb, depth, sorted_ids,
                                         tile_ranges, color, depth_map, alpha_map, T_final, n_contrib, topk_ids,
-                                        topk_w, stream);
+                                        topk_w, tile_order, stream);
 }
 
 extern "C" lgs_status lgs_rasterize_topk_bwd_views(
@@ -553,7 +607,7 @@ extern "C" lgs_status lgs_rasterize_topk_bwd_views(
     const int32_t *tile_ranges, const float *T_final, const int32_t *n_contrib, const int32_t *topk_ids,
     const float *topk_w, const float *dL_dcolor, const float *dL_ddepth, const float *dL_dalpha,
     const float *dL_dtopkw, float *dL_dmean2d, float *dL_dconic, float *dL_dopacity, float *dL_drgb,
-    float *dL_ddepth_g, hipStream_t stream) {
+    float *dL_ddepth_g, const int32_t *tile_order, hipStream_t stream) {
     RasterArgs a;
     lgs_status st = raster_args(cams, views, n, a);
     if (st) return st;
@@ -571,6 +625,7 @@ extern "C" lgs_status lgs_rasterize_topk_bwd_views(
     a.depth = depth;
     a.sorted_ids = sorted_ids;
     a.ranges = (const int2 *)tile_ranges;
+    a.order = tile_order;
 #define CALL_BWD(KK)                                                                             \
     launch_bwd<KK>(a, T_final, n_contrib, topk_ids, topk_w, dL_dtopkw, dL_dcolor, dL_ddepth, dL_dalpha, \
                    dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream)
@@ -585,11 +640,11 @@ extern "C" lgs_status lgs_rasterize_topk_bwd(
     const float *T_final, const int32_t *n_contrib, const int32_t *topk_ids, const float *topk_w,
     const float *dL_dcolor, const float *dL_ddepth, const float *dL_dalpha, const float *dL_dtopkw,
     float *dL_dmean2d, float *dL_dconic, float *dL_dopacity, float *dL_drgb, float *dL_ddepth_g,
-    hipStream_t stream) {
+    const int32_t *tile_order, hipStream_t stream) {
     return lgs_rasterize_topk_bwd_views(cam, 1, k, 0x7FFFFFFF, mean2d, conic, opacity, rgb, depth, sorted_ids,
                                         tile_ranges, T_final, n_contrib, topk_ids, topk_w, dL_dcolor, dL_ddepth,
                                         dL_dalpha, dL_dtopkw, dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb,
-                                        dL_ddepth_g, stream);
+                                        dL_ddepth_g, tile_order, stream);
 }
 
 extern "C" lgs_status lgs_prune_stats_views(const lgs_camera *cams, int32_t views, int32_t k, int32_t n,
@@ -626,4 +681,23 @@ extern "C" lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const fl
                                       hipStream_t stream) {
     return lgs_prune_stats_views(cam, 1, k, 0x7FFFFFFF, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib,
                                  topk_ids, topk_count, max_w, stream);
+}
+
+extern "C" int64_t lgs_tile_order_size(int32_t width, int32_t height, int32_t views) {
+    if (width <= 0 || height <= 0 || views <= 0) return 0;
+    return strip_grid((long long)tiles_x(width) * tiles_y(height) * views);
+}
+
+extern "C" lgs_status lgs_tile_order(const lgs_camera *cams, int32_t views, const int32_t *tile_ranges,
+                                     int32_t *order, hipStream_t stream) {
+    RasterArgs a;
+    lgs_status st = raster_args(cams, views, 0, a);
+    if (st) return st;
+    LGS_REQUIRE(tile_ranges && order, LGS_ERR_INVALID_ARG, "lgs_tile_order: NULL pointer");
+    LGS_REQUIRE(((uintptr_t)tile_ranges & 7u) == 0, LGS_ERR_INVALID_ARG, "tile_ranges must be 8-byte aligned");
+    a.ranges = (const int2 *)tile_ranges;
+    const long long grid = strip_grid((long long)a.ntx * a.nty * a.views);
+    LGS_REQUIRE(grid % 8 == 0 && grid <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG, "too many tiles");
+    hipLaunchKernelGGL(tile_order_kernel, dim3(8), dim3(1024), 0, stream, a, (int)grid, order);
+    return check_launch("tile_order");
 }

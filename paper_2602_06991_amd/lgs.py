@@ -62,7 +62,7 @@ _SIG = {
     "lgs_bin_sort_count": [_I32, _I64, _P, ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_bin_sort_noalloc": [_CAM, _I32, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_rasterize_topk_fwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
-                               _P, _P],
+                               _P, _P, _P],
     "lgs_feature_render_fwd": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                ctypes.c_int, _P, _P],
     "lgs_feature_render_bwd": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
@@ -75,15 +75,16 @@ _SIG = {
     "lgs_feature_render_fwd_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                       ctypes.c_int, _P, _P, _F, _P, _P, _P],
     "lgs_rasterize_topk_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
-                               _P, _P, _P, _P, _P, _P, _P, _P],
+                               _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_bwd": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_fwd_views": [_CAM, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_bin_sort_views": [_CAM, _I32, _I32, _P, _P, _P, _P, ctypes.c_size_t, _I64, _P, _P,
                            ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_rasterize_topk_fwd_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
-                                     _P, _P, _P],
+                                     _P, _P, _P, _P],
+    "lgs_tile_order": [_CAM, _I32, _P, _P, _P],
     "lgs_rasterize_topk_bwd_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
-                                     _P, _P, _P, _P, _P, _P, _P, _P, _P],
+                                     _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_bwd_views": [_CAM, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_prune_stats_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_feature_render_vanilla_fwd": [_CAM, _P, _P, _P, _P, _P, _P, _I32, ctypes.c_int, _P, _P, ctypes.c_int,
@@ -98,7 +99,7 @@ _SIG = {
     "lgs_zero_marked_rows": [_I32, _I32, _I32, _P, _P, _P],
     "lgs_quantize_marked_rows": [_I32, _I32, _I32, _P, _P, ctypes.c_int, _P, _P, _P],
 }
-EXPORTS = ["lgs_abi_version", "lgs_last_error", "lgs_supported_k", *_SIG]
+EXPORTS = ["lgs_abi_version", "lgs_last_error", "lgs_supported_k", "lgs_tile_order_size", *_SIG]
 
 _lib = None
 
@@ -125,6 +126,8 @@ def load():
     L.lgs_last_error.restype = ctypes.c_char_p
     L.lgs_supported_k.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     L.lgs_supported_k.restype = ctypes.POINTER(ctypes.c_int32)
+    L.lgs_tile_order_size.argtypes = [_I32, _I32, _I32]
+    L.lgs_tile_order_size.restype = ctypes.c_int64
     _lib = L
     return L
 
@@ -197,10 +200,10 @@ def lgs_bin_sort_noalloc(cam, n, depth, tile_rect, tiles_touched, max_pairs, sor
 
 def lgs_rasterize_topk_fwd(cam, k, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,
                            color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w,
-                           stream=None):
+                           stream=None, tile_order=None):
     return _check(load().lgs_rasterize_topk_fwd(ctypes.byref(cam), k, mean2d, conic, opacity, rgb,
                                                 depth, sorted_ids, tile_ranges, color, depth_map,
-                                                alpha_map, T_final, n_contrib, topk_ids, topk_w,
+                                                alpha_map, T_final, n_contrib, topk_ids, topk_w, tile_order,
                                                 stream))
 
 
@@ -252,12 +255,12 @@ def lgs_prune_select(n, topk_count, max_w, count_below, expo, keep_ratio, worksp
 def lgs_rasterize_topk_bwd(cam, k, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,
                            T_final, n_contrib, topk_ids, topk_w, dL_dcolor, dL_ddepth, dL_dalpha,
                            dL_dtopkw, dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g,
-                           stream=None):
+                           stream=None, tile_order=None):
     return _check(load().lgs_rasterize_topk_bwd(ctypes.byref(cam), k, mean2d, conic, opacity, rgb,
                                                 depth, sorted_ids, tile_ranges, T_final, n_contrib,
                                                 topk_ids, topk_w, dL_dcolor, dL_ddepth, dL_dalpha,
                                                 dL_dtopkw, dL_dmean2d, dL_dconic, dL_dopacity,
-                                                dL_drgb, dL_ddepth_g, stream))
+                                                dL_drgb, dL_ddepth_g, tile_order, stream))
 
 
 def lgs_project_bwd(cam, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,
@@ -319,20 +322,30 @@ def lgs_bin_sort_views(cams, views, n, depth, tile_rect, tiles_touched, workspac
 
 
 def lgs_rasterize_topk_fwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,
-                                 color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w, stream=None):
+                                 color, depth_map, alpha_map, T_final, n_contrib, topk_ids, topk_w, stream=None,
+                                 tile_order=None):
     return _check(load().lgs_rasterize_topk_fwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth,
                                                       sorted_ids, tile_ranges, color, depth_map, alpha_map,
-                                                      T_final, n_contrib, topk_ids, topk_w, stream))
+                                                      T_final, n_contrib, topk_ids, topk_w, tile_order, stream))
+
+
+def lgs_tile_order_size(width, height, views):
+    return int(load().lgs_tile_order_size(width, height, views))
+
+
+def lgs_tile_order(cams, views, tile_ranges, order, stream=None):
+    return _check(load().lgs_tile_order(cams, views, tile_ranges, order, stream))
 
 
 def lgs_rasterize_topk_bwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,
                                  T_final, n_contrib, topk_ids, topk_w, dL_dcolor, dL_ddepth, dL_dalpha, dL_dtopkw,
-                                 dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream=None):
+                                 dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g, stream=None,
+                                 tile_order=None):
     return _check(load().lgs_rasterize_topk_bwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth,
                                                       sorted_ids, tile_ranges, T_final, n_contrib, topk_ids,
                                                       topk_w, dL_dcolor, dL_ddepth, dL_dalpha, dL_dtopkw,
                                                       dL_dmean2d, dL_dconic, dL_dopacity, dL_drgb, dL_ddepth_g,
-                                                      stream))
+                                                      tile_order, stream))
 
 
 def lgs_project_bwd_views(cams, views, n, means, log_scales, quats, opacity_logits, rgb, dL_dmean2d, dL_dconic,

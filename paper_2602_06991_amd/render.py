@@ -13,6 +13,8 @@ stale copy is never rendered.  ``r.set_features(feat)`` refreshes it explicitly.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import lgs
@@ -120,7 +122,19 @@ def project(cam, P):
     return out
 
 
-def rasterize(cam, K, proj, rgb, sorted_ids, ranges):
+def tile_order(cams, ranges, views=1, out=None):
+    """The blend's dispatch order for these tile ranges (longest runs first within each
+    XCD; it changes no result).  cams: one camera, or the camera array of `views`."""
+    cam0 = cams[0] if views > 1 else cams
+    size = lgs.lgs_tile_order_size(cam0.width, cam0.height, views)
+    if out is None or out.numel() < size:
+        out = torch.empty(size, dtype=torch.int32, device=ranges.device)
+    _need_cuda(ranges, out)
+    lgs.lgs_tile_order(cams if views > 1 else ctypes.byref(cams), views, _p(ranges), _p(out), _stream())
+    return out
+
+
+def rasterize(cam, K, proj, rgb, sorted_ids, ranges, order=None):
     H, W = cam.height, cam.width
     dev = rgb.device
     out = dict(C=torch.empty(H, W, 3, device=dev), D=torch.empty(H, W, device=dev),
@@ -131,7 +145,7 @@ def rasterize(cam, K, proj, rgb, sorted_ids, ranges):
     lgs.lgs_rasterize_topk_fwd(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(out["C"]),
                                _p(out["D"]), _p(out["O"]), _p(out["T"]), _p(out["n_contrib"]),
-                               _p(out["ids"]), _p(out["w"]), _stream())
+                               _p(out["ids"]), _p(out["w"]), _stream(), tile_order=_p(order))
     return out
 
 
@@ -261,12 +275,13 @@ def feature_vanilla_bwd(cam, proj, sorted_ids, ranges, fwd, feat_store, feat_sca
                                        _stream())
 
 
-def rasterize_bwd(cam, K, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads):
+def rasterize_bwd(cam, K, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads, order=None):
     lgs.lgs_rasterize_topk_bwd(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(fwd["T"]),
                                _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(fwd["w"]), _p(gC), _p(gD),
                                _p(gO), _p(dtw), _p(grads["mean2d"]), _p(grads["conic"]),
-                               _p(grads["opacity"]), _p(grads["rgb"]), _p(grads["depth"]), _stream())
+                               _p(grads["opacity"]), _p(grads["rgb"]), _p(grads["depth"]), _stream(),
+                               tile_order=_p(order))
 
 
 def project_bwd(cam, P, sgrads, pgrads):
@@ -311,7 +326,7 @@ def project_views(cams, P):
     return out
 
 
-def rasterize_views(cams, K, n, proj, rgb, sorted_ids, ranges):
+def rasterize_views(cams, K, n, proj, rgb, sorted_ids, ranges, order=None):
     V = len(cams)
     H, W = cams[0].height, cams[0].width
     dev = rgb.device
@@ -323,16 +338,17 @@ def rasterize_views(cams, K, n, proj, rgb, sorted_ids, ranges):
     lgs.lgs_rasterize_topk_fwd_views(cams, V, K, n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]),
                                      _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges), _p(out["C"]),
                                      _p(out["D"]), _p(out["O"]), _p(out["T"]), _p(out["n_contrib"]),
-                                     _p(out["ids"]), _p(out["w"]), _stream())
+                                     _p(out["ids"]), _p(out["w"]), _stream(), tile_order=_p(order))
     return out
 
 
-def rasterize_bwd_views(cams, K, n, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads):
+def rasterize_bwd_views(cams, K, n, proj, rgb, sorted_ids, ranges, fwd, gC, gD, gO, dtw, grads, order=None):
     lgs.lgs_rasterize_topk_bwd_views(cams, len(cams), K, n, _p(proj["mean2d"]), _p(proj["conic"]),
                                      _p(proj["opacity"]), _p(rgb), _p(proj["depth"]), _p(sorted_ids), _p(ranges),
                                      _p(fwd["T"]), _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(fwd["w"]), _p(gC),
                                      _p(gD), _p(gO), _p(dtw), _p(grads["mean2d"]), _p(grads["conic"]),
-                                     _p(grads["opacity"]), _p(grads["rgb"]), _p(grads["depth"]), _stream())
+                                     _p(grads["opacity"]), _p(grads["rgb"]), _p(grads["depth"]), _stream(),
+                                     tile_order=_p(order))
 
 
 def project_bwd_views(cams, P, sgrads, pgrads=None, dpose=None):
@@ -422,11 +438,12 @@ class _TopKRender(torch.autograd.Function):
         proj = project(cam, P)
         ids, ranges, _ = r.binner(cam, means.shape[0], proj["depth"], proj["tile_rect"],
                                   proj["tiles_touched"])
-        fw = rasterize(cam, r.K, proj, rgb, ids, ranges)
+        order = tile_order(cam, ranges)
+        fw = rasterize(cam, r.K, proj, rgb, ids, ranges, order)
         store, scale = (feat, None) if r.feat_dtype == "f32" else (r.store, r.scale)
         F = feature_fwd(fw["ids"], fw["w"], store, scale, r.feat_dtype, r.map_dtype)
         ctx.r, ctx.cam, ctx.P, ctx.proj, ctx.fw = r, cam, P, proj, fw
-        ctx.sorted_ids, ctx.ranges = ids.clone(), ranges
+        ctx.sorted_ids, ctx.ranges, ctx.order = ids.clone(), ranges, order
         ctx.store, ctx.scale, ctx.n, ctx.d = store, scale, means.shape[0], feat.shape[1]
         return fw["C"], fw["D"], fw["O"], F
 
@@ -445,7 +462,7 @@ class _TopKRender(torch.autograd.Function):
             dtw = None
         sg = screen_grad_buffers(ctx.n, dev)
         rasterize_bwd(cam, r.K, ctx.proj, ctx.P["rgb"], ctx.sorted_ids, ctx.ranges, fw, gC, gD, gO,
-                      dtw, sg)
+                      dtw, sg, ctx.order)
         pg = dict(means=torch.zeros(ctx.n, 3, device=dev), log_scales=torch.zeros(ctx.n, 3, device=dev),
                   quats=torch.zeros(ctx.n, 4, device=dev), opacity_logits=torch.zeros(ctx.n, device=dev))
         project_bwd(cam, ctx.P, sg, pg)

@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_version_and_k_set():
-    assert lgs.lgs_abi_version() == 1
+    assert lgs.lgs_abi_version() == 2
     assert lgs.lgs_supported_k() == [1, 2, 3, 4, 5, 8, 10, 16]
 
 
@@ -160,3 +160,20 @@ def test_marked_row_quantize_validation():
         with pytest.raises(lgs.LgsError) as e:
             lgs.lgs_quantize_marked_rows(*args)
         assert e.value.status == status, args
+
+
+def test_tile_order_size_and_validation():
+    # padded to whole strips of 16 tiles over the 8 XCDs (128 workgroups)
+    assert lgs.lgs_tile_order_size(1200, 680, 1) == 3328       # 75 x 43 = 3225 tiles
+    assert lgs.lgs_tile_order_size(640, 480, 8) == 9600        # 8 x 40 x 30
+    assert lgs.lgs_tile_order_size(16, 16, 1) == 128
+    assert lgs.lgs_tile_order_size(0, 480, 1) == 0
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_tile_order(_cam(), 1, None, FAKE)
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_tile_order(_cam(), 1, FAKE + 4, FAKE)          # tile_ranges not 8-byte aligned
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
+    with pytest.raises(lgs.LgsError) as e:
+        lgs.lgs_tile_order(_cam(f=0.0), 1, FAKE, FAKE)
+    assert e.value.status == lgs.LGS_ERR_INVALID_ARG
