@@ -172,7 +172,7 @@ class Step:
         self.gflat, self.sg, self.pg = _geometry_grads(torch, n, n, dev)
         self.npix = cam.width * cam.height
         self.events = None
-        self.order = None   # the blend's dispatch order, rewritten each step
+        self.order = self.border = None   # the blend's and its adjoint's dispatch orders
         self.kmarks = None
         _side_init(self, torch, None if geometry_only else form, n, d, dev, not geometry_only and not vanilla,
                    dense_quantize)
@@ -234,7 +234,9 @@ class Step:
             self.kmarks.append((ka, kb))
         if not self.geometry_only:
             self._mark("feature_render_fwd_bwd" if self.fused and not self.vanilla else "feature_render_bwd")
-        r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg, order)
+        self.border = border = r.tile_order(c, ranges, n_contrib=fw["n_contrib"], out=self.border)
+        self._mark("tile_order_bwd")
+        r.rasterize_bwd(c, self.K, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg, border)
         self._mark("rasterize_topk_bwd")
         r.project_bwd(c, P, self.sg, self.pg)
         self._mark("project_bwd")
@@ -262,7 +264,7 @@ class StepViews:
         self.dpose = torch.empty(6 * self.V, device=dev)
         self.npix = cams[0].width * cams[0].height * self.V
         self.events = None
-        self.order = None
+        self.order = self.border = None
         self.kmarks = None
         _side_init(self, torch, form, n, d, dev, True, dense_quantize)
 
@@ -298,7 +300,9 @@ class StepViews:
             kb.record()
             self.kmarks.append((ka, kb))
         self._mark("feature_render_fwd_bwd")
-        r.rasterize_bwd_views(c, self.K, n, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg, order)
+        self.border = border = r.tile_order(c, ranges, views=V, n_contrib=fw["n_contrib"], out=self.border)
+        self._mark("tile_order_bwd")
+        r.rasterize_bwd_views(c, self.K, n, proj, P["rgb"], ids, ranges, fw, gC, gD, None, dtw, self.sg, border)
         self._mark("rasterize_topk_bwd")
         r.project_bwd_views(c, P, self.sg, self.pg, self.dpose)
         self._mark("project_bwd")

@@ -400,11 +400,15 @@ lgs_status lgs_rasterize_topk_bwd_views(const lgs_camera *cams, int32_t views, i
  * adjoint; a scheduling aid that changes no result).  A tile's cost grows with its
  * sorted run, and runs differ by an order of magnitude across a frame, so with tiles
  * in raster order a few long ones finish last on an otherwise idle GPU.  This writes,
- * on the device, an order in which each XCD's tiles start longest run first (pair
- * counts in log-spaced buckets, eight per octave), from the tile_ranges of
- * lgs_bin_sort / lgs_bin_sort_views for the same cameras and views.
- * order[lgs_tile_order_size(width, height, views)] int32, caller-owned: entry b is the
- * tile workgroup b renders (values >= the tile count are padding).  Pass it as
+ * on the device, an order in which each XCD's tiles start longest run first (weights
+ * in log-spaced buckets, eight per octave), from the tile_ranges of lgs_bin_sort /
+ * lgs_bin_sort_views for the same cameras and views.  The weight is the tile's pair
+ * count, or, when n_contrib (lgs_rasterize_topk_fwd's output, P entries) is given, the
+ * largest n_contrib over the tile's pixels: the length of list the adjoint walks, the
+ * better weight for the adjoint where early termination leaves most of a run unused.
+ * order[lgs_tile_order_size(width, height, views)] int32, caller-owned; its first
+ * lgs_tile_order_size / 2 entries are the order (entry b is the tile workgroup b
+ * renders; values >= the tile count are padding), the rest holds the tile weights.  Pass it as
  * tile_order to lgs_rasterize_topk_fwd(_views) and lgs_rasterize_topk_bwd(_views); a
  * NULL tile_order keeps the fixed mapping.  The blend's outputs are the same bits
  * either way; the adjoint's atomic sums may round in another order, as they may between
@@ -415,7 +419,7 @@ lgs_status lgs_rasterize_topk_bwd_views(const lgs_camera *cams, int32_t views, i
  */
 int64_t lgs_tile_order_size(int32_t width, int32_t height, int32_t views);
 lgs_status lgs_tile_order(const lgs_camera *cams, int32_t views, const int32_t *tile_ranges,
-                          int32_t *order, hipStream_t stream);
+                          const int32_t *n_contrib, int32_t *order, hipStream_t stream);
 
 /* Projection adjoint of every view: the parameter gradients summed over the views (one
  * thread per Gaussian adds its views in order and writes once: deterministic), and,

@@ -497,9 +497,11 @@ void launch_prune(RasterArgs a, const int *n_contrib, const int *topk_ids, int *
 // so that tiles with more pairs start first and the short ones fill the tail.  The
 // weight is the tile's pair count in log-spaced buckets, eight per octave (a counting
 // sort in LDS; the order inside a bucket is whatever the atomics give: the tile
-// kernels' outputs do not depend on it).  One block per XCD.
+// kernels' outputs do not depend on it).  One block per XCD.  weight: null for the
+// pair counts, else one weight per tile (tile_weight_kernel).
 constexpr int kOrderBins = 257;   // 256 weight buckets, heaviest first, then the padding slots
-__global__ __launch_bounds__(1024) void tile_order_kernel(RasterArgs a, int grid, int *__restrict__ order) {
+__global__ __launch_bounds__(1024) void tile_order_kernel(RasterArgs a, int grid, const int *__restrict__ weight,
+                                                          int *__restrict__ order) {
     __shared__ int cnt[kOrderBins];
     __shared__ int off[kOrderBins];
     const int x = blockIdx.x, per = grid / 8, ntiles = a.ntx * a.nty * a.views;
@@ -509,26 +511,54 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(RasterArgs a, int grid
     };
     auto bin_of = [&](int tile) {
         if (tile >= ntiles) return kOrderBins - 1;
-        const int2 r = a.ranges[tile];
-        const int w = max(r.y - r.x, 0);
+        int w;
+        if (weight) {
+            w = max(weight[tile], 0);
+        } else {
+            const int2 r = a.ranges[tile];
+            w = max(r.y - r.x, 0);
+        }
         return 255 - min(255, (int)(8.0f * __log2f((float)w + 1.0f)));
     };
     for (int i = threadIdx.x; i < kOrderBins; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < per; i += blockDim.x) atomicAdd(&cnt[bin_of(tile_of(i))], 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int sum = 0;
-        for (int k = 0; k < kOrderBins; ++k) {
-            off[k] = sum;
-            sum += cnt[k];
+    if (threadIdx.x < 64) {   // one wave scans the 256 weight bins, four per lane, then the padding bin
+        const int l = threadIdx.x;
+        const int c0 = cnt[4 * l], c1 = cnt[4 * l + 1], c2 = cnt[4 * l + 2], c3 = cnt[4 * l + 3];
+        const int own = c0 + c1 + c2 + c3;
+        int inc = own;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(inc, d);
+            if (l >= d) inc += y;
         }
+        const int ex = inc - own;
+        off[4 * l] = ex;
+        off[4 * l + 1] = ex + c0;
+        off[4 * l + 2] = ex + c0 + c1;
+        off[4 * l + 3] = ex + c0 + c1 + c2;
+        if (l == 63) off[kOrderBins - 1] = inc;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < per; i += blockDim.x) {
         const int t = tile_of(i);
         order[x + 8 * atomicAdd(&off[bin_of(t)], 1)] = t;
     }
+}
+
+// A tile's weight for the adjoint's order: the largest n_contrib over its pixels, the
+// length of list its adjoint walks.  One 256-thread block per tile.
+__global__ __launch_bounds__(256) void tile_weight_kernel(RasterArgs a, const int *__restrict__ n_contrib,
+                                                          int *__restrict__ weight) {
+    __shared__ int s_max[4];
+    const TilePos tp = tile_pos(a, blockIdx.x);
+    const int t = threadIdx.x, px = tp.x0 + (t & 15), py = tp.y0 + (t >> 4);
+    int v = (px < a.W && py < a.H) ? n_contrib[tp.pix0 + (long)py * a.W + px] : 0;
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
+    if ((t & 63) == 0) s_max[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) weight[blockIdx.x] = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
 }
 
 // Checks the batched cameras (one image size) and fills the geometry part of RasterArgs.
@@ -683,13 +713,14 @@ extern "C" lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const fl
                                  topk_ids, topk_count, max_w, stream);
 }
 
+// The order buffer: the grid's entries, then as many again for the tile weights.
 extern "C" int64_t lgs_tile_order_size(int32_t width, int32_t height, int32_t views) {
     if (width <= 0 || height <= 0 || views <= 0) return 0;
-    return strip_grid((long long)tiles_x(width) * tiles_y(height) * views);
+    return 2ll * strip_grid((long long)tiles_x(width) * tiles_y(height) * views);
 }
 
 extern "C" lgs_status lgs_tile_order(const lgs_camera *cams, int32_t views, const int32_t *tile_ranges,
-                                     int32_t *order, hipStream_t stream) {
+                                     const int32_t *n_contrib, int32_t *order, hipStream_t stream) {
     RasterArgs a;
     lgs_status st = raster_args(cams, views, 0, a);
     if (st) return st;
@@ -698,6 +729,12 @@ extern "C" lgs_status lgs_tile_order(const lgs_camera *cams, int32_t views, cons
     a.ranges = (const int2 *)tile_ranges;
     const long long grid = strip_grid((long long)a.ntx * a.nty * a.views);
     LGS_REQUIRE(grid % 8 == 0 && grid <= 0x7FFFFFFF, LGS_ERR_INVALID_ARG, "too many tiles");
-    hipLaunchKernelGGL(tile_order_kernel, dim3(8), dim3(1024), 0, stream, a, (int)grid, order);
+    const int ntiles = a.ntx * a.nty * a.views;
+    int *weight = nullptr;
+    if (n_contrib) {
+        weight = order + grid;
+        hipLaunchKernelGGL(tile_weight_kernel, dim3(ntiles), dim3(256), 0, stream, a, n_contrib, weight);
+    }
+    hipLaunchKernelGGL(tile_order_kernel, dim3(8), dim3(1024), 0, stream, a, (int)grid, weight, order);
     return check_launch("tile_order");
 }

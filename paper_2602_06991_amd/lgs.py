@@ -82,7 +82,7 @@ _SIG = {
                            ctypes.POINTER(ctypes.c_int64), _P],
     "lgs_rasterize_topk_fwd_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                      _P, _P, _P, _P],
-    "lgs_tile_order": [_CAM, _I32, _P, _P, _P],
+    "lgs_tile_order": [_CAM, _I32, _P, _P, _P, _P],
     "lgs_rasterize_topk_bwd_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_bwd_views": [_CAM, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -333,8 +333,8 @@ def lgs_tile_order_size(width, height, views):
     return int(load().lgs_tile_order_size(width, height, views))
 
 
-def lgs_tile_order(cams, views, tile_ranges, order, stream=None):
-    return _check(load().lgs_tile_order(cams, views, tile_ranges, order, stream))
+def lgs_tile_order(cams, views, tile_ranges, n_contrib, order, stream=None):
+    return _check(load().lgs_tile_order(cams, views, tile_ranges, n_contrib, order, stream))
 
 
 def lgs_rasterize_topk_bwd_views(cams, views, k, n, mean2d, conic, opacity, rgb, depth, sorted_ids, tile_ranges,

@@ -122,15 +122,22 @@ def project(cam, P):
     return out
 
 
-def tile_order(cams, ranges, views=1, out=None):
+def tile_order(cams, ranges, views=1, n_contrib=None, out=None):
     """The blend's dispatch order for these tile ranges (longest runs first within each
-    XCD; it changes no result).  cams: one camera, or the camera array of `views`."""
+    XCD; it changes no result), weighted by the pair counts, or with the forward's
+    n_contrib by the list length the adjoint walks.  cams: one camera, or the camera
+    array of `views`."""
     cam0 = cams[0] if views > 1 else cams
     size = lgs.lgs_tile_order_size(cam0.width, cam0.height, views)
     if out is None or out.numel() < size:
         out = torch.empty(size, dtype=torch.int32, device=ranges.device)
     _need_cuda(ranges, out)
-    lgs.lgs_tile_order(cams if views > 1 else ctypes.byref(cams), views, _p(ranges), _p(out), _stream())
+    if n_contrib is not None:
+        _need_cuda(n_contrib)
+        if n_contrib.numel() != views * cam0.width * cam0.height or n_contrib.dtype != torch.int32:
+            raise ValueError("tile_order: n_contrib must be the forward's int32 map of every view")
+    lgs.lgs_tile_order(cams if views > 1 else ctypes.byref(cams), views, _p(ranges), _p(n_contrib), _p(out),
+                       _stream())
     return out
 
 
@@ -462,7 +469,7 @@ class _TopKRender(torch.autograd.Function):
             dtw = None
         sg = screen_grad_buffers(ctx.n, dev)
         rasterize_bwd(cam, r.K, ctx.proj, ctx.P["rgb"], ctx.sorted_ids, ctx.ranges, fw, gC, gD, gO,
-                      dtw, sg, ctx.order)
+                      dtw, sg, tile_order(cam, ctx.ranges, n_contrib=fw["n_contrib"], out=ctx.order))
         pg = dict(means=torch.zeros(ctx.n, 3, device=dev), log_scales=torch.zeros(ctx.n, 3, device=dev),
                   quats=torch.zeros(ctx.n, 4, device=dev), opacity_logits=torch.zeros(ctx.n, device=dev))
         project_bwd(cam, ctx.P, sg, pg)

@@ -163,17 +163,17 @@ def test_marked_row_quantize_validation():
 
 
 def test_tile_order_size_and_validation():
-    # padded to whole strips of 16 tiles over the 8 XCDs (128 workgroups)
-    assert lgs.lgs_tile_order_size(1200, 680, 1) == 3328       # 75 x 43 = 3225 tiles
-    assert lgs.lgs_tile_order_size(640, 480, 8) == 9600        # 8 x 40 x 30
-    assert lgs.lgs_tile_order_size(16, 16, 1) == 128
+    # the grid (whole strips of 16 tiles over the 8 XCDs: 128 workgroups), twice
+    assert lgs.lgs_tile_order_size(1200, 680, 1) == 2 * 3328   # 75 x 43 = 3225 tiles
+    assert lgs.lgs_tile_order_size(640, 480, 8) == 2 * 9600    # 8 x 40 x 30
+    assert lgs.lgs_tile_order_size(16, 16, 1) == 2 * 128
     assert lgs.lgs_tile_order_size(0, 480, 1) == 0
     with pytest.raises(lgs.LgsError) as e:
-        lgs.lgs_tile_order(_cam(), 1, None, FAKE)
+        lgs.lgs_tile_order(_cam(), 1, None, None, FAKE)
     assert e.value.status == lgs.LGS_ERR_INVALID_ARG
     with pytest.raises(lgs.LgsError) as e:
-        lgs.lgs_tile_order(_cam(), 1, FAKE + 4, FAKE)          # tile_ranges not 8-byte aligned
+        lgs.lgs_tile_order(_cam(), 1, FAKE + 4, None, FAKE)    # tile_ranges not 8-byte aligned
     assert e.value.status == lgs.LGS_ERR_INVALID_ARG
     with pytest.raises(lgs.LgsError) as e:
-        lgs.lgs_tile_order(_cam(f=0.0), 1, FAKE, FAKE)
+        lgs.lgs_tile_order(_cam(f=0.0), 1, FAKE, FAKE, FAKE)
     assert e.value.status == lgs.LGS_ERR_INVALID_ARG

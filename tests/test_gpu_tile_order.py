@@ -1,9 +1,10 @@
 """The blend's dispatch order (lgs_tile_order): a scheduling aid that must change no
 result.  Checked on one 1200x680 view (tiles dealt to the XCDs in strips) and on the
-8 keyframes of the 640x480 room workload (whole views per XCD): the order is a
-permutation of the padded grid; each XCD keeps the tiles the fixed mapping gives it,
-heaviest pair-count bucket first; the blend with the order gives the same bits as
-without; the adjoint's atomic sums match to summation order."""
+8 keyframes of the 640x480 room workload (whole views per XCD), for both weights (the
+pair counts; the forward's largest n_contrib per tile): the order is a permutation of
+the padded grid; each XCD keeps the tiles the fixed mapping gives it, heaviest weight
+bucket first; the blend with the order gives the same bits as without; the adjoint's
+atomic sums match to summation order."""
 import numpy as np
 import pytest
 
@@ -70,22 +71,26 @@ def test_tile_order_changes_no_result(torch, cfg, K, N):
     order = render.tile_order(cams, ranges, views=V)
     torch.cuda.synchronize()
     nt = ((W + 15) // 16) * ((H + 15) // 16) * V
-    G = lgs.lgs_tile_order_size(W, H, V)
+    G = lgs.lgs_tile_order_size(W, H, V) // 2
     print(f"config {cfg}: {V} x {W}x{H}, N={n}, {nt} tiles, grid {G}, {m} pairs", flush=True)
     assert G % 128 == 0 and nt <= G < nt + 128
-    o = order.cpu().numpy().astype(np.int64)
-    assert o.shape == (G,) and np.array_equal(np.sort(o), np.arange(G))
     fixed = _fixed_mapping(G, V % 8 == 0)
     assert np.array_equal(np.sort(fixed), np.arange(G))
+
+    def check(order, wt):
+        o = order[:G].cpu().numpy().astype(np.int64)
+        assert np.array_equal(np.sort(o), np.arange(G))
+        w = np.full(G, -1, np.int64)
+        w[:nt] = wt
+        for x in range(8):
+            got, want = o[x::8], fixed[x::8]
+            assert np.array_equal(np.sort(got), np.sort(want)), x    # the XCD keeps its tiles
+            real = got[got < nt]
+            assert np.all(got[len(real):] >= nt), x                   # padding last
+            assert _heaviest_first(w[real]), x                        # heaviest bucket first
+
     r = ranges.cpu().numpy().astype(np.int64)
-    w = np.full(G, -1, np.int64)
-    w[:nt] = r[:, 1] - r[:, 0]
-    for x in range(8):
-        got, want = o[x::8], fixed[x::8]
-        assert np.array_equal(np.sort(got), np.sort(want)), x        # the XCD keeps its tiles
-        real = got[got < nt]
-        assert np.all(got[len(real):] >= nt), x                       # padding last
-        assert _heaviest_first(w[real]), x                            # heaviest bucket first
+    check(order, r[:, 1] - r[:, 0])
     # the blend: the same bits with and without the order
     f0, f1 = fwd(None), fwd(order)
     torch.cuda.synchronize()
@@ -97,12 +102,20 @@ def test_tile_order_changes_no_result(torch, cfg, K, N):
     gC, gD, gO = t(gC.reshape(V * H, W, 3)), t(gD.reshape(V * H, W)), t(gO.reshape(V * H, W))
     gen = torch.Generator(device="cuda").manual_seed(11)
     dtw = torch.randn(V * H, W, K, device="cuda", generator=gen)
-    s0, s1 = sgb(), sgb()
+    # the adjoint's order, weighted by the largest n_contrib of each tile
+    border = render.tile_order(cams, ranges, views=V, n_contrib=f0["n_contrib"])
+    torch.cuda.synchronize()
+    nc = np.zeros((V, (H + 15) // 16 * 16, (W + 15) // 16 * 16), np.int64)
+    nc[:, :H, :W] = f0["n_contrib"].cpu().numpy().reshape(V, H, W)
+    check(border, nc.reshape(V, (H + 15) // 16, 16, (W + 15) // 16, 16).max(axis=(2, 4)).reshape(-1))
+    s0, s1, s2 = sgb(), sgb(), sgb()
     bwd(f0, s0, None)
     bwd(f0, s1, order)
+    bwd(f0, s2, border)
     torch.cuda.synchronize()
     for k in s0:
-        a, b_ = s0[k].double(), s1[k].double()
-        e = float((a - b_).norm() / a.norm().clamp_min(1e-30))
-        print(f"   {k}: ordered vs fixed mapping rel {e:.2e}", flush=True)
-        assert e <= 1e-5, (k, e)
+        a = s0[k].double()
+        for name, sx in (("pair-count order", s1), ("n_contrib order", s2)):
+            e = float((a - sx[k].double()).norm() / a.norm().clamp_min(1e-30))
+            print(f"   {k}: {name} vs fixed mapping rel {e:.2e}", flush=True)
+            assert e <= 1e-5, (k, name, e)
