@@ -635,8 +635,10 @@ def main():
         cnt = torch.zeros(P["feat"].shape[0], dtype=torch.int32, device="cuda")
         mxw = torch.zeros(P["feat"].shape[0], device="cuda")
         st = step.last
-        prune_ms = timed(torch, lambda: render.prune_stats(cam, K, st["proj"], st["ids"], st["ranges"], fw, cnt,
-                                                           mxw))
+        # with the dispatch order of the replay, weighted by the forward's n_contrib
+        prune_ms = timed(torch, lambda: render.prune_stats(
+            cam, K, st["proj"], st["ids"], st["ranges"], fw, cnt, mxw,
+            render.tile_order(cam, st["ranges"], n_contrib=fw["n_contrib"])))
         # the hybrid schedule's geometry-only iterations: no feature passes, no gamma term
         geo = Step(torch, render, lgs, P, target, cam, K, form, fused, geometry_only=True)
         geo_ms, _, _, _ = time_steps(torch, geo, args.steps, args.warmup)

@@ -440,7 +440,7 @@ lgs_status lgs_prune_stats_views(const lgs_camera *cams, int32_t views, int32_t 
                                  const float *mean2d, const float *conic, const float *opacity,
                                  const int32_t *sorted_ids, const int32_t *tile_ranges,
                                  const int32_t *n_contrib, const int32_t *topk_ids, int32_t *topk_count,
-                                 float *max_w, hipStream_t stream);
+                                 float *max_w, const int32_t *tile_order, hipStream_t stream);
 
 /*
  * Statistics of the semantic-geometric consistency pruning (Sec. 3.3, Eq. 5) for one
@@ -454,11 +454,14 @@ lgs_status lgs_prune_stats_views(const lgs_camera *cams, int32_t views, int32_t 
  * over all keyframes; the caller zeroes them first (max_w entries must be >= 0).
  * The weights are recomputed with the forward's own arithmetic and equal its weights
  * bit for bit.  topk_count[n] int32, max_w[n] FP32 (4-byte aligned).
+ * tile_order: NULL or lgs_tile_order's output for these tile_ranges (with n_contrib, the
+ * weight that fits this replay); the counts and maxima are the same either way (integer
+ * adds and maxima of non-negative floats do not depend on their order).
  */
 lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const float *mean2d, const float *conic,
                            const float *opacity, const int32_t *sorted_ids, const int32_t *tile_ranges,
                            const int32_t *n_contrib, const int32_t *topk_ids, int32_t *topk_count,
-                           float *max_w, hipStream_t stream);
+                           float *max_w, const int32_t *tile_order, hipStream_t stream);
 
 /*
  * Workspace bytes of lgs_prune_select for n Gaussians.  *bytes is a host pointer.

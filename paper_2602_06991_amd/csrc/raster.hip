@@ -681,7 +681,7 @@ extern "C" lgs_status lgs_prune_stats_views(const lgs_camera *cams, int32_t view
                                             const float *mean2d, const float *conic, const float *opacity,
                                             const int32_t *sorted_ids, const int32_t *tile_ranges,
                                             const int32_t *n_contrib, const int32_t *topk_ids, int32_t *topk_count,
-                                            float *max_w, hipStream_t stream) {
+                                            float *max_w, const int32_t *tile_order, hipStream_t stream) {
     RasterArgs a;
     lgs_status st = raster_args(cams, views, n, a);
     if (st) return st;
@@ -698,6 +698,7 @@ extern "C" lgs_status lgs_prune_stats_views(const lgs_camera *cams, int32_t view
     a.depth = nullptr;
     a.sorted_ids = sorted_ids;
     a.ranges = (const int2 *)tile_ranges;
+    a.order = tile_order;
 #define CALL_PRUNE(KK) launch_prune<KK>(a, n_contrib, topk_ids, topk_count, max_w, stream)
     LGS_K_SWITCH(k, CALL_PRUNE)
 #undef CALL_PRUNE
@@ -708,9 +709,9 @@ extern "C" lgs_status lgs_prune_stats(const lgs_camera *cam, int32_t k, const fl
                                       const float *opacity, const int32_t *sorted_ids,
                                       const int32_t *tile_ranges, const int32_t *n_contrib,
                                       const int32_t *topk_ids, int32_t *topk_count, float *max_w,
-                                      hipStream_t stream) {
+                                      const int32_t *tile_order, hipStream_t stream) {
     return lgs_prune_stats_views(cam, 1, k, 0x7FFFFFFF, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib,
-                                 topk_ids, topk_count, max_w, stream);
+                                 topk_ids, topk_count, max_w, tile_order, stream);
 }
 
 // The order buffer: the grid's entries, then as many again for the tile weights.

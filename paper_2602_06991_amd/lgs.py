@@ -69,7 +69,7 @@ _SIG = {
                                ctypes.c_int, _P, _P, _P, _P],
     "lgs_feature_render_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
                                   ctypes.c_int, _P, _F, _P, _P, _P],
-    "lgs_prune_stats": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_prune_stats": [_CAM, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_prune_select_workspace": [_I32, ctypes.POINTER(ctypes.c_size_t)],
     "lgs_prune_select": [_I32, _P, _P, _I32, _P, _F, _P, ctypes.c_size_t, _P, _P],
     "lgs_feature_render_fwd_bwd_l1": [_I32, _I32, _I32, _I32, _I32, ctypes.c_int, _P, _P, _P, _P,
@@ -86,7 +86,7 @@ _SIG = {
     "lgs_rasterize_topk_bwd_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                      _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_project_bwd_views": [_CAM, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
-    "lgs_prune_stats_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lgs_prune_stats_views": [_CAM, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lgs_feature_render_vanilla_fwd": [_CAM, _P, _P, _P, _P, _P, _P, _I32, ctypes.c_int, _P, _P, ctypes.c_int,
                                        _P, _P],
     "lgs_feature_render_vanilla_bwd": [_CAM, _P, _P, _P, _P, _P, _P, _P, _I32, ctypes.c_int, _P, _P,
@@ -235,9 +235,9 @@ def lgs_feature_render_fwd_bwd_l1(width, height, views, k, d, feat_dt, feat, fea
 
 
 def lgs_prune_stats(cam, k, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib, topk_ids, topk_count,
-                    max_w, stream=None):
+                    max_w, stream=None, tile_order=None):
     return _check(load().lgs_prune_stats(ctypes.byref(cam), k, mean2d, conic, opacity, sorted_ids, tile_ranges,
-                                         n_contrib, topk_ids, topk_count, max_w, stream))
+                                         n_contrib, topk_ids, topk_count, max_w, tile_order, stream))
 
 
 def lgs_prune_select_workspace(n):
@@ -357,9 +357,9 @@ def lgs_project_bwd_views(cams, views, n, means, log_scales, quats, opacity_logi
 
 
 def lgs_prune_stats_views(cams, views, k, n, mean2d, conic, opacity, sorted_ids, tile_ranges, n_contrib, topk_ids,
-                          topk_count, max_w, stream=None):
+                          topk_count, max_w, stream=None, tile_order=None):
     return _check(load().lgs_prune_stats_views(cams, views, k, n, mean2d, conic, opacity, sorted_ids, tile_ranges,
-                                               n_contrib, topk_ids, topk_count, max_w, stream))
+                                               n_contrib, topk_ids, topk_count, max_w, tile_order, stream))
 
 
 def lgs_quantize_features(n, d, src, dst_dt, dst, dst_scale, stream=None):

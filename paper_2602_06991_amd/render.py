@@ -156,12 +156,13 @@ def rasterize(cam, K, proj, rgb, sorted_ids, ranges, order=None):
     return out
 
 
-def prune_stats(cam, K, proj, sorted_ids, ranges, fwd, topk_count, max_w):
+def prune_stats(cam, K, proj, sorted_ids, ranges, fwd, topk_count, max_w, order=None):
     """Sec. 3.3 statistics of one view, accumulated: Top-K participation counts
     (int32 [N]) and the maximum blending weight S (FP32 [N], Eq. 5)."""
     _need_cuda(topk_count, max_w)
     lgs.lgs_prune_stats(cam, K, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["opacity"]), _p(sorted_ids),
-                        _p(ranges), _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(topk_count), _p(max_w), _stream())
+                        _p(ranges), _p(fwd["n_contrib"]), _p(fwd["ids"]), _p(topk_count), _p(max_w), _stream(),
+                        tile_order=_p(order))
 
 
 def prune_select(topk_count, max_w, count_below, expo, keep_ratio=0.5):

@@ -3,8 +3,8 @@ result.  Checked on one 1200x680 view (tiles dealt to the XCDs in strips) and on
 8 keyframes of the 640x480 room workload (whole views per XCD), for both weights (the
 pair counts; the forward's largest n_contrib per tile): the order is a permutation of
 the padded grid; each XCD keeps the tiles the fixed mapping gives it, heaviest weight
-bucket first; the blend with the order gives the same bits as without; the adjoint's
-atomic sums match to summation order."""
+bucket first; the blend and the pruning statistics with the order give the same bits
+as without; the adjoint's atomic sums match to summation order."""
 import numpy as np
 import pytest
 
@@ -113,6 +113,20 @@ def test_tile_order_changes_no_result(torch, cfg, K, N):
     bwd(f0, s1, order)
     bwd(f0, s2, border)
     torch.cuda.synchronize()
+    # the pruning statistics (integer counts, maxima of non-negative weights): the same bits
+    stats = []
+    for o in (None, border):
+        cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+        mxw = torch.zeros(n, device="cuda")
+        lgs.lgs_prune_stats_views(cams if V > 1 else lgs.camera_array([cams]), V, K, n, proj["mean2d"].data_ptr(),
+                                  proj["conic"].data_ptr(), proj["opacity"].data_ptr(), ids.data_ptr(),
+                                  ranges.data_ptr(), f0["n_contrib"].data_ptr(), f0["ids"].data_ptr(),
+                                  cnt.data_ptr(), mxw.data_ptr(), torch.cuda.current_stream().cuda_stream,
+                                  tile_order=None if o is None else o.data_ptr())
+        stats.append((cnt, mxw))
+    torch.cuda.synchronize()
+    assert torch.equal(stats[0][0], stats[1][0]) and torch.equal(stats[0][1], stats[1][1])
+    assert int(stats[0][0].sum()) > 0
     for k in s0:
         a = s0[k].double()
         for name, sx in (("pair-count order", s1), ("n_contrib order", s2)):
